@@ -1,0 +1,139 @@
+"""CPU oracle for the lane-detection hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  The product library never imports, links
+or calls it; the oracle imports nothing from the product.
+
+``lane_oracle.c`` holds the integer path (Sobel + binarize, Q14 vote, greedy
+NMS peaks) as plain nested loops; ``cnn.py`` the FP64 proposal network and its
+analytic backward; ``learned.py`` tile labels, masks and peak agreement.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblane_oracle.so")
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile lane_oracle.c with gcc (plain -O2, no vector intrinsics)."""
+    src = os.path.join(_HERE, "lane_oracle.c")
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int
+        lib.oracle_sobel_binarize.restype = ctypes.c_int64
+        lib.oracle_sobel_binarize.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+        lib.oracle_hough_vote.restype = ctypes.c_int64
+        lib.oracle_hough_vote.argtypes = [vp, i32, i32, i32, vp, vp, i32, i32, i32, vp, vp,
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_hough_peaks.restype = i32
+        lib.oracle_hough_peaks.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp]
+        lib.oracle_band_bits.restype = i32
+        lib.oracle_band_bits.argtypes = [i32, i32]
+        lib.oracle_r_offset.restype = i32
+        lib.oracle_r_offset.argtypes = [i32, i32]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def sobel_binarize(img: np.ndarray, W: int | None = None, threshold: int = 128,
+                   border_mode: int = 1):
+    """Return (edges[H][W] uint8 0/255, mag[H][W] uint8, n_edges).
+
+    ``img`` is uint8 [H][pitch]; ``W`` defaults to the pitch."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, pitch = img.shape
+    W = pitch if W is None else W
+    edges = np.zeros((H, W), np.uint8)
+    mag = np.zeros((H, W), np.uint8)
+    n = _load().oracle_sobel_binarize(_ptr(img), W, H, pitch, int(threshold), int(border_mode),
+                                      _ptr(edges), _ptr(mag))
+    return edges, mag, int(n)
+
+
+def hough_vote(edges: np.ndarray, cos_q14: np.ndarray, sin_q14: np.ndarray, r_offset: int,
+               n_r: int, tile_mask: np.ndarray | None = None, W: int | None = None):
+    """Return (acc[n_theta][n_r] int32, votes cast, dropped)."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint8)
+    H, epitch = edges.shape
+    W = epitch if W is None else W
+    C = np.ascontiguousarray(cos_q14, dtype=np.int16)
+    S = np.ascontiguousarray(sin_q14, dtype=np.int16)
+    n_theta = C.shape[0]
+    acc = np.zeros((n_theta, n_r), np.int32)
+    if tile_mask is not None:
+        tile_mask = np.ascontiguousarray(tile_mask, dtype=np.uint8)
+        assert tile_mask.shape == ((H + 7) // 8, (W + 7) // 8)
+    dropped = ctypes.c_int64(0)
+    cast = _load().oracle_hough_vote(_ptr(edges), W, H, epitch, _ptr(C), _ptr(S), n_theta,
+                                     int(r_offset), int(n_r), _ptr(tile_mask), _ptr(acc),
+                                     ctypes.byref(dropped))
+    return acc, int(cast), int(dropped.value)
+
+
+def default_nms(n_theta: int, n_r: int) -> tuple[int, int]:
+    """Default half-window: max(1, ceil(n/100)) on each axis."""
+    return max(1, -(-n_theta // 100)), max(1, -(-n_r // 100))
+
+
+def hough_peaks(acc: np.ndarray, r_offset: int, k: int, h_theta: int | None = None,
+                h_r: int | None = None, min_votes: int = 1):
+    """Return (theta_idx[k], r_idx[k], votes[k]) int32, -1 padded, and count."""
+    acc = np.ascontiguousarray(acc, dtype=np.int32)
+    n_theta, n_r = acc.shape
+    dt, dr = default_nms(n_theta, n_r)
+    h_theta = dt if h_theta is None else h_theta
+    h_r = dr if h_r is None else h_r
+    t = np.zeros(k, np.int32)
+    r = np.zeros(k, np.int32)
+    v = np.zeros(k, np.int32)
+    n = _load().oracle_hough_peaks(_ptr(acc), n_theta, n_r, int(r_offset), int(k), int(h_theta),
+                                   int(h_r), int(min_votes), _ptr(t), _ptr(r), _ptr(v))
+    if n < 0:
+        raise ValueError("bad peak arguments")
+    return t, r, v, n
+
+
+def band_bits(n_theta: int) -> np.ndarray:
+    lib = _load()
+    return np.array([lib.oracle_band_bits(n_theta, k) for k in range(n_theta)], np.uint8)
+
+
+def r_offset(W: int, H: int) -> int:
+    return int(_load().oracle_r_offset(W, H))
+
+
+def pipeline(img: np.ndarray, cos_q14, sin_q14, k: int, threshold: int = 128,
+             border_mode: int = 1, tile_mask=None):
+    """Sobel -> binarize -> vote -> peaks on one frame; returns a dict."""
+    H, W = img.shape
+    D = r_offset(W, H)
+    n_r = 2 * D + 1
+    edges, mag, n_e = sobel_binarize(img, W, threshold, border_mode)
+    acc, cast, dropped = hough_vote(edges, cos_q14, sin_q14, D, n_r, tile_mask)
+    t, r, v, n = hough_peaks(acc, D, k)
+    return dict(edges=edges, mag=mag, n_edges=n_e, acc=acc, cast=cast, dropped=dropped,
+                theta_idx=t, r_idx=r, votes=v, count=n, D=D, n_r=n_r)

@@ -1,0 +1,359 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test names the passage of the paper it follows.  None of them re-types
+the oracle's own formula as the expectation: they use closed forms of the
+Sobel operator (Sec. 2.1 Eq. 1), invariants of the vote (Sec. 2.3 Eq. 3),
+the real-valued line equation with its Q14 error bound, a library
+correlation, and brute force on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+# Sobel kernels written out (Sec. 2.1; coefficients only take the forms
+# 0, 1 and 2 per Sec. 3.1).  Correlation (not convolution) orientation; the
+# absolute values in Eq. (1) make the orientation irrelevant.
+KX = np.array([[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]], np.int64)
+KY = KX.T.copy()
+
+
+def lib_sobel(img):
+    a = img.astype(np.int64)
+    gx = ndimage.correlate(a, KX, mode="constant", cval=0)
+    gy = ndimage.correlate(a, KY, mode="constant", cval=0)
+    return np.abs(gx) + np.abs(gy)
+
+
+# ------------------------------------------------------------ Sobel (P1-P4)
+
+@pytest.mark.parametrize("c", [0, 1, 7, 40, 63, 64, 90, 200, 255])
+def test_constant_image_closed_form(oracle, c):
+    H, W = 9, 13
+    img = np.full((H, W), c, np.uint8)
+    edges, mag, n = oracle.sobel_binarize(img, threshold=128, border_mode=0)
+    # interior gradient is zero
+    assert (mag[1:-1, 1:-1] == 0).all()
+    # zero padding: sides see 4c, corners 6c (gx = gy = 3c)
+    side = min(4 * c, 255)
+    corner = min(6 * c, 255)
+    assert (mag[0, 1:-1] == side).all() and (mag[-1, 1:-1] == side).all()
+    assert (mag[1:-1, 0] == side).all() and (mag[1:-1, -1] == side).all()
+    for y, x in [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1)]:
+        assert mag[y, x] == corner
+    assert (edges[1:-1, 1:-1] == 0).all()
+    assert (edges[0, 1:-1] == (255 if 4 * c > 128 else 0)).all()
+    # mode 1 forces the ring to non-edge but keeps the magnitude
+    e1, m1, n1 = oracle.sobel_binarize(img, threshold=128, border_mode=1)
+    assert n1 == 0 and (e1 == 0).all() and (m1 == mag).all()
+
+
+@pytest.mark.parametrize("a,b,c0", [(1, 0, 3), (0, 2, 5), (3, 4, 0), (-2, 1, 120), (5, -3, 150)])
+def test_linear_ramp_closed_form(oracle, a, b, c0):
+    H, W = 12, 15
+    y, x = np.mgrid[0:H, 0:W]
+    v = a * x + b * y + c0
+    assert v.min() >= 0 and v.max() <= 255
+    img = v.astype(np.uint8)
+    _, mag, _ = oracle.sobel_binarize(img, threshold=255, border_mode=0)
+    assert (mag[1:-1, 1:-1] == min(8 * (abs(a) + abs(b)), 255)).all()
+
+
+@pytest.mark.parametrize("h", [1, 10, 31, 32, 33, 60])
+def test_vertical_step(oracle, h):
+    H, W, x0 = 10, 16, 7
+    img = np.full((H, W), 50, np.uint8)
+    img[:, x0:] += h
+    edges, mag, _ = oracle.sobel_binarize(img, threshold=128, border_mode=1)
+    g = np.zeros((H, W), np.int64)
+    g[:, x0 - 1] = 4 * h
+    g[:, x0] = 4 * h
+    assert (mag[1:-1, 1:-1] == np.minimum(g, 255)[1:-1, 1:-1]).all()
+    # threshold is strict: 4*32 = 128 is not an edge, 4*33 = 132 is
+    want = 255 if 4 * h > 128 else 0
+    assert (edges[1:-1, x0 - 1] == want).all() and (edges[1:-1, x0] == want).all()
+    others = np.delete(edges[1:-1, 1:-1], [x0 - 2, x0 - 1], axis=1)
+    assert (others == 0).all()
+
+
+def test_step_threshold_boundary(oracle):
+    img = np.zeros((5, 6), np.uint8)
+    img[:, 3:] = 32
+    e, _, _ = oracle.sobel_binarize(img, threshold=128, border_mode=1)
+    assert (e == 0).all()
+    img[:, 3:] = 33
+    e, _, _ = oracle.sobel_binarize(img, threshold=128, border_mode=1)
+    assert (e[1:-1, 2:4] == 255).all()
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (7, 1), (3, 3), (8, 8), (13, 29), (32, 32)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sobel_vs_library_correlation(oracle, shape, seed):
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 256, size=shape, dtype=np.uint8)
+    g = lib_sobel(img)
+    for T in (0, 100, 128, 254):
+        for mode in (0, 1):
+            e, m, n = oracle.sobel_binarize(img, threshold=T, border_mode=mode)
+            want_e = np.where(g > T, 255, 0)
+            if mode == 1:
+                want_e[0, :] = 0
+                want_e[-1, :] = 0
+                want_e[:, 0] = 0
+                want_e[:, -1] = 0
+            assert (m == np.minimum(g, 255)).all()
+            assert (e == want_e).all()
+            assert n == int((want_e == 255).sum())
+
+
+def test_sobel_pitch(oracle):
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(11, 20), dtype=np.uint8)
+    e0, m0, _ = oracle.sobel_binarize(img[:, :17].copy(), threshold=128)
+    e1, m1, _ = oracle.sobel_binarize(img, W=17, threshold=128)
+    assert (e0 == e1).all() and (m0 == m1).all()
+
+
+# ------------------------------------------------------------ vote (P5-P9)
+
+def test_trig_table_spot_values(synth):
+    c, s = synth.trig_q14(180)
+    assert c[0] == 16384 and s[0] == 0          # theta = 0
+    assert c[90] == 0 and s[90] == 16384        # theta = 90 deg
+    assert c[60] == 8192 and s[30] == 8192      # cos 60 = sin 30 = 1/2
+    assert c[45] == 11585 and s[45] == 11585    # 2^14/sqrt(2) = 11585.24
+    assert c[135] == -11585 and s[135] == 11585
+    # symmetry of Eq. (4)-(5): sin(180-t) = sin t, cos(180-t) = -cos t
+    for k in range(1, 180):
+        assert s[180 - k] == s[k] and c[180 - k] == -c[k]
+
+
+def _single_point(W, H, x, y):
+    e = np.zeros((H, W), np.uint8)
+    e[y, x] = 255
+    return e
+
+
+@pytest.mark.parametrize("n_theta", [4, 180, 360])
+@pytest.mark.parametrize("pt", [(0, 0), (5, 3), (39, 29), (17, 0), (0, 22)])
+def test_one_point_one_vote_per_theta(oracle, synth, n_theta, pt):
+    W, H = 40, 30
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, cast, dropped = oracle.hough_vote(_single_point(W, H, *pt), C, S, D, 2 * D + 1)
+    assert dropped == 0 and cast == n_theta
+    assert (acc.sum(axis=1) == 1).all()
+    x, y = pt
+    # theta = 0 gives r = x, theta = 90 deg gives r = y (Eq. 3 exactly)
+    assert acc[0, x + D] == 1
+    if n_theta % 2 == 0:
+        assert acc[n_theta // 2, y + D] == 1
+    # every vote lies within the Q14 error bound of the real-valued Eq. (3)
+    ks, ii = np.nonzero(acc)
+    th = ks * math.pi / n_theta
+    r_true = x * np.cos(th) + y * np.sin(th)
+    assert (np.abs((ii - D) - r_true) <= 0.5 + (x + y) / 2 ** 15 + 1e-9).all()
+
+
+def test_total_votes_invariant(oracle, synth):
+    rng = np.random.default_rng(11)
+    W, H = 53, 37
+    e = np.where(rng.random((H, W)) < 0.2, 255, 0).astype(np.uint8)
+    n_e = int((e == 255).sum())
+    for n_theta in (180, 360, 7):
+        C, S = synth.trig_q14(n_theta)
+        D = synth.r_offset(W, H)
+        acc, cast, dropped = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+        assert dropped == 0
+        assert acc.sum() + dropped == n_e * n_theta
+        assert (acc.sum(axis=1) == n_e).all()
+
+
+def test_dropped_counted_when_range_too_small(oracle, synth):
+    rng = np.random.default_rng(5)
+    W, H = 30, 20
+    e = np.where(rng.random((H, W)) < 0.3, 255, 0).astype(np.uint8)
+    n_e = int((e == 255).sum())
+    C, S = synth.trig_q14(90)
+    acc, cast, dropped = oracle.hough_vote(e, C, S, 3, 11)
+    assert dropped > 0 and acc.sum() == cast and cast + dropped == n_e * 90
+
+
+def test_extremes_at_corners(oracle, synth):
+    """r is monotone in x and y, so per theta the extreme r of a full frame
+    is reached at one of the four corners."""
+    W, H = 31, 17
+    e = np.full((H, W), 255, np.uint8)
+    C, S = synth.trig_q14(180)
+    D = synth.r_offset(W, H)
+    acc, _, dropped = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    assert dropped == 0
+    corners = np.zeros((H, W), np.uint8)
+    for (x, y) in [(0, 0), (W - 1, 0), (0, H - 1), (W - 1, H - 1)]:
+        corners[y, x] = 255
+    accc, _, _ = oracle.hough_vote(corners, C, S, D, 2 * D + 1)
+    for k in range(180):
+        nz = np.nonzero(acc[k])[0]
+        nzc = np.nonzero(accc[k])[0]
+        assert nz.min() == nzc.min() and nz.max() == nzc.max()
+
+
+@pytest.mark.parametrize("k0,r0", [(0, 20), (30, 25), (45, 60), (90, 12), (120, 5), (150, -8),
+                                   (179, -3), (100, 40), (60, 90)])
+def test_drawn_line_peaks_at_its_own_bin(oracle, synth, k0, r0):
+    """Mark the pixels on the real line x cos t + y sin t = r0 (within 0.3 px;
+    the Q14 error is far below the remaining 0.2 px), vote, and the cell
+    (k0, r0) must count every marked pixel and be the strict maximum (the
+    frame is large enough that no neighbouring bin holds the whole line)."""
+    W, H, n_theta = 220, 160, 180
+    th = k0 * math.pi / n_theta
+    y, x = np.mgrid[0:H, 0:W]
+    on = np.abs(x * math.cos(th) + y * math.sin(th) - r0) < 0.3
+    if on.sum() < 8:
+        pytest.skip("line too short in this frame")
+    e = np.where(on, 255, 0).astype(np.uint8)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, _, dropped = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    assert dropped == 0
+    assert acc[k0, r0 + D] == on.sum()
+    flat = acc.ravel()
+    assert flat.max() == on.sum()
+    assert (flat == flat.max()).sum() == 1
+    t, r, v, n = oracle.hough_peaks(acc, D, 1)
+    assert n == 1 and t[0] == k0 and r[0] == r0 + D and v[0] == on.sum()
+
+
+def test_band_bits_cover_each_theta_twice(oracle):
+    for n in (8, 180, 360):
+        bb = oracle.band_bits(n)
+        assert all(bin(int(b)).count("1") == 2 for b in bb)
+    bb = oracle.band_bits(360)
+    # band b = [45b, 45b+90) mod 360 for 360 bins
+    for b in range(8):
+        ks = [k for k in range(360) if bb[k] >> b & 1]
+        assert len(ks) == 90
+        assert set(ks) == {(45 * b + j) % 360 for j in range(90)}
+
+
+def test_mask_all_ones_zero_and_subset(oracle, synth):
+    rng = np.random.default_rng(2)
+    W, H = 45, 27
+    e = np.where(rng.random((H, W)) < 0.25, 255, 0).astype(np.uint8)
+    C, S = synth.trig_q14(180)
+    D = synth.r_offset(W, H)
+    plain, cast, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    th, tw = (H + 7) // 8, (W + 7) // 8
+    full = np.full((th, tw), 0xFF, np.uint8)
+    a1, c1, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1, full)
+    assert (a1 == plain).all() and c1 == cast
+    zero = np.zeros((th, tw), np.uint8)
+    a0, c0, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1, zero)
+    assert a0.sum() == 0 and c0 == 0
+    m = rng.integers(0, 256, size=(th, tw), dtype=np.uint8)
+    am, cm, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1, m)
+    assert (am <= plain).all()
+    # brute-force count of the pruned votes from the band definition
+    bb = oracle.band_bits(180)
+    ys, xs = np.nonzero(e == 255)
+    want = sum(int(((m[y // 8, x // 8] & bb) != 0).sum()) for y, x in zip(ys, xs))
+    assert cm == want
+
+
+def test_vote_vs_brute_force_histogram(oracle, synth):
+    """Independent formulation: for every theta, a histogram (np.bincount) of
+    the rounded r of all edge pixels, with r rounded by real division."""
+    rng = np.random.default_rng(9)
+    W, H = 33, 21
+    e = np.where(rng.random((H, W)) < 0.3, 255, 0).astype(np.uint8)
+    C, S = synth.trig_q14(60)
+    D = synth.r_offset(W, H)
+    acc, _, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    ys, xs = np.nonzero(e == 255)
+    for k in range(60):
+        v = xs.astype(np.int64) * int(C[k]) + ys.astype(np.int64) * int(S[k])
+        r = np.array([math.floor(val / 16384 + 0.5) for val in v.tolist()])
+        hist = np.bincount(r + D, minlength=2 * D + 1)
+        assert (hist == acc[k]).all()
+
+
+# ------------------------------------------------------------ peaks (P10)
+
+def _brute_peaks(acc, D, k, ht, hr, min_votes=1):
+    """Greedy NMS stated on lines rather than rows/columns: cell (t, i) is the
+    line (theta_t, r = i - D), and (t + n, i) is the same line as
+    (t, 2D - i) because (r, theta + 180) == (-r, theta).  A cell is
+    suppressed if some selected line lies within the window after unfolding
+    theta by any whole number of half turns."""
+    n_theta, n_r = acc.shape
+    sel = []
+    alive = np.ones_like(acc, dtype=bool)
+    out = []
+    for _ in range(k):
+        best = None
+        for t in range(n_theta):
+            for i in range(n_r):
+                if alive[t, i] and (best is None or acc[t, i] > acc[best]):
+                    best = (t, i)
+        if best is None or acc[best] < max(1, min_votes):
+            break
+        out.append((best[0], best[1], int(acc[best])))
+        sel.append(best)
+        t0, i0 = best
+        for t in range(n_theta):
+            for i in range(n_r):
+                for q in range(-3, 4):
+                    tt = t + q * n_theta
+                    ii = (2 * D - i) if q % 2 else i
+                    if abs(tt - t0) <= ht and abs(ii - i0) <= hr:
+                        alive[t, i] = False
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_peaks_vs_brute_force(oracle, seed):
+    rng = np.random.default_rng(seed)
+    n_theta, D = int(rng.integers(3, 9)), int(rng.integers(2, 6))
+    n_r = 2 * D + 1
+    acc = rng.integers(0, 6, size=(n_theta, n_r)).astype(np.int32)
+    for k in (1, 3, 6):
+        for ht, hr in ((0, 0), (1, 1), (2, 1), (1, 3)):
+            t, r, v, n = oracle.hough_peaks(acc, D, k, ht, hr)
+            want = _brute_peaks(acc, D, k, ht, hr)
+            assert n == len(want)
+            got = [(int(t[j]), int(r[j]), int(v[j])) for j in range(n)]
+            assert got == want
+            assert (t[n:] == -1).all() and (r[n:] == -1).all() and (v[n:] == -1).all()
+
+
+def test_peaks_tie_and_wrap_cases(oracle):
+    D = 3
+    acc = np.zeros((5, 7), np.int32)
+    # two equal maxima: the smaller theta-major index wins
+    acc[1, 2] = 9
+    acc[3, 5] = 9
+    t, r, v, n = oracle.hough_peaks(acc, D, 1, 0, 0)
+    assert (t[0], r[0], v[0]) == (1, 2, 9)
+    # wrap: a peak in the last row suppresses mirrored columns of row 0
+    acc = np.zeros((5, 7), np.int32)
+    acc[4, 1] = 10
+    acc[0, 5] = 8      # mirror of column 1 is 2*3 - 1 = 5 -> suppressed
+    acc[0, 1] = 7      # same column, not mirrored -> survives
+    t, r, v, n = oracle.hough_peaks(acc, D, 3, 1, 0)
+    assert n == 2
+    assert (t[0], r[0]) == (4, 1) and (t[1], r[1], v[1]) == (0, 1, 7)
+    # min_votes stops early
+    t, r, v, n = oracle.hough_peaks(acc, D, 3, 0, 0, min_votes=9)
+    assert n == 1 and t[1] == -1
+    # all-zero accumulator: no peaks
+    t, r, v, n = oracle.hough_peaks(np.zeros((4, 7), np.int32), D, 2)
+    assert n == 0 and (t == -1).all()
+
+
+def test_r_offset_matches_integer_sqrt(oracle, synth):
+    for W, H in [(1, 1), (2, 1), (640, 480), (1920, 1080), (3840, 2160), (1280, 720), (8192, 8192)]:
+        assert oracle.r_offset(W, H) == synth.r_offset(W, H)
+        d = oracle.r_offset(W, H)
+        q = (W - 1) ** 2 + (H - 1) ** 2
+        assert d * d >= q and (d - 1) * (d - 1) < q or q == 0
