@@ -1,0 +1,155 @@
+/*
+ * lane.h -- C ABI of the MI355X (gfx950) lane-detection hot path.
+ *
+ * The path follows "Hardware Acceleration of Lane Detection Algorithm: A GPU
+ * Versus FPGA Comparison" (arXiv 2212.09460):
+ *   Sobel edge magnitude |Sx*Img| + |Sy*Img|            Sec. 2.1, Eq. (1)
+ *   zero padding so the output keeps the input size     Sec. 3.1, Sec. 4.1
+ *   binarization of every pixel to 255 or 0             Sec. 2.2
+ *   Hough voting r = x cos(theta) + y sin(theta)        Sec. 2.3, Eq. (3)
+ *   into a (theta, r) accumulator ("Hough matrix")      Sec. 2.3, Sec. 3.3
+ *   peak extraction (largest counts = lines)            Sec. 2.3
+ *
+ * Conventions for every entry point:
+ *   - Return value: LANE_OK (0) or a negative LANE_E_* code.  Argument errors
+ *     are detected before anything is enqueued; a kernel fault surfaces at the
+ *     caller's next synchronisation of the stream.
+ *   - Pointers named "device" are HIP device pointers (e.g. from a torch
+ *     tensor); "host" pointers are ordinary host memory.  The caller owns all
+ *     buffers.  Data-path calls never allocate and keep no pointer after they
+ *     return.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued asynchronously on it.
+ *   - Frames are uint8 gray images [H][pitch], row-major, pitch >= W.
+ *     1 <= W, H <= 8192.
+ *   - Coordinates: origin at the top-left pixel, x = column, y = row.
+ *   - theta_k = k * 180 / n_theta degrees, k in [0, n_theta).
+ *   - cos/sin come as a Q14 table: C[k] ~ 2^14 cos(theta_k), S[k] ~ 2^14
+ *     sin(theta_k), int16.  A pixel (x, y) votes in row k at column
+ *       r_idx = floor((x*C[k] + y*S[k] + 2^13) / 2^14) + r_offset,
+ *     i.e. Eq. (3) rounded half up; a vote with r_idx outside [0, n_r) is
+ *     dropped and counted.
+ *   - Calls are stateless and reentrant.
+ */
+#ifndef LANE_H_
+#define LANE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LANE_ABI_VERSION 1
+
+enum {
+    LANE_OK = 0,
+    LANE_E_ARG = -1,         /* null required pointer, size <= 0, pitch < W, k < 1, misaligned buffer */
+    LANE_E_SIZE = -2,        /* W or H > 8192, or a product overflowing the index types */
+    LANE_E_RANGE = -3,       /* r_offset / n_r not as required (peaks need n_r == 2*r_offset + 1) */
+    LANE_E_WS = -4,          /* workspace too small */
+    LANE_E_DEVICE = -5,      /* HIP launch or runtime error */
+    LANE_E_UNSUPPORTED = -6  /* e.g. an unsupported border mode */
+};
+
+enum { LANE_BORDER_ZERO = 0, LANE_BORDER_ZERO_MASKRING = 1 };
+
+#define LANE_MAX_DIM 8192
+
+int lane_abi_version(void);
+const char *lane_strerror(int status);
+
+/* Host helper.  Fills cos_q14[n_theta], sin_q14[n_theta] (host) with
+ * round-half-away-from-zero of 2^14 cos / sin of theta_k (Sec. 3.3: the
+ * per-angle constants of each processing element; Sec. 4.3: cos and sin
+ * computed once per angle).  Any table may be passed to the vote; this one
+ * is the usual choice. */
+int lane_make_trig_q14(int32_t n_theta, int16_t *cos_q14, int16_t *sin_q14);
+
+/* Host helper.  *D_out = ceil(sqrt((W-1)^2 + (H-1)^2)), the largest |r| of
+ * Eq. (3) over the frame; the usual accumulator is r_offset = D,
+ * n_r = 2*D + 1. */
+int lane_r_offset(int32_t W, int32_t H, int32_t *D_out);
+
+/* Size in bytes of the compacted edge list of a W x H frame (the buffer
+ * `list` below).  Layout, all uint32, counted from the buffer start:
+ *   seg_count[n_seg]              edges in each segment
+ *   tile_info[th*tw]              (count << 16) | start of each 8x8 tile's
+ *                                 run inside its segment
+ *   entries[n_seg][8192] at a 16-byte aligned offset: (y << 16) | x of each
+ *                                 edge pixel, grouped by tile, tiles of a
+ *                                 segment in x order, pixels of a tile in
+ *                                 row-major order
+ * with th = ceil(H/8), tw = ceil(W/8), a segment = one 8-row tile row times
+ * 1024 columns, n_seg = th * ceil(W/1024). */
+int lane_edge_list_size(int32_t W, int32_t H, size_t *bytes);
+
+/* Sobel + binarize (Sec. 2.1 Eq. (1), Sec. 2.2, zero padding Sec. 3.1/4.1),
+ * fused with the edge compaction the vote reads (Sec. 4.3: the vote reads
+ * the coordinates of the edge pixels from global memory).
+ *   img       device, uint8 [H][pitch]
+ *   threshold a pixel is an edge iff |gx| + |gy| > threshold (0..255)
+ *   border_mode LANE_BORDER_ZERO: plain zero padding; LANE_BORDER_ZERO_MASKRING:
+ *             zero padding, and the one-pixel frame ring is forced to 0 in
+ *             `edges` (the magnitude is unchanged)
+ *   edges     device, uint8 [H][W], receives 255 / 0
+ *   mag_opt   device, uint8 [H][W] or NULL: min(|gx| + |gy|, 255)
+ *   list_opt  device, lane_edge_list_size() bytes, 16-byte aligned, or NULL
+ *   edge_count_opt device uint32 scalar or NULL: number of edge pixels */
+int lane_sobel_binarize(const uint8_t *img, int32_t W, int32_t H, int32_t pitch,
+                        int32_t threshold, int32_t border_mode, uint8_t *edges,
+                        uint8_t *mag_opt, uint32_t *list_opt, uint32_t *edge_count_opt,
+                        void *stream);
+
+/* Compaction alone: builds the edge list from an existing edge map (a pixel
+ * is an edge iff it equals 255, Sec. 3.3).  edges: device uint8 [H][pitch]. */
+int lane_edges_to_list(const uint8_t *edges, int32_t W, int32_t H, int32_t pitch,
+                       uint32_t *list, uint32_t *edge_count_opt, void *stream);
+
+/* Hough vote (Sec. 2.3 Eq. (3); one accumulator row per theta as in the
+ * per-angle partition of Sec. 4.3).
+ *   list      device, the edge list of a W x H frame (lane_sobel_binarize or
+ *             lane_edges_to_list)
+ *   cos_q14, sin_q14  device, int16 [n_theta]
+ *   r_offset, n_r     accumulator columns: r_idx = r + r_offset in [0, n_r)
+ *   tile_mask_opt     device uint8 [ceil(H/8)][ceil(W/8)] or NULL.  If given,
+ *             an edge in tile t votes in row k only if
+ *             tile_mask[t] & band_bits(k) != 0, where band b (0..7) holds
+ *             the k with ((k - floor(b*n_theta/8)) mod n_theta) < n_theta/4
+ *             (requires n_theta % 4 == 0); NULL votes every row.
+ *   acc       device, int32 [n_theta][n_r], fully overwritten
+ *   dropped_opt device uint32 scalar or NULL: votes outside [0, n_r)
+ * Results do not depend on the order of the list (integer sums). */
+int lane_hough_vote(const uint32_t *list, int32_t W, int32_t H, const int16_t *cos_q14,
+                    const int16_t *sin_q14, int32_t n_theta, int32_t r_offset, int32_t n_r,
+                    const uint8_t *tile_mask_opt, int32_t *acc, uint32_t *dropped_opt,
+                    void *stream);
+
+/* Workspace bytes for lane_hough_peaks on an n_theta x n_r accumulator. */
+int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t *bytes);
+
+/* Hough peaks (Sec. 2.3: the largest counts are the lines; the paper leaves
+ * the procedure to MATLAB, so it is specified here).  Greedy non-maximum
+ * suppression: repeat up to k times -- take the largest cell not yet
+ * suppressed (ties: smallest theta-major index); stop if its count is below
+ * max(1, min_votes); emit it; suppress the cells with |dtheta| <= h_theta
+ * and |dr| <= h_r around it, where a row index past either end wraps around
+ * and, for an odd number of wraps, the column window is centred on the
+ * mirrored index 2*r_offset - r_idx (the line (r, theta + 180deg) is the
+ * line (-r, theta)).
+ *   acc        device int32 [n_theta][n_r]; requires n_r == 2*r_offset + 1
+ *   k >= 1, h_theta >= 0, h_r >= 0
+ *   theta_idx, r_idx, votes  device int32 [k], -1 after the last peak
+ *   count      device int32 scalar: peaks found
+ *   ws         device, >= lane_hough_peaks_workspace_size() bytes, 16-byte aligned */
+int lane_hough_peaks(const int32_t *acc, int32_t n_theta, int32_t n_r, int32_t r_offset,
+                     int32_t k, int32_t h_theta, int32_t h_r, int32_t min_votes,
+                     int32_t *theta_idx, int32_t *r_idx, int32_t *votes, int32_t *count,
+                     void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LANE_H_ */

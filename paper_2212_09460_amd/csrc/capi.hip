@@ -1,0 +1,224 @@
+// C ABI of liblane.so: argument validation, then asynchronous launches on
+// the caller's stream.  No allocation, no synchronisation, no state.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/lane.h"
+#include "lane_internal.h"
+
+using namespace lane;
+
+extern "C" hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+extern "C" hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
+extern "C" hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
+extern "C" hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
+
+namespace {
+
+inline bool dims_ok(int W, int H) { return W >= 1 && H >= 1; }
+inline bool dims_small(int W, int H) { return W <= LANE_MAX_DIM && H <= LANE_MAX_DIM; }
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+inline int dev_status(hipError_t e) { return e == hipSuccess ? LANE_OK : LANE_E_DEVICE; }
+
+int isqrt_ceil(int64_t q) {
+    int64_t d = (int64_t)sqrt((double)q);
+    while (d * d < q) ++d;
+    while (d > 0 && (d - 1) * (d - 1) >= q) --d;
+    return (int)d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lane_abi_version(void) { return LANE_ABI_VERSION; }
+
+const char* lane_strerror(int status) {
+    switch (status) {
+        case LANE_OK: return "ok";
+        case LANE_E_ARG: return "invalid argument";
+        case LANE_E_SIZE: return "size out of range";
+        case LANE_E_RANGE: return "accumulator range invalid";
+        case LANE_E_WS: return "workspace too small";
+        case LANE_E_DEVICE: return "HIP device error";
+        case LANE_E_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int lane_make_trig_q14(int32_t n_theta, int16_t* cos_q14, int16_t* sin_q14) {
+    if (n_theta <= 0 || !cos_q14 || !sin_q14) return LANE_E_ARG;
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < n_theta; ++k) {
+        const double a = (double)k * pi / (double)n_theta;
+        const double c = cos(a) * 16384.0, s = sin(a) * 16384.0;
+        cos_q14[k] = (int16_t)(c >= 0 ? floor(c + 0.5) : -floor(-c + 0.5));
+        sin_q14[k] = (int16_t)(s >= 0 ? floor(s + 0.5) : -floor(-s + 0.5));
+    }
+    return LANE_OK;
+}
+
+int lane_r_offset(int32_t W, int32_t H, int32_t* D_out) {
+    if (!dims_ok(W, H) || !D_out) return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    *D_out = isqrt_ceil((int64_t)(W - 1) * (W - 1) + (int64_t)(H - 1) * (H - 1));
+    return LANE_OK;
+}
+
+int lane_edge_list_size(int32_t W, int32_t H, size_t* bytes) {
+    if (!dims_ok(W, H) || !bytes) return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    *bytes = list_layout(W, H).words * sizeof(uint32_t);
+    return LANE_OK;
+}
+
+int lane_sobel_binarize(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
+                        int32_t border_mode, uint8_t* edges, uint8_t* mag_opt, uint32_t* list_opt,
+                        uint32_t* edge_count_opt, void* stream) {
+    if (!img || !edges || !dims_ok(W, H) || pitch < W || threshold < 0 || threshold > 255)
+        return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    if (border_mode != LANE_BORDER_ZERO && border_mode != LANE_BORDER_ZERO_MASKRING)
+        return LANE_E_UNSUPPORTED;
+    if (list_opt && !aligned16(list_opt)) return LANE_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    SobelDesc d;
+    memset(&d, 0, sizeof(d));
+    d.img = img;
+    d.W = W;
+    d.H = H;
+    d.pitch = pitch;
+    d.threshold = threshold;
+    d.border_mode = border_mode;
+    d.edges = edges;
+    d.mag = mag_opt;
+    d.list = list_opt;
+    d.edge_count = edge_count_opt;
+    if (edge_count_opt) {
+        hipError_t e = lane_launch_fill_u32(edge_count_opt, 1, 0u, s);
+        if (e != hipSuccess) return LANE_E_DEVICE;
+    }
+    return dev_status(lane_launch_sobel(&d, 0, s));
+}
+
+int lane_edges_to_list(const uint8_t* edges, int32_t W, int32_t H, int32_t pitch, uint32_t* list,
+                       uint32_t* edge_count_opt, void* stream) {
+    if (!edges || !list || !dims_ok(W, H) || pitch < W) return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    if (!aligned16(list)) return LANE_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    SobelDesc d;
+    memset(&d, 0, sizeof(d));
+    d.img = edges;
+    d.W = W;
+    d.H = H;
+    d.pitch = pitch;
+    d.list = list;
+    d.edge_count = edge_count_opt;
+    if (edge_count_opt) {
+        hipError_t e = lane_launch_fill_u32(edge_count_opt, 1, 0u, s);
+        if (e != hipSuccess) return LANE_E_DEVICE;
+    }
+    return dev_status(lane_launch_sobel(&d, 1, s));
+}
+
+// Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
+// whose rows fit in LDS, each row holding up to D + 3 cells (the r range of
+// one angle across the frame, plus rounding).
+int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
+    int32_t D = 0;
+    lane_r_offset(W, H, &D);
+    int row = D + 3;
+    if (row > n_r) row = n_r;
+    int T = kMaxT;
+    while (T > 1 && (T > n_theta || (long)T * row > kVoteLdsWords)) T >>= 1;
+    return T;
+}
+
+int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* cos_q14,
+                    const int16_t* sin_q14, int32_t n_theta, int32_t r_offset, int32_t n_r,
+                    const uint8_t* tile_mask_opt, int32_t* acc, uint32_t* dropped_opt,
+                    void* stream) {
+    if (!list || !cos_q14 || !sin_q14 || !acc || !dims_ok(W, H) || n_theta <= 0 || n_r <= 0)
+        return LANE_E_ARG;
+    if (!aligned16(list)) return LANE_E_ARG;
+    if (!dims_small(W, H) || (int64_t)n_theta * n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
+    if (tile_mask_opt && (n_theta % 4) != 0) return LANE_E_UNSUPPORTED;
+    if (r_offset < -32768 * 4 || r_offset > 32768 * 4) return LANE_E_RANGE;
+    hipStream_t s = (hipStream_t)stream;
+    VoteDesc d;
+    memset(&d, 0, sizeof(d));
+    d.list = list;
+    d.W = W;
+    d.H = H;
+    d.cos_q14 = cos_q14;
+    d.sin_q14 = sin_q14;
+    d.n_theta = n_theta;
+    d.r_offset = r_offset;
+    d.n_r = n_r;
+    d.tile_mask = tile_mask_opt;
+    d.acc = acc;
+    d.dropped = dropped_opt;
+    d.T = lane_vote_rows_per_group(W, H, n_theta, n_r);
+    d.log2T = ilog2_floor((unsigned)d.T);
+    d.n_slices = (n_theta + d.T - 1) / d.T;
+    if (dropped_opt) {
+        hipError_t e = lane_launch_fill_u32(dropped_opt, 1, 0u, s);
+        if (e != hipSuccess) return LANE_E_DEVICE;
+    }
+    return dev_status(lane_launch_vote(&d, s));
+}
+
+static int peaks_block_log2(int32_t n_theta, int32_t n_r) {
+    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
+    int lg = 8;
+    while (((ncell + (1ull << lg) - 1) >> lg) > (uint64_t)kPeaksMaxBlocksLds) ++lg;
+    return lg;
+}
+
+int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t* bytes) {
+    if (n_theta <= 0 || n_r <= 0 || !bytes) return LANE_E_ARG;
+    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
+    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
+    const int lg = peaks_block_log2(n_theta, n_r);
+    *bytes = (size_t)((ncell + (1ull << lg) - 1) >> lg) * sizeof(unsigned long long);
+    return LANE_OK;
+}
+
+int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r_offset, int32_t k,
+                     int32_t h_theta, int32_t h_r, int32_t min_votes, int32_t* theta_idx,
+                     int32_t* r_idx, int32_t* votes, int32_t* count, void* ws, size_t ws_bytes,
+                     void* stream) {
+    if (!acc || !theta_idx || !r_idx || !votes || !count || !ws || n_theta <= 0 || n_r <= 0 ||
+        k < 1 || k > 1024 || h_theta < 0 || h_r < 0)
+        return LANE_E_ARG;
+    if (!aligned16(ws)) return LANE_E_ARG;
+    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll || h_theta > 1000000 || h_r > 1000000)
+        return LANE_E_SIZE;
+    if (n_r != 2 * r_offset + 1) return LANE_E_RANGE;
+    size_t need = 0;
+    lane_hough_peaks_workspace_size(n_theta, n_r, &need);
+    if (ws_bytes < need) return LANE_E_WS;
+    PeaksDesc d;
+    memset(&d, 0, sizeof(d));
+    d.acc = acc;
+    d.n_theta = n_theta;
+    d.n_r = n_r;
+    d.r_offset = r_offset;
+    d.k = k;
+    d.h_theta = h_theta;
+    d.h_r = h_r;
+    d.min_votes = min_votes;
+    d.theta_idx = theta_idx;
+    d.r_idx = r_idx;
+    d.votes = votes;
+    d.count = count;
+    d.keys = (unsigned long long*)ws;
+    d.block_log2 = peaks_block_log2(n_theta, n_r);
+    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
+    d.n_blocks = (int)((ncell + (1ull << d.block_log2) - 1) >> d.block_log2);
+    return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));
+}
+
+}  // extern "C"

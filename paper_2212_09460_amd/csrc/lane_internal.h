@@ -1,0 +1,87 @@
+// Internal descriptors and helpers shared by the HIP kernels and the C ABI.
+// gfx950 (CDNA4) only: wave64, 160 KB LDS per workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lane {
+
+constexpr int kWave = 64;
+constexpr int kTile = 8;                 // edge tiles are 8x8 pixels
+constexpr int kChunkPx = 1024;           // one wave covers 64 lanes x 16 px
+constexpr int kTilesPerChunk = kChunkPx / kTile;
+constexpr int kSegCap = kTile * kChunkPx;  // entries a segment can hold
+constexpr int kStripRows = 32;           // rows one Sobel wave walks down
+constexpr int kSobelWaves = 4;           // waves per Sobel workgroup
+constexpr int kVoteThreads = 1024;       // 16 waves per vote workgroup
+constexpr int kVoteLdsWords = 40704;     // accumulator dwords in LDS (159 KB)
+constexpr int kMaxT = 64;                // theta rows per vote workgroup (max)
+
+// Layout of the compacted edge list of one frame (offsets in uint32 words).
+struct ListLayout {
+    int th, tw, nchunk, nseg;
+    size_t off_info, off_ent, words;
+};
+
+__host__ __device__ inline ListLayout list_layout(int W, int H) {
+    ListLayout L;
+    L.th = (H + kTile - 1) / kTile;
+    L.tw = (W + kTile - 1) / kTile;
+    L.nchunk = (W + kChunkPx - 1) / kChunkPx;
+    L.nseg = L.th * L.nchunk;
+    L.off_info = (size_t)L.nseg;
+    L.off_ent = ((L.off_info + (size_t)L.th * L.tw) + 3) & ~(size_t)3;
+    L.words = L.off_ent + (size_t)L.nseg * kSegCap;
+    return L;
+}
+
+// One frame for the Sobel + binarize + compaction pass.
+struct SobelDesc {
+    const uint8_t* img;
+    int W, H, pitch;
+    int threshold, border_mode;
+    uint8_t* edges;      // [H][W]
+    uint8_t* mag;        // [H][W] or null
+    uint32_t* list;      // edge list or null
+    uint32_t* edge_count;  // device scalar or null (zeroed beforehand)
+    int item0;           // first work item of this frame in a batch
+};
+
+// One frame for the vote.
+struct VoteDesc {
+    const uint32_t* list;
+    int W, H;
+    const int16_t* cos_q14;
+    const int16_t* sin_q14;
+    int n_theta, r_offset, n_r;
+    const uint8_t* tile_mask;  // [th][tw] or null
+    int32_t* acc;              // [n_theta][n_r]
+    uint32_t* dropped;         // device scalar or null (zeroed beforehand)
+    int T;                     // theta rows per workgroup (power of two <= 64)
+    int log2T;
+    int n_slices;
+    int item0;
+};
+
+// One frame for the peak search.
+struct PeaksDesc {
+    const int32_t* acc;
+    int n_theta, n_r, r_offset;
+    int k, h_theta, h_r, min_votes;
+    int32_t* theta_idx;
+    int32_t* r_idx;
+    int32_t* votes;
+    int32_t* count;
+    unsigned long long* keys;  // workspace: one key per block
+    int block_log2;            // cells per block = 1 << block_log2
+    int n_blocks;
+    int item0;
+};
+
+constexpr int kPeaksMaxBlocksLds = 8192;  // keys held in LDS by the select pass
+
+inline int ilog2_floor(unsigned v) { int r = -1; while (v) { v >>= 1; ++r; } return r; }
+
+}  // namespace lane

@@ -1,0 +1,108 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+function include/lane.h declares, its host helpers agree with the inputs
+module / the mathematics, and bad arguments are rejected before any launch.
+(No call here reaches a kernel: each one fails validation first.)"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lane.h")
+LIB = os.path.join(ROOT, "paper_2212_09460_amd", "liblane.so")
+
+E_ARG, E_SIZE, E_RANGE, E_WS, E_UNSUP = -1, -2, -3, -4, -6
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(lane_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblane.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_lists_every_declared_symbol():
+    import paper_2212_09460_amd.lane as lane
+
+    assert sorted(lane.EXPORTS) == declared()
+
+
+def test_abi_version_and_strerror(lib):
+    assert lib.lane_abi_version() == 1
+    lib.lane_strerror.restype = ctypes.c_char_p
+    assert lib.lane_strerror(0) == b"ok"
+    assert b"workspace" in lib.lane_strerror(E_WS)
+
+
+def test_trig_table_matches_inputs_module(lib, synth):
+    for n in (1, 7, 180, 360, 1024):
+        c = np.zeros(n, np.int16)
+        s = np.zeros(n, np.int16)
+        assert lib.lane_make_trig_q14(n, c.ctypes.data_as(ctypes.c_void_p),
+                                      s.ctypes.data_as(ctypes.c_void_p)) == 0
+        c2, s2 = synth.trig_q14(n)
+        assert (c == c2).all() and (s == s2).all()
+    assert lib.lane_make_trig_q14(0, None, None) == E_ARG
+
+
+def test_r_offset(lib, oracle):
+    d = ctypes.c_int32(0)
+    for W, H in [(1, 1), (3, 1), (640, 480), (1920, 1080), (3840, 2160), (8192, 8192), (8192, 3)]:
+        assert lib.lane_r_offset(W, H, ctypes.byref(d)) == 0
+        assert d.value == oracle.r_offset(W, H)
+    assert lib.lane_r_offset(8193, 4, ctypes.byref(d)) == E_SIZE
+    assert lib.lane_r_offset(0, 4, ctypes.byref(d)) == E_ARG
+
+
+def test_edge_list_size(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.lane_edge_list_size(1920, 1080, ctypes.byref(n)) == 0
+    th, tw, nchunk = 135, 240, 2
+    nseg = th * nchunk
+    off_ent = (nseg + th * tw + 3) // 4 * 4
+    assert n.value == 4 * (off_ent + nseg * 8192)
+    assert lib.lane_edge_list_size(9000, 4, ctypes.byref(n)) == E_SIZE
+
+
+def test_argument_errors_before_launch(lib):
+    P = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation
+    P1 = ctypes.c_void_p(17)
+    f = lib.lane_sobel_binarize
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    assert f(None, 8, 8, 8, 128, 1, P, None, None, None, None) == E_ARG
+    assert f(P, 8, 8, 7, 128, 1, P, None, None, None, None) == E_ARG        # pitch < W
+    assert f(P, 8, 8, 8, 256, 1, P, None, None, None, None) == E_ARG        # threshold
+    assert f(P, 9000, 8, 9000, 128, 1, P, None, None, None, None) == E_SIZE
+    assert f(P, 8, 8, 8, 128, 7, P, None, None, None, None) == E_UNSUP
+    assert f(P, 8, 8, 8, 128, 1, P, None, P1, None, None) == E_ARG          # misaligned list
+    v = lib.lane_hough_vote
+    v.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert v(P, 8, 8, P, P, 0, 5, 11, None, P, None, None) == E_ARG
+    assert v(P, 8, 8, P, P, 180, 5, 0, None, P, None, None) == E_ARG
+    assert v(P, 8, 8, P, P, 90, 5, 11, P, P, None, None) == E_UNSUP        # mask needs n%4==0
+    pk = lib.lane_hough_peaks
+    pk.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    assert pk(P, 180, 11, 5, 0, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_ARG   # k < 1
+    assert pk(P, 180, 12, 5, 2, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_RANGE  # n_r != 2D+1
+    assert pk(P, 180, 11, 5, 2, 1, 1, 1, P, P, P, P, P, 8, None) == E_WS
