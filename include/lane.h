@@ -148,6 +148,55 @@ int lane_hough_peaks(const int32_t *acc, int32_t n_theta, int32_t n_r, int32_t r
                      int32_t *theta_idx, int32_t *r_idx, int32_t *votes, int32_t *count,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ batch
+ * Many frames of mixed sizes through the whole path (Sobel + binarize +
+ * compaction, vote, peaks) in one HIP graph launch.  A plan is built once
+ * per set of buffers (creation allocates a small device descriptor table and
+ * instantiates the graph; launching allocates nothing).  Each stage is a
+ * persistent kernel that walks a work table covering every frame; the
+ * paper's GPU grid of one block per 16x16 pixels (Sec. 4.1 Eq. (6)) and of
+ * one block per angle (Sec. 4.3) become these tables. */
+typedef struct lane_frame {
+    const uint8_t *img;       /* device uint8 [H][pitch] */
+    int32_t W, H, pitch;
+    int32_t threshold, border_mode;
+    uint8_t *edges;           /* device uint8 [H][W] */
+    uint8_t *mag_opt;         /* device uint8 [H][W] or NULL */
+    uint32_t *list;           /* device, lane_edge_list_size(W, H) bytes, 16-byte aligned */
+    const int16_t *cos_q14;   /* device int16 [n_theta] */
+    const int16_t *sin_q14;   /* device int16 [n_theta] */
+    int32_t n_theta, r_offset, n_r;
+    const uint8_t *tile_mask_opt; /* device uint8 [ceil(H/8)][ceil(W/8)] or NULL */
+    int32_t *acc;             /* device int32 [n_theta][n_r] */
+    int32_t k, h_theta, h_r, min_votes; /* peaks; k == 0 skips the peak step */
+    int32_t *peaks;           /* device int32 [3k + 1]: theta_idx[k], r_idx[k], votes[k], count */
+    void *peaks_ws;           /* device, lane_hough_peaks_workspace_size() bytes, 16-byte aligned */
+    size_t peaks_ws_bytes;
+    uint32_t *counters_opt;   /* device uint32 [2] or NULL: edge pixels, dropped votes */
+} lane_frame;
+
+typedef struct lane_tune {
+    int32_t vote_rows;        /* theta rows per vote workgroup, power of two; 0 = largest that fits LDS */
+    int32_t vote_queue;       /* 1 = dynamic ticket queue (longest items first), 0 = static stride
+                                 with each frame's slices on one XCD, -1 = automatic */
+    int32_t sobel_groups_per_cu; /* persistent Sobel workgroups per CU; 0 = occupancy limit */
+} lane_tune;
+
+typedef struct lane_batch lane_batch;
+
+/* frames: host array of n descriptors (copied).  tune_opt may be NULL.
+ * Validation is the same as for the single-frame calls. */
+int lane_batch_create(const lane_frame *frames, int32_t n, const lane_tune *tune_opt,
+                      lane_batch **out);
+/* Enqueue the whole path for every frame: one hipGraphLaunch on `stream`. */
+int lane_batch_launch(lane_batch *b, void *stream);
+/* Enqueue one stage without the graph (0 = clear counters, 1 = Sobel,
+ * 2 = vote, 3 = peaks), e.g. to time the stages separately. */
+int lane_batch_launch_stage(lane_batch *b, int32_t stage, void *stream);
+/* Frees the plan's device table and graph (waits for nothing: the caller
+ * must make sure no launch of this plan is still running). */
+int lane_batch_destroy(lane_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,351 @@
+// Batched plans: many frames of mixed sizes through Sobel + compaction, the
+// vote and the peak search in one HIP graph launch.
+//
+// Each stage is one persistent kernel walking a work table built here:
+//   Sobel  (frame, strip item) pairs, one wave each, grid = occupancy limit;
+//   vote   (frame, theta slice) pairs, one 1024-thread workgroup each;
+//   peaks  block keys over a per-frame prefix table, then one workgroup per
+//          frame for the greedy selection.
+// The vote table is laid out for the XCD round-robin of workgroup dispatch:
+// with a static stride that is a multiple of 8, table slot i always runs on
+// XCD i mod 8, so slots are filled such that all slices of a frame share one
+// XCD (and its L2 holds that frame's edge list once).  With mixed sizes a
+// ticket queue over the table sorted by estimated cost balances better; the
+// tuner (or the caller) chooses.
+#include <algorithm>
+#include <new>
+#include <string.h>
+#include <vector>
+
+#include "../../include/lane.h"
+#include "lane_internal.h"
+
+using namespace lane;
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
+                                              int grid, hipStream_t s);
+extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy();
+extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H);
+extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode);
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
+                                             uint32_t* queue, int grid, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
+                                              int total_blocks, int grid_keys, int grid_select,
+                                              hipStream_t s);
+extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
+extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
+
+namespace {
+
+__global__ void k_clear_counters(uint32_t* const* ptrs, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && ptrs[i]) {
+        ptrs[i][0] = 0;
+        ptrs[i][1] = 0;
+    }
+}
+
+__global__ void k_reset_queue(uint32_t* queue) { *queue = 0; }
+
+}  // namespace
+
+struct lane_batch {
+    int n = 0;
+    int n_peak_frames = 0;
+    // device tables (one allocation)
+    void* dmem = nullptr;
+    SobelDesc* d_sobel = nullptr;
+    VoteDesc* d_vote = nullptr;
+    PeaksDesc* d_peaks = nullptr;
+    int2* d_sobel_items = nullptr;
+    int2* d_vote_items = nullptr;
+    int* d_prefix = nullptr;
+    uint32_t** d_counters = nullptr;
+    uint32_t* d_queue = nullptr;
+    int n_sobel_items = 0, n_vote_items = 0, total_blocks = 0;
+    int grid_sobel = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
+    bool vote_dynamic = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int validate(const lane_frame& f) {
+    if (!f.img || !f.edges || !f.list || !f.cos_q14 || !f.sin_q14 || !f.acc) return LANE_E_ARG;
+    if (f.W < 1 || f.H < 1 || f.pitch < f.W || f.threshold < 0 || f.threshold > 255) return LANE_E_ARG;
+    if (f.W > LANE_MAX_DIM || f.H > LANE_MAX_DIM) return LANE_E_SIZE;
+    if (f.border_mode != LANE_BORDER_ZERO && f.border_mode != LANE_BORDER_ZERO_MASKRING)
+        return LANE_E_UNSUPPORTED;
+    if (((uintptr_t)f.list & 15u) != 0) return LANE_E_ARG;
+    if (f.n_theta <= 0 || f.n_r <= 0) return LANE_E_ARG;
+    if ((int64_t)f.n_theta * f.n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
+    if (f.tile_mask_opt && (f.n_theta % 4) != 0) return LANE_E_UNSUPPORTED;
+    if (f.r_offset < -32768 * 4 || f.r_offset > 32768 * 4) return LANE_E_RANGE;
+    if (f.k < 0 || f.k > 1024) return LANE_E_ARG;
+    if (f.k > 0) {
+        if (!f.peaks || !f.peaks_ws || f.h_theta < 0 || f.h_r < 0) return LANE_E_ARG;
+        if (((uintptr_t)f.peaks_ws & 15u) != 0) return LANE_E_ARG;
+        if (f.h_theta > 1000000 || f.h_r > 1000000) return LANE_E_SIZE;
+        if (f.n_r != 2 * f.r_offset + 1) return LANE_E_RANGE;
+        size_t need = 0;
+        lane_hough_peaks_workspace_size(f.n_theta, f.n_r, &need);
+        if (f.peaks_ws_bytes < need) return LANE_E_WS;
+    }
+    return LANE_OK;
+}
+
+int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
+    switch (stage) {
+        case 0:
+            hipLaunchKernelGGL(k_clear_counters, dim3((b->n + 255) / 256), dim3(256), 0, s,
+                               b->d_counters, b->n);
+            return hipGetLastError();
+        case 1:
+            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->n_sobel_items, b->grid_sobel, s);
+        case 2:
+            if (b->vote_dynamic) {
+                // a kernel, not a memset node: the ticket restarts on every replay
+                hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, b->d_queue);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            return lane_launch_vote_batch(b->d_vote, b->d_vote_items, b->n_vote_items,
+                                          b->vote_dynamic ? b->d_queue : nullptr, b->grid_vote, s);
+        case 3:
+            if (b->n_peak_frames == 0) return hipSuccess;
+            return lane_launch_peaks_batch(b->d_peaks, b->d_prefix, b->n_peak_frames, b->total_blocks,
+                                           b->grid_keys, b->grid_select, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+void free_plan(lane_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->dmem) hipFree(b->dmem);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune_opt,
+                      lane_batch** out) {
+    if (!frames || n < 1 || !out) return LANE_E_ARG;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        const int st = validate(frames[i]);
+        if (st != LANE_OK) return st;
+    }
+    lane_tune tune = {0, -1, 0};
+    if (tune_opt) tune = *tune_opt;
+    if (tune.vote_rows < 0 || (tune.vote_rows & (tune.vote_rows - 1)) != 0) return LANE_E_ARG;
+
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return LANE_E_DEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return LANE_E_DEVICE;
+
+    std::vector<SobelDesc> sd(n);
+    std::vector<VoteDesc> vd(n);
+    std::vector<PeaksDesc> pd;
+    std::vector<int2> sitems, vitems;
+    std::vector<int> prefix(1, 0);
+    std::vector<uint32_t*> counters(n, nullptr);
+    std::vector<double> vcost;
+    bool mixed = false;
+    for (int i = 0; i < n; ++i) {
+        const lane_frame& f = frames[i];
+        if (i > 0 && (f.W != frames[0].W || f.H != frames[0].H)) mixed = true;
+        SobelDesc& s = sd[i];
+        memset(&s, 0, sizeof(s));
+        s.img = f.img;
+        s.W = f.W;
+        s.H = f.H;
+        s.pitch = f.pitch;
+        s.threshold = f.threshold;
+        s.border_mode = f.border_mode;
+        s.edges = f.edges;
+        s.mag = f.mag_opt;
+        s.list = f.list;
+        s.edge_count = f.counters_opt;
+        s.fast = lane_sobel_fast_ok(&s, 0);
+        counters[i] = f.counters_opt;
+        const int ns = lane_sobel_items(f.W, f.H);
+        for (int j = 0; j < ns; ++j) sitems.push_back(make_int2(i, j));
+
+        VoteDesc& v = vd[i];
+        memset(&v, 0, sizeof(v));
+        v.list = f.list;
+        v.W = f.W;
+        v.H = f.H;
+        v.cos_q14 = f.cos_q14;
+        v.sin_q14 = f.sin_q14;
+        v.n_theta = f.n_theta;
+        v.r_offset = f.r_offset;
+        v.n_r = f.n_r;
+        v.tile_mask = f.tile_mask_opt;
+        v.acc = f.acc;
+        v.dropped = f.counters_opt ? f.counters_opt + 1 : nullptr;
+        const int tmax = lane_vote_rows_per_group(f.W, f.H, f.n_theta, f.n_r);
+        v.T = tune.vote_rows > 0 ? std::min(tmax, std::min(tune.vote_rows, pow2_floor(f.n_theta))) : tmax;
+        v.log2T = ilog2_floor((unsigned)v.T);
+        v.n_slices = (f.n_theta + v.T - 1) / v.T;
+
+        if (f.k > 0) {
+            PeaksDesc p;
+            memset(&p, 0, sizeof(p));
+            p.acc = f.acc;
+            p.n_theta = f.n_theta;
+            p.n_r = f.n_r;
+            p.r_offset = f.r_offset;
+            p.k = f.k;
+            p.h_theta = f.h_theta;
+            p.h_r = f.h_r;
+            p.min_votes = f.min_votes;
+            p.theta_idx = f.peaks;
+            p.r_idx = f.peaks + f.k;
+            p.votes = f.peaks + 2 * f.k;
+            p.count = f.peaks + 3 * f.k;
+            p.keys = (unsigned long long*)f.peaks_ws;
+            p.block_log2 = lane_peaks_block_log2(f.n_theta, f.n_r);
+            const uint64_t ncell = (uint64_t)f.n_theta * (uint64_t)f.n_r;
+            p.n_blocks = (int)((ncell + (1ull << p.block_log2) - 1) >> p.block_log2);
+            pd.push_back(p);
+            prefix.push_back(prefix.back() + p.n_blocks);
+        }
+    }
+    // vote table
+    bool dynamic = tune.vote_queue == 1 || (tune.vote_queue < 0 && mixed);
+    if (dynamic) {
+        std::vector<std::pair<double, int2>> all;
+        for (int i = 0; i < n; ++i) {
+            const double cost = (double)vd[i].T * frames[i].W * frames[i].H;
+            for (int s = 0; s < vd[i].n_slices; ++s) all.push_back({cost, make_int2(i, s)});
+        }
+        std::stable_sort(all.begin(), all.end(),
+                         [](const std::pair<double, int2>& a, const std::pair<double, int2>& b) {
+                             return a.first > b.first;
+                         });
+        for (auto& a : all) vitems.push_back(a.second);
+    } else {
+        std::vector<std::vector<int2>> per(8);
+        for (int i = 0; i < n; ++i)
+            for (int s = 0; s < vd[i].n_slices; ++s) per[i % 8].push_back(make_int2(i, s));
+        size_t longest = 0;
+        for (auto& p : per) longest = std::max(longest, p.size());
+        vitems.assign(longest * 8, make_int2(-1, -1));
+        for (int x = 0; x < 8; ++x)
+            for (size_t j = 0; j < per[x].size(); ++j) vitems[j * 8 + x] = per[x][j];
+    }
+
+    lane_batch* b = new (std::nothrow) lane_batch();
+    if (!b) return LANE_E_DEVICE;
+    b->n = n;
+    b->n_peak_frames = (int)pd.size();
+    b->n_sobel_items = (int)sitems.size();
+    b->n_vote_items = (int)vitems.size();
+    b->total_blocks = prefix.back();
+    b->vote_dynamic = dynamic;
+
+    // one device allocation for every table
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_sobel = off; off = al(off + sizeof(SobelDesc) * n);
+    const size_t o_vote = off; off = al(off + sizeof(VoteDesc) * n);
+    const size_t o_peaks = off; off = al(off + sizeof(PeaksDesc) * std::max<size_t>(pd.size(), 1));
+    const size_t o_sitems = off; off = al(off + sizeof(int2) * sitems.size());
+    const size_t o_vitems = off; off = al(off + sizeof(int2) * vitems.size());
+    const size_t o_prefix = off; off = al(off + sizeof(int) * prefix.size());
+    const size_t o_cnt = off; off = al(off + sizeof(uint32_t*) * n);
+    const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
+    if (hipMalloc(&b->dmem, off) != hipSuccess) {
+        free_plan(b);
+        return LANE_E_DEVICE;
+    }
+    char* base = (char*)b->dmem;
+    b->d_sobel = (SobelDesc*)(base + o_sobel);
+    b->d_vote = (VoteDesc*)(base + o_vote);
+    b->d_peaks = (PeaksDesc*)(base + o_peaks);
+    b->d_sobel_items = (int2*)(base + o_sitems);
+    b->d_vote_items = (int2*)(base + o_vitems);
+    b->d_prefix = (int*)(base + o_prefix);
+    b->d_counters = (uint32_t**)(base + o_cnt);
+    b->d_queue = (uint32_t*)(base + o_queue);
+    bool ok = hipMemcpy(b->d_sobel, sd.data(), sizeof(SobelDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_vote, vd.data(), sizeof(VoteDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
+    if (!pd.empty())
+        ok = ok && hipMemcpy(b->d_peaks, pd.data(), sizeof(PeaksDesc) * pd.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_sobel_items, sitems.data(), sizeof(int2) * sitems.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_vote_items, vitems.data(), sizeof(int2) * vitems.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 4) == hipSuccess;
+    if (!ok) {
+        free_plan(b);
+        return LANE_E_DEVICE;
+    }
+
+    const int occ = tune.sobel_groups_per_cu > 0 ? tune.sobel_groups_per_cu : lane_sobel_batch_occupancy();
+    b->grid_sobel = std::max(1, std::min((b->n_sobel_items + kSobelWaves - 1) / kSobelWaves, cus * occ));
+    if (dynamic) {
+        b->grid_vote = std::max(1, std::min(b->n_vote_items, cus));
+    } else {
+        // a multiple of 8 keeps every table slot on its XCD
+        b->grid_vote = std::max(8, std::min(b->n_vote_items, cus) / 8 * 8);
+    }
+    b->grid_keys = std::max(1, std::min((b->total_blocks + 3) / 4, cus * 8));
+    b->grid_select = std::max(1, std::min(b->n_peak_frames, cus));
+
+    // capture the four stages into one graph
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        free_plan(b);
+        return LANE_E_DEVICE;
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int st = 0; st < 4 && e == hipSuccess; ++st) e = enqueue_stage(b, st, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) {
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    } else if (g) {
+        hipGraphDestroy(g);
+    }
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        free_plan(b);
+        return LANE_E_DEVICE;
+    }
+    *out = b;
+    return LANE_OK;
+}
+
+int lane_batch_launch(lane_batch* b, void* stream) {
+    if (!b || !b->exec) return LANE_E_ARG;
+    return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {
+    if (!b || stage < 0 || stage > 3) return LANE_E_ARG;
+    return enqueue_stage(b, stage, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_batch_destroy(lane_batch* b) {
+    if (!b) return LANE_E_ARG;
+    free_plan(b);
+    return LANE_OK;
+}
+
+}  // extern "C"

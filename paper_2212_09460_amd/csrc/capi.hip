@@ -9,10 +9,10 @@
 
 using namespace lane;
 
-extern "C" hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-extern "C" hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
-extern "C" hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
-extern "C" hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
 
 namespace {
 
@@ -126,7 +126,7 @@ int lane_edges_to_list(const uint8_t* edges, int32_t W, int32_t H, int32_t pitch
 // Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
 // whose rows fit in LDS, each row holding up to D + 3 cells (the r range of
 // one angle across the frame, plus rounding).
-int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
+LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
     int32_t D = 0;
     lane_r_offset(W, H, &D);
     int row = D + 3;
@@ -170,7 +170,7 @@ int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* c
     return dev_status(lane_launch_vote(&d, s));
 }
 
-static int peaks_block_log2(int32_t n_theta, int32_t n_r) {
+LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r) {
     const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
     int lg = 8;
     while (((ncell + (1ull << lg) - 1) >> lg) > (uint64_t)kPeaksMaxBlocksLds) ++lg;
@@ -181,7 +181,7 @@ int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t* bytes)
     if (n_theta <= 0 || n_r <= 0 || !bytes) return LANE_E_ARG;
     if ((int64_t)n_theta * n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
     const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
-    const int lg = peaks_block_log2(n_theta, n_r);
+    const int lg = lane_peaks_block_log2(n_theta, n_r);
     *bytes = (size_t)((ncell + (1ull << lg) - 1) >> lg) * sizeof(unsigned long long);
     return LANE_OK;
 }
@@ -215,7 +215,7 @@ int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r
     d.votes = votes;
     d.count = count;
     d.keys = (unsigned long long*)ws;
-    d.block_log2 = peaks_block_log2(n_theta, n_r);
+    d.block_log2 = lane_peaks_block_log2(n_theta, n_r);
     const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
     d.n_blocks = (int)((ncell + (1ull << d.block_log2) - 1) >> d.block_log2);
     return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));

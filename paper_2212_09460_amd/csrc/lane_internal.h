@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#define LANE_INTERNAL __attribute__((visibility("hidden")))
+
 namespace lane {
 
 constexpr int kWave = 64;
@@ -46,7 +48,7 @@ struct SobelDesc {
     uint8_t* mag;        // [H][W] or null
     uint32_t* list;      // edge list or null
     uint32_t* edge_count;  // device scalar or null (zeroed beforehand)
-    int item0;           // first work item of this frame in a batch
+    int fast;            // 16-byte aligned rows: vector loads/stores (batched path)
 };
 
 // One frame for the vote.
@@ -62,7 +64,6 @@ struct VoteDesc {
     int T;                     // theta rows per workgroup (power of two <= 64)
     int log2T;
     int n_slices;
-    int item0;
 };
 
 // One frame for the peak search.
@@ -77,7 +78,6 @@ struct PeaksDesc {
     unsigned long long* keys;  // workspace: one key per block
     int block_log2;            // cells per block = 1 << block_log2
     int n_blocks;
-    int item0;
 };
 
 constexpr int kPeaksMaxBlocksLds = 8192;  // keys held in LDS by the select pass

@@ -57,10 +57,7 @@ __device__ __forceinline__ bool in_window(int t, int i, int tp, int ip, const Pe
     return false;
 }
 
-__global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (b >= d.n_blocks) return;
+__device__ __forceinline__ void block_key(const PeaksDesc& d, int b, int lane) {
     const uint32_t ncell = (uint32_t)d.n_theta * (uint32_t)d.n_r;
     const uint32_t B = 1u << d.block_log2;
     const uint32_t c0 = (uint32_t)b << d.block_log2;
@@ -74,6 +71,29 @@ __global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
     if (lane == 0) d.keys[b] = best;
 }
 
+__global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= d.n_blocks) return;
+    block_key(d, b, threadIdx.x & (kWave - 1));
+}
+
+// Batched: wave-granular grid stride over all blocks of all frames; the frame
+// of a global block index is found by binary search in the prefix table.
+__global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs,
+                                                          const int* __restrict__ prefix, int n_frames) {
+    const int total = prefix[n_frames];
+    for (int gb = blockIdx.x * 4 + (threadIdx.x >> 6); gb < total; gb += gridDim.x * 4) {
+        int lo = 0, hi = n_frames - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= gb) lo = mid;
+            else hi = mid - 1;
+        }
+        const PeaksDesc d = descs[lo];
+        block_key(d, gb - prefix[lo], threadIdx.x & (kWave - 1));
+    }
+}
+
 __shared__ unsigned long long s_keys[kPeaksMaxBlocksLds];
 __shared__ uint32_t s_mark[kPeaksMaxBlocksLds / 32];
 __shared__ int s_list[kPeaksMaxBlocksLds];
@@ -82,7 +102,7 @@ __shared__ int s_sel_t[1024], s_sel_i[1024];
 __shared__ unsigned long long s_red[16];
 __shared__ int s_found, s_stop;
 
-__global__ void __launch_bounds__(1024) k_peaks_select(PeaksDesc d) {
+__device__ void peaks_select(const PeaksDesc& d) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
     const uint32_t ncell = (uint32_t)d.n_theta * (uint32_t)d.n_r;
@@ -172,15 +192,36 @@ __global__ void __launch_bounds__(1024) k_peaks_select(PeaksDesc d) {
     if (tid == 0) *d.count = found;
 }
 
+__global__ void __launch_bounds__(1024) k_peaks_select(PeaksDesc d) { peaks_select(d); }
+
+__global__ void __launch_bounds__(1024) k_peaks_select_batch(const PeaksDesc* __restrict__ descs,
+                                                             int n_frames) {
+    for (int f = blockIdx.x; f < n_frames; f += gridDim.x) {
+        const PeaksDesc d = descs[f];
+        peaks_select(d);
+        __syncthreads();
+    }
+}
+
 }  // namespace lane
 
 using namespace lane;
 
-extern "C" hipError_t lane_launch_peaks(const PeaksDesc* dp, hipStream_t s) {
+extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* dp, hipStream_t s) {
     const PeaksDesc& d = *dp;
     hipLaunchKernelGGL(k_block_keys, dim3((d.n_blocks + 3) / 4), dim3(256), 0, s, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_peaks_select, dim3(1), dim3(1024), 0, s, d);
+    return hipGetLastError();
+}
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
+                                              int total_blocks, int grid_keys, int grid_select,
+                                              hipStream_t s) {
+    hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys), dim3(256), 0, s, descs, prefix, n_frames);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_peaks_select_batch, dim3(grid_select), dim3(1024), 0, s, descs, n_frames);
     return hipGetLastError();
 }

@@ -26,11 +26,6 @@ namespace lane {
 
 enum { kModeSobel = 0, kModeFromEdges = 1 };
 
-template <int MODE>
-struct SobelArgs {
-    SobelDesc d;
-};
-
 // Loads the 16 pixels of one row owned by this lane plus the left and right
 // neighbour; pixels outside the frame (or past W) are 0.
 template <bool FAST>
@@ -247,6 +242,21 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) k_sobel(SobelDesc d, int 
     sobel_item<FAST, MODE>(d, item);
 }
 
+// Batched, persistent: each wave walks the (frame, item) table with a grid
+// stride.  Frames of any size and alignment mix in one launch; the aligned
+// fast path is chosen per frame.
+__global__ void __launch_bounds__(kWave * kSobelWaves)
+    k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items, int n_items) {
+    const int wave = threadIdx.x >> 6;
+    for (int it = blockIdx.x * kSobelWaves + wave; it < n_items; it += gridDim.x * kSobelWaves) {
+        const int2 w = items[it];
+        if (w.x < 0) continue;
+        const SobelDesc d = descs[w.x];
+        if (d.fast) sobel_item<true, kModeSobel>(d, w.y);
+        else sobel_item<false, kModeSobel>(d, w.y);
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -257,19 +267,41 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
 using namespace lane;
 
 // Host-side launchers (called by the C ABI after validation).
-extern "C" hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
-extern "C" int lane_sobel_items(int W, int H) {
+extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H) {
     const ListLayout L = list_layout(W, H);
     return L.nchunk * ((H + kStripRows - 1) / kStripRows);
 }
 
-extern "C" hipError_t lane_launch_sobel(const SobelDesc* dp, int mode, hipStream_t s) {
+extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
+    const SobelDesc& d = *dp;
+    return ((uintptr_t)d.img % 16 == 0) && (d.pitch % 16 == 0) && (d.W % 16 == 0) &&
+           (mode == kModeFromEdges ||
+            (((uintptr_t)d.edges % 16 == 0) && ((uintptr_t)d.mag % 16 == 0)));
+}
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
+                                              int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_sobel_batch, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs, items,
+                       n_items);
+    return hipGetLastError();
+}
+
+extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sobel_batch, kWave * kSobelWaves, 0) !=
+        hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* dp, int mode, hipStream_t s) {
     const SobelDesc& d = *dp;
     const int n_items = lane_sobel_items(d.W, d.H);
     const unsigned blocks = (unsigned)((n_items + kSobelWaves - 1) / kSobelWaves);

@@ -210,11 +210,45 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
 
 __global__ void __launch_bounds__(kVoteThreads) k_vote(VoteDesc d) { vote_item(d, blockIdx.x); }
 
+__shared__ int s_item;
+
+// Batched, persistent.  queue == null: static grid stride over the item
+// table (the table is laid out so that a frame's slices land on one XCD and
+// share its L2).  queue != null: items are taken in table order from an
+// atomic ticket (longest items first balances mixed sizes).
+__global__ void __launch_bounds__(kVoteThreads)
+    k_vote_batch(const VoteDesc* __restrict__ descs, const int2* __restrict__ items, int n_items,
+                 uint32_t* queue) {
+    int it = blockIdx.x;
+    for (;;) {
+        if (queue) {
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+            __syncthreads();
+            it = s_item;
+        }
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        if (w.x >= 0) {
+            const VoteDesc d = descs[w.x];
+            vote_item(d, w.y);
+        }
+        __syncthreads();
+        if (!queue) it += gridDim.x;
+    }
+}
+
 }  // namespace lane
 
 using namespace lane;
 
-extern "C" hipError_t lane_launch_vote(const VoteDesc* dp, hipStream_t s) {
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* dp, hipStream_t s) {
     hipLaunchKernelGGL(k_vote, dim3(dp->n_slices), dim3(kVoteThreads), 0, s, *dp);
+    return hipGetLastError();
+}
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
+                                             uint32_t* queue, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_vote_batch, dim3(grid), dim3(kVoteThreads), 0, s, descs, items, n_items,
+                       queue);
     return hipGetLastError();
 }

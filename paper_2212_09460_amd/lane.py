@@ -49,7 +49,8 @@ LANE_BORDER_ZERO_MASKRING = 1
 # Exported entry points of the C ABI (also checked by the CPU tests).
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
-           "lane_hough_peaks_workspace_size", "lane_hough_peaks")
+           "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_batch_create",
+           "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy")
 
 
 class LaneError(RuntimeError):
@@ -188,3 +189,126 @@ def pipeline(img: torch.Tensor, cos_q14: torch.Tensor, sin_q14: torch.Tensor, k:
     t, r, v, c = hough_peaks(acc, D, k, stream=stream)
     return dict(edges=edges, mag=mag, edge_list=lst, n_edges=cnt, acc=acc, dropped=dropped,
                 theta_idx=t, r_idx=r, votes=v, count=c, D=D, n_r=n_r)
+
+
+# ------------------------------------------------------------------ batch --
+
+class LaneFrame(ctypes.Structure):
+    _fields_ = [("img", _vp), ("W", _i32), ("H", _i32), ("pitch", _i32),
+                ("threshold", _i32), ("border_mode", _i32),
+                ("edges", _vp), ("mag_opt", _vp), ("list", _vp),
+                ("cos_q14", _vp), ("sin_q14", _vp),
+                ("n_theta", _i32), ("r_offset", _i32), ("n_r", _i32),
+                ("tile_mask_opt", _vp), ("acc", _vp),
+                ("k", _i32), ("h_theta", _i32), ("h_r", _i32), ("min_votes", _i32),
+                ("peaks", _vp), ("peaks_ws", _vp), ("peaks_ws_bytes", _sz),
+                ("counters_opt", _vp)]
+
+
+class LaneTune(ctypes.Structure):
+    _fields_ = [("vote_rows", _i32), ("vote_queue", _i32), ("sobel_groups_per_cu", _i32)]
+
+
+_batch_create = _sig("lane_batch_create", [ctypes.POINTER(LaneFrame), _i32,
+                                           ctypes.POINTER(LaneTune), ctypes.POINTER(_vp)])
+_batch_launch = _sig("lane_batch_launch", [_vp, _vp])
+_batch_stage = _sig("lane_batch_launch_stage", [_vp, _i32, _vp])
+_batch_destroy = _sig("lane_batch_destroy", [_vp])
+
+
+class FrameBuffers:
+    """Device buffers of one frame for the batched path (allocated with torch)."""
+
+    def __init__(self, img: torch.Tensor, W: int | None = None, n_theta: int = 360, k: int = 8,
+                 cos_q14=None, sin_q14=None, threshold: int = 128,
+                 border_mode: int = LANE_BORDER_ZERO_MASKRING, tile_mask=None,
+                 want_mag: bool = False, h_theta=None, h_r=None, min_votes: int = 1):
+        H, pitch = img.shape
+        W = pitch if W is None else W
+        dev = img.device
+        self.img, self.W, self.H, self.pitch = img, W, H, pitch
+        self.threshold, self.border_mode = threshold, border_mode
+        self.D = r_offset(W, H)
+        self.n_r = 2 * self.D + 1
+        self.n_theta = n_theta if cos_q14 is None else cos_q14.shape[0]
+        if cos_q14 is None:
+            c, s = make_trig_q14(n_theta)
+            cos_q14, sin_q14 = torch.from_numpy(c).to(dev), torch.from_numpy(s).to(dev)
+        self.cos_q14, self.sin_q14 = cos_q14, sin_q14
+        self.tile_mask = tile_mask
+        self.edges = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        self.mag = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_mag else None
+        self.edge_list = new_edge_list(W, H, dev)
+        self.acc = torch.empty((self.n_theta, self.n_r), dtype=torch.int32, device=dev)
+        self.k = k
+        self.h_theta = max(1, -(-self.n_theta // 100)) if h_theta is None else h_theta
+        self.h_r = max(1, -(-self.n_r // 100)) if h_r is None else h_r
+        self.min_votes = min_votes
+        self.peaks = torch.empty(3 * k + 1, dtype=torch.int32, device=dev)
+        nws = peaks_workspace_size(self.n_theta, self.n_r)
+        self.peaks_ws = torch.empty(nws // 8 + 2, dtype=torch.int64, device=dev)
+        self.counters = torch.empty(2, dtype=torch.int32, device=dev)
+
+    def desc(self) -> LaneFrame:
+        f = LaneFrame()
+        f.img = self.img.data_ptr()
+        f.W, f.H, f.pitch = self.W, self.H, self.pitch
+        f.threshold, f.border_mode = self.threshold, self.border_mode
+        f.edges = self.edges.data_ptr()
+        f.mag_opt = None if self.mag is None else self.mag.data_ptr()
+        f.list = self.edge_list.data_ptr()
+        f.cos_q14, f.sin_q14 = self.cos_q14.data_ptr(), self.sin_q14.data_ptr()
+        f.n_theta, f.r_offset, f.n_r = self.n_theta, self.D, self.n_r
+        f.tile_mask_opt = None if self.tile_mask is None else self.tile_mask.data_ptr()
+        f.acc = self.acc.data_ptr()
+        f.k, f.h_theta, f.h_r, f.min_votes = self.k, self.h_theta, self.h_r, self.min_votes
+        f.peaks = self.peaks.data_ptr() if self.k > 0 else None
+        f.peaks_ws = self.peaks_ws.data_ptr()
+        f.peaks_ws_bytes = self.peaks_ws.numel() * 8
+        f.counters_opt = self.counters.data_ptr()
+        return f
+
+    def theta_idx(self):
+        return self.peaks[0:self.k]
+
+    def r_idx(self):
+        return self.peaks[self.k:2 * self.k]
+
+    def votes(self):
+        return self.peaks[2 * self.k:3 * self.k]
+
+    def count(self):
+        return self.peaks[3 * self.k]
+
+
+class Batch:
+    """A plan over a list of FrameBuffers: launch() runs the whole path for
+    every frame as one graph launch."""
+
+    def __init__(self, frames, vote_rows: int = 0, vote_queue: int = -1,
+                 sobel_groups_per_cu: int = 0):
+        self.frames = list(frames)
+        arr = (LaneFrame * len(self.frames))(*[f.desc() for f in self.frames])
+        tune = LaneTune(vote_rows, vote_queue, sobel_groups_per_cu)
+        h = _vp()
+        _check(_batch_create(arr, len(self.frames), ctypes.byref(tune), ctypes.byref(h)),
+               "lane_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_batch_launch(self._h, _stream(stream)), "lane_batch_launch")
+
+    def launch_stage(self, stage: int, stream=None):
+        _check(_batch_stage(self._h, stage, _stream(stream)), "lane_batch_launch_stage")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize()
+            _batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

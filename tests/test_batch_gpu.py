@@ -1,0 +1,125 @@
+"""Batched plans (one HIP graph per launch) against the CPU oracle: every
+frame's outputs in a mixed batch equal the oracle's, bit-exactly, on every
+replay of the graph, with eager work between the replays."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lane():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2212_09460_amd.lane as lane_mod
+
+    return lane_mod
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def make_frames(lane, synth, oracle, specs, n_theta=360, k=8):
+    frames, wants = [], []
+    C, S = synth.trig_q14(n_theta)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    for (Wf, Hf, pitch, seed, masked) in specs:
+        img = synth.gen_frame(synth.scene_road(Wf, Hf), seed, pitch=pitch)
+        mask = None
+        if masked:
+            rng = np.random.default_rng(seed)
+            mask = rng.integers(0, 256, ((Hf + 7) // 8, (Wf + 7) // 8)).astype(np.uint8)
+        fb = lane.FrameBuffers(torch.from_numpy(img).cuda(), Wf, n_theta, k, Cd, Sd,
+                               tile_mask=None if mask is None else torch.from_numpy(mask).cuda())
+        frames.append(fb)
+        want = oracle.pipeline(img[:, :Wf].copy(), C, S, k, tile_mask=mask)
+        wants.append(want)
+    return frames, wants
+
+
+def check(frames, wants):
+    torch.cuda.synchronize()
+    for i, (f, w) in enumerate(zip(frames, wants)):
+        assert (f.edges.cpu().numpy() == w["edges"]).all(), i
+        assert (f.acc.cpu().numpy() == w["acc"]).all(), i
+        c = f.counters.cpu().numpy()
+        assert int(c[0]) == w["n_edges"] and int(c[1]) == w["dropped"], i
+        assert int(f.count().cpu()) == w["count"], i
+        assert (f.theta_idx().cpu().numpy() == w["theta_idx"]).all(), i
+        assert (f.r_idx().cpu().numpy() == w["r_idx"]).all(), i
+        assert (f.votes().cpu().numpy() == w["votes"]).all(), i
+
+
+def scribble(frames):
+    for f in frames:
+        f.edges.fill_(3)
+        f.acc.fill_(-7)
+        f.peaks.fill_(-5)
+        f.counters.fill_(99)
+        f.edge_list.fill_(0x7FFF7FFF)
+
+
+@pytest.mark.parametrize("queue", [-1, 0, 1])
+def test_mixed_batch_graph_replays(lane, synth, oracle, queue):
+    say("mixed batch queue", queue)
+    specs = [(640, 480, 640, 11, False), (1280, 720, 1280, 12, False), (1920, 1080, 1920, 13, False),
+             (3840, 2160, 3840, 14, False), (997, 41, 1000, 15, False), (33, 17, 33, 16, False),
+             (640, 480, 640, 17, True), (1920, 1080, 1920, 18, True)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, vote_queue=queue)
+    for rep in range(3):
+        say("replay", rep)
+        b.launch()
+        check(frames, wants)
+        scribble(frames)
+        torch.cuda.synchronize()
+    b.launch()
+    check(frames, wants)
+    b.close()
+
+
+def test_same_size_static_and_stages(lane, synth, oracle):
+    say("same-size static")
+    specs = [(640, 480, 640, 100 + i, False) for i in range(12)]
+    frames, wants = make_frames(lane, synth, oracle, specs, n_theta=180, k=2)
+    b = lane.Batch(frames, vote_queue=0)
+    b.launch()
+    check(frames, wants)
+    scribble(frames)
+    for st in range(4):
+        b.launch_stage(st)
+    check(frames, wants)
+    b.close()
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16])
+def test_vote_rows_override(lane, synth, oracle, rows):
+    say("vote rows", rows)
+    specs = [(1280, 720, 1280, 7, False), (640, 480, 640, 8, True)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, vote_rows=rows)
+    b.launch()
+    check(frames, wants)
+    b.close()
+
+
+def test_batch_matches_single_frame_calls(lane, synth):
+    """A frame gives the same bytes alone (single-frame entry points) and in
+    a batch."""
+    say("alone == in batch")
+    img = torch.from_numpy(synth.plain_1080(5)).cuda()
+    C, S = synth.trig_q14(360)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    alone = lane.pipeline(img, Cd, Sd, 8)
+    others = [lane.FrameBuffers(torch.from_numpy(synth.road(1280, 720, 900 + i)).cuda(), None,
+                                360, 8, Cd, Sd) for i in range(3)]
+    fb = lane.FrameBuffers(img, None, 360, 8, Cd, Sd)
+    b = lane.Batch(others[:2] + [fb] + others[2:])
+    b.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(fb.acc, alone["acc"]) and torch.equal(fb.edges, alone["edges"])
+    assert torch.equal(fb.theta_idx(), alone["theta_idx"]) and torch.equal(fb.votes(), alone["votes"])
+    b.close()
