@@ -124,6 +124,9 @@ def main():
     t_vote = event_time(torch, lambda: batch.launch_stage(2, stream), stage_iters, stream)
     t_peaks = event_time(torch, lambda: batch.launch_stage(3, stream), stage_iters, stream)
 
+    # one clean full pass so the per-frame counters hold one run's counts
+    batch.launch(stream)
+    torch.cuda.synchronize()
     counters = torch.stack([f.counters for f in frames]).cpu().numpy()
     n_edges = counters[:, 0].astype(np.int64)
     dropped = int(counters[:, 1].sum())

@@ -8,7 +8,21 @@
 
 #define LANE_INTERNAL __attribute__((visibility("hidden")))
 
+// Global-memory accessors.  Pointers read out of descriptor tables are
+// generic to the compiler, which then emits flat instructions; flat loads
+// share the LDS wait counter, so every wait on them would also drain the
+// vote's LDS atomics.  These casts make the accesses global_load/store.
+#define LANE_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 namespace lane {
+
+template <class T>
+__device__ __forceinline__ T gld(const T* p) { return *(const LANE_GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) { *(LANE_GLOBAL T*)p = v; }
+__device__ __forceinline__ u32x4 gld4(const void* p) { return *(const LANE_GLOBAL u32x4*)p; }
+__device__ __forceinline__ void gst4(void* p, u32x4 v) { *(LANE_GLOBAL u32x4*)p = v; }
 
 constexpr int kWave = 64;
 constexpr int kTile = 8;                 // edge tiles are 8x8 pixels

@@ -64,11 +64,11 @@ __device__ __forceinline__ void block_key(const PeaksDesc& d, int b, int lane) {
     const uint32_t c1 = min(ncell, c0 + B);
     unsigned long long best = 0;
     for (uint32_t c = c0 + lane; c < c1; c += kWave) {
-        const unsigned long long k = make_key(d.acc[c], c);
+        const unsigned long long k = make_key(gld(d.acc + c), c);
         best = k > best ? k : best;
     }
     best = wave_max_u64(best);
-    if (lane == 0) d.keys[b] = best;
+    if (lane == 0) gst(d.keys + b, best);
 }
 
 __global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {

@@ -34,15 +34,15 @@ __device__ __forceinline__ void load_row(const uint8_t* __restrict__ img, int W,
                                          int& left, int& right) {
     const bool yin = (y >= 0) && (y < H);
     if (FAST) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (active && yin) v = *reinterpret_cast<const uint4*>(img + (size_t)y * pitch + x0);
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (active && yin) v = gld4(img + (size_t)y * pitch + x0);
         p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
         uint32_t up = __shfl((int)v.w, lane > 0 ? lane - 1 : 0);
         uint32_t dn = __shfl((int)v.x, lane < kWave - 1 ? lane + 1 : kWave - 1);
         left = (int)(up >> 24);
         right = (int)(dn & 0xFFu);
-        if (lane == 0) left = (yin && x0 > 0 && x0 - 1 < W) ? img[(size_t)y * pitch + x0 - 1] : 0;
-        if (lane == kWave - 1) right = (yin && x0 + 16 < W) ? img[(size_t)y * pitch + x0 + 16] : 0;
+        if (lane == 0) left = (yin && x0 > 0 && x0 - 1 < W) ? gld(img + (size_t)y * pitch + x0 - 1) : 0;
+        if (lane == kWave - 1) right = (yin && x0 + 16 < W) ? gld(img + (size_t)y * pitch + x0 + 16) : 0;
     } else {
 #pragma unroll
         for (int w = 0; w < 4; ++w) p[w] = 0;
@@ -112,11 +112,11 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1);
     const int seg = ty * L.nchunk + chunk;
     uint32_t* list = d.list;
-    if (lane == 0) list[seg] = total;
+    if (lane == 0) gst(list + seg, total);
     uint32_t* info = list + L.off_info + (size_t)ty * L.tw;
     const int txa = chunk * kTilesPerChunk + 2 * lane;
-    if (txa < L.tw) info[txa] = (ca << 16) | off;
-    if (txa + 1 < L.tw) info[txa + 1] = (cb << 16) | (off + ca);
+    if (txa < L.tw) gst(info + txa, (ca << 16) | off);
+    if (txa + 1 < L.tw) gst(info + txa + 1, (cb << 16) | (off + ca));
     if (total == 0) return;
     uint32_t* ents = list + L.off_ent + (size_t)seg * kSegCap;
     const int ntiles = min(kTilesPerChunk, L.tw - chunk * kTilesPerChunk);
@@ -138,7 +138,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
             if ((m >> lane) & 1ull) {
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
                 const uint32_t x = (uint32_t)((chunk * kTilesPerChunk + 2 * src + half) * kTile + (lane & 7));
-                ents[start + rank] = ybase | x;
+                gst(ents + start + rank, ybase | x);
             }
         }
     }
@@ -167,8 +167,8 @@ __device__ __forceinline__ void sobel_row_out(const SobelDesc& d, int y, int x0,
     if (!active) return;
     const size_t o = (size_t)y * d.W + x0;
     if (FAST) {
-        *reinterpret_cast<uint4*>(d.edges + o) = make_uint4(eb[0], eb[1], eb[2], eb[3]);
-        if (d.mag) *reinterpret_cast<uint4*>(d.mag + o) = make_uint4(mb[0], mb[1], mb[2], mb[3]);
+        gst4(d.edges + o, u32x4{eb[0], eb[1], eb[2], eb[3]});
+        if (d.mag) gst4(d.mag + o, u32x4{mb[0], mb[1], mb[2], mb[3]});
     } else {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {

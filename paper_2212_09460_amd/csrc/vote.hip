@@ -78,7 +78,7 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
     __syncthreads();
     if (tid < T) {
         const int k = k0 + tid;
-        const int C = d.cos_q14[k], S = d.sin_q14[k];
+        const int C = gld(d.cos_q14 + k), S = gld(d.sin_q14 + k);
         const int xs[4] = {0, d.W - 1, 0, d.W - 1};
         const int ys[4] = {0, 0, d.H - 1, d.H - 1};
         int rmin = 0x7FFFFFFF, rmax = -0x7FFFFFFF;
@@ -106,7 +106,7 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
     __syncthreads();
     const bool fast = s_fast != 0;
     const int kk = k0 + j;
-    const int C = d.cos_q14[kk], S = d.sin_q14[kk];
+    const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
     const bool masked = d.tile_mask != nullptr;
     const int bb = masked ? band_bits_dev(d.n_theta, kk) : 0xFF;
     int slice_bits = 0;
@@ -122,23 +122,43 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
         __syncthreads();
         if (!masked) {
+            auto vote4 = [&](u32x4 q) {
+                lds_vote((uint32_t)dot2_i16((int)q.x, CS, K));
+                lds_vote((uint32_t)dot2_i16((int)q.y, CS, K));
+                lds_vote((uint32_t)dot2_i16((int)q.z, CS, K));
+                lds_vote((uint32_t)dot2_i16((int)q.w, CS, K));
+            };
             for (int seg = wave; seg < L.nseg; seg += nwaves) {
-                const int n = min((int)list[seg], kSegCap);
+                const int n = min((int)gld(list + seg), kSegCap);
                 const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap;
-                const int step = 4 * G;
+                const int step = 4 * G;        // entries one wave-iteration covers
                 const int nfull = n / step;
                 const uint32_t* p = ents + 4 * g;
-                for (int it = 0; it < nfull; ++it, p += step) {
-                    const uint4 q = *reinterpret_cast<const uint4*>(p);
-                    lds_vote((uint32_t)dot2_i16((int)q.x, CS, K));
-                    lds_vote((uint32_t)dot2_i16((int)q.y, CS, K));
-                    lds_vote((uint32_t)dot2_i16((int)q.z, CS, K));
-                    lds_vote((uint32_t)dot2_i16((int)q.w, CS, K));
+                // software pipeline: U 128-bit loads per lane stay in flight
+                // while the previous U are voted
+                constexpr int U = 4;
+                int it = 0;
+                if (nfull >= U) {
+                    u32x4 cur[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) cur[u] = gld4(p + u * step);
+                    for (it = U; it + U <= nfull; it += U) {
+                        u32x4 nxt[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) nxt[u] = gld4(p + (it + u) * step);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) vote4(cur[u]);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) vote4(cur[u]);
                 }
+                for (; it < nfull; ++it) vote4(gld4(p + it * step));
                 const int i0 = nfull * step + 4 * g;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (i0 + q < n) lds_vote((uint32_t)dot2_i16((int)ents[i0 + q], CS, K));
+                    if (i0 + q < n) lds_vote((uint32_t)dot2_i16((int)gld(ents + i0 + q), CS, K));
                 }
             }
         } else {
@@ -150,14 +170,14 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
                 const uint32_t* info = list + L.off_info + (size_t)ty * L.tw;
                 const uint8_t* mrow = d.tile_mask + (size_t)ty * L.tw;
                 for (int tx = tx0; tx < tx1; ++tx) {
-                    const uint32_t inf = info[tx];
+                    const uint32_t inf = gld(info + tx);
                     const int cnt = min((int)(inf >> 16), kTile * kTile);
                     if (cnt == 0 || (int)(inf & 0xFFFFu) > kSegCap - cnt) continue;
-                    const int m = mrow[tx];
+                    const int m = gld(mrow + tx);
                     if ((m & slice_bits) == 0) continue;
                     if ((m & bb) == 0) continue;  // this lane's angle is pruned in this tile
                     const uint32_t* te = ents + (inf & 0xFFFFu);
-                    for (int e = g; e < cnt; e += G) lds_vote((uint32_t)dot2_i16((int)te[e], CS, K));
+                    for (int e = g; e < cnt; e += G) lds_vote((uint32_t)dot2_i16((int)gld(te + e), CS, K));
                 }
             }
         }
@@ -169,7 +189,7 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
             int32_t* out = d.acc + (size_t)row * d.n_r;
             for (int i = tid; i < d.n_r; i += blockDim.x) {
                 const int o = i - rlo;
-                out[i] = (o >= 0 && o < rwin) ? s_acc[rbase + o] : 0;
+                gst(out + i, (o >= 0 && o < rwin) ? s_acc[rbase + o] : 0);
             }
         }
     } else {
