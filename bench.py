@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU-oracle budget for the baseline sample (0 = skip)")
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--vote-rows", type=int, default=0,
+                    help="theta rows per vote workgroup (0 = tuned default)")
+    ap.add_argument("--vote-queue", type=int, default=-1)
     return ap.parse_args()
 
 
@@ -104,7 +107,7 @@ def main():
         img = torch.empty((H, W), dtype=torch.uint8, device=dev)
         img.copy_(pool_d[i % POOL])
         frames.append(lane.FrameBuffers(img, W, N_THETA, TOPK, Cd, Sd))
-    batch = lane.Batch(frames)
+    batch = lane.Batch(frames, vote_rows=args.vote_rows, vote_queue=args.vote_queue)
 
     # correctness guard on one frame: edges and peaks against the oracle
     batch.launch(stream)
@@ -142,7 +145,7 @@ def main():
     vote_gvotes = votes / (t_vote * 1e-3) / 1e9
 
     # single-frame latency: a one-frame plan, each launch timed alone
-    one = lane.Batch([frames[0]])
+    one = lane.Batch([frames[0]], vote_rows=args.vote_rows)
     lat = []
     for i in range(args.latency_iters + 5):
         a = torch.cuda.Event(enable_timing=True)
@@ -172,7 +175,8 @@ def main():
         "config": {"workload": "1920x1080 seeded road frames: 4 lanes (inner 2 dashed), 200 "
                                "clutter segments, 2% salt; threshold 128, ring masked; 360 theta, "
                                "r step 1 px, Q14 trig, int32 accumulator; top-8 peaks",
-                   "frames_per_step": B, "launch": "one HIP graph per step"},
+                   "frames_per_step": B, "launch": "one HIP graph per step",
+                   "vote_rows": args.vote_rows},
         "frames_per_s": round(B / (ms_step * 1e-3), 1),
         "edge_fraction": round(float(n_edges.sum()) / px, 4),
         "dropped_votes": dropped,

@@ -23,17 +23,19 @@
 using namespace lane;
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
-                                              int grid, hipStream_t s);
+                                              int fast, int grid, hipStream_t s);
 extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy();
 extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H);
 extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode);
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
-                                             uint32_t* queue, int grid, hipStream_t s);
+                                             uint32_t* queue, int half_lds, int grid, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
                                               int total_blocks, int grid_keys, int grid_select,
                                               hipStream_t s);
 extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
+extern "C" LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
+extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
 namespace {
 
@@ -62,9 +64,10 @@ struct lane_batch {
     int* d_prefix = nullptr;
     uint32_t** d_counters = nullptr;
     uint32_t* d_queue = nullptr;
-    int n_sobel_items = 0, n_vote_items = 0, total_blocks = 0;
-    int grid_sobel = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
+    int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0, total_blocks = 0;
+    int grid_sobel = 1, grid_sobel_slow = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
     bool vote_dynamic = false;
+    int vote_half_lds = 0;   // every slice fits half the LDS: two vote workgroups per CU
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -83,6 +86,7 @@ int validate(const lane_frame& f) {
     if (f.tile_mask_opt && (f.n_theta % 4) != 0) return LANE_E_UNSUPPORTED;
     if (f.r_offset < -32768 * 4 || f.r_offset > 32768 * 4) return LANE_E_RANGE;
     if (f.k < 0 || f.k > 1024) return LANE_E_ARG;
+    if (f.k > 0 && f.n_theta > 8192) return LANE_E_SIZE;
     if (f.k > 0) {
         if (!f.peaks || !f.peaks_ws || f.h_theta < 0 || f.h_r < 0) return LANE_E_ARG;
         if (((uintptr_t)f.peaks_ws & 15u) != 0) return LANE_E_ARG;
@@ -107,8 +111,14 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
             hipLaunchKernelGGL(k_clear_counters, dim3((b->n + 255) / 256), dim3(256), 0, s,
                                b->d_counters, b->n);
             return hipGetLastError();
-        case 1:
-            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->n_sobel_items, b->grid_sobel, s);
+        case 1: {
+            // aligned frames first (vector loads), then the rest
+            const hipError_t e = lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->n_sobel_fast, 1,
+                                                         b->grid_sobel, s);
+            if (e != hipSuccess) return e;
+            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items + b->n_sobel_fast,
+                                           b->n_sobel_items - b->n_sobel_fast, 0, b->grid_sobel_slow, s);
+        }
         case 2:
             if (b->vote_dynamic) {
                 // a kernel, not a memset node: the ticket restarts on every replay
@@ -117,11 +127,12 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
                 if (e != hipSuccess) return e;
             }
             return lane_launch_vote_batch(b->d_vote, b->d_vote_items, b->n_vote_items,
-                                          b->vote_dynamic ? b->d_queue : nullptr, b->grid_vote, s);
+                                          b->vote_dynamic ? b->d_queue : nullptr, b->vote_half_lds,
+                                          b->grid_vote, s);
         case 3:
             if (b->n_peak_frames == 0) return hipSuccess;
             return lane_launch_peaks_batch(b->d_peaks, b->d_prefix, b->n_peak_frames, b->total_blocks,
-                                           b->grid_keys, b->grid_select, s);
+                                           0, b->grid_select, s);
         default:
             return hipErrorInvalidValue;
     }
@@ -158,11 +169,12 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     std::vector<SobelDesc> sd(n);
     std::vector<VoteDesc> vd(n);
     std::vector<PeaksDesc> pd;
-    std::vector<int2> sitems, vitems;
+    std::vector<int2> sitems, sitems_slow, vitems;
     std::vector<int> prefix(1, 0);
     std::vector<uint32_t*> counters(n, nullptr);
     std::vector<double> vcost;
     bool mixed = false;
+    bool all_half = true;
     for (int i = 0; i < n; ++i) {
         const lane_frame& f = frames[i];
         if (i > 0 && (f.W != frames[0].W || f.H != frames[0].H)) mixed = true;
@@ -181,7 +193,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         s.fast = lane_sobel_fast_ok(&s, 0);
         counters[i] = f.counters_opt;
         const int ns = lane_sobel_items(f.W, f.H);
-        for (int j = 0; j < ns; ++j) sitems.push_back(make_int2(i, j));
+        for (int j = 0; j < ns; ++j) (s.fast ? sitems : sitems_slow).push_back(make_int2(i, j));
 
         VoteDesc& v = vd[i];
         memset(&v, 0, sizeof(v));
@@ -200,6 +212,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.T = tune.vote_rows > 0 ? std::min(tmax, std::min(tune.vote_rows, pow2_floor(f.n_theta))) : tmax;
         v.log2T = ilog2_floor((unsigned)v.T);
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
+        if ((long)v.T * lane_vote_row_cap(f.W, f.H, f.n_r) > kVoteLdsWordsHalf) all_half = false;
 
         if (f.k > 0) {
             PeaksDesc p;
@@ -218,9 +231,13 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
             p.count = f.peaks + 3 * f.k;
             p.keys = (unsigned long long*)f.peaks_ws;
             p.block_log2 = lane_peaks_block_log2(f.n_theta, f.n_r);
-            const uint64_t ncell = (uint64_t)f.n_theta * (uint64_t)f.n_r;
-            p.n_blocks = (int)((ncell + (1ull << p.block_log2) - 1) >> p.block_log2);
+            p.nbr = lane_peaks_blocks_per_row(f.n_r, p.block_log2);
+            p.n_blocks = f.n_theta * p.nbr;
             pd.push_back(p);
+            // the vote writes the block keys while its rows are still in LDS
+            v.keys = p.keys;
+            v.key_log2 = p.block_log2;
+            v.nbr = p.nbr;
             prefix.push_back(prefix.back() + p.n_blocks);
         }
     }
@@ -248,14 +265,18 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
             for (size_t j = 0; j < per[x].size(); ++j) vitems[j * 8 + x] = per[x][j];
     }
 
+    const int n_fast = (int)sitems.size();
+    sitems.insert(sitems.end(), sitems_slow.begin(), sitems_slow.end());
     lane_batch* b = new (std::nothrow) lane_batch();
     if (!b) return LANE_E_DEVICE;
     b->n = n;
+    b->n_sobel_fast = n_fast;
     b->n_peak_frames = (int)pd.size();
     b->n_sobel_items = (int)sitems.size();
     b->n_vote_items = (int)vitems.size();
     b->total_blocks = prefix.back();
     b->vote_dynamic = dynamic;
+    b->vote_half_lds = all_half ? 1 : 0;
 
     // one device allocation for every table
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -296,12 +317,14 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     }
 
     const int occ = tune.sobel_groups_per_cu > 0 ? tune.sobel_groups_per_cu : lane_sobel_batch_occupancy();
-    b->grid_sobel = std::max(1, std::min((b->n_sobel_items + kSobelWaves - 1) / kSobelWaves, cus * occ));
+    b->grid_sobel = std::max(1, std::min((n_fast + kSobelWaves - 1) / kSobelWaves, cus * occ));
+    b->grid_sobel_slow = std::max(1, std::min((b->n_sobel_items - n_fast + kSobelWaves - 1) / kSobelWaves, cus * occ));
+    const int vote_per_cu = all_half ? 2 : 1;
     if (dynamic) {
-        b->grid_vote = std::max(1, std::min(b->n_vote_items, cus));
+        b->grid_vote = std::max(1, std::min(b->n_vote_items, cus * vote_per_cu));
     } else {
         // a multiple of 8 keeps every table slot on its XCD
-        b->grid_vote = std::max(8, std::min(b->n_vote_items, cus) / 8 * 8);
+        b->grid_vote = std::max(8, std::min(b->n_vote_items, cus * vote_per_cu) / 8 * 8);
     }
     b->grid_keys = std::max(1, std::min((b->total_blocks + 3) / 4, cus * 8));
     b->grid_select = std::max(1, std::min(b->n_peak_frames, cus));

@@ -126,11 +126,18 @@ int lane_edges_to_list(const uint8_t* edges, int32_t W, int32_t H, int32_t pitch
 // Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
 // whose rows fit in LDS, each row holding up to D + 3 cells (the r range of
 // one angle across the frame, plus rounding).
-LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
+// LDS cells one theta row needs: the r range of one angle across the frame
+// (at most D + 1 cells, plus rounding), never more than n_r.
+LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r) {
     int32_t D = 0;
     lane_r_offset(W, H, &D);
-    int row = D + 3;
-    if (row > n_r) row = n_r;
+    return D + 3 < n_r ? D + 3 : n_r;
+}
+
+// Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
+// whose rows fit in LDS.
+LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
+    const int row = lane_vote_row_cap(W, H, n_r);
     int T = kMaxT;
     while (T > 1 && (T > n_theta || (long)T * row > kVoteLdsWords)) T >>= 1;
     return T;
@@ -170,19 +177,23 @@ int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* c
     return dev_status(lane_launch_vote(&d, s));
 }
 
+// Key blocks are row chunks of 1 << lg cells; the smallest lg >= 6 (one
+// wave per block) whose block count fits the selection pass's LDS table.
 LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r) {
-    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
-    int lg = 8;
-    while (((ncell + (1ull << lg) - 1) >> lg) > (uint64_t)kPeaksMaxBlocksLds) ++lg;
+    int lg = 6;
+    while ((int64_t)n_theta * (((int64_t)n_r + (1ll << lg) - 1) >> lg) > kPeaksMaxBlocksLds) ++lg;
     return lg;
+}
+
+LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg) {
+    return (int)(((int64_t)n_r + (1ll << lg) - 1) >> lg);
 }
 
 int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t* bytes) {
     if (n_theta <= 0 || n_r <= 0 || !bytes) return LANE_E_ARG;
-    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
-    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
+    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll || n_theta > kPeaksMaxBlocksLds) return LANE_E_SIZE;
     const int lg = lane_peaks_block_log2(n_theta, n_r);
-    *bytes = (size_t)((ncell + (1ull << lg) - 1) >> lg) * sizeof(unsigned long long);
+    *bytes = (size_t)n_theta * (size_t)lane_peaks_blocks_per_row(n_r, lg) * sizeof(unsigned long long);
     return LANE_OK;
 }
 
@@ -194,7 +205,8 @@ int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r
         k < 1 || k > 1024 || h_theta < 0 || h_r < 0)
         return LANE_E_ARG;
     if (!aligned16(ws)) return LANE_E_ARG;
-    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll || h_theta > 1000000 || h_r > 1000000)
+    if ((int64_t)n_theta * n_r > 0x7FFFFFFFll || h_theta > 1000000 || h_r > 1000000 ||
+        n_theta > kPeaksMaxBlocksLds)
         return LANE_E_SIZE;
     if (n_r != 2 * r_offset + 1) return LANE_E_RANGE;
     size_t need = 0;
@@ -216,8 +228,8 @@ int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r
     d.count = count;
     d.keys = (unsigned long long*)ws;
     d.block_log2 = lane_peaks_block_log2(n_theta, n_r);
-    const uint64_t ncell = (uint64_t)n_theta * (uint64_t)n_r;
-    d.n_blocks = (int)((ncell + (1ull << d.block_log2) - 1) >> d.block_log2);
+    d.nbr = lane_peaks_blocks_per_row(n_r, d.block_log2);
+    d.n_blocks = n_theta * d.nbr;
     return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));
 }
 

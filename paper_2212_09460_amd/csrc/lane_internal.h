@@ -32,7 +32,8 @@ constexpr int kSegCap = kTile * kChunkPx;  // entries a segment can hold
 constexpr int kStripRows = 32;           // rows one Sobel wave walks down
 constexpr int kSobelWaves = 4;           // waves per Sobel workgroup
 constexpr int kVoteThreads = 1024;       // 16 waves per vote workgroup
-constexpr int kVoteLdsWords = 40704;     // accumulator dwords in LDS (159 KB)
+constexpr int kVoteLdsWords = 40704;     // accumulator dwords in LDS (159 KB): 1 workgroup/CU
+constexpr int kVoteLdsWordsHalf = 20224; // 79 KB: 2 workgroups/CU
 constexpr int kMaxT = 64;                // theta rows per vote workgroup (max)
 
 // Layout of the compacted edge list of one frame (offsets in uint32 words).
@@ -78,6 +79,9 @@ struct VoteDesc {
     int T;                     // theta rows per workgroup (power of two <= 64)
     int log2T;
     int n_slices;
+    unsigned long long* keys;  // or null: peak-search block keys written with the rows
+    int key_log2;              // cells per key block = 1 << key_log2
+    int nbr;                   // key blocks per row
 };
 
 // One frame for the peak search.
@@ -90,9 +94,28 @@ struct PeaksDesc {
     int32_t* votes;
     int32_t* count;
     unsigned long long* keys;  // workspace: one key per block
-    int block_log2;            // cells per block = 1 << block_log2
-    int n_blocks;
+    int block_log2;            // a block is 1 << block_log2 cells of one row
+    int nbr;                   // blocks per row, ceil(n_r / block size)
+    int n_blocks;              // n_theta * nbr
 };
+
+// Peak-search key of a cell: one unsigned max picks the largest count and,
+// among equal counts, the smallest theta-major index.
+__device__ __forceinline__ unsigned long long make_key(int v, uint32_t idx) {
+    return ((unsigned long long)((uint32_t)v ^ 0x80000000u) << 32) |
+           (unsigned long long)(0xFFFFFFFFu - idx);
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+        const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+        v = w > v ? w : v;
+    }
+    return v;
+}
 
 constexpr int kPeaksMaxBlocksLds = 8192;  // keys held in LDS by the select pass
 

@@ -18,9 +18,6 @@
 
 namespace lane {
 
-__device__ __forceinline__ unsigned long long make_key(int v, uint32_t idx) {
-    return ((unsigned long long)((uint32_t)v ^ 0x80000000u) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
-}
 __device__ __forceinline__ int key_value(unsigned long long k) {
     return (int)((uint32_t)(k >> 32) ^ 0x80000000u);
 }
@@ -28,16 +25,6 @@ __device__ __forceinline__ uint32_t key_index(unsigned long long k) {
     return 0xFFFFFFFFu - (uint32_t)k;
 }
 
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
-        const unsigned long long w = ((unsigned long long)hi << 32) | lo;
-        v = w > v ? w : v;
-    }
-    return v;
-}
 
 __device__ __forceinline__ int floor_div_i(int a, int b) {
     int q = a / b;
@@ -57,14 +44,15 @@ __device__ __forceinline__ bool in_window(int t, int i, int tp, int ip, const Pe
     return false;
 }
 
+// key of block b = (row t, column chunk j): cells t*n_r + [j*B, min(n_r, (j+1)*B))
 __device__ __forceinline__ void block_key(const PeaksDesc& d, int b, int lane) {
-    const uint32_t ncell = (uint32_t)d.n_theta * (uint32_t)d.n_r;
-    const uint32_t B = 1u << d.block_log2;
-    const uint32_t c0 = (uint32_t)b << d.block_log2;
-    const uint32_t c1 = min(ncell, c0 + B);
+    const int t = b / d.nbr, j = b - t * d.nbr;
+    const int B = 1 << d.block_log2;
+    const int i0 = j * B, i1 = min(d.n_r, i0 + B);
+    const uint32_t rowc = (uint32_t)t * (uint32_t)d.n_r;
     unsigned long long best = 0;
-    for (uint32_t c = c0 + lane; c < c1; c += kWave) {
-        const unsigned long long k = make_key(gld(d.acc + c), c);
+    for (int i = i0 + lane; i < i1; i += kWave) {
+        const unsigned long long k = make_key(gld(d.acc + rowc + i), rowc + (uint32_t)i);
         best = k > best ? k : best;
     }
     best = wave_max_u64(best);
@@ -105,9 +93,8 @@ __shared__ int s_found, s_stop;
 __device__ void peaks_select(const PeaksDesc& d) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
-    const uint32_t ncell = (uint32_t)d.n_theta * (uint32_t)d.n_r;
     const int floor_votes = d.min_votes > 1 ? d.min_votes : 1;
-    for (int b = tid; b < d.n_blocks; b += blockDim.x) s_keys[b] = d.keys[b];
+    for (int b = tid; b < d.n_blocks; b += blockDim.x) s_keys[b] = gld(d.keys + b);
     if (tid == 0) {
         s_found = 0;
         s_stop = 0;
@@ -143,8 +130,7 @@ __device__ void peaks_select(const PeaksDesc& d) {
                     const int centre = (q & 1) ? 2 * d.r_offset - i : i;
                     const int ca = max(0, centre - d.h_r), cb = min(d.n_r - 1, centre + d.h_r);
                     if (ca > cb) continue;
-                    const uint32_t f0 = (uint32_t)row * d.n_r + ca, f1 = (uint32_t)row * d.n_r + cb;
-                    for (uint32_t b = f0 >> d.block_log2; b <= (f1 >> d.block_log2); ++b)
+                    for (int b = row * d.nbr + (ca >> d.block_log2); b <= row * d.nbr + (cb >> d.block_log2); ++b)
                         s_mark[b >> 5] |= 1u << (b & 31);
                 }
                 int n = 0;
@@ -165,15 +151,15 @@ __device__ void peaks_select(const PeaksDesc& d) {
         const int nsel = j + 1;
         for (int li = wave; li < s_nlist; li += nwaves) {
             const int b = s_list[li];
-            const uint32_t c0 = (uint32_t)b << d.block_log2;
-            const uint32_t c1 = min(ncell, c0 + (1u << d.block_log2));
+            const int t = b / d.nbr, jb = b - t * d.nbr;
+            const int i0 = jb << d.block_log2, i1 = min(d.n_r, i0 + (1 << d.block_log2));
+            const uint32_t rowc = (uint32_t)t * (uint32_t)d.n_r;
             unsigned long long bk = 0;
-            for (uint32_t c = c0 + lane; c < c1; c += kWave) {
-                const int t = (int)(c / (uint32_t)d.n_r), i = (int)(c % (uint32_t)d.n_r);
+            for (int i = i0 + lane; i < i1; i += kWave) {
                 bool sup = false;
                 for (int p = 0; p < nsel && !sup; ++p) sup = in_window(t, i, s_sel_t[p], s_sel_i[p], d);
                 if (!sup) {
-                    const unsigned long long kk = make_key(d.acc[c], c);
+                    const unsigned long long kk = make_key(gld(d.acc + rowc + i), rowc + (uint32_t)i);
                     bk = kk > bk ? kk : bk;
                 }
             }
@@ -219,9 +205,11 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* dp, hipSt
 extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
                                               int total_blocks, int grid_keys, int grid_select,
                                               hipStream_t s) {
-    hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys), dim3(256), 0, s, descs, prefix, n_frames);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (grid_keys > 0) {  // 0: the vote already wrote the keys
+        hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys), dim3(256), 0, s, descs, prefix, n_frames);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_peaks_select_batch, dim3(grid_select), dim3(1024), 0, s, descs, n_frames);
     return hipGetLastError();
 }

@@ -7,91 +7,194 @@
 //
 // Work decomposition: one wave walks a strip of 32 rows x 1024 columns; each
 // lane owns 16 adjacent columns, read with one 128-bit load per row, so a
-// wave moves 1 KB per row in a single coalesced instruction.  The 3x3
-// stencil is split into a horizontal pass per row ([1 2 1] smooth and
-// [-1 0 1] difference, using the two neighbour bytes taken from the adjacent
-// lanes) and a vertical pass over three rows held in registers, rotated
-// without copies.  No LDS is needed and nothing is re-read except the two
-// halo rows of the strip.
+// wave moves 1 KB per row in a single coalesced instruction.  Loads run six
+// rows ahead of the arithmetic (a ring of raw rows in registers) so enough
+// bytes are in flight to cover HBM latency.  The 3x3 stencil is split into a
+// horizontal pass per row ([1 2 1] smooth, [-1 0 1] difference, the two
+// neighbour bytes come from the adjacent lanes) and a vertical pass over
+// three rows held in registers.  All of it runs on packed 16-bit pairs
+// (v_pk_* instructions, two pixels per operation): |gx| + |gy| <= 2040 fits.
 //
 // Compaction (the vote reads a list of edge coordinates, Sec. 4.3): after
 // every 8 rows each lane holds the 64-bit edge masks of its two 8x8 tiles.
-// Tile counts are prefix-summed across the wave; then, tile by tile, the
-// tile's mask is broadcast to the wave, every lane whose pixel is an edge
-// takes its rank among the set bits (mbcnt of the mask) and the wave writes
-// the tile's coordinates as one coalesced store.
+// Tile counts are prefix-summed across the wave (the segment offsets); each
+// lane then writes the coordinates of its two tiles' edge pixels in order.
 #include "lane_internal.h"
 
 namespace lane {
 
 enum { kModeSobel = 0, kModeFromEdges = 1 };
 
-// Loads the 16 pixels of one row owned by this lane plus the left and right
-// neighbour; pixels outside the frame (or past W) are 0.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// 16 pixels of one row for one lane, plus the neighbours the lane cannot get
+// from its own wave (lane 0's left, lane 63's right; others come by shuffle)
+struct RawRow {
+    u32x4 v;
+    uint32_t lr;  // left | right << 8
+};
+
 template <bool FAST>
-__device__ __forceinline__ void load_row(const uint8_t* __restrict__ img, int W, int H, int pitch,
-                                         int y, int x0, bool active, int lane, uint32_t (&p)[4],
-                                         int& left, int& right) {
+__device__ __forceinline__ RawRow load_raw(const uint8_t* __restrict__ img, int W, int H, int pitch,
+                                           int y, int x0, bool active, int lane) {
+    RawRow o;
+    o.v = u32x4{0u, 0u, 0u, 0u};
+    o.lr = 0;
     const bool yin = (y >= 0) && (y < H);
+    if (!(active && yin)) return o;
+    const uint8_t* row = img + (size_t)y * pitch;
     if (FAST) {
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (active && yin) v = gld4(img + (size_t)y * pitch + x0);
-        p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
-        uint32_t up = __shfl((int)v.w, lane > 0 ? lane - 1 : 0);
-        uint32_t dn = __shfl((int)v.x, lane < kWave - 1 ? lane + 1 : kWave - 1);
-        left = (int)(up >> 24);
-        right = (int)(dn & 0xFFu);
-        if (lane == 0) left = (yin && x0 > 0 && x0 - 1 < W) ? gld(img + (size_t)y * pitch + x0 - 1) : 0;
-        if (lane == kWave - 1) right = (yin && x0 + 16 < W) ? gld(img + (size_t)y * pitch + x0 + 16) : 0;
+        o.v = gld4(row + x0);
+        if (lane == 0 && x0 > 0) o.lr = gld(row + x0 - 1);
+        if (lane == kWave - 1 && x0 + 16 < W) o.lr = (uint32_t)gld(row + x0 + 16) << 8;
     } else {
+        uint32_t p[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int w = 0; w < 4; ++w) p[w] = 0;
-        left = right = 0;
-        if (active && yin) {
-            const uint8_t* row = img + (size_t)y * pitch;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                int x = x0 + i;
-                uint32_t b = (x < W) ? row[x] : 0u;
-                p[i >> 2] |= b << ((i & 3) * 8);
-            }
-            left = (x0 > 0) ? row[x0 - 1] : 0;
-            right = (x0 + 16 < W) ? row[x0 + 16] : 0;
+        for (int i = 0; i < 16; ++i) {
+            const int x = x0 + i;
+            const uint32_t b = (x < W) ? (uint32_t)gld(row + x) : 0u;
+            p[i >> 2] |= b << ((i & 3) * 8);
         }
+        o.v = u32x4{p[0], p[1], p[2], p[3]};
+        const uint32_t l = (x0 > 0) ? gld(row + x0 - 1) : 0u;
+        const uint32_t rr = (x0 + 16 < W) ? gld(row + x0 + 16) : 0u;
+        o.lr = l | (rr << 8);
+    }
+    return o;
+}
+
+// Horizontal pass on packed pairs: pixel pair k = (a[2k], a[2k+1]).
+struct HRow {
+    u16x2 hs[8];  // [1 2 1] smooth
+    s16x2 hd[8];  // [-1 0 1] difference
+};
+
+template <bool FAST>
+__device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
+    int left = (int)(r.lr & 0xFFu), right = (int)(r.lr >> 8);
+    if (FAST) {
+        // neighbours from the adjacent lanes (lane 0 / 63 loaded theirs)
+        const uint32_t up = (uint32_t)__shfl((int)r.v.w, lane > 0 ? lane - 1 : 0);
+        const uint32_t dn = (uint32_t)__shfl((int)r.v.x, lane < kWave - 1 ? lane + 1 : kWave - 1);
+        if (lane > 0) left = (int)(up >> 24);
+        if (lane < kWave - 1) right = (int)(dn & 0xFFu);
+    }
+    const uint32_t dw[4] = {r.v.x, r.v.y, r.v.z, r.v.w};
+    u16x2 P[8], S[9];
+    // P[k] = (a[2k], a[2k+1]);  S[k] = (a[2k-1], a[2k]) with a[-1] = left, a[16] = right
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        P[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, dw[k >> 1], (k & 1) ? 0x0c030c02u : 0x0c010c00u));
+    S[0] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(dw[0], (uint32_t)left, 0x0c040c00u));
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        if (k & 1) S[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, dw[k >> 1], 0x0c020c01u));
+        else S[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(dw[k >> 1], dw[(k >> 1) - 1], 0x0c040c03u));
+    }
+    S[8] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm((uint32_t)right, dw[3], 0x0c040c03u));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        h.hs[k] = S[k] + P[k] * (unsigned short)2 + S[k + 1];
+        h.hd[k] = __builtin_bit_cast(s16x2, S[k + 1]) - __builtin_bit_cast(s16x2, S[k]);
     }
 }
 
-// Horizontal pass of one row: hs = [1 2 1] smooth, hd = [-1 0 1] difference.
-template <bool FAST>
-__device__ __forceinline__ void row_filter(const SobelDesc& d, int y, int x0, bool active,
-                                           int lane, int (&hs)[16], int (&hd)[16]) {
-    uint32_t p[4];
-    int left, right;
-    load_row<FAST>(d.img, d.W, d.H, d.pitch, y, x0, active, lane, p, left, right);
-    int a[18];
-    a[0] = left;
-    a[17] = right;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) a[i + 1] = (int)((p[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
+// Per-lane constants of the output masking: which of the lane's 16 columns
+// may be edges (inside the frame; not on the ring in border mode 1).
+struct ColMask {
+    uint32_t bits;     // bit i: column x0 + i may be an edge
+    uint32_t bytes[4]; // 0xFF per allowed column, as the edge-map bytes
+};
+
+__device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
+    ColMask c;
+    c.bits = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        hs[i] = a[i] + 2 * a[i + 1] + a[i + 2];
-        hd[i] = a[i + 2] - a[i];
+        const int x = x0 + i;
+        const bool ok = (x < d.W) && !(d.border_mode == 1 && (x == 0 || x == d.W - 1));
+        c.bits |= (uint32_t)ok << i;
     }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b |= ((c.bits >> (4 * w + i)) & 1u) ? (0xFFu << (8 * i)) : 0u;
+        c.bytes[w] = b;
+    }
+    return c;
+}
+
+// Vertical pass and output of row y.  X = hd(y-1) + 2 hd(y) and
+// HU = hs(y-1) were kept from earlier rows; D is row y+1.  Returns the row's
+// 16 edge bits.
+template <bool FAST>
+__device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool active,
+                                         const ColMask& cm, const s16x2 (&X)[8],
+                                         const u16x2 (&HU)[8], const HRow& D) {
+    const unsigned short T = (unsigned short)d.threshold;
+    u16x2 g[8], e16[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const s16x2 gx = X[k] + D.hd[k];
+        const s16x2 gy = __builtin_bit_cast(s16x2, D.hs[k]) - __builtin_bit_cast(s16x2, HU[k]);
+        const s16x2 ax = __builtin_elementwise_max(gx, -gx);
+        const s16x2 ay = __builtin_elementwise_max(gy, -gy);
+        g[k] = __builtin_bit_cast(u16x2, ax + ay);
+        const u16x2 f = __builtin_elementwise_min(__builtin_elementwise_sub_sat(g[k], (u16x2)T),
+                                                  (u16x2)(unsigned short)1);
+        e16[k] = (f << (unsigned short)8) - f;  // 255 or 0
+    }
+    uint32_t eb[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        eb[w] = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, e16[2 * w + 1]),
+                                      __builtin_bit_cast(uint32_t, e16[2 * w]), 0x06040200u);
+    const bool ring_row = (d.border_mode == 1) && (y == 0 || y == d.H - 1);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        eb[w] = ring_row ? 0u : (eb[w] & cm.bytes[w]);
+        // byte flags -> 4 bits: (b & 0x01010101) * 0x01020408 puts them in bits 24..27
+        bits |= (((eb[w] & 0x01010101u) * 0x01020408u) >> 24) << (4 * w);
+    }
+    if (active) {
+        const size_t o = (size_t)y * d.W + x0;
+        uint32_t mb[4] = {0u, 0u, 0u, 0u};
+        if (d.mag) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const u16x2 m0 = __builtin_elementwise_min(g[2 * w], (u16x2)(unsigned short)255);
+                const u16x2 m1 = __builtin_elementwise_min(g[2 * w + 1], (u16x2)(unsigned short)255);
+                mb[w] = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, m1),
+                                              __builtin_bit_cast(uint32_t, m0), 0x06040200u);
+            }
+        }
+        if (FAST) {
+            gst4(d.edges + o, u32x4{eb[0], eb[1], eb[2], eb[3]});
+            if (d.mag) gst4(d.mag + o, u32x4{mb[0], mb[1], mb[2], mb[3]});
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (x0 + i < d.W) {
+                    gst(d.edges + o + i, (uint8_t)(eb[i >> 2] >> ((i & 3) * 8)));
+                    if (d.mag) gst(d.mag + o + i, (uint8_t)(mb[i >> 2] >> ((i & 3) * 8)));
+                }
+            }
+        }
+    }
+    return bits;
 }
 
 // Edge bits of one row of an existing edge map (pixel == 255).
-template <bool FAST>
-__device__ __forceinline__ uint32_t row_edge_bits(const SobelDesc& d, int y, int x0, bool active,
-                                                  int lane) {
-    uint32_t p[4];
-    int left, right;
-    load_row<FAST>(d.img, d.W, d.H, d.pitch, y, x0, active, lane, p, left, right);
+__device__ __forceinline__ uint32_t raw_edge_bits(const RawRow& r, int x0, int W) {
+    const uint32_t dw[4] = {r.v.x, r.v.y, r.v.z, r.v.w};
     uint32_t bits = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        uint32_t b = (p[i >> 2] >> ((i & 3) * 8)) & 0xFFu;
-        bits |= (uint32_t)(b == 255u && x0 + i < d.W) << i;
+        const uint32_t b = (dw[i >> 2] >> ((i & 3) * 8)) & 0xFFu;
+        bits |= (uint32_t)(b == 255u && x0 + i < W) << i;
     }
     return bits;
 }
@@ -105,7 +208,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     uint32_t incl = tot;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)incl, o);
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, o);
         if (lane >= o) incl += t;
     }
     const uint32_t off = incl - tot;
@@ -118,64 +221,18 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     if (txa < L.tw) gst(info + txa, (ca << 16) | off);
     if (txa + 1 < L.tw) gst(info + txa + 1, (cb << 16) | (off + ca));
     if (total == 0) return;
-    uint32_t* ents = list + L.off_ent + (size_t)seg * kSegCap;
-    const int ntiles = min(kTilesPerChunk, L.tw - chunk * kTilesPerChunk);
-    const uint32_t ybase = (uint32_t)(ty * kTile + (lane >> 3)) << 16;
-    const int npairs = (ntiles + 1) >> 1;
-    for (int src = 0; src < npairs; ++src) {
-        const uint32_t src_tot = (uint32_t)__builtin_amdgcn_readlane((int)tot, src);
-        if (src_tot == 0) continue;
-        const uint32_t src_off = (uint32_t)__builtin_amdgcn_readlane((int)off, src);
-        const uint32_t src_ca = (uint32_t)__builtin_amdgcn_readlane((int)ca, src);
+    // each lane writes its own run: tile a then tile b, row-major in a tile
+    uint32_t* dst = list + L.off_ent + (size_t)seg * kSegCap + off;
+    const uint32_t xa = (uint32_t)(txa * kTile);
+    const uint32_t y0 = (uint32_t)(ty * kTile) << 16;
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const uint64_t mm = half ? m1 : m0;
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mm, src);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mm >> 32), src);
-            if ((lo | hi) == 0) continue;
-            const uint32_t start = src_off + (half ? src_ca : 0u);
-            const uint64_t m = ((uint64_t)hi << 32) | lo;
-            if ((m >> lane) & 1ull) {
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-                const uint32_t x = (uint32_t)((chunk * kTilesPerChunk + 2 * src + half) * kTile + (lane & 7));
-                gst(ents + start + rank, ybase | x);
-            }
-        }
-    }
-}
-
-template <bool FAST>
-__device__ __forceinline__ void sobel_row_out(const SobelDesc& d, int y, int x0, bool active,
-                                              const int (&hsU)[16], const int (&hdU)[16],
-                                              const int (&hdM)[16], const int (&hsD)[16],
-                                              const int (&hdD)[16], uint32_t& bits) {
-    uint32_t eb[4] = {0, 0, 0, 0}, mb[4] = {0, 0, 0, 0};
-    bits = 0;
-    const bool ring_row = (d.border_mode == 1) && (y == 0 || y == d.H - 1);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int gx = hdU[i] + 2 * hdM[i] + hdD[i];
-        const int gy = hsD[i] - hsU[i];
-        const int g = abs(gx) + abs(gy);
-        const int x = x0 + i;
-        bool e = (g > d.threshold) && (x < d.W);
-        if (d.border_mode == 1 && (ring_row || x == 0 || x == d.W - 1)) e = false;
-        bits |= (uint32_t)e << i;
-        eb[i >> 2] |= (e ? 0xFFu : 0u) << ((i & 3) * 8);
-        mb[i >> 2] |= (uint32_t)min(g, 255) << ((i & 3) * 8);
-    }
-    if (!active) return;
-    const size_t o = (size_t)y * d.W + x0;
-    if (FAST) {
-        gst4(d.edges + o, u32x4{eb[0], eb[1], eb[2], eb[3]});
-        if (d.mag) gst4(d.mag + o, u32x4{mb[0], mb[1], mb[2], mb[3]});
-    } else {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (x0 + i < d.W) {
-                d.edges[o + i] = (uint8_t)(eb[i >> 2] >> ((i & 3) * 8));
-                if (d.mag) d.mag[o + i] = (uint8_t)(mb[i >> 2] >> ((i & 3) * 8));
-            }
+    for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
+        uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
+        const uint32_t base = y0 + ((uint32_t)((q & 1) * 4) << 16) + xa + (uint32_t)((q >> 1) * kTile);
+        while (m) {
+            const uint32_t b = (uint32_t)__builtin_ctz(m);
+            m &= m - 1u;
+            gst(dst++, base + ((b >> 3) << 16) + (b & 7u));
         }
     }
 }
@@ -190,6 +247,7 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
     const bool active = x0 < d.W;
     const int y_begin = strip * kStripRows;
     const int y_end = min(y_begin + kStripRows, d.H);
+    const int y_load_end = min(y_end + 1, d.H);  // rows this strip reads: [y_begin - 1, y_end]
     uint64_t m0 = 0, m1 = 0;
     uint32_t nedge = 0;
 
@@ -198,34 +256,56 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
         const int ly = y & (kTile - 1);
         m0 |= (uint64_t)(bits & 0xFFu) << (ly * 8);
         m1 |= (uint64_t)((bits >> 8) & 0xFFu) << (ly * 8);
-        if (ly == kTile - 1 || y == y_end - 1) {
-            if (d.list) compact_tile_row(d, L, chunk, y >> 3, m0, m1, lane);
-            m0 = 0;
-            m1 = 0;
-        }
+    };
+    auto flush = [&](int ty) {
+        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane);
+        m0 = 0;
+        m1 = 0;
+    };
+    auto load = [&](int y) {
+        return load_raw<FAST>(d.img, d.W, d.H, d.pitch, y, x0, active && y < y_load_end, lane);
     };
 
     if (MODE == kModeFromEdges) {
-        for (int y = y_begin; y < y_end; ++y) account(y, row_edge_bits<FAST>(d, y, x0, active, lane));
-    } else {
-        int hsA[16], hdA[16], hsB[16], hdB[16], hsC[16], hdC[16];
-        row_filter<FAST>(d, y_begin - 1, x0, active, lane, hsA, hdA);
-        row_filter<FAST>(d, y_begin, x0, active, lane, hsB, hdB);
-        // rows rotate A -> B -> C without register copies
-        for (int y = y_begin; y < y_end; y += 3) {
-            uint32_t bits;
-            row_filter<FAST>(d, y + 1, x0, active, lane, hsC, hdC);
-            sobel_row_out<FAST>(d, y, x0, active, hsA, hdA, hdB, hsC, hdC, bits);
-            account(y, bits);
-            if (y + 1 >= y_end) break;
-            row_filter<FAST>(d, y + 2, x0, active, lane, hsA, hdA);
-            sobel_row_out<FAST>(d, y + 1, x0, active, hsB, hdB, hdC, hsA, hdA, bits);
-            account(y + 1, bits);
-            if (y + 2 >= y_end) break;
-            row_filter<FAST>(d, y + 3, x0, active, lane, hsB, hdB);
-            sobel_row_out<FAST>(d, y + 2, x0, active, hsC, hdC, hdA, hsB, hdB, bits);
-            account(y + 2, bits);
+        for (int y = y_begin; y < y_end; ++y) {
+            account(y, raw_edge_bits(load(y), x0, d.W));
+            if ((y & (kTile - 1)) == kTile - 1 || y == y_end - 1) flush(y >> 3);
         }
+    } else {
+        const ColMask cm = col_mask(d, x0);
+        // raw rows y+1 .. y+4 in flight; Q0/Q1 alternate as "row y" and
+        // "row y+1"; X = hd(y-1) + 2 hd(y) and HU = hs(y-1) carry over
+        RawRow R0 = load(y_begin + 1), R1 = load(y_begin + 2);
+        RawRow R2 = load(y_begin + 3), R3 = load(y_begin + 4);
+        HRow Q0, Q1;
+        s16x2 X[8];
+        u16x2 HU[8];
+        hfilter<FAST>(load(y_begin - 1), lane, Q1);
+        hfilter<FAST>(load(y_begin), lane, Q0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            X[k] = Q1.hd[k] + Q0.hd[k] * (short)2;
+            HU[k] = Q1.hs[k];
+        }
+#define LANE_SOBEL_STEP(QC, QN, R_, dy)                                           \
+    if (y + (dy) < y_end) {                                                       \
+        const int yy = y + (dy);                                                  \
+        hfilter<FAST>(R_, lane, QN);                                              \
+        R_ = load(yy + 5);                                                        \
+        account(yy, vout<FAST>(d, yy, x0, active, cm, X, HU, QN));                \
+        _Pragma("unroll") for (int k = 0; k < 8; ++k) {                           \
+            X[k] = QC.hd[k] + QN.hd[k] * (short)2;                                \
+            HU[k] = QC.hs[k];                                                     \
+        }                                                                         \
+    }
+        for (int y = y_begin; y < y_end; y += 4) {
+            LANE_SOBEL_STEP(Q0, Q1, R0, 0)
+            LANE_SOBEL_STEP(Q1, Q0, R1, 1)
+            LANE_SOBEL_STEP(Q0, Q1, R2, 2)
+            LANE_SOBEL_STEP(Q1, Q0, R3, 3)
+            if (((y + 4) & (kTile - 1)) == 0 || y + 4 >= y_end) flush(y >> 3);
+        }
+#undef LANE_SOBEL_STEP
     }
     if (d.edge_count) {
         uint32_t s = nedge;
@@ -236,24 +316,26 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
 }
 
 template <bool FAST, int MODE>
-__global__ void __launch_bounds__(kWave * kSobelWaves) k_sobel(SobelDesc d, int n_items) {
-    const int item = blockIdx.x * kSobelWaves + (threadIdx.x >> 6);
+__global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
+    k_sobel(SobelDesc d, int n_items) {
+    const int item = blockIdx.x * kSobelWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (item >= n_items) return;  // whole wave leaves; no barriers in this kernel
     sobel_item<FAST, MODE>(d, item);
 }
 
 // Batched, persistent: each wave walks the (frame, item) table with a grid
-// stride.  Frames of any size and alignment mix in one launch; the aligned
-// fast path is chosen per frame.
-__global__ void __launch_bounds__(kWave * kSobelWaves)
+// stride.  Frames of any size mix in one launch; frames whose rows are
+// 16-byte aligned go to the vector-load instance, the rest to the byte one.
+template <bool FAST>
+__global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items, int n_items) {
-    const int wave = threadIdx.x >> 6;
+    // wave-uniform indices, so the table and descriptor loads are scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int it = blockIdx.x * kSobelWaves + wave; it < n_items; it += gridDim.x * kSobelWaves) {
         const int2 w = items[it];
         if (w.x < 0) continue;
         const SobelDesc d = descs[w.x];
-        if (d.fast) sobel_item<true, kModeSobel>(d, w.y);
-        else sobel_item<false, kModeSobel>(d, w.y);
+        sobel_item<FAST, kModeSobel>(d, w.y);
     }
 }
 
@@ -287,15 +369,20 @@ extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
 }
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
-                                              int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_sobel_batch, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs, items,
-                       n_items);
+                                              int fast, int grid, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (fast)
+        hipLaunchKernelGGL(k_sobel_batch<true>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
+                           items, n_items);
+    else
+        hipLaunchKernelGGL(k_sobel_batch<false>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
+                           items, n_items);
     return hipGetLastError();
 }
 
 extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sobel_batch, kWave * kSobelWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sobel_batch<true>, kWave * kSobelWaves, 0) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;

@@ -45,19 +45,26 @@ __device__ __forceinline__ int band_bits_dev(int n_theta, int k) {
     return bits;
 }
 
-__shared__ int32_t s_acc[kVoteLdsWords];
-__shared__ int s_lo[kMaxT], s_win[kMaxT], s_base[kMaxT];
-__shared__ int s_fast, s_total;
-__shared__ uint32_t s_dropped;
+// Workgroup state.  The accumulator array is declared per LDS-size variant
+// (kVoteLdsWords: one workgroup per CU; kVoteLdsWordsHalf: two).
+template <int LDSW>
+struct VoteLds {
+    int32_t acc[LDSW];
+    int lo[kMaxT], win[kMaxT], base[kMaxT];
+    int fast, total, item;
+    uint32_t dropped;
+};
 
-__device__ __forceinline__ void lds_vote(uint32_t v) {
-    const uint32_t adr = (v >> 12) & 0x3FFFCu;
+template <int LDSW>
+__device__ __forceinline__ void lds_vote(VoteLds<LDSW>& L, uint32_t v) {
+    const uint32_t adr = (v >> 12) & 0x3FFFCu;  // 4 * floor(v / 2^14)
     __hip_atomic_fetch_add(reinterpret_cast<int32_t*>(
-                               __builtin_assume_aligned(reinterpret_cast<char*>(s_acc) + adr, 4)),
+                               __builtin_assume_aligned(reinterpret_cast<char*>(L.acc) + adr, 4)),
                            1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ void vote_item(const VoteDesc& d, int slice) {
+template <int LDSW>
+__device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
@@ -72,8 +79,8 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
     const uint32_t* __restrict__ list = d.list;
 
     if (tid == 0) {
-        s_fast = 1;
-        s_dropped = 0;
+        sm.fast = 1;
+        sm.dropped = 0;
     }
     __syncthreads();
     if (tid < T) {
@@ -89,22 +96,22 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
             rmax = max(rmax, r);
         }
         const int lo = rmin + d.r_offset, hi = rmax + d.r_offset;
-        s_lo[tid] = lo;
-        s_win[tid] = hi - lo + 1;
-        if (lo < 0 || hi >= d.n_r) s_fast = 0;
+        sm.lo[tid] = lo;
+        sm.win[tid] = hi - lo + 1;
+        if (lo < 0 || hi >= d.n_r) sm.fast = 0;
     }
     __syncthreads();
     if (tid == 0) {
         int base = 0;
         for (int q = 0; q < T; ++q) {
-            s_base[q] = base;
-            base += s_win[q];
+            sm.base[q] = base;
+            base += sm.win[q];
         }
-        s_total = base;
-        if (base > kVoteLdsWords) s_fast = 0;
+        sm.total = base;
+        if (base > LDSW) sm.fast = 0;
     }
     __syncthreads();
-    const bool fast = s_fast != 0;
+    const bool fast = sm.fast != 0;
     const int kk = k0 + j;
     const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
     const bool masked = d.tile_mask != nullptr;
@@ -115,25 +122,28 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
     }
 
     if (fast) {
-        const int total = s_total;
-        for (int c = tid; c < total; c += blockDim.x) s_acc[c] = 0;
-        const int lo = s_lo[j], base = s_base[j];
+        const int total = sm.total;
+        for (int c = tid; c < total; c += blockDim.x) sm.acc[c] = 0;
+        const int lo = sm.lo[j], base = sm.base[j];
         const int K = 8192 + (base - lo + d.r_offset) * 16384;
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
         __syncthreads();
         if (!masked) {
             auto vote4 = [&](u32x4 q) {
-                lds_vote((uint32_t)dot2_i16((int)q.x, CS, K));
-                lds_vote((uint32_t)dot2_i16((int)q.y, CS, K));
-                lds_vote((uint32_t)dot2_i16((int)q.z, CS, K));
-                lds_vote((uint32_t)dot2_i16((int)q.w, CS, K));
+                lds_vote(sm, (uint32_t)dot2_i16((int)q.x, CS, K));
+                lds_vote(sm, (uint32_t)dot2_i16((int)q.y, CS, K));
+                lds_vote(sm, (uint32_t)dot2_i16((int)q.z, CS, K));
+                lds_vote(sm, (uint32_t)dot2_i16((int)q.w, CS, K));
             };
             for (int seg = wave; seg < L.nseg; seg += nwaves) {
                 const int n = min((int)gld(list + seg), kSegCap);
                 const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap;
-                const int step = 4 * G;        // entries one wave-iteration covers
-                const int nfull = n / step;
-                const uint32_t* p = ents + 4 * g;
+                // each of the G slots takes its own part of the segment (a
+                // different stretch of columns), so slots voting for the same
+                // theta rarely hit the same r cell at once
+                const int part = (n / (4 * G)) * 4;  // entries per slot, multiple of 4
+                const int nfull = part / 4;
+                const uint32_t* p = ents + g * part;
                 // software pipeline: U 128-bit loads per lane stay in flight
                 // while the previous U are voted
                 constexpr int U = 4;
@@ -141,11 +151,11 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
                 if (nfull >= U) {
                     u32x4 cur[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) cur[u] = gld4(p + u * step);
+                    for (int u = 0; u < U; ++u) cur[u] = gld4(p + 4 * u);
                     for (it = U; it + U <= nfull; it += U) {
                         u32x4 nxt[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) nxt[u] = gld4(p + (it + u) * step);
+                        for (int u = 0; u < U; ++u) nxt[u] = gld4(p + 4 * (it + u));
 #pragma unroll
                         for (int u = 0; u < U; ++u) vote4(cur[u]);
 #pragma unroll
@@ -154,11 +164,12 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
 #pragma unroll
                     for (int u = 0; u < U; ++u) vote4(cur[u]);
                 }
-                for (; it < nfull; ++it) vote4(gld4(p + it * step));
-                const int i0 = nfull * step + 4 * g;
+                for (; it < nfull; ++it) vote4(gld4(p + 4 * it));
+                // remainder (fewer than 4G entries), shared by all slots
+                const int i0 = G * part + 4 * g;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (i0 + q < n) lds_vote((uint32_t)dot2_i16((int)gld(ents + i0 + q), CS, K));
+                    if (i0 + q < n) lds_vote(sm, (uint32_t)dot2_i16((int)gld(ents + i0 + q), CS, K));
                 }
             }
         } else {
@@ -177,19 +188,43 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
                     if ((m & slice_bits) == 0) continue;
                     if ((m & bb) == 0) continue;  // this lane's angle is pruned in this tile
                     const uint32_t* te = ents + (inf & 0xFFFFu);
-                    for (int e = g; e < cnt; e += G) lds_vote((uint32_t)dot2_i16((int)gld(te + e), CS, K));
+                    for (int e = g; e < cnt; e += G) lds_vote(sm, (uint32_t)dot2_i16((int)gld(te + e), CS, K));
                 }
             }
         }
         __syncthreads();
-        for (int q = 0; q < T; ++q) {
-            const int row = k0 + q;
-            if (row < own_from) continue;
-            const int rlo = s_lo[q], rwin = s_win[q], rbase = s_base[q];
-            int32_t* out = d.acc + (size_t)row * d.n_r;
-            for (int i = tid; i < d.n_r; i += blockDim.x) {
-                const int o = i - rlo;
-                gst(out + i, (o >= 0 && o < rwin) ? s_acc[rbase + o] : 0);
+        const int q0 = own_from - k0;  // first owned row of the slice
+        if (d.keys) {
+            // write the rows and, block by block, the peak-search keys
+            const int B = 1 << d.key_log2;
+            const int ntask = (T - q0) * d.nbr;
+            for (int task = wave; task < ntask; task += nwaves) {
+                const int q = q0 + task / d.nbr, jb = task % d.nbr;
+                const int row = k0 + q;
+                const int rlo = sm.lo[q], rwin = sm.win[q], rbase = sm.base[q];
+                int32_t* out = d.acc + (size_t)row * d.n_r;
+                const uint32_t rowc = (uint32_t)row * (uint32_t)d.n_r;
+                const int i0 = jb * B, i1 = min(d.n_r, i0 + B);
+                unsigned long long best = 0;
+                for (int i = i0 + lane; i < i1; i += kWave) {
+                    const int o = i - rlo;
+                    const int v = (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0;
+                    gst(out + i, v);
+                    const unsigned long long kk = make_key(v, rowc + (uint32_t)i);
+                    best = kk > best ? kk : best;
+                }
+                best = wave_max_u64(best);
+                if (lane == 0) gst(d.keys + (size_t)row * d.nbr + jb, best);
+            }
+        } else {
+            for (int q = q0; q < T; ++q) {
+                const int row = k0 + q;
+                const int rlo = sm.lo[q], rwin = sm.win[q], rbase = sm.base[q];
+                int32_t* out = d.acc + (size_t)row * d.n_r;
+                for (int i = tid; i < d.n_r; i += blockDim.x) {
+                    const int o = i - rlo;
+                    gst(out + i, (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0);
+                }
             }
         }
     } else {
@@ -222,35 +257,61 @@ __device__ void vote_item(const VoteDesc& d, int slice) {
                 else ++drop;
             }
         }
-        if (drop) atomicAdd(&s_dropped, drop);
+        if (drop) atomicAdd(&sm.dropped, drop);
+        __threadfence();
         __syncthreads();
-        if (tid == 0 && d.dropped && s_dropped) atomicAdd(d.dropped, s_dropped);
+        if (tid == 0 && d.dropped && sm.dropped) atomicAdd(d.dropped, sm.dropped);
+        if (d.keys) {
+            // keys from the finished rows, read back at device scope
+            const int B = 1 << d.key_log2;
+            const int q0 = own_from - k0;
+            const int ntask = (T - q0) * d.nbr;
+            for (int task = wave; task < ntask; task += nwaves) {
+                const int q = q0 + task / d.nbr, jb = task % d.nbr;
+                const int row = k0 + q;
+                int32_t* rowp = d.acc + (size_t)row * d.n_r;
+                const uint32_t rowc = (uint32_t)row * (uint32_t)d.n_r;
+                const int i0 = jb * B, i1 = min(d.n_r, i0 + B);
+                unsigned long long best = 0;
+                for (int i = i0 + lane; i < i1; i += kWave) {
+                    const int v = __hip_atomic_load(rowp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long kk = make_key(v, rowc + (uint32_t)i);
+                    best = kk > best ? kk : best;
+                }
+                best = wave_max_u64(best);
+                if (lane == 0) gst(d.keys + (size_t)row * d.nbr + jb, best);
+            }
+        }
     }
 }
 
-__global__ void __launch_bounds__(kVoteThreads) k_vote(VoteDesc d) { vote_item(d, blockIdx.x); }
-
-__shared__ int s_item;
+__global__ void __launch_bounds__(kVoteThreads) k_vote(VoteDesc d) {
+    __shared__ VoteLds<kVoteLdsWords> sm;
+    vote_item(sm, d, blockIdx.x);
+}
 
 // Batched, persistent.  queue == null: static grid stride over the item
 // table (the table is laid out so that a frame's slices land on one XCD and
 // share its L2).  queue != null: items are taken in table order from an
 // atomic ticket (longest items first balances mixed sizes).
+template <int LDSW>
 __global__ void __launch_bounds__(kVoteThreads)
+    __attribute__((amdgpu_waves_per_eu(LDSW == kVoteLdsWordsHalf ? 8 : 4)))
     k_vote_batch(const VoteDesc* __restrict__ descs, const int2* __restrict__ items, int n_items,
                  uint32_t* queue) {
+    __shared__ VoteLds<LDSW> sm;
     int it = blockIdx.x;
     for (;;) {
         if (queue) {
-            if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+            if (threadIdx.x == 0) sm.item = (int)atomicAdd(queue, 1u);
             __syncthreads();
-            it = s_item;
+            it = __builtin_amdgcn_readfirstlane(sm.item);
         }
         if (it >= n_items) break;
         const int2 w = items[it];
         if (w.x >= 0) {
             const VoteDesc d = descs[w.x];
-            vote_item(d, w.y);
+            vote_item(sm, d, w.y);
         }
         __syncthreads();
         if (!queue) it += gridDim.x;
@@ -267,8 +328,12 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* dp, hipStre
 }
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
-                                             uint32_t* queue, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_vote_batch, dim3(grid), dim3(kVoteThreads), 0, s, descs, items, n_items,
-                       queue);
+                                             uint32_t* queue, int half_lds, int grid, hipStream_t s) {
+    if (half_lds)
+        hipLaunchKernelGGL(k_vote_batch<kVoteLdsWordsHalf>, dim3(grid), dim3(kVoteThreads), 0, s,
+                           descs, items, n_items, queue);
+    else
+        hipLaunchKernelGGL(k_vote_batch<kVoteLdsWords>, dim3(grid), dim3(kVoteThreads), 0, s, descs,
+                           items, n_items, queue);
     return hipGetLastError();
 }
