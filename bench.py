@@ -102,12 +102,20 @@ def main():
     Cd, Sd = torch.from_numpy(C).to(dev), torch.from_numpy(S).to(dev)
     pool_d = [torch.from_numpy(f).to(dev) for f in pool]
     B = args.frames
+    # autotune (outside the timed region): theta-slice width, vote work
+    # distribution, Sobel strip height and grid, for this batch size
+    from paper_2212_09460_amd import tune as tuner
+    if args.vote_rows > 0:
+        tune = lane.LaneTune(args.vote_rows, args.vote_queue, 0, 0)
+        tune_info = lane.tune_dict(tune)
+    else:
+        tune, tune_info = tuner.tuned(pool_d[0], N_THETA, B, W, use_cache=False)
     frames = []
     for i in range(B):
         img = torch.empty((H, W), dtype=torch.uint8, device=dev)
         img.copy_(pool_d[i % POOL])
         frames.append(lane.FrameBuffers(img, W, N_THETA, TOPK, Cd, Sd))
-    batch = lane.Batch(frames, vote_rows=args.vote_rows, vote_queue=args.vote_queue)
+    batch = lane.Batch(frames, tune=tune)
 
     # correctness guard on one frame: edges and peaks against the oracle
     batch.launch(stream)
@@ -145,7 +153,7 @@ def main():
     vote_gvotes = votes / (t_vote * 1e-3) / 1e9
 
     # single-frame latency: a one-frame plan, each launch timed alone
-    one = lane.Batch([frames[0]], vote_rows=args.vote_rows)
+    one = lane.Batch([frames[0]], vote_rows=tune.vote_rows)
     lat = []
     for i in range(args.latency_iters + 5):
         a = torch.cuda.Event(enable_timing=True)
@@ -176,7 +184,7 @@ def main():
                                "clutter segments, 2% salt; threshold 128, ring masked; 360 theta, "
                                "r step 1 px, Q14 trig, int32 accumulator; top-8 peaks",
                    "frames_per_step": B, "launch": "one HIP graph per step",
-                   "vote_rows": args.vote_rows},
+                   "tuned": tune_info},
         "frames_per_s": round(B / (ms_step * 1e-3), 1),
         "edge_fraction": round(float(n_edges.sum()) / px, 4),
         "dropped_votes": dropped,

@@ -180,6 +180,7 @@ typedef struct lane_tune {
     int32_t vote_queue;       /* 1 = dynamic ticket queue (longest items first), 0 = static stride
                                  with each frame's slices on one XCD, -1 = automatic */
     int32_t sobel_groups_per_cu; /* persistent Sobel workgroups per CU; 0 = occupancy limit */
+    int32_t sobel_strip_rows; /* rows per Sobel work item, a multiple of 8; 0 = 32 */
 } lane_tune;
 
 typedef struct lane_batch lane_batch;
@@ -196,6 +197,17 @@ int lane_batch_launch_stage(lane_batch *b, int32_t stage, void *stream);
 /* Frees the plan's device table and graph (waits for nothing: the caller
  * must make sure no launch of this plan is still running). */
 int lane_batch_destroy(lane_batch *b);
+
+/* Autotuner (set-up call: allocates scratch buffers and synchronizes).
+ * Builds plans over n_frames copies of `sample` (device uint8 [H][pitch]),
+ * times the vote for every theta-slice width (rows per workgroup, down to
+ * 1/16 of the largest that fits LDS) and both work distributions, then the
+ * Sobel pass for strip heights 16..128 and 0-2 persistent workgroups per
+ * CU, and writes the fastest setting to *out.  ms_opt: host float[2] or
+ * NULL, receives the best vote and Sobel times in ms. */
+int lane_tune_run(const uint8_t *sample, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
+                  int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune *out,
+                  float *ms_opt);
 
 #ifdef __cplusplus
 }

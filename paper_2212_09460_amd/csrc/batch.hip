@@ -25,7 +25,7 @@ using namespace lane;
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
                                               int fast, int grid, hipStream_t s);
 extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy();
-extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H);
+extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows);
 extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode);
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
                                              uint32_t* queue, int half_lds, int grid, hipStream_t s);
@@ -157,9 +157,11 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         const int st = validate(frames[i]);
         if (st != LANE_OK) return st;
     }
-    lane_tune tune = {0, -1, 0};
+    lane_tune tune = {0, -1, 0, 0};
     if (tune_opt) tune = *tune_opt;
     if (tune.vote_rows < 0 || (tune.vote_rows & (tune.vote_rows - 1)) != 0) return LANE_E_ARG;
+    if (tune.sobel_strip_rows < 0 || (tune.sobel_strip_rows % 8) != 0 || tune.sobel_strip_rows > 1024)
+        return LANE_E_ARG;
 
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) return LANE_E_DEVICE;
@@ -191,8 +193,9 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         s.list = f.list;
         s.edge_count = f.counters_opt;
         s.fast = lane_sobel_fast_ok(&s, 0);
+        s.strip_rows = tune.sobel_strip_rows > 0 ? tune.sobel_strip_rows : kStripRows;
         counters[i] = f.counters_opt;
-        const int ns = lane_sobel_items(f.W, f.H);
+        const int ns = lane_sobel_items(f.W, f.H, s.strip_rows);
         for (int j = 0; j < ns; ++j) (s.fast ? sitems : sitems_slow).push_back(make_int2(i, j));
 
         VoteDesc& v = vd[i];
@@ -368,6 +371,148 @@ int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {
 int lane_batch_destroy(lane_batch* b) {
     if (!b) return LANE_E_ARG;
     free_plan(b);
+    return LANE_OK;
+}
+
+// ------------------------------------------------------------- autotuner --
+
+namespace {
+
+struct TuneBufs {
+    std::vector<void*> ptrs;
+    ~TuneBufs() {
+        for (void* p : ptrs) hipFree(p);
+    }
+    void* get(size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+};
+
+// average ms of `iters` launches of one stage (after one untimed launch)
+float time_stage(lane_batch* b, int stage, int iters, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (enqueue_stage(b, stage, s) != hipSuccess) return -1.f;
+    hipEventRecord(e0, s);
+    for (int i = 0; i < iters; ++i) enqueue_stage(b, stage, s);
+    hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms / (float)iters;
+}
+
+}  // namespace
+
+int lane_tune_run(const uint8_t* sample, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
+                  int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune* out,
+                  float* ms_opt) {
+    if (!sample || !out || W < 1 || H < 1 || pitch < W || n_theta < 1 || n_frames < 1 ||
+        n_frames > 4096 || threshold < 0 || threshold > 255)
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM) return LANE_E_SIZE;
+    int32_t D = 0;
+    lane_r_offset(W, H, &D);
+    const int n_r = 2 * D + 1;
+    size_t list_bytes = 0;
+    lane_edge_list_size(W, H, &list_bytes);
+    const int ipitch = (W + 15) / 16 * 16;
+    TuneBufs bufs;
+    std::vector<int16_t> hc(n_theta), hs(n_theta);
+    lane_make_trig_q14(n_theta, hc.data(), hs.data());
+    int16_t* dc = (int16_t*)bufs.get(sizeof(int16_t) * n_theta * 2);
+    if (!dc) return LANE_E_DEVICE;
+    int16_t* ds = dc + n_theta;
+    if (hipMemcpy(dc, hc.data(), sizeof(int16_t) * n_theta, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ds, hs.data(), sizeof(int16_t) * n_theta, hipMemcpyHostToDevice) != hipSuccess)
+        return LANE_E_DEVICE;
+    std::vector<lane_frame> frames(n_frames);
+    for (int i = 0; i < n_frames; ++i) {
+        lane_frame& f = frames[i];
+        memset(&f, 0, sizeof(f));
+        uint8_t* img = (uint8_t*)bufs.get((size_t)ipitch * H);
+        uint8_t* edges = (uint8_t*)bufs.get((size_t)W * H);
+        uint32_t* list = (uint32_t*)bufs.get(list_bytes);
+        int32_t* acc = (int32_t*)bufs.get(sizeof(int32_t) * (size_t)n_theta * n_r);
+        uint32_t* cnt = (uint32_t*)bufs.get(16);
+        if (!img || !edges || !list || !acc || !cnt) return LANE_E_DEVICE;
+        if (hipMemcpy2D(img, ipitch, sample, pitch, W, H, hipMemcpyDeviceToDevice) != hipSuccess)
+            return LANE_E_DEVICE;
+        f.img = img;
+        f.W = W;
+        f.H = H;
+        f.pitch = ipitch;
+        f.threshold = threshold;
+        f.border_mode = border_mode;
+        f.edges = edges;
+        f.list = list;
+        f.cos_q14 = dc;
+        f.sin_q14 = ds;
+        f.n_theta = n_theta;
+        f.r_offset = D;
+        f.n_r = n_r;
+        f.acc = acc;
+        f.counters_opt = cnt;
+    }
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LANE_E_DEVICE;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const int tmax = lane_vote_rows_per_group(W, H, n_theta, n_r);
+    lane_tune best = {tmax, -1, 0, 0};
+    float best_vote = 1e30f, best_sobel = 1e30f;
+    int status = LANE_OK;
+    // theta rows per vote workgroup x work distribution
+    for (int T = tmax; T >= 1 && T * 16 >= tmax; T >>= 1) {
+        for (int q = 0; q <= 1; ++q) {
+            lane_tune t = {T, q, 0, 0};
+            lane_batch* b = nullptr;
+            status = lane_batch_create(frames.data(), n_frames, &t, &b);
+            if (status != LANE_OK) break;
+            enqueue_stage(b, 0, st);
+            enqueue_stage(b, 1, st);
+            const float ms = time_stage(b, 2, 3, st, e0, e1);
+            lane_batch_destroy(b);
+            if (ms > 0 && ms < best_vote) {
+                best_vote = ms;
+                best.vote_rows = T;
+                best.vote_queue = q;
+            }
+        }
+        if (status != LANE_OK) break;
+    }
+    // Sobel strip height x persistent workgroups per CU
+    const int strips[4] = {16, 32, 64, 128};
+    for (int si = 0; si < 4 && status == LANE_OK; ++si) {
+        for (int gpc = 0; gpc <= 2; ++gpc) {
+            lane_tune t = best;
+            t.sobel_strip_rows = strips[si];
+            t.sobel_groups_per_cu = gpc;
+            lane_batch* b = nullptr;
+            status = lane_batch_create(frames.data(), n_frames, &t, &b);
+            if (status != LANE_OK) break;
+            enqueue_stage(b, 0, st);
+            const float ms = time_stage(b, 1, 3, st, e0, e1);
+            lane_batch_destroy(b);
+            if (ms > 0 && ms < best_sobel) {
+                best_sobel = ms;
+                best.sobel_strip_rows = strips[si];
+                best.sobel_groups_per_cu = gpc;
+            }
+        }
+    }
+    hipStreamSynchronize(st);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(st);
+    if (status != LANE_OK) return status;
+    *out = best;
+    if (ms_opt) {
+        ms_opt[0] = best_vote;
+        ms_opt[1] = best_sobel;
+    }
     return LANE_OK;
 }
 

@@ -95,6 +95,7 @@ int lane_sobel_binarize(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
     d.mag = mag_opt;
     d.list = list_opt;
     d.edge_count = edge_count_opt;
+    d.strip_rows = kStripRows;
     if (edge_count_opt) {
         hipError_t e = lane_launch_fill_u32(edge_count_opt, 1, 0u, s);
         if (e != hipSuccess) return LANE_E_DEVICE;
@@ -116,6 +117,7 @@ int lane_edges_to_list(const uint8_t* edges, int32_t W, int32_t H, int32_t pitch
     d.pitch = pitch;
     d.list = list;
     d.edge_count = edge_count_opt;
+    d.strip_rows = kStripRows;
     if (edge_count_opt) {
         hipError_t e = lane_launch_fill_u32(edge_count_opt, 1, 0u, s);
         if (e != hipSuccess) return LANE_E_DEVICE;

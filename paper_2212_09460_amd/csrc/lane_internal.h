@@ -29,7 +29,7 @@ constexpr int kTile = 8;                 // edge tiles are 8x8 pixels
 constexpr int kChunkPx = 1024;           // one wave covers 64 lanes x 16 px
 constexpr int kTilesPerChunk = kChunkPx / kTile;
 constexpr int kSegCap = kTile * kChunkPx;  // entries a segment can hold
-constexpr int kStripRows = 32;           // rows one Sobel wave walks down
+constexpr int kStripRows = 32;           // default rows one Sobel wave walks down (multiple of 8)
 constexpr int kSobelWaves = 4;           // waves per Sobel workgroup
 constexpr int kVoteThreads = 1024;       // 16 waves per vote workgroup
 constexpr int kVoteLdsWords = 40704;     // accumulator dwords in LDS (159 KB): 1 workgroup/CU
@@ -64,6 +64,7 @@ struct SobelDesc {
     uint32_t* list;      // edge list or null
     uint32_t* edge_count;  // device scalar or null (zeroed beforehand)
     int fast;            // 16-byte aligned rows: vector loads/stores (batched path)
+    int strip_rows;      // rows per work item, a multiple of 8
 };
 
 // One frame for the vote.

@@ -245,8 +245,8 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
     const int strip = item / L.nchunk;
     const int x0 = chunk * kChunkPx + lane * 16;
     const bool active = x0 < d.W;
-    const int y_begin = strip * kStripRows;
-    const int y_end = min(y_begin + kStripRows, d.H);
+    const int y_begin = strip * d.strip_rows;
+    const int y_end = min(y_begin + d.strip_rows, d.H);
     const int y_load_end = min(y_end + 1, d.H);  // rows this strip reads: [y_begin - 1, y_end]
     uint64_t m0 = 0, m1 = 0;
     uint32_t nedge = 0;
@@ -356,9 +356,9 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, 
     return hipGetLastError();
 }
 
-extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H) {
+extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows) {
     const ListLayout L = list_layout(W, H);
-    return L.nchunk * ((H + kStripRows - 1) / kStripRows);
+    return L.nchunk * ((H + strip_rows - 1) / strip_rows);
 }
 
 extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
@@ -390,7 +390,7 @@ extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy() {
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* dp, int mode, hipStream_t s) {
     const SobelDesc& d = *dp;
-    const int n_items = lane_sobel_items(d.W, d.H);
+    const int n_items = lane_sobel_items(d.W, d.H, d.strip_rows);
     const unsigned blocks = (unsigned)((n_items + kSobelWaves - 1) / kSobelWaves);
     const bool fast = ((uintptr_t)d.img % 16 == 0) && (d.pitch % 16 == 0) && (d.W % 16 == 0) &&
                       (mode == kModeFromEdges ||

@@ -50,7 +50,7 @@ LANE_BORDER_ZERO_MASKRING = 1
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
            "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_batch_create",
-           "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy")
+           "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run")
 
 
 class LaneError(RuntimeError):
@@ -206,7 +206,8 @@ class LaneFrame(ctypes.Structure):
 
 
 class LaneTune(ctypes.Structure):
-    _fields_ = [("vote_rows", _i32), ("vote_queue", _i32), ("sobel_groups_per_cu", _i32)]
+    _fields_ = [("vote_rows", _i32), ("vote_queue", _i32), ("sobel_groups_per_cu", _i32),
+                ("sobel_strip_rows", _i32)]
 
 
 _batch_create = _sig("lane_batch_create", [ctypes.POINTER(LaneFrame), _i32,
@@ -214,6 +215,25 @@ _batch_create = _sig("lane_batch_create", [ctypes.POINTER(LaneFrame), _i32,
 _batch_launch = _sig("lane_batch_launch", [_vp, _vp])
 _batch_stage = _sig("lane_batch_launch_stage", [_vp, _i32, _vp])
 _batch_destroy = _sig("lane_batch_destroy", [_vp])
+_tune_run = _sig("lane_tune_run", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32,
+                                   ctypes.POINTER(LaneTune), ctypes.POINTER(ctypes.c_float)])
+
+
+def tune_run(sample: torch.Tensor, n_theta: int, n_frames: int, W: int | None = None,
+             threshold: int = 128, border_mode: int = LANE_BORDER_ZERO_MASKRING):
+    """Run the native autotuner on a device frame; returns (LaneTune, vote_ms, sobel_ms)."""
+    H, pitch = sample.shape
+    W = pitch if W is None else W
+    t = LaneTune()
+    ms = (ctypes.c_float * 2)()
+    _check(_tune_run(_p(sample), W, H, pitch, threshold, border_mode, n_theta, n_frames,
+                     ctypes.byref(t), ms), "lane_tune_run")
+    return t, float(ms[0]), float(ms[1])
+
+
+def tune_dict(t: LaneTune) -> dict:
+    return {"vote_rows": t.vote_rows, "vote_queue": t.vote_queue,
+            "sobel_groups_per_cu": t.sobel_groups_per_cu, "sobel_strip_rows": t.sobel_strip_rows}
 
 
 class FrameBuffers:
@@ -286,10 +306,12 @@ class Batch:
     every frame as one graph launch."""
 
     def __init__(self, frames, vote_rows: int = 0, vote_queue: int = -1,
-                 sobel_groups_per_cu: int = 0):
+                 sobel_groups_per_cu: int = 0, sobel_strip_rows: int = 0, tune=None):
         self.frames = list(frames)
         arr = (LaneFrame * len(self.frames))(*[f.desc() for f in self.frames])
-        tune = LaneTune(vote_rows, vote_queue, sobel_groups_per_cu)
+        if tune is None:
+            tune = LaneTune(vote_rows, vote_queue, sobel_groups_per_cu, sobel_strip_rows)
+        self.tune = tune
         h = _vp()
         _check(_batch_create(arr, len(self.frames), ctypes.byref(tune), ctypes.byref(h)),
                "lane_batch_create")

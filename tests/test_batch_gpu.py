@@ -123,3 +123,33 @@ def test_batch_matches_single_frame_calls(lane, synth):
     assert torch.equal(fb.acc, alone["acc"]) and torch.equal(fb.edges, alone["edges"])
     assert torch.equal(fb.theta_idx(), alone["theta_idx"]) and torch.equal(fb.votes(), alone["votes"])
     b.close()
+
+
+def test_autotuner_choice_is_valid_and_exact(lane, synth, oracle):
+    """The tuner returns a setting within its search space, and a plan built
+    with it gives the oracle's results."""
+    say("autotuner")
+    from paper_2212_09460_amd import tune as tuner
+
+    img = torch.from_numpy(synth.road(1280, 720, 4242)).cuda()
+    t, info = tuner.tuned(img, 360, 4, use_cache=False)
+    assert t.vote_rows in (1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1)
+    assert t.sobel_strip_rows in (16, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
+    assert info["vote_ms"] > 0 and info["sobel_ms"] > 0
+    specs = [(1280, 720, 1280, 50 + i, False) for i in range(3)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, tune=t)
+    b.launch()
+    check(frames, wants)
+    b.close()
+
+
+@pytest.mark.parametrize("strip", [8, 16, 64, 128])
+def test_sobel_strip_heights(lane, synth, oracle, strip):
+    say("strip", strip)
+    specs = [(640, 480, 640, 70, False), (997, 41, 1000, 71, False), (1280, 720, 1280, 72, True)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, sobel_strip_rows=strip, sobel_groups_per_cu=1)
+    b.launch()
+    check(frames, wants)
+    b.close()
