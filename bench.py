@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--vote-rows", type=int, default=0,
                     help="theta rows per vote workgroup (0 = tuned default)")
     ap.add_argument("--vote-queue", type=int, default=-1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-tune-cache", action="store_true")
     return ap.parse_args()
 
 
@@ -64,6 +67,25 @@ def event_time(torch, fn, iters, stream):
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / iters
+
+
+def profiled_traffic(kernel: str, src: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_1080p_x256.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(kernel + r":.*?\n\s+traffic_bytes_per_launch (\S+)\s+\(source (\S+) sha256\[:16\] (\w+)\)",
+                  text, re.S)
+    if not m:
+        return None
+    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_2212_09460_amd", "csrc", src), "rb")
+                         .read()).hexdigest()[:16]
+    return float(m.group(1)) if cur == m.group(3) else None
 
 
 def cpu_baseline(pool, C, S, budget_s):
@@ -109,7 +131,7 @@ def main():
         tune = lane.LaneTune(args.vote_rows, args.vote_queue, 0, 0)
         tune_info = lane.tune_dict(tune)
     else:
-        tune, tune_info = tuner.tuned(pool_d[0], N_THETA, B, W, use_cache=False)
+        tune, tune_info = tuner.tuned(pool_d[0], N_THETA, B, W, use_cache=not args.no_tune_cache)
     frames = []
     for i in range(B):
         img = torch.empty((H, W), dtype=torch.uint8, device=dev)
@@ -153,18 +175,27 @@ def main():
     vote_gvotes = votes / (t_vote * 1e-3) / 1e9
 
     # single-frame latency: a one-frame plan, each launch timed alone
-    one = lane.Batch([frames[0]], vote_rows=tune.vote_rows)
     lat = []
-    for i in range(args.latency_iters + 5):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        one.launch(stream)
-        b.record(stream)
-        b.synchronize()
-        if i >= 5:
-            lat.append(a.elapsed_time(b))
-    lat = np.array(lat)
+    if args.latency_iters > 0:
+        one = lane.Batch([frames[0]], tune=tune)
+        for i in range(args.latency_iters + 5):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            one.launch(stream)
+            b.record(stream)
+            b.synchronize()
+            if i >= 5:
+                lat.append(a.elapsed_time(b))
+        one.close()
+    lat = np.array(lat if lat else [float("nan")])
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     value = px / (ms_step * 1e-3) / 1e6
     out = {
@@ -192,17 +223,18 @@ def main():
                      "peaks": round(t_peaks, 4)},
         "roofline": {"bound": "alu", "kernel": "k_vote_batch", "achieved": round(vote_gvotes, 1),
                      "peak": round(LDS_BANK_PEAK_GVOTES, 1), "unit": "Gvote/s",
-                     "frac": round(vote_gvotes / LDS_BANK_PEAK_GVOTES, 4), "traffic": None,
+                     "frac": round(vote_gvotes / LDS_BANK_PEAK_GVOTES, 4),
+                     "traffic": profiled_traffic("k_vote_batch", "vote.hip") if B == 256 else None,
                      "votes_per_launch": votes},
         "roofline_sobel": {"bound": "hbm", "kernel": "k_sobel_batch",
                            "achieved": round(sobel_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(sobel_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                           "frac": round(sobel_gbs / HBM_PEAK_GBS, 4),
+                           "traffic": profiled_traffic("k_sobel_batch", "sobel.hip") if B == 256 else None,
                            "bytes_per_launch": sobel_bytes},
         "latency_ms_single_frame": {"p50": round(float(np.percentile(lat, 50)), 4),
                                     "p99": round(float(np.percentile(lat, 99)), 4)},
         "wall_s_timed": round(wall, 3),
     }
-    one.close()
     batch.close()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(pool, C, S, args.cpu_seconds)
