@@ -209,6 +209,63 @@ int lane_tune_run(const uint8_t *sample, int32_t W, int32_t H, int32_t pitch, in
                   int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune *out,
                   float *ms_opt);
 
+/* ---------------------------------------------------- learned proposal
+ * A small CNN predicts, per 8x8 tile, whether the tile carries lane votes
+ * and which theta bands they fall in, so the vote can skip the rest (task
+ * addition; the paper has no learned part).  Network, zero padding 1:
+ * conv1 1->16 stride 2 + ReLU, conv2 16->16 s2 + ReLU, conv3 16->16 s2 +
+ * ReLU, head 16->9 s1; input gray / 255; FP16 weights and activations, FP32
+ * accumulation on MFMA.  Output logits [batch][9][ceil(H/8)][ceil(W/8)]:
+ * channel 0 keep, 1..8 bands (band definition as for lane_hough_vote).
+ * Master parameters: LANE_CNN_PARAMS floats, per layer weights
+ * [c_out][c_in][3][3] then biases [c_out]. */
+#define LANE_CNN_PARAMS 6105
+
+int lane_cnn_param_count(void);
+/* Byte sizes (any pointer may be NULL): packed kernel weights, activation
+ * workspace for `batch` frames of W x H (forward + backward), and the
+ * backward pass's partial-sum workspace. */
+int lane_cnn_sizes(int32_t W, int32_t H, int32_t batch, size_t *packed_bytes, size_t *act_bytes,
+                   size_t *partial_bytes);
+/* FP32 master parameters (device) -> packed FP16 kernel layouts (device,
+ * 16-byte aligned). */
+int lane_cnn_pack(const float *params, void *packed, void *stream);
+/* Forward for `batch` frames img + b * img_stride (device uint8 [H][pitch]);
+ * activations kept in `act` for the backward; logits device float. */
+int lane_cnn_forward(const uint8_t *img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                     int32_t batch, const void *packed, void *act, float *logits, void *stream);
+/* Per frame: loss = mean over tiles of BCE(keep) + mean over keep tiles of
+ * the mean over bands of BCE(band) -> loss[b] (device float); writes
+ * scale * dloss/dlogits into `act` for the backward.  keep: device uint8
+ * [batch][th][tw] in {0,1}; bands: device uint8 band bits. */
+int lane_cnn_loss(const float *logits, const uint8_t *keep, const uint8_t *bands, int32_t W,
+                  int32_t H, int32_t batch, float scale, void *act, float *loss, void *stream);
+/* Backward after lane_cnn_forward + lane_cnn_loss on the same `act`: writes
+ * the gradient, summed over the batch and times the loss scale, into grads
+ * [LANE_CNN_PARAMS] (device float).  Deterministic (fixed reduction order). */
+int lane_cnn_backward(const uint8_t *img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                      int32_t batch, const void *packed, void *act, void *partial,
+                      size_t partial_bytes, float *grads, void *stream);
+/* Adam on device float vectors of length n; the gradient is multiplied by
+ * grad_scale first; step counts from 1. */
+int lane_adam_step(float *params, const float *grads, float *m, float *v, int32_t n, float lr,
+                   float beta1, float beta2, float eps, int32_t step, float grad_scale,
+                   void *stream);
+/* Training labels from the plain pipeline: tile t is keep iff one of its
+ * edge pixels has, for the angle of one of the top-k peaks (device int32
+ * [3k+1] as written by the batch plan: theta_idx, r_idx, votes, count), an
+ * r within 1 of that peak's r; bands[t] = union of those peaks' band bits.
+ * list: the frame's edge list; keep, bands: device uint8 [th][tw]. */
+int lane_tile_labels(const uint32_t *list, int32_t W, int32_t H, const int16_t *cos_q14,
+                     const int16_t *sin_q14, int32_t n_theta, int32_t r_offset,
+                     const int32_t *peaks, int32_t k, uint8_t *keep, uint8_t *bands, void *stream);
+/* Tile mask for lane_hough_vote from float logits: keep logit >= t ->
+ * the bands with logit >= 0 (at least the largest); keep <= -t -> 0 (skip);
+ * otherwise 0xFF (fall back to every band), t = float(log(conf/(1-conf))),
+ * 0.5 < conf < 1.  mask: device uint8 [batch][th][tw]. */
+int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t batch, float conf,
+                          uint8_t *mask, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ agreement metric are the task's additions and are specified here:
   mask     per tile, from float32 logits: keep >= t_hi -> the bands with
            logit >= 0 (at least the largest); keep <= -t_hi -> nothing;
            otherwise every band (fallback to the full Hough).  t_hi =
-           float32(log(conf / (1 - conf))).
+           float32(log(c / (1 - c))), c = float32(conf).
   agreement  fraction of plain top-k peaks with a pruned top-k peak within
            +-1 theta bin and +-1 r bin (theta wrapping, r mirrored per half
            turn, as in the peak suppression)
@@ -188,7 +188,8 @@ def mask_from_logits(logits32: np.ndarray, conf: float = 0.9) -> np.ndarray:
     """Decision rule on float32 logits (the GPU compares the same float32
     values against the same float32 threshold)."""
     z = logits32.astype(np.float32)
-    t_hi = np.float32(math.log(conf / (1.0 - conf)))
+    c = float(np.float32(conf))  # the confidence as the float32 the GPU call receives
+    t_hi = np.float32(math.log(c / (1.0 - c)))
     _, th, tw = z.shape
     m = np.zeros((th, tw), np.uint8)
     for y in range(th):

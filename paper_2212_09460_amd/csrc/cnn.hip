@@ -1,0 +1,743 @@
+// Learned tile / theta-band proposal for gfx950: a 4-layer 3x3 CNN in FP16
+// with FP32 accumulation on MFMA (v_mfma_f32_16x16x16_f16), its backward
+// pass, BCE loss, Adam, plain-pipeline tile labels and the mask rule.
+//
+// Network (zero padding 1):  conv1 1->16 s2 ReLU, conv2 16->16 s2 ReLU,
+// conv3 16->16 s2 ReLU, head 16->9 s1; input gray/255; output logits at 1/8
+// resolution, channel 0 = keep logit of an 8x8 tile, 1..8 = theta bands.
+//
+// Layouts.  Activations are NHWC FP16 with 16 channels (32 B per pixel), so
+// the 4 consecutive channels an MFMA lane supplies are one 8-byte load.
+// Every convolution tile is one wave: 16 output pixels of a row x 16 output
+// channels, K = 16 input channels per kernel tap, 9 MFMAs (conv1: K = the 9
+// taps of the single input channel, one MFMA).  With M = output channel and
+// N = pixel the accumulator lane holds 4 consecutive channels of one pixel,
+// which is again an 8-byte NHWC store.  Backward data swaps the roles of the
+// channel axes (transposed weights); backward weights reduces over pixels
+// (K = 16 pixels per MFMA) into per-wave partials that a fixed-order pass
+// sums, so training is deterministic.
+//
+// Master parameters are FP32 in the flat order: for each layer the weights
+// [c_out][c_in][3][3] then the biases [c_out] (6105 values).
+#include <math.h>
+#include <string.h>
+
+#include "lane_internal.h"
+
+namespace lane {
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCnnParams = 6105;
+// offsets of each layer's weights and biases in the master vector
+constexpr int kW1 = 0, kB1 = 144, kW2 = 160, kB2 = 2464, kW3 = 2480, kB3 = 4784, kW4 = 4800,
+              kB4 = 6096;
+// packed buffer: f32 biases [4][16], then f16 blocks
+constexpr int kPkBias = 0;                 // floats
+constexpr int kPkW1 = 0;                   // halves, after the biases: [16 co][16 tap]
+constexpr int kPkBlock = 9 * 16 * 16;      // [tap][16][16]
+constexpr int kPkW2 = 256, kPkW2T = kPkW2 + kPkBlock, kPkW3 = kPkW2T + kPkBlock,
+              kPkW3T = kPkW3 + kPkBlock, kPkW4 = kPkW3T + kPkBlock, kPkW4T = kPkW4 + kPkBlock;
+constexpr int kPkHalves = kPkW4T + kPkBlock;
+constexpr size_t kPackedBytes = 4 * 16 * sizeof(float) + (size_t)kPkHalves * sizeof(_Float16);
+
+__device__ __forceinline__ const _Float16* pk_h(const void* pk) {
+    return reinterpret_cast<const _Float16*>(reinterpret_cast<const char*>(pk) + 4 * 16 * sizeof(float));
+}
+__device__ __forceinline__ const float* pk_bias(const void* pk, int layer) {
+    return reinterpret_cast<const float*>(pk) + layer * 16;
+}
+
+__device__ __forceinline__ h4 ld_h4(const _Float16* p) { return *(const LANE_GLOBAL h4*)p; }
+__device__ __forceinline__ void st_h4(_Float16* p, h4 v) { *(LANE_GLOBAL h4*)p = v; }
+
+__device__ __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ pack --
+// master f32 -> kernel layouts (f16): W[tap][co][ci], W^T[tap][ci][co],
+// conv1 as [co][tap], biases f32 [layer][16]; unused slots are zero.
+__global__ void k_cnn_pack(const float* __restrict__ m, void* __restrict__ pk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float* bias = reinterpret_cast<float*>(pk);
+    _Float16* h = reinterpret_cast<_Float16*>(reinterpret_cast<char*>(pk) + 4 * 16 * sizeof(float));
+    if (i < 64) {
+        const int l = i >> 4, co = i & 15;
+        const int boff[4] = {kB1, kB2, kB3, kB4};
+        const int cout = l == 3 ? 9 : 16;
+        bias[i] = co < cout ? m[boff[l] + co] : 0.f;
+    }
+    if (i < 256) {  // conv1 [co][tap]
+        const int co = i >> 4, tap = i & 15;
+        h[kPkW1 + i] = (_Float16)(tap < 9 ? m[kW1 + co * 9 + tap] : 0.f);
+    }
+    if (i < 3 * 2 * kPkBlock) {
+        const int which = i / kPkBlock, r = i % kPkBlock;  // which: layer-pair index
+        const int l = 1 + (which >> 1), transposed = which & 1;
+        const int tap = r >> 8, a = (r >> 4) & 15, b = r & 15;
+        const int co = transposed ? b : a, ci = transposed ? a : b;
+        const int woff[4] = {kW1, kW2, kW3, kW4};
+        const int cout = l == 3 ? 9 : 16;
+        const float v = co < cout ? m[woff[l] + (co * 16 + ci) * 9 + tap] : 0.f;
+        h[kPkW2 + i] = (_Float16)v;
+    }
+}
+
+// --------------------------------------------------------------- forward --
+struct CnnFwd {
+    const uint8_t* img;       // conv1 input, [B][H][pitch] with frame stride
+    int W, H, pitch;
+    long long img_stride;
+    const void* pk;
+    _Float16* a1;             // [B][H1][W1][16]
+    _Float16* a2;
+    _Float16* a3;
+    float* logits;            // [B][9][H4][W4]
+    int H1, W1, H2, W2, H3, W3;  // layer output sizes; head = (H3, W3)
+    long long s1, s2, s3;     // per-frame strides in halves
+    int batch;
+};
+
+// conv1: K = the 9 taps of the one input channel
+__global__ void __launch_bounds__(256) k_cnn_fwd1(CnnFwd p) {
+    const int lane = threadIdx.x & 63;
+    const int ntx = (p.W1 + 15) >> 4;
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= p.batch * p.H1 * ntx) return;
+    const int b = item / (p.H1 * ntx), rem = item - b * p.H1 * ntx;
+    const int oy = rem / ntx, ox0 = (rem - (rem / ntx) * ntx) * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const _Float16* w = pk_h(p.pk) + kPkW1;
+    const h4 A = ld_h4(w + col * 16 + 4 * grp);  // W1[co = col][tap = 4 grp + j]
+    const int ox = ox0 + col;
+    const uint8_t* img = p.img + (size_t)b * p.img_stride;
+    h4 B;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int tap = 4 * grp + j;
+        float v = 0.f;
+        if (tap < 9 && ox < p.W1) {
+            const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+            if (iy >= 0 && iy < p.H && ix >= 0 && ix < p.W)
+                v = (float)gld(img + (size_t)iy * p.pitch + ix) * (1.0f / 255.0f);
+        }
+        B[j] = (_Float16)v;
+    }
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma16(A, B, acc);
+    if (ox < p.W1) {
+        const float* bias = pk_bias(p.pk, 0);
+        h4 o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = (_Float16)fmaxf(acc[j] + bias[4 * grp + j], 0.f);
+        st_h4(p.a1 + (size_t)b * p.s1 + ((size_t)oy * p.W1 + ox) * 16 + 4 * grp, o);
+    }
+}
+
+// conv2 / conv3 / head: 16 input channels, 9 taps
+__global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
+    const int lane = threadIdx.x & 63;
+    const _Float16* in = layer == 1 ? p.a1 : layer == 2 ? p.a2 : p.a3;
+    const int Hi = layer == 1 ? p.H1 : layer == 2 ? p.H2 : p.H3;
+    const int Wi = layer == 1 ? p.W1 : layer == 2 ? p.W2 : p.W3;
+    const long long si = layer == 1 ? p.s1 : layer == 2 ? p.s2 : p.s3;
+    const int Ho = layer == 1 ? p.H2 : p.H3, Wo = layer == 1 ? p.W2 : p.W3;
+    const int stride = layer == 3 ? 1 : 2;
+    const int ntx = (Wo + 15) >> 4;
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= p.batch * Ho * ntx) return;
+    const int b = item / (Ho * ntx), rem = item - b * Ho * ntx;
+    const int oy = rem / ntx, ox0 = (rem - (rem / ntx) * ntx) * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const _Float16* w = pk_h(p.pk) + (layer == 1 ? kPkW2 : layer == 2 ? kPkW3 : kPkW4);
+    const int ox = ox0 + col;
+    const _Float16* x = in + (size_t)b * si;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const h4 A = ld_h4(w + (tap * 16 + col) * 16 + 4 * grp);  // W[tap][co = col][ci = 4 grp + j]
+        const int iy = oy * stride + tap / 3 - 1, ix = ox * stride + tap % 3 - 1;
+        h4 B = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0};
+        if (ox < Wo && iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+            B = ld_h4(x + ((size_t)iy * Wi + ix) * 16 + 4 * grp);  // X[ci = 4 grp + j][pixel = col]
+        acc = mfma16(A, B, acc);
+    }
+    if (ox >= Wo) return;
+    const float* bias = pk_bias(p.pk, layer);
+    if (layer < 3) {
+        _Float16* out = (layer == 1 ? p.a2 : p.a3) + (size_t)b * (layer == 1 ? p.s2 : p.s3);
+        h4 o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = (_Float16)fmaxf(acc[j] + bias[4 * grp + j], 0.f);
+        st_h4(out + ((size_t)oy * Wo + ox) * 16 + 4 * grp, o);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = 4 * grp + j;
+            if (co < 9)
+                gst(p.logits + (((size_t)b * 9 + co) * Ho + oy) * Wo + ox, acc[j] + bias[co]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ loss --
+// One workgroup per frame.  dL/dlogits, times `scale`, goes to dy4 as NHWC
+// f16 with channels 9..15 zero; loss (unscaled, float) per frame.
+__global__ void __launch_bounds__(1024) k_cnn_loss(const float* __restrict__ logits,
+                                                   const uint8_t* __restrict__ keep,
+                                                   const uint8_t* __restrict__ bands, int th,
+                                                   int tw, float scale, _Float16* dy4,
+                                                   float* loss) {
+    __shared__ float s_red[32];
+    __shared__ int s_npos;
+    const int b = blockIdx.x, tid = threadIdx.x, n = th * tw;
+    const float* z = logits + (size_t)b * 9 * n;
+    const uint8_t* yk = keep + (size_t)b * n;
+    const uint8_t* yb = bands + (size_t)b * n;
+    if (tid == 0) s_npos = 0;
+    __syncthreads();
+    int np = 0;
+    for (int t = tid; t < n; t += blockDim.x) np += yk[t] ? 1 : 0;
+    atomicAdd(&s_npos, np);  // integer: order-free
+    __syncthreads();
+    const int npos = s_npos;
+    float lsum = 0.f;
+    for (int t = tid; t < n; t += blockDim.x) {
+        const float y = yk[t] ? 1.f : 0.f;
+        const float zk = z[t];
+        lsum += (fmaxf(zk, 0.f) - zk * y + log1pf(expf(-fabsf(zk)))) / (float)n;
+        h4 g0 = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0}, g1 = g0, g2 = g0, g3 = g0;
+        const float sk = 1.f / (1.f + expf(-zk));
+        g0[0] = (_Float16)((sk - y) / (float)n * scale);
+        float gb[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float zb = z[(size_t)(1 + c) * n + t];
+            const float ybit = ((yb[t] >> c) & 1) ? 1.f : 0.f;
+            gb[c] = 0.f;
+            if (npos > 0 && y > 0.f) {
+                lsum += (fmaxf(zb, 0.f) - zb * ybit + log1pf(expf(-fabsf(zb)))) / (float)(npos * 8);
+                gb[c] = (1.f / (1.f + expf(-zb)) - ybit) / (float)(npos * 8) * scale;
+            }
+        }
+        g0[1] = (_Float16)gb[0];
+        g0[2] = (_Float16)gb[1];
+        g0[3] = (_Float16)gb[2];
+        g1[0] = (_Float16)gb[3];
+        g1[1] = (_Float16)gb[4];
+        g1[2] = (_Float16)gb[5];
+        g1[3] = (_Float16)gb[6];
+        g2[0] = (_Float16)gb[7];
+        _Float16* d = dy4 + ((size_t)b * n + t) * 16;
+        st_h4(d, g0);
+        st_h4(d + 4, g1);
+        st_h4(d + 8, g2);
+        st_h4(d + 12, g3);
+    }
+    // fixed-order reduction of the loss
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+    if ((tid & 63) == 0) s_red[tid >> 6] = lsum;
+    __syncthreads();
+    if (tid == 0) {
+        float s = 0.f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_red[w];
+        loss[b] = s;
+    }
+}
+
+// -------------------------------------------------------- backward data --
+// dPre_{l-1}[iy][ix][ci] = (a_{l-1} > 0) * sum_{tap, co} W[co][ci][tap] dY[oy][ox][co]
+// for the input pixels (iy, ix) of layer l (l = head, conv3, conv2).
+struct CnnBwd {
+    const void* pk;
+    const _Float16 *a1, *a2, *a3;
+    _Float16 *d1, *d2, *d3;   // gradients of the pre-activations of conv1..3
+    const _Float16* dy4;      // gradient of the head output
+    const uint8_t* img;
+    int W, H, pitch;
+    long long img_stride;
+    int H1, W1, H2, W2, H3, W3;
+    long long s1, s2, s3;
+    int batch;
+    float* partial;           // per-wave dW partials
+    int rows_per_wave;
+};
+
+__global__ void __launch_bounds__(256) k_cnn_bwd_data(CnnBwd p, int layer) {
+    // layer: 3 = head (dy4 -> d3), 2 = conv3 (d3 -> d2), 1 = conv2 (d2 -> d1)
+    const int lane = threadIdx.x & 63;
+    const _Float16* dy = layer == 3 ? p.dy4 : layer == 2 ? p.d3 : p.d2;
+    const int Ho = layer == 3 ? p.H3 : layer == 2 ? p.H3 : p.H2;
+    const int Wo = layer == 3 ? p.W3 : layer == 2 ? p.W3 : p.W2;
+    const long long so = layer == 3 ? p.s3 : layer == 2 ? p.s3 : p.s2;
+    const _Float16* act = layer == 3 ? p.a3 : layer == 2 ? p.a2 : p.a1;
+    _Float16* dx = layer == 3 ? p.d3 : layer == 2 ? p.d2 : p.d1;
+    const int Hi = layer == 3 ? p.H3 : layer == 2 ? p.H2 : p.H1;
+    const int Wi = layer == 3 ? p.W3 : layer == 2 ? p.W2 : p.W1;
+    const long long si = layer == 3 ? p.s3 : layer == 2 ? p.s2 : p.s1;
+    const int stride = layer == 3 ? 1 : 2;
+    const _Float16* wT = pk_h(p.pk) + (layer == 3 ? kPkW4T : layer == 2 ? kPkW3T : kPkW2T);
+    const int ntx = (Wi + 15) >> 4;
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= p.batch * Hi * ntx) return;
+    const int b = item / (Hi * ntx), rem = item - b * Hi * ntx;
+    const int iy = rem / ntx, ix0 = (rem - (rem / ntx) * ntx) * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const int ix = ix0 + col;
+    const _Float16* dyb = dy + (size_t)b * so;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const h4 A = ld_h4(wT + (tap * 16 + col) * 16 + 4 * grp);  // W^T[tap][ci = col][co = 4 grp + j]
+        const int ny = iy + 1 - tap / 3, nx = ix + 1 - tap % 3;
+        h4 B = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0};
+        if (ix < Wi && ny >= 0 && nx >= 0 && (ny % stride) == 0 && (nx % stride) == 0) {
+            const int oy = ny / stride, ox = nx / stride;
+            if (oy < Ho && ox < Wo) B = ld_h4(dyb + ((size_t)oy * Wo + ox) * 16 + 4 * grp);
+        }
+        acc = mfma16(A, B, acc);
+    }
+    if (ix >= Wi) return;
+    const size_t o = (size_t)b * si + ((size_t)iy * Wi + ix) * 16 + 4 * grp;
+    const h4 a = ld_h4(act + o);
+    h4 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = a[j] > (_Float16)0 ? (_Float16)acc[j] : (_Float16)0;
+    st_h4(dx + o, r);
+}
+
+// ------------------------------------------------------ backward weights --
+// dW[tap][co][ci] = sum_pixels dY[p][co] * X[p + tap][ci], K = 16 pixels per
+// MFMA; each wave covers rows_per_wave output rows of one frame and writes
+// its partial sums (2304 weights + 16 biases) to partial[wave].
+constexpr int kPartial = 9 * 16 * 16 + 16;
+
+__global__ void __launch_bounds__(256) k_cnn_bwd_w16(CnnBwd p, int layer) {
+    // layer: 3 = head (dy4, x = a3), 2 = conv3 (d3, x = a2), 1 = conv2 (d2, x = a1)
+    const int lane = threadIdx.x & 63;
+    const _Float16* dy = layer == 3 ? p.dy4 : layer == 2 ? p.d3 : p.d2;
+    const int Ho = layer == 1 ? p.H2 : p.H3, Wo = layer == 1 ? p.W2 : p.W3;
+    const long long so = layer == 1 ? p.s2 : p.s3;
+    const _Float16* x = layer == 3 ? p.a3 : layer == 2 ? p.a2 : p.a1;
+    const int Hi = layer == 3 ? p.H3 : layer == 2 ? p.H2 : p.H1;
+    const int Wi = layer == 3 ? p.W3 : layer == 2 ? p.W2 : p.W1;
+    const long long si = layer == 3 ? p.s3 : layer == 2 ? p.s2 : p.s1;
+    const int stride = layer == 3 ? 1 : 2;
+    const int R = p.rows_per_wave;
+    const int nchunk = (Ho + R - 1) / R;
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= p.batch * nchunk) return;
+    const int b = item / nchunk, r0 = (item - b * nchunk) * R, r1 = min(Ho, r0 + R);
+    const int col = lane & 15, grp = lane >> 4;
+    const _Float16* dyb = dy + (size_t)b * so;
+    const _Float16* xb = x + (size_t)b * si;
+    f4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 accb = {0.f, 0.f, 0.f, 0.f};
+    const h4 ones = {(_Float16)1, (_Float16)1, (_Float16)1, (_Float16)1};
+    for (int oy = r0; oy < r1; ++oy) {
+        for (int ox0 = 0; ox0 < Wo; ox0 += 16) {
+            h4 A;  // A[co = col][pixel = 4 grp + j] = dY[oy][ox0 + 4 grp + j][co]
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ox = ox0 + 4 * grp + j;
+                A[j] = ox < Wo ? gld(dyb + ((size_t)oy * Wo + ox) * 16 + col) : (_Float16)0;
+            }
+            accb = mfma16(A, ones, accb);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                h4 B;  // B[pixel = 4 grp + j][ci = col] = X[iy][ix][ci]
+                const int iy = oy * stride + tap / 3 - 1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ox = ox0 + 4 * grp + j;
+                    const int ix = ox * stride + tap % 3 - 1;
+                    B[j] = (ox < Wo && iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+                               ? gld(xb + ((size_t)iy * Wi + ix) * 16 + col)
+                               : (_Float16)0;
+                }
+                acc[tap] = mfma16(A, B, acc[tap]);
+            }
+        }
+    }
+    // D[co = 4 grp + j][ci = col]
+    float* part = p.partial + (size_t)item * kPartial;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gst(part + (tap * 16 + 4 * grp + j) * 16 + col, acc[tap][j]);
+    if (col == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gst(part + 9 * 256 + 4 * grp + j, accb[j]);
+    }
+}
+
+// conv1: dW1[co][tap] = sum_pixels dPre1[p][co] * x(p, tap)
+__global__ void __launch_bounds__(256) k_cnn_bwd_w1(CnnBwd p) {
+    const int lane = threadIdx.x & 63;
+    const int R = p.rows_per_wave;
+    const int nchunk = (p.H1 + R - 1) / R;
+    const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= p.batch * nchunk) return;
+    const int b = item / nchunk, r0 = (item - b * nchunk) * R, r1 = min(p.H1, r0 + R);
+    const int col = lane & 15, grp = lane >> 4;
+    const _Float16* dyb = p.d1 + (size_t)b * p.s1;
+    const uint8_t* img = p.img + (size_t)b * p.img_stride;
+    f4 acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+    const h4 ones = {(_Float16)1, (_Float16)1, (_Float16)1, (_Float16)1};
+    for (int oy = r0; oy < r1; ++oy) {
+        for (int ox0 = 0; ox0 < p.W1; ox0 += 16) {
+            h4 A, B;  // A[co = col][pixel], B[pixel][tap = col]
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ox = ox0 + 4 * grp + j;
+                A[j] = ox < p.W1 ? gld(dyb + ((size_t)oy * p.W1 + ox) * 16 + col) : (_Float16)0;
+                float v = 0.f;
+                if (ox < p.W1 && col < 9) {
+                    const int iy = 2 * oy + col / 3 - 1, ix = 2 * ox + col % 3 - 1;
+                    if (iy >= 0 && iy < p.H && ix >= 0 && ix < p.W)
+                        v = (float)gld(img + (size_t)iy * p.pitch + ix) * (1.0f / 255.0f);
+                }
+                B[j] = (_Float16)v;
+            }
+            acc = mfma16(A, B, acc);
+            accb = mfma16(A, ones, accb);
+        }
+    }
+    float* part = p.partial + (size_t)item * kPartial;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gst(part + (4 * grp + j) * 16 + col, acc[j]);
+    if (col == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gst(part + 9 * 256 + 4 * grp + j, accb[j]);
+    }
+}
+
+// Sum the partials in fixed order into the master-layout gradient of one
+// layer (overwrites that layer's slice of grads).
+__global__ void k_cnn_reduce(const float* __restrict__ partial, int nparts, int layer,
+                             float* __restrict__ grads) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cin = layer == 0 ? 1 : 16, cout = layer == 3 ? 9 : 16;
+    const int woff[4] = {kW1, kW2, kW3, kW4}, boff[4] = {kB1, kB2, kB3, kB4};
+    const int nw = cout * cin * 9;
+    if (i >= nw + cout) return;
+    int src, dst;
+    if (i < nw) {
+        const int co = i / (cin * 9), ci = (i / 9) % cin, tap = i % 9;
+        src = layer == 0 ? co * 16 + tap : (tap * 16 + co) * 16 + ci;
+        dst = woff[layer] + i;
+    } else {
+        src = 9 * 256 + (i - nw);
+        dst = boff[layer] + (i - nw);
+    }
+    float s = 0.f;
+    for (int w = 0; w < nparts; ++w) s += partial[(size_t)w * kPartial + src];
+    grads[dst] = s;
+}
+
+// ------------------------------------------------------------------ adam --
+__global__ void k_adam(float* __restrict__ prm, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, float gscale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] * gscale;
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    prm[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------- labels --
+// One thread per 8x8 tile: keep iff one of the tile's edge pixels has, for
+// the angle of one of the top-k plain peaks, r within 1 of that peak's r;
+// the band label is the union of those peaks' band bits.
+__global__ void k_tile_labels(const uint32_t* __restrict__ list, int W, int H,
+                              const int16_t* __restrict__ cq, const int16_t* __restrict__ sq,
+                              int n_theta, int r_offset, const int32_t* __restrict__ peaks, int k,
+                              uint8_t* keep, uint8_t* bands) {
+    const ListLayout L = list_layout(W, H);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L.th * L.tw) return;
+    const int ty = t / L.tw, tx = t - ty * L.tw;
+    const uint32_t inf = gld(list + L.off_info + t);
+    const int cnt = min((int)(inf >> 16), 64), start = (int)(inf & 0xFFFFu);
+    const int seg = ty * L.nchunk + tx / kTilesPerChunk;
+    const uint32_t* ents = list + L.off_ent + (size_t)seg * kSegCap + start;
+    const int count = min(gld(peaks + 3 * k), k);
+    int kp = 0, bits = 0;
+    for (int q = 0; q < count; ++q) {
+        const int th = gld(peaks + q), rp = gld(peaks + k + q) - r_offset;
+        if (th < 0 || th >= n_theta) continue;
+        const int C = gld(cq + th), S = gld(sq + th);
+        bool hit = false;
+        for (int e = 0; e < cnt && !hit; ++e) {
+            const uint32_t xy = gld(ents + e);
+            const int r = ((int)(xy & 0xFFFFu) * C + (int)(xy >> 16) * S + 8192) >> 14;
+            hit = abs(r - rp) <= 1;
+        }
+        if (hit) {
+            kp = 1;
+            int bb = 0;
+            for (int b = 0; b < 8; ++b) {
+                const int st = (b * n_theta) / 8;
+                int dd = (th - st) % n_theta;
+                if (dd < 0) dd += n_theta;
+                if (dd < n_theta / 4) bb |= 1 << b;
+            }
+            bits |= bb;
+        }
+    }
+    keep[t] = (uint8_t)kp;
+    bands[t] = (uint8_t)bits;
+}
+
+// ------------------------------------------------------------------ mask --
+__global__ void k_mask_from_logits(const float* __restrict__ logits, int th, int tw, int batch,
+                                   float t_hi, uint8_t* mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = th * tw;
+    if (i >= n * batch) return;
+    const int b = i / n, t = i - b * n;
+    const float* z = logits + (size_t)b * 9 * n;
+    const float zk = z[t];
+    uint8_t m;
+    if (zk >= t_hi) {
+        int bits = 0, arg = 0;
+        float best = z[n + t];
+        for (int c = 0; c < 8; ++c) {
+            const float zb = z[(size_t)(1 + c) * n + t];
+            if (zb >= 0.f) bits |= 1 << c;
+            if (zb > best) {
+                best = zb;
+                arg = c;
+            }
+        }
+        m = (uint8_t)(bits ? bits : (1 << arg));
+    } else if (zk <= -t_hi) {
+        m = 0;
+    } else {
+        m = 0xFF;
+    }
+    mask[i] = m;
+}
+
+}  // namespace lane
+
+// ------------------------------------------------------------------- ABI --
+#include "../../include/lane.h"
+using namespace lane;
+
+namespace {
+struct Geo {
+    int H1, W1, H2, W2, H3, W3;
+    long long s1, s2, s3;
+};
+inline int osz(int n, int s) { return (n + 2 - 3) / s + 1; }
+Geo geo(int W, int H) {
+    Geo g;
+    g.H1 = osz(H, 2);
+    g.W1 = osz(W, 2);
+    g.H2 = osz(g.H1, 2);
+    g.W2 = osz(g.W1, 2);
+    g.H3 = osz(g.H2, 2);
+    g.W3 = osz(g.W2, 2);
+    g.s1 = (long long)g.H1 * g.W1 * 16;
+    g.s2 = (long long)g.H2 * g.W2 * 16;
+    g.s3 = (long long)g.H3 * g.W3 * 16;
+    return g;
+}
+// activation buffer: a1 a2 a3 dy4 d3 d2 d1 (halves), each [batch][...]
+struct ActPtrs {
+    _Float16 *a1, *a2, *a3, *dy4, *d3, *d2, *d1;
+    size_t halves;
+};
+ActPtrs act_ptrs(void* base, const Geo& g, int batch) {
+    ActPtrs a;
+    _Float16* h = (_Float16*)base;
+    size_t o = 0;
+    auto take = [&](long long per) {
+        _Float16* p = h + o;
+        o += (size_t)per * batch;
+        o = (o + 127) & ~(size_t)127;
+        return p;
+    };
+    a.a1 = take(g.s1);
+    a.a2 = take(g.s2);
+    a.a3 = take(g.s3);
+    a.dy4 = take(g.s3);
+    a.d3 = take(g.s3);
+    a.d2 = take(g.s2);
+    a.d1 = take(g.s1);
+    a.halves = o;
+    return a;
+}
+constexpr int kRowsPerWave = 4;
+int n_parts(const Geo& g, int layer, int batch) {
+    const int Ho = layer == 0 ? g.H1 : layer == 1 ? g.H2 : g.H3;
+    return batch * ((Ho + kRowsPerWave - 1) / kRowsPerWave);
+}
+inline bool a16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+}  // namespace
+
+extern "C" {
+
+int lane_cnn_param_count(void) { return kCnnParams; }
+
+int lane_cnn_sizes(int32_t W, int32_t H, int32_t batch, size_t* packed_bytes, size_t* act_bytes,
+                   size_t* partial_bytes) {
+    if (W < 1 || H < 1 || batch < 1) return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    const Geo g = geo(W, H);
+    if (packed_bytes) *packed_bytes = kPackedBytes;
+    if (act_bytes) *act_bytes = act_ptrs(nullptr, g, batch).halves * sizeof(_Float16);
+    if (partial_bytes) {
+        int np = 0;
+        for (int l = 0; l < 4; ++l) np = n_parts(g, l, batch) > np ? n_parts(g, l, batch) : np;
+        *partial_bytes = (size_t)np * kPartial * sizeof(float);
+    }
+    return LANE_OK;
+}
+
+int lane_cnn_pack(const float* params, void* packed, void* stream) {
+    if (!params || !packed || !a16(packed)) return LANE_E_ARG;
+    const int n = 3 * 2 * kPkBlock;
+    hipLaunchKernelGGL(k_cnn_pack, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
+                       packed);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_cnn_forward(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                     int32_t batch, const void* packed, void* act, float* logits, void* stream) {
+    if (!img || !packed || !act || !logits || W < 1 || H < 1 || pitch < W || batch < 1 ||
+        img_stride < (int64_t)H * pitch || !a16(packed) || !a16(act))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    const Geo g = geo(W, H);
+    const ActPtrs a = act_ptrs(act, g, batch);
+    CnnFwd p;
+    memset(&p, 0, sizeof(p));
+    p.img = img;
+    p.W = W;
+    p.H = H;
+    p.pitch = pitch;
+    p.img_stride = img_stride;
+    p.pk = packed;
+    p.a1 = a.a1;
+    p.a2 = a.a2;
+    p.a3 = a.a3;
+    p.logits = logits;
+    p.H1 = g.H1; p.W1 = g.W1; p.H2 = g.H2; p.W2 = g.W2; p.H3 = g.H3; p.W3 = g.W3;
+    p.s1 = g.s1; p.s2 = g.s2; p.s3 = g.s3;
+    p.batch = batch;
+    hipStream_t s = (hipStream_t)stream;
+    auto waves = [&](int Ho, int Wo) { return batch * Ho * ((Wo + 15) / 16); };
+    hipLaunchKernelGGL(k_cnn_fwd1, dim3((waves(g.H1, g.W1) + 3) / 4), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_cnn_fwd16, dim3((waves(g.H2, g.W2) + 3) / 4), dim3(256), 0, s, p, 1);
+    hipLaunchKernelGGL(k_cnn_fwd16, dim3((waves(g.H3, g.W3) + 3) / 4), dim3(256), 0, s, p, 2);
+    hipLaunchKernelGGL(k_cnn_fwd16, dim3((waves(g.H3, g.W3) + 3) / 4), dim3(256), 0, s, p, 3);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_cnn_loss(const float* logits, const uint8_t* keep, const uint8_t* bands, int32_t W,
+                  int32_t H, int32_t batch, float scale, void* act, float* loss, void* stream) {
+    if (!logits || !keep || !bands || !act || !loss || W < 1 || H < 1 || batch < 1 || !a16(act))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    const Geo g = geo(W, H);
+    const ActPtrs a = act_ptrs(act, g, batch);
+    hipLaunchKernelGGL(k_cnn_loss, dim3(batch), dim3(1024), 0, (hipStream_t)stream, logits, keep,
+                       bands, g.H3, g.W3, scale, a.dy4, loss);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_cnn_backward(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                      int32_t batch, const void* packed, void* act, void* partial, size_t partial_bytes,
+                      float* grads, void* stream) {
+    if (!img || !packed || !act || !partial || !grads || W < 1 || H < 1 || pitch < W ||
+        batch < 1 || img_stride < (int64_t)H * pitch || !a16(packed) || !a16(act) || !a16(partial))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    size_t need = 0;
+    lane_cnn_sizes(W, H, batch, nullptr, nullptr, &need);
+    if (partial_bytes < need) return LANE_E_WS;
+    const Geo g = geo(W, H);
+    const ActPtrs a = act_ptrs(act, g, batch);
+    CnnBwd p;
+    memset(&p, 0, sizeof(p));
+    p.pk = packed;
+    p.a1 = a.a1; p.a2 = a.a2; p.a3 = a.a3;
+    p.d1 = a.d1; p.d2 = a.d2; p.d3 = a.d3;
+    p.dy4 = a.dy4;
+    p.img = img;
+    p.W = W; p.H = H; p.pitch = pitch; p.img_stride = img_stride;
+    p.H1 = g.H1; p.W1 = g.W1; p.H2 = g.H2; p.W2 = g.W2; p.H3 = g.H3; p.W3 = g.W3;
+    p.s1 = g.s1; p.s2 = g.s2; p.s3 = g.s3;
+    p.batch = batch;
+    p.partial = (float*)partial;
+    p.rows_per_wave = kRowsPerWave;
+    hipStream_t s = (hipStream_t)stream;
+    auto waves_px = [&](int Hx, int Wx) { return batch * Hx * ((Wx + 15) / 16); };
+    // head: weights from (dy4, a3); then data gradient into d3
+    for (int layer = 3; layer >= 1; --layer) {
+        const int np = n_parts(g, layer, batch);
+        hipLaunchKernelGGL(k_cnn_bwd_w16, dim3((np + 3) / 4), dim3(256), 0, s, p, layer);
+        hipLaunchKernelGGL(k_cnn_reduce, dim3((kPartial + 255) / 256), dim3(256), 0, s,
+                           (const float*)partial, np, layer, grads);
+        const int Hi = layer == 3 ? g.H3 : layer == 2 ? g.H2 : g.H1;
+        const int Wi = layer == 3 ? g.W3 : layer == 2 ? g.W2 : g.W1;
+        hipLaunchKernelGGL(k_cnn_bwd_data, dim3((waves_px(Hi, Wi) + 3) / 4), dim3(256), 0, s, p,
+                           layer);
+    }
+    const int np1 = n_parts(g, 0, batch);
+    hipLaunchKernelGGL(k_cnn_bwd_w1, dim3((np1 + 3) / 4), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_cnn_reduce, dim3((kPartial + 255) / 256), dim3(256), 0, s,
+                       (const float*)partial, np1, 0, grads);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_adam_step(float* params, const float* grads, float* m, float* v, int32_t n, float lr,
+                   float beta1, float beta2, float eps, int32_t step, float grad_scale,
+                   void* stream) {
+    if (!params || !grads || !m || !v || n < 1 || step < 1 || !(lr >= 0.f)) return LANE_E_ARG;
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
+                       grads, m, v, n, lr, beta1, beta2, eps, c1, c2, grad_scale);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_tile_labels(const uint32_t* list, int32_t W, int32_t H, const int16_t* cos_q14,
+                     const int16_t* sin_q14, int32_t n_theta, int32_t r_offset,
+                     const int32_t* peaks, int32_t k, uint8_t* keep, uint8_t* bands, void* stream) {
+    if (!list || !cos_q14 || !sin_q14 || !peaks || !keep || !bands || W < 1 || H < 1 ||
+        n_theta < 1 || k < 1 || k > 1024 || !a16(list))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM) return LANE_E_SIZE;
+    const ListLayout L = list_layout(W, H);
+    const int n = L.th * L.tw;
+    hipLaunchKernelGGL(k_tile_labels, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, list,
+                       W, H, cos_q14, sin_q14, n_theta, r_offset, peaks, k, keep, bands);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_mask_from_logits(const float* logits, int32_t W, int32_t H, int32_t batch, float conf,
+                          uint8_t* mask, void* stream) {
+    if (!logits || !mask || W < 1 || H < 1 || batch < 1 || !(conf > 0.5f && conf < 1.f))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    const Geo g = geo(W, H);
+    // the decision threshold in float32, the same value the CPU rule uses
+    const float t_hi = (float)log((double)conf / (1.0 - (double)conf));
+    const int n = g.H3 * g.W3 * batch;
+    hipLaunchKernelGGL(k_mask_from_logits, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       logits, g.H3, g.W3, batch, t_hi, mask);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+}  // extern "C"

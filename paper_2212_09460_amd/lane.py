@@ -50,7 +50,10 @@ LANE_BORDER_ZERO_MASKRING = 1
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
            "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_batch_create",
-           "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run")
+           "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
+           "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
+           "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
+           "lane_mask_from_logits")
 
 
 class LaneError(RuntimeError):
@@ -334,3 +337,82 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------- learned proposal --
+
+_i64, _f32 = ctypes.c_int64, ctypes.c_float
+_cnn_count = _sig("lane_cnn_param_count", [])
+_cnn_sizes = _sig("lane_cnn_sizes", [_i32, _i32, _i32, ctypes.POINTER(_sz), ctypes.POINTER(_sz),
+                                     ctypes.POINTER(_sz)])
+_cnn_pack = _sig("lane_cnn_pack", [_vp, _vp, _vp])
+_cnn_fwd = _sig("lane_cnn_forward", [_vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp])
+_cnn_loss = _sig("lane_cnn_loss", [_vp, _vp, _vp, _i32, _i32, _i32, _f32, _vp, _vp, _vp])
+_cnn_bwd = _sig("lane_cnn_backward", [_vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _sz, _vp,
+                                      _vp])
+_adam = _sig("lane_adam_step", [_vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _f32, _vp])
+_labels = _sig("lane_tile_labels", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp,
+                                    _vp])
+_mask = _sig("lane_mask_from_logits", [_vp, _i32, _i32, _i32, _f32, _vp, _vp])
+
+CNN_PARAMS = 6105
+
+
+def cnn_param_count() -> int:
+    return int(_cnn_count())
+
+
+def cnn_sizes(W: int, H: int, batch: int):
+    a, b, c = _sz(0), _sz(0), _sz(0)
+    _check(_cnn_sizes(W, H, batch, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "lane_cnn_sizes")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def _bytes_tensor(n: int, device):
+    return torch.empty((n + 255) // 256 * 256, dtype=torch.uint8, device=device)
+
+
+def cnn_pack(params: torch.Tensor, packed: torch.Tensor, stream=None):
+    _check(_cnn_pack(_p(params), _p(packed), _stream(stream)), "lane_cnn_pack")
+
+
+def cnn_forward(imgs: torch.Tensor, packed, act, logits, W: int | None = None, stream=None):
+    """imgs: uint8 [B][H][pitch] (contiguous frames)."""
+    B, H, pitch = imgs.shape
+    W = pitch if W is None else W
+    _check(_cnn_fwd(_p(imgs), W, H, pitch, H * pitch, B, _p(packed), _p(act), _p(logits),
+                    _stream(stream)), "lane_cnn_forward")
+
+
+def cnn_loss(logits, keep, bands, W: int, H: int, batch: int, scale: float, act, loss,
+             stream=None):
+    _check(_cnn_loss(_p(logits), _p(keep), _p(bands), W, H, batch, float(scale), _p(act), _p(loss),
+                     _stream(stream)), "lane_cnn_loss")
+
+
+def cnn_backward(imgs: torch.Tensor, packed, act, partial, grads, W: int | None = None,
+                 stream=None):
+    B, H, pitch = imgs.shape
+    W = pitch if W is None else W
+    _check(_cnn_bwd(_p(imgs), W, H, pitch, H * pitch, B, _p(packed), _p(act), _p(partial),
+                    partial.numel() * partial.element_size(), _p(grads), _stream(stream)),
+           "lane_cnn_backward")
+
+
+def adam_step(params, grads, m, v, lr: float, step: int, grad_scale: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    _check(_adam(_p(params), _p(grads), _p(m), _p(v), params.numel(), float(lr), float(beta1),
+                 float(beta2), float(eps), int(step), float(grad_scale), _stream(stream)),
+           "lane_adam_step")
+
+
+def tile_labels(fb: "FrameBuffers", keep, bands, stream=None):
+    """Labels of one frame from its plain-pipeline results in a batch plan."""
+    _check(_labels(_p(fb.edge_list), fb.W, fb.H, _p(fb.cos_q14), _p(fb.sin_q14), fb.n_theta, fb.D,
+                   _p(fb.peaks), fb.k, _p(keep), _p(bands), _stream(stream)), "lane_tile_labels")
+
+
+def mask_from_logits(logits, W: int, H: int, batch: int, conf: float, mask, stream=None):
+    _check(_mask(_p(logits), W, H, batch, float(conf), _p(mask), _stream(stream)),
+           "lane_mask_from_logits")

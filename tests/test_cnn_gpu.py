@@ -1,0 +1,192 @@
+"""Proposal network on the GPU (MFMA FP16, FP32 accumulation) against the FP64
+oracle: forward within 2e-2 of the largest logit, gradients with cosine
+similarity >= 0.999 and relative L2 <= 2e-2 per layer; labels and masks
+bit-exact; Adam against a float64 reference; training deterministic and
+resumable bit-exactly."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lane():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2212_09460_amd.lane as lane_mod
+
+    return lane_mod
+
+
+@pytest.fixture(scope="module")
+def ocnn():
+    import oracle.cnn as c
+
+    return c
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def make_net(seed=3, bias_scale=0.05):
+    from paper_2212_09460_amd.learned.model import ProposalNet, he_uniform
+
+    p = he_uniform(seed)
+    rng = np.random.default_rng(seed)
+    # non-zero biases so the bias paths are exercised
+    offs = [(144, 16), (2464, 16), (4784, 16), (6096, 9)]
+    for o, n in offs:
+        p[o:o + n] = rng.normal(scale=bias_scale, size=n)
+    return ProposalNet(p), p
+
+
+def frames(synth, W, H, B, seed0=777):
+    return np.stack([synth.road(W, H, seed0 + i)[:, :W] for i in range(B)])
+
+
+@pytest.mark.parametrize("W,H,B", [(136, 72, 2), (1920, 1080, 1), (97, 43, 3)])
+def test_forward_matches_oracle(lane, synth, ocnn, W, H, B):
+    say("cnn forward", W, H, B)
+    net, p = make_net()
+    imgs = frames(synth, W, H, B)
+    logits = net.forward(torch.from_numpy(imgs).cuda()).cpu().numpy()
+    params = ocnn.unflatten(p.astype(np.float64))
+    for b in range(B):
+        ref, _ = ocnn.forward(imgs[b], params)
+        err = np.abs(logits[b] - ref).max()
+        assert err <= 2e-2 * np.abs(ref).max(), (b, err, np.abs(ref).max())
+
+
+def _labels(rng, th, tw):
+    keep = (rng.random((th, tw)) < 0.3).astype(np.uint8)
+    keep[0, 0] = 1
+    bands = rng.integers(0, 256, (th, tw)).astype(np.uint8)
+    return keep, bands
+
+
+@pytest.mark.parametrize("W,H,B", [(136, 72, 2), (640, 480, 1)])
+def test_backward_matches_oracle(lane, synth, ocnn, W, H, B):
+    say("cnn backward", W, H, B)
+    net, p = make_net(5)
+    imgs = frames(synth, W, H, B, 900)
+    th, tw = (H + 7) // 8, (W + 7) // 8
+    rng = np.random.default_rng(11)
+    labs = [_labels(rng, th, tw) for _ in range(B)]
+    keep = np.stack([k for k, _ in labs])
+    bands = np.stack([b for _, b in labs])
+    it = torch.from_numpy(imgs).cuda()
+    ws = net.workspace(W, H, B)
+    scale = float(th * tw)
+    lane.cnn_forward(it, net.packed, ws["act"], ws["logits"])
+    lane.cnn_loss(ws["logits"], torch.from_numpy(keep).cuda(), torch.from_numpy(bands).cuda(), W, H,
+                  B, scale, ws["act"], ws["loss"])
+    lane.cnn_backward(it, net.packed, ws["act"], ws["partial"], net.grads)
+    torch.cuda.synchronize()
+    g_gpu = net.grads.cpu().numpy().astype(np.float64) / scale
+    loss_gpu = ws["loss"].cpu().numpy()
+    params = ocnn.unflatten(p.astype(np.float64))
+    g_ref = np.zeros(p.size)
+    for b in range(B):
+        logits, acts = ocnn.forward(imgs[b], params)
+        loss, g = ocnn.loss_and_grad(logits, keep[b], bands[b])
+        assert abs(loss_gpu[b] - loss) <= 2e-3 * max(1.0, abs(loss))
+        grads = ocnn.backward(acts, params, g)
+        g_ref += ocnn.flatten(grads)
+    offs = [(0, 144), (144, 160), (160, 2464), (2464, 2480), (2480, 4784), (4784, 4800),
+            (4800, 6096), (6096, 6105)]
+    for a, z in offs:
+        x, y = g_gpu[a:z], g_ref[a:z]
+        cos = x @ y / (np.linalg.norm(x) * np.linalg.norm(y) + 1e-30)
+        rel = np.linalg.norm(x - y) / (np.linalg.norm(y) + 1e-30)
+        assert cos >= 0.999 and rel <= 2e-2, (a, z, cos, rel)
+
+
+def test_labels_and_mask_bit_exact(lane, synth, oracle, ocnn):
+    say("labels + mask")
+    import paper_2212_09460_amd.lane as L
+
+    W, H = 1280, 720
+    C, S = synth.trig_q14(360)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    imgs = frames(synth, W, H, 2, 321)
+    fbs = [L.FrameBuffers(torch.from_numpy(imgs[b].copy()).cuda(), W, 360, 8, Cd, Sd) for b in range(2)]
+    plan = L.Batch(fbs)
+    plan.launch()
+    th, tw = (H + 7) // 8, (W + 7) // 8
+    for b, fb in enumerate(fbs):
+        keep = torch.empty((th, tw), dtype=torch.uint8, device="cuda")
+        bands = torch.empty_like(keep)
+        L.tile_labels(fb, keep, bands)
+        torch.cuda.synchronize()
+        want = oracle.pipeline(imgs[b], C, S, 8)
+        k_o, b_o = ocnn.tile_labels(want["edges"], C, S, want["D"], want["theta_idx"], want["r_idx"],
+                                    want["count"])
+        assert (keep.cpu().numpy() == k_o).all() and (bands.cpu().numpy() == b_o).all()
+        assert k_o.sum() > 0
+    plan.close()
+    net, _ = make_net(9, bias_scale=1.0)
+    logits = net.forward(torch.from_numpy(imgs).cuda())
+    mask = torch.empty((2, th, tw), dtype=torch.uint8, device="cuda")
+    for conf in (0.9, 0.6, 0.99):
+        L.mask_from_logits(logits, W, H, 2, conf, mask)
+        torch.cuda.synchronize()
+        lg = logits.cpu().numpy()
+        for b in range(2):
+            assert (mask[b].cpu().numpy() == ocnn.mask_from_logits(lg[b], conf)).all()
+
+
+def test_adam_matches_reference(lane):
+    say("adam")
+    rng = np.random.default_rng(0)
+    n = 6105
+    p = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    m = rng.normal(size=n).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=n)).astype(np.float32) * 0.1
+    pt, gt, mt, vt = (torch.from_numpy(a.copy()).cuda() for a in (p, g, m, v))
+    lane.adam_step(pt, gt, mt, vt, 1e-3, 7, 0.5)
+    torch.cuda.synchronize()
+    gd = g.astype(np.float64) * 0.5
+    m2 = 0.9 * m + 0.1 * gd
+    v2 = 0.999 * v + 0.001 * gd * gd
+    p2 = p - 1e-3 * (m2 / (1 - 0.9 ** 7)) / (np.sqrt(v2 / (1 - 0.999 ** 7)) + 1e-8)
+    assert np.allclose(mt.cpu().numpy(), m2, rtol=1e-5, atol=1e-6)
+    assert np.allclose(vt.cpu().numpy(), v2, rtol=1e-5, atol=1e-7)
+    assert np.allclose(pt.cpu().numpy(), p2, rtol=1e-5, atol=1e-6)
+
+
+def test_training_deterministic_and_resumable(lane, synth, tmp_path):
+    say("train determinism / resume")
+    from paper_2212_09460_amd.learned.model import ProposalNet
+
+    W, H, B = 320, 184, 2
+    imgs = [torch.from_numpy(frames(synth, W, H, B, 50 + 10 * s)).cuda() for s in range(4)]
+    th, tw = (H + 7) // 8, (W + 7) // 8
+    rng = np.random.default_rng(2)
+    labs = []
+    for s in range(4):
+        k, b = zip(*[_labels(rng, th, tw) for _ in range(B)])
+        labs.append((torch.from_numpy(np.stack(k)).cuda(), torch.from_numpy(np.stack(b)).cuda()))
+
+    def run(net, steps):
+        for s in steps:
+            net.train_step(imgs[s], labs[s][0], labs[s][1], 3e-3)
+        torch.cuda.synchronize()
+        return net.params.cpu().numpy()
+
+    a = run(ProposalNet(seed=4), range(4))
+    b = run(ProposalNet(seed=4), range(4))
+    assert np.array_equal(a, b)
+    half = ProposalNet(seed=4)
+    run(half, range(2))
+    path = str(tmp_path / "ck.npz")
+    half.save(path)
+    resumed, _ = ProposalNet.load(path)
+    c = run(resumed, range(2, 4))
+    assert np.array_equal(a, c)
+    assert not np.array_equal(a, ProposalNet(seed=4).params.cpu().numpy())
