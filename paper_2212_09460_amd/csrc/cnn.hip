@@ -467,7 +467,9 @@ __global__ void k_tile_labels(const uint32_t* __restrict__ list, int W, int H,
     if (t >= L.th * L.tw) return;
     const int ty = t / L.tw, tx = t - ty * L.tw;
     const uint32_t inf = gld(list + L.off_info + t);
-    const int cnt = min((int)(inf >> 16), 64), start = (int)(inf & 0xFFFFu);
+    int cnt = min((int)(inf >> 16), 64);
+    const int start = (int)(inf & 0xFFFFu);
+    if (start > kSegCap - cnt) cnt = 0;  // malformed list: stay inside the segment
     const int seg = ty * L.nchunk + tx / kTilesPerChunk;
     const uint32_t* ents = list + L.off_ent + (size_t)seg * kSegCap + start;
     const int count = min(gld(peaks + 3 * k), k);
