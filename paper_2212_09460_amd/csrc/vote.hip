@@ -128,13 +128,13 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
         const int K = 8192 + (base - lo + d.r_offset) * 16384;
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
         __syncthreads();
+        auto vote4 = [&](u32x4 q) {
+            lds_vote(sm, (uint32_t)dot2_i16((int)q.x, CS, K));
+            lds_vote(sm, (uint32_t)dot2_i16((int)q.y, CS, K));
+            lds_vote(sm, (uint32_t)dot2_i16((int)q.z, CS, K));
+            lds_vote(sm, (uint32_t)dot2_i16((int)q.w, CS, K));
+        };
         if (!masked) {
-            auto vote4 = [&](u32x4 q) {
-                lds_vote(sm, (uint32_t)dot2_i16((int)q.x, CS, K));
-                lds_vote(sm, (uint32_t)dot2_i16((int)q.y, CS, K));
-                lds_vote(sm, (uint32_t)dot2_i16((int)q.z, CS, K));
-                lds_vote(sm, (uint32_t)dot2_i16((int)q.w, CS, K));
-            };
             for (int seg = wave; seg < L.nseg; seg += nwaves) {
                 const int n = min((int)gld(list + seg), kSegCap);
                 const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap;
@@ -173,22 +173,71 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
                 }
             }
         } else {
+            // Masked vote.  A segment's 128 tiles are scanned at once (tiles
+            // l and l + 64 per lane); tiles with edges whose band bits meet
+            // this slice's angles form runs of equal mask byte, and a run's
+            // entries are contiguous in the segment, so each run is voted
+            // like the unmasked stream, with the lane predicate "this lane's
+            // angle lies in a band of the run's mask".
             for (int seg = wave; seg < L.nseg; seg += nwaves) {
                 const int ty = seg / L.nchunk, chunk = seg - ty * L.nchunk;
+                const int n = min((int)gld(list + seg), kSegCap);
+                if (n == 0) continue;
                 const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap;
                 const int tx0 = chunk * kTilesPerChunk;
-                const int tx1 = min(L.tw, tx0 + kTilesPerChunk);
-                const uint32_t* info = list + L.off_info + (size_t)ty * L.tw;
-                const uint8_t* mrow = d.tile_mask + (size_t)ty * L.tw;
-                for (int tx = tx0; tx < tx1; ++tx) {
-                    const uint32_t inf = gld(info + tx);
-                    const int cnt = min((int)(inf >> 16), kTile * kTile);
-                    if (cnt == 0 || (int)(inf & 0xFFFFu) > kSegCap - cnt) continue;
-                    const int m = gld(mrow + tx);
-                    if ((m & slice_bits) == 0) continue;
-                    if ((m & bb) == 0) continue;  // this lane's angle is pruned in this tile
-                    const uint32_t* te = ents + (inf & 0xFFFFu);
-                    for (int e = g; e < cnt; e += G) lds_vote(sm, (uint32_t)dot2_i16((int)gld(te + e), CS, K));
+                const int ntx = min(L.tw - tx0, kTilesPerChunk);
+                const uint32_t* info = list + L.off_info + (size_t)ty * L.tw + tx0;
+                const uint8_t* mrow = d.tile_mask + (size_t)ty * L.tw + tx0;
+                uint32_t inf[2];
+                int mk[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int t = h * kWave + lane;
+                    inf[h] = t < ntx ? gld(info + t) : 0u;
+                    mk[h] = t < ntx ? (int)gld(mrow + t) : 0;
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bool rel = (inf[h] >> 16) != 0 && (mk[h] & slice_bits) != 0;
+                    const int mprev = __shfl_up(mk[h], 1);
+                    const uint32_t iprev = (uint32_t)__shfl_up((int)inf[h], 1);
+                    const bool relprev = lane > 0 && (iprev >> 16) != 0 && (mprev & slice_bits) != 0;
+                    const bool brk = rel && (!relprev || mprev != mk[h]);
+                    const uint64_t relm = __ballot(rel);
+                    uint64_t brkm = __ballot(brk);
+                    while (brkm) {
+                        const int a = __builtin_ctzll(brkm);
+                        brkm &= brkm - 1;
+                        const uint64_t stop = (~relm | brkm) & ~((2ull << a) - 1ull);
+                        const int b = stop ? __builtin_ctzll(stop) : kWave;
+                        const uint32_t ia = (uint32_t)__builtin_amdgcn_readlane((int)inf[h], a);
+                        const uint32_t iz = (uint32_t)__builtin_amdgcn_readlane((int)inf[h], b - 1);
+                        const int mr = __builtin_amdgcn_readlane(mk[h], a);
+                        const int start = (int)(ia & 0xFFFFu);
+                        const int end = min((int)(iz & 0xFFFFu) + (int)(iz >> 16), n);
+                        if ((mr & bb) == 0 || start >= end) continue;
+                        // full quads [qa, qz), then up to 3 loose entries at
+                        // each end
+                        const int qa = (start + 3) >> 2, qz = end >> 2;
+                        int q = qa + g;
+                        if (q < qz) {
+                            u32x4 cur = gld4(ents + 4 * q);
+                            for (q += G; q < qz; q += G) {
+                                const u32x4 nxt = gld4(ents + 4 * q);
+                                vote4(cur);
+                                cur = nxt;
+                            }
+                            vote4(cur);
+                        }
+                        const int h1 = min(4 * qa, end);
+                        const int nh = h1 - start;
+                        const int t0 = max(4 * qz, 4 * qa);
+                        const int nl = nh + max(0, end - t0);
+                        for (int t = g; t < nl; t += G) {
+                            const int e = t < nh ? start + t : t0 + (t - nh);
+                            lds_vote(sm, (uint32_t)dot2_i16((int)gld(ents + e), CS, K));
+                        }
+                    }
                 }
             }
         }

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import time
 from concurrent.futures import ThreadPoolExecutor
 
@@ -36,14 +37,33 @@ def same_line(t1, r1, t2, r2, n_theta, D, tol=1):
     return False
 
 
-def agreement_counts(pt, pr, pn, qt, qr, qn, k, n_theta, D):
-    """(matched, total) for the top-k plain peaks against the top-k pruned."""
+def agreement_counts(pt, pr, pn, qt, qr, qn, k, n_theta, D, only=None):
+    """(matched, total) for the top-k plain peaks against the top-k pruned;
+    `only` restricts the plain peaks counted (a boolean per peak)."""
     kk = min(k, pn)
-    m = 0
+    m = n = 0
     for i in range(kk):
+        if only is not None and not only[i]:
+            continue
+        n += 1
         if any(same_line(pt[i], pr[i], qt[j], qr[j], n_theta, D) for j in range(min(k, qn))):
             m += 1
-    return m, kk
+    return m, n
+
+
+def lane_flags(segs, pt, pr, pn, n_theta, D, tol_px=8.0):
+    """Which peaks lie on a painted lane: both ends of the lane's centre
+    segment are within tol_px of the peak's line (the band is 6 px wide and
+    its edge pixels lie up to about 4 px from the centre line)."""
+    out = np.zeros(pn, bool)
+    for i in range(pn):
+        th = pt[i] * math.pi / n_theta
+        c, s_ = math.cos(th), math.sin(th)
+        r = pr[i] - D
+        for x0, y0, x1, y1 in segs:
+            if max(abs(x0 * c + y0 * s_ - r), abs(x1 * c + y1 * s_ - r)) <= tol_px:
+                out[i] = True
+    return out
 
 
 class EvalPlans:
@@ -77,11 +97,12 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
     rand_net = ProposalNet(seed=12345) if baselines else None
     gpool = ThreadPoolExecutor(max_workers=workers)
     stream = torch.cuda.current_stream()
-    agg = dict(m4=0, n4=0, m8=0, n8=0, votes_plain=0, votes_pruned=0, tiles=0, t_skip=0,
+    agg = dict(m4=0, n4=0, m8=0, n8=0, l4=0, ln4=0, l8=0, ln8=0, votes_plain=0, votes_pruned=0, tiles=0, t_skip=0,
                t_fall=0, t_band=0, ms_plain=0.0, ms_pruned=0.0, ms_cnn=0.0, frames=0)
     rnd = dict(m4=0, n4=0, m8=0, n8=0, votes=0)
     heur_stats = []  # per frame: (tile counts, plain peaks) for the budget-matched heuristic
     nb = n_frames // batch
+    scene = synth.scene_road(W, H)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
 
     def run_pruned(mask_src):
@@ -134,6 +155,14 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
             a, n = agreement_counts(pt, pr, pn, qt, qr, qn, 8, N_THETA, P.D)
             agg["m8"] += a
             agg["n8"] += n
+            segs = synth.lane_segments(scene, seeds[b])
+            lf = lane_flags(segs, pt, pr, pn, N_THETA, P.D)
+            a, n = agreement_counts(pt, pr, pn, qt, qr, qn, 4, N_THETA, P.D, only=lf)
+            agg["l4"] += a
+            agg["ln4"] += n
+            a, n = agreement_counts(pt, pr, pn, qt, qr, qn, 8, N_THETA, P.D, only=lf)
+            agg["l8"] += a
+            agg["ln8"] += n
             agg["votes_plain"] += int(P.plain[b].counters[0].item()) * N_THETA
             agg["votes_pruned"] += int(P.pruned[b].acc.sum().item())
             agg["frames"] += 1
@@ -164,6 +193,10 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
         frames=agg["frames"], conf=conf, size=[W, H],
         agreement_top4=agg["m4"] / max(1, agg["n4"]),
         agreement_top8=agg["m8"] / max(1, agg["n8"]),
+        lane_share_top4=agg["ln4"] / max(1, agg["n4"]),
+        lane_share_top8=agg["ln8"] / max(1, agg["n8"]),
+        agreement_top4_lane_peaks=agg["l4"] / max(1, agg["ln4"]),
+        agreement_top8_lane_peaks=agg["l8"] / max(1, agg["ln8"]),
         missed_top4=1 - agg["m4"] / max(1, agg["n4"]),
         missed_top8=1 - agg["m8"] / max(1, agg["n8"]),
         votes_fraction=frac,
@@ -229,14 +262,18 @@ def main():
     ap.add_argument("--weights", required=True)
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--conf", type=float, default=0.9)
+    ap.add_argument("--conf", type=float, nargs="+", default=[0.9])
+    ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     net, _ = ProposalNet.load(a.weights)
-    res = evaluate(net, a.frames, a.batch, conf=a.conf)
-    print(json.dumps(res), flush=True)
+    allres = []
+    for c in a.conf:
+        res = evaluate(net, a.frames, a.batch, conf=c, baselines=not a.no_baselines)
+        print(json.dumps(res), flush=True)
+        allres.append(res)
     if a.out:
-        json.dump(res, open(a.out, "w"), indent=1)
+        json.dump(allres if len(allres) > 1 else allres[0], open(a.out, "w"), indent=1)
 
 
 if __name__ == "__main__":

@@ -190,20 +190,51 @@ def test_vote_unusual_tables_and_ranges(lane, synth, oracle, seed):
     assert a.sum() + d == int((e == 255).sum()) * n_theta
 
 
-@pytest.mark.parametrize("kind", ["random", "ones", "zeros", "sparse"])
-def test_vote_masked(lane, synth, oracle, kind):
-    say("vote masked", kind)
-    img = synth.plain_640(1)
+def _masked_frame(synth, which):
+    if which == "640":
+        return synth.plain_640(1)
+    if which == "wide":   # three 1024-px chunks, the last one ragged
+        return synth.road(2100, 96, 41)
+    # noise-only background: many tiles without edges
+    return synth.gen_frame(synth.Scene(W=1100, H=120, n_lanes=3), 5)
+
+
+def _mask(rng, kind, th, tw):
+    if kind == "random":
+        return rng.integers(0, 256, (th, tw))
+    if kind == "ones":
+        return np.full((th, tw), 255)
+    if kind == "zeros":
+        return np.zeros((th, tw))
+    if kind == "sparse":
+        return np.where(rng.random((th, tw)) < 0.1, 1 << rng.integers(0, 8, (th, tw)), 0)
+    # runs of equal bytes of random length, some of them zero
+    m = np.zeros((th, tw), np.int64)
+    for y in range(th):
+        x = 0
+        while x < tw:
+            n = int(rng.integers(1, 90))
+            v = 0 if rng.random() < 0.3 else int(rng.integers(1, 256))
+            m[y, x:x + n] = v
+            x += n
+    return m
+
+
+@pytest.mark.parametrize("which,kind", [("640", "random"), ("640", "ones"), ("640", "zeros"),
+                                        ("640", "sparse"), ("640", "runs"), ("wide", "runs"),
+                                        ("wide", "random"), ("wide", "sparse"), ("quiet", "runs"),
+                                        ("quiet", "ones")])
+def test_vote_masked(lane, synth, oracle, which, kind):
+    say("vote masked", which, kind)
+    img = _masked_frame(synth, which)
     H, W = img.shape
-    C, S = synth.trig_q14(180)
+    n_theta = 180 if which == "640" else 360
+    C, S = synth.trig_q14(n_theta)
     D = synth.r_offset(W, H)
     e, _, _ = oracle.sobel_binarize(img, W, 128, 1)
     rng = np.random.default_rng(7)
     th, tw = (H + 7) // 8, (W + 7) // 8
-    mask = {"random": rng.integers(0, 256, (th, tw)), "ones": np.full((th, tw), 255),
-            "zeros": np.zeros((th, tw)),
-            "sparse": np.where(rng.random((th, tw)) < 0.1, 1 << rng.integers(0, 8, (th, tw)), 0)}[kind]
-    mask = mask.astype(np.uint8)
+    mask = _mask(rng, kind, th, tw).astype(np.uint8)
     a, d, a_o, d_o = vote_both(lane, oracle, e, W, H, C, S, D, 2 * D + 1, mask)
     assert (a == a_o).all() and d == d_o == 0
     if kind == "ones":
