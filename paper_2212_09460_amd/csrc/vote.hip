@@ -63,6 +63,9 @@ __device__ __forceinline__ void lds_vote(VoteLds<LDSW>& L, uint32_t v) {
                            1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// slots of one wave that share a segment when the slice has few rows
+constexpr int kSlotsPerSegment = 8;
+
 template <int LDSW>
 __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
     const int tid = threadIdx.x;
@@ -135,15 +138,14 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
             lds_vote(sm, (uint32_t)dot2_i16((int)q.w, CS, K));
         };
         if (!masked) {
-            for (int seg = wave; seg < L.nseg; seg += nwaves) {
-                const int n = min((int)gld(list + seg), kSegCap);
-                const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap;
-                // each of the G slots takes its own part of the segment (a
-                // different stretch of columns), so slots voting for the same
-                // theta rarely hit the same r cell at once
-                const int part = (n / (4 * G)) * 4;  // entries per slot, multiple of 4
+            // One segment's entries split over Gs slots (slot gs): each slot
+            // takes its own part of the segment (a different stretch of
+            // columns), so slots voting for the same theta rarely hit the
+            // same r cell at once.
+            auto run_segment = [&](const uint32_t* __restrict__ ents, int n, int Gs, int gs) {
+                const int part = (n / (4 * Gs)) * 4;  // entries per slot, multiple of 4
                 const int nfull = part / 4;
-                const uint32_t* p = ents + g * part;
+                const uint32_t* p = ents + gs * part;
                 // software pipeline: U 128-bit loads per lane stay in flight
                 // while the previous U are voted
                 constexpr int U = 4;
@@ -165,11 +167,29 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
                     for (int u = 0; u < U; ++u) vote4(cur[u]);
                 }
                 for (; it < nfull; ++it) vote4(gld4(p + 4 * it));
-                // remainder (fewer than 4G entries), shared by all slots
-                const int i0 = G * part + 4 * g;
+                // remainder (fewer than 4 Gs entries), shared by all slots
+                const int i0 = Gs * part + 4 * gs;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (i0 + q < n) lds_vote(sm, (uint32_t)dot2_i16((int)gld(ents + i0 + q), CS, K));
+                }
+            };
+            if (G <= kSlotsPerSegment) {
+                for (int seg = wave; seg < L.nseg; seg += nwaves) {
+                    const int n = min((int)gld(list + seg), kSegCap);
+                    run_segment(list + L.off_ent + (size_t)seg * kSegCap, n, G, g);
+                }
+            } else {
+                // few theta rows, many slots: a wave works on G / 8 segments at
+                // once, 8 slots each, so every slot has a long run of loads to
+                // pipeline instead of a few per segment
+                const int P = G / kSlotsPerSegment;
+                const int sub = g / kSlotsPerSegment, gs = g - sub * kSlotsPerSegment;
+                for (int seg0 = wave * P; seg0 < L.nseg; seg0 += nwaves * P) {
+                    const int seg = seg0 + sub;
+                    const int n = seg < L.nseg ? min((int)gld(list + seg), kSegCap) : 0;
+                    run_segment(list + L.off_ent + (size_t)min(seg, L.nseg - 1) * kSegCap, n,
+                                kSlotsPerSegment, gs);
                 }
             }
         } else {
@@ -191,10 +211,17 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
                 uint32_t inf[2];
                 int mk[2];
 #pragma unroll
+                for (int h = 0; h < 2; ++h) {  // clamped, so the four loads go out together
+                    const int t = min(h * kWave + lane, ntx - 1);
+                    inf[h] = gld(info + t);
+                    mk[h] = (int)gld(mrow + t);
+                }
+#pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int t = h * kWave + lane;
-                    inf[h] = t < ntx ? gld(info + t) : 0u;
-                    mk[h] = t < ntx ? (int)gld(mrow + t) : 0;
+                    if (h * kWave + lane >= ntx) {
+                        inf[h] = 0u;
+                        mk[h] = 0;
+                    }
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
