@@ -50,7 +50,8 @@ enum {
     LANE_E_RANGE = -3,       /* r_offset / n_r not as required (peaks need n_r == 2*r_offset + 1) */
     LANE_E_WS = -4,          /* workspace too small */
     LANE_E_DEVICE = -5,      /* HIP launch or runtime error */
-    LANE_E_UNSUPPORTED = -6  /* e.g. an unsupported border mode */
+    LANE_E_UNSUPPORTED = -6, /* e.g. an unsupported border mode */
+    LANE_E_BUSY = -7         /* serving: request dropped (stream queue full) or a replay already running */
 };
 
 enum { LANE_BORDER_ZERO = 0, LANE_BORDER_ZERO_MASKRING = 1 };
@@ -194,6 +195,12 @@ int lane_batch_launch(lane_batch *b, void *stream);
 /* Enqueue one stage without the graph (0 = clear counters, 1 = Sobel,
  * 2 = vote, 3 = peaks), e.g. to time the stages separately. */
 int lane_batch_launch_stage(lane_batch *b, int32_t stage, void *stream);
+/* Device address (*flags) of the plan's per-frame switches, uint8 [n] in
+ * frame order, owned by the plan and all 1 after creation.  A launch (graph
+ * or stage) runs the frames whose switch is non-zero; a frame switched off
+ * keeps its previous outputs and counters.  The caller may rewrite the
+ * switches between launches with stream-ordered copies. */
+int lane_batch_active_flags(lane_batch *b, uint8_t **flags);
 /* Frees the plan's device table and graph (waits for nothing: the caller
  * must make sure no launch of this plan is still running). */
 int lane_batch_destroy(lane_batch *b);
@@ -265,6 +272,103 @@ int lane_tile_labels(const uint32_t *list, int32_t W, int32_t H, const int16_t *
  * 0.5 < conf < 1.  mask: device uint8 [batch][th][tw]. */
 int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t batch, float conf,
                           uint8_t *mask, void *stream);
+
+/* ------------------------------------------------------------- serving
+ * Continuous batching of frames from many camera streams (task addition:
+ * the paper times one frame from input image to lines, Sec. 5; a deployment
+ * serves many cameras).  A server keeps each admitted stream's state
+ * resident in device memory: its frame slot, edge map, edge list,
+ * accumulator, peak buffers and, when pruned, the proposal logits and tile
+ * mask.  Streams with the same configuration form a class whose frame slots
+ * are contiguous, so the proposal network runs over a class as one batch.
+ * One worker thread repeats: take the oldest pending request of every
+ * stream (at most one per stream), copy those frames into their slots, switch
+ * on exactly those slots, launch one graph (network and mask per class when
+ * pruned, then clear, Sobel, vote, peaks; switched-off slots return at once),
+ * copy the peaks back and complete the requests.  Requests arriving while a
+ * batch runs join the next one.  A frame's results do not depend on the
+ * other frames of its batch. */
+#define LANE_SERVE_MAX_K 64
+
+typedef struct lane_stream_cfg {
+    int32_t W, H;             /* frame size */
+    int32_t n_theta;          /* theta bins, <= 8192 (a multiple of 4 when pruned) */
+    int32_t k;                /* peaks per frame, 1..LANE_SERVE_MAX_K */
+    int32_t threshold;        /* binarization threshold 0..255 */
+    int32_t border_mode;
+} lane_stream_cfg;
+
+typedef struct lane_server_cfg {
+    size_t hbm_budget;        /* device bytes the streams' state may take */
+    int32_t pruned;           /* 1: proposal network + masked vote; 0: plain */
+    float conf;               /* pruned: mask confidence, 0.5 < conf < 1 */
+    const float *cnn_params;  /* pruned: host float [LANE_CNN_PARAMS], copied at creation */
+    int32_t max_pending;      /* per-stream queue bound, >= 1; a request beyond it is dropped */
+    int32_t vote_rows;        /* theta rows per vote workgroup (power of two); 0 = 1 */
+    int32_t sobel_strip_rows; /* rows per Sobel work item (multiple of 8); 0 = 8 */
+} lane_server_cfg;
+
+typedef struct lane_result {
+    int32_t stream;           /* the caller's stream index */
+    int32_t status;           /* LANE_OK, LANE_E_BUSY (dropped) or LANE_E_DEVICE */
+    uint64_t frame_id;        /* as submitted */
+    int64_t t_submit_ns;      /* steady clock: submission */
+    int64_t t_start_ns;       /* its batch taken from the queues */
+    int64_t t_done_ns;        /* peaks in host memory */
+    int32_t batch_frames;     /* frames in the batch that ran it */
+    int32_t count;            /* peaks found */
+    int32_t theta_idx[LANE_SERVE_MAX_K], r_idx[LANE_SERVE_MAX_K], votes[LANE_SERVE_MAX_K];
+} lane_result;
+
+typedef struct lane_request {
+    int32_t stream;
+    int32_t pitch;
+    int64_t t_offset_ns;      /* arrival time after the replay starts, non-decreasing */
+    const uint8_t *frame;     /* host uint8 [H][pitch] */
+    uint64_t frame_id;
+} lane_request;
+
+typedef struct lane_server_stats {
+    int64_t submitted, completed, dropped, batches, frames_in_batches;
+    int64_t device_bytes;     /* the server's device allocation */
+    int32_t streams_admitted;
+    int32_t error;            /* LANE_OK, or the first device error */
+} lane_server_stats;
+
+typedef struct lane_server lane_server;
+
+/* Host only, no device calls.  Admission: streams are taken in order and
+ * admitted while the device bytes of the admitted ones (their state, their
+ * share of the class's network activations, shared tables and weights) stay
+ * within hbm_budget.  admitted (host uint8 [n], 1/0), stream_bytes (host
+ * size_t [n], each stream's added bytes) and total_bytes may be NULL. */
+int lane_server_plan(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,
+                     uint8_t *admitted, size_t *stream_bytes, size_t *total_bytes);
+/* Set-up call: admits as lane_server_plan, allocates the device state in one
+ * allocation plus page-locked result buffers, builds the plan and graph and
+ * starts the worker thread.  LANE_E_WS if no stream fits the budget. */
+int lane_server_create(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,
+                       lane_server **out, uint8_t *admitted_opt);
+/* Queue a frame (host uint8 [H][pitch] of the stream's size).  The bytes are
+ * read when the request's batch starts, so they must stay valid and unchanged
+ * until its result is taken (page-locked memory copies fastest).  Returns
+ * LANE_E_BUSY, and completes the request as dropped, when the stream already
+ * has max_pending requests waiting; LANE_E_ARG for a stream not admitted.
+ * Thread-safe. */
+int lane_server_submit(lane_server *s, int32_t stream, const uint8_t *frame, int32_t pitch,
+                       uint64_t frame_id);
+/* Up to max finished results (host array) in completion order; waits up to
+ * wait_ms for the first (0: no wait, negative: until one is there). */
+int lane_server_poll(lane_server *s, lane_result *out, int32_t max, int32_t wait_ms,
+                     int32_t *n_out);
+/* Open-loop load: submits reqs[i] at (call time + t_offset_ns) from the
+ * calling thread, waits for every request and writes results[i] (host [n]).
+ * These results do not go to lane_server_poll.  One replay at a time. */
+int lane_server_replay(lane_server *s, const lane_request *reqs, int32_t n, lane_result *results);
+int lane_server_stats_get(lane_server *s, lane_server_stats *out);
+/* Stops the worker after the batch in flight (queued requests are discarded)
+ * and frees everything.  No other call on s may be running. */
+int lane_server_destroy(lane_server *s);
 
 #ifdef __cplusplus
 }

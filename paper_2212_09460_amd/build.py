@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "liblane.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["sobel.hip", "vote.hip", "peaks.hip", "capi.hip", "batch.hip", "cnn.hip"]
+SOURCES = ["sobel.hip", "vote.hip", "peaks.hip", "capi.hip", "batch.hip", "cnn.hip", "serve.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -35,7 +35,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB_PATH + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-shared", *objs, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, "-shared", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

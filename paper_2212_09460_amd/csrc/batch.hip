@@ -39,9 +39,9 @@ extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
 namespace {
 
-__global__ void k_clear_counters(uint32_t* const* ptrs, int n) {
+__global__ void k_clear_counters(uint32_t* const* ptrs, const uint8_t* active, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && ptrs[i]) {
+    if (i < n && ptrs[i] && active[i]) {
         ptrs[i][0] = 0;
         ptrs[i][1] = 0;
     }
@@ -64,6 +64,7 @@ struct lane_batch {
     int* d_prefix = nullptr;
     uint32_t** d_counters = nullptr;
     uint32_t* d_queue = nullptr;
+    uint8_t* d_active = nullptr;   // one flag per frame, 1 after creation
     int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0, total_blocks = 0;
     int grid_sobel = 1, grid_sobel_slow = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
     bool vote_dynamic = false;
@@ -109,7 +110,7 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
     switch (stage) {
         case 0:
             hipLaunchKernelGGL(k_clear_counters, dim3((b->n + 255) / 256), dim3(256), 0, s,
-                               b->d_counters, b->n);
+                               b->d_counters, b->d_active, b->n);
             return hipGetLastError();
         case 1: {
             // aligned frames first (vector loads), then the rest
@@ -236,6 +237,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
             p.block_log2 = lane_peaks_block_log2(f.n_theta, f.n_r);
             p.nbr = lane_peaks_blocks_per_row(f.n_r, p.block_log2);
             p.n_blocks = f.n_theta * p.nbr;
+            p.active_index = i;
             pd.push_back(p);
             // the vote writes the block keys while its rows are still in LDS
             v.keys = p.keys;
@@ -292,6 +294,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_prefix = off; off = al(off + sizeof(int) * prefix.size());
     const size_t o_cnt = off; off = al(off + sizeof(uint32_t*) * n);
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
+    const size_t o_active = off; off = al(off + (size_t)n);
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -305,6 +308,12 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->d_prefix = (int*)(base + o_prefix);
     b->d_counters = (uint32_t**)(base + o_cnt);
     b->d_queue = (uint32_t*)(base + o_queue);
+    b->d_active = (uint8_t*)(base + o_active);
+    for (int i = 0; i < n; ++i) {
+        sd[i].active = b->d_active + i;
+        vd[i].active = b->d_active + i;
+    }
+    for (auto& p : pd) p.active = b->d_active + p.active_index;
     bool ok = hipMemcpy(b->d_sobel, sd.data(), sizeof(SobelDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_vote, vd.data(), sizeof(VoteDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
     if (!pd.empty())
@@ -314,6 +323,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     ok = ok && hipMemcpy(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 4) == hipSuccess;
+    ok = ok && hipMemset(b->d_active, 1, (size_t)n) == hipSuccess;
     if (!ok) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -361,6 +371,12 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
 int lane_batch_launch(lane_batch* b, void* stream) {
     if (!b || !b->exec) return LANE_E_ARG;
     return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_batch_active_flags(lane_batch* b, uint8_t** flags) {
+    if (!b || !flags) return LANE_E_ARG;
+    *flags = b->d_active;
+    return LANE_OK;
 }
 
 int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {

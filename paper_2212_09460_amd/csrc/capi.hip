@@ -43,6 +43,7 @@ const char* lane_strerror(int status) {
         case LANE_E_WS: return "workspace too small";
         case LANE_E_DEVICE: return "HIP device error";
         case LANE_E_UNSUPPORTED: return "unsupported option";
+        case LANE_E_BUSY: return "request dropped or server busy";
         default: return "unknown status";
     }
 }

@@ -98,6 +98,7 @@ struct CnnFwd {
     int H1, W1, H2, W2, H3, W3;  // layer output sizes; head = (H3, W3)
     long long s1, s2, s3;     // per-frame strides in halves
     int batch;
+    const uint8_t* active;    // frame b runs iff active[b] != 0 (null = all)
 };
 
 // conv1: K = the 9 taps of the one input channel
@@ -107,6 +108,7 @@ __global__ void __launch_bounds__(256) k_cnn_fwd1(CnnFwd p) {
     const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (item >= p.batch * p.H1 * ntx) return;
     const int b = item / (p.H1 * ntx), rem = item - b * p.H1 * ntx;
+    if (p.active && gld(p.active + b) == 0) return;
     const int oy = rem / ntx, ox0 = (rem - (rem / ntx) * ntx) * 16;
     const int col = lane & 15, grp = lane >> 4;
     const _Float16* w = pk_h(p.pk) + kPkW1;
@@ -149,6 +151,7 @@ __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
     const int item = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (item >= p.batch * Ho * ntx) return;
     const int b = item / (Ho * ntx), rem = item - b * Ho * ntx;
+    if (p.active && gld(p.active + b) == 0) return;
     const int oy = rem / ntx, ox0 = (rem - (rem / ntx) * ntx) * 16;
     const int col = lane & 15, grp = lane >> 4;
     const _Float16* w = pk_h(p.pk) + (layer == 1 ? kPkW2 : layer == 2 ? kPkW3 : kPkW4);
@@ -502,11 +505,12 @@ __global__ void k_tile_labels(const uint32_t* __restrict__ list, int W, int H,
 
 // ------------------------------------------------------------------ mask --
 __global__ void k_mask_from_logits(const float* __restrict__ logits, int th, int tw, int batch,
-                                   float t_hi, uint8_t* mask) {
+                                   float t_hi, uint8_t* mask, const uint8_t* active) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = th * tw;
     if (i >= n * batch) return;
     const int b = i / n, t = i - b * n;
+    if (active && active[b] == 0) return;
     const float* z = logits + (size_t)b * 9 * n;
     const float zk = z[t];
     uint8_t m;
@@ -590,6 +594,14 @@ inline bool a16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 extern "C" {
 
+LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                          int64_t img_stride, int32_t batch, const void* packed,
+                                          void* act, float* logits, const uint8_t* active,
+                                          void* stream);
+LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
+                                               int32_t batch, float conf, uint8_t* mask,
+                                               const uint8_t* active, void* stream);
+
 int lane_cnn_param_count(void) { return kCnnParams; }
 
 int lane_cnn_sizes(int32_t W, int32_t H, int32_t batch, size_t* packed_bytes, size_t* act_bytes,
@@ -617,6 +629,16 @@ int lane_cnn_pack(const float* params, void* packed, void* stream) {
 
 int lane_cnn_forward(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
                      int32_t batch, const void* packed, void* act, float* logits, void* stream) {
+    return lane_cnn_forward_active(img, W, H, pitch, img_stride, batch, packed, act, logits, nullptr,
+                                   stream);
+}
+
+// Forward with per-frame flags (device uint8 [batch] or null): frames whose
+// flag is 0 are skipped and keep their previous logits.
+LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                          int64_t img_stride, int32_t batch, const void* packed,
+                                          void* act, float* logits, const uint8_t* active,
+                                          void* stream) {
     if (!img || !packed || !act || !logits || W < 1 || H < 1 || pitch < W || batch < 1 ||
         img_stride < (int64_t)H * pitch || !a16(packed) || !a16(act))
         return LANE_E_ARG;
@@ -638,6 +660,7 @@ int lane_cnn_forward(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, in
     p.H1 = g.H1; p.W1 = g.W1; p.H2 = g.H2; p.W2 = g.W2; p.H3 = g.H3; p.W3 = g.W3;
     p.s1 = g.s1; p.s2 = g.s2; p.s3 = g.s3;
     p.batch = batch;
+    p.active = active;
     hipStream_t s = (hipStream_t)stream;
     auto waves = [&](int Ho, int Wo) { return batch * Ho * ((Wo + 15) / 16); };
     hipLaunchKernelGGL(k_cnn_fwd1, dim3((waves(g.H1, g.W1) + 3) / 4), dim3(256), 0, s, p);
@@ -730,6 +753,12 @@ int lane_tile_labels(const uint32_t* list, int32_t W, int32_t H, const int16_t* 
 
 int lane_mask_from_logits(const float* logits, int32_t W, int32_t H, int32_t batch, float conf,
                           uint8_t* mask, void* stream) {
+    return lane_mask_from_logits_active(logits, W, H, batch, conf, mask, nullptr, stream);
+}
+
+LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
+                                               int32_t batch, float conf, uint8_t* mask,
+                                               const uint8_t* active, void* stream) {
     if (!logits || !mask || W < 1 || H < 1 || batch < 1 || !(conf > 0.5f && conf < 1.f))
         return LANE_E_ARG;
     if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
@@ -738,7 +767,7 @@ int lane_mask_from_logits(const float* logits, int32_t W, int32_t H, int32_t bat
     const float t_hi = (float)log((double)conf / (1.0 - (double)conf));
     const int n = g.H3 * g.W3 * batch;
     hipLaunchKernelGGL(k_mask_from_logits, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                       logits, g.H3, g.W3, batch, t_hi, mask);
+                       logits, g.H3, g.W3, batch, t_hi, mask, active);
     return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
 }
 

@@ -65,6 +65,7 @@ struct SobelDesc {
     uint32_t* edge_count;  // device scalar or null (zeroed beforehand)
     int fast;            // 16-byte aligned rows: vector loads/stores (batched path)
     int strip_rows;      // rows per work item, a multiple of 8
+    const uint8_t* active;  // batched path: the frame runs iff *active != 0 (null = always)
 };
 
 // One frame for the vote.
@@ -83,6 +84,7 @@ struct VoteDesc {
     unsigned long long* keys;  // or null: peak-search block keys written with the rows
     int key_log2;              // cells per key block = 1 << key_log2
     int nbr;                   // key blocks per row
+    const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
 };
 
 // One frame for the peak search.
@@ -98,6 +100,8 @@ struct PeaksDesc {
     int block_log2;            // a block is 1 << block_log2 cells of one row
     int nbr;                   // blocks per row, ceil(n_r / block size)
     int n_blocks;              // n_theta * nbr
+    int active_index;          // host bookkeeping: the frame this descriptor belongs to
+    const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
 };
 
 // Peak-search key of a cell: one unsigned max picks the largest count and,
@@ -118,7 +122,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-constexpr int kPeaksMaxBlocksLds = 8192;  // keys held in LDS by the select pass
+constexpr int kPeaksMaxBlocksLds = 8192;
+
+// A frame switched off in a batched launch keeps its previous outputs.
+__device__ __forceinline__ bool frame_on(const uint8_t* active) { return !active || gld(active) != 0; }  // keys held in LDS by the select pass
 
 inline int ilog2_floor(unsigned v) { int r = -1; while (v) { v >>= 1; ++r; } return r; }
 

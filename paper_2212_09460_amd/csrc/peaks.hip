@@ -80,6 +80,7 @@ __global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __res
             else hi = mid - 1;
         }
         const PeaksDesc d = descs[lo];
+        if (!frame_on(d.active)) continue;
         block_key(d, gb - prefix[lo], threadIdx.x & (kWave - 1));
     }
 }
@@ -242,6 +243,7 @@ __global__ void __launch_bounds__(1024) k_peaks_select_batch(const PeaksDesc* __
                                                              int n_frames) {
     for (int f = blockIdx.x; f < n_frames; f += gridDim.x) {
         const PeaksDesc d = descs[f];
+        if (!frame_on(d.active)) continue;
         peaks_select(d);
         __syncthreads();
     }

@@ -1,0 +1,675 @@
+// Serving: continuous batching of frames from many camera streams.
+//
+// The paper measures the latency of one frame from input image to detected
+// lines (Sec. 5); a deployment feeds many cameras at once.  The server keeps
+// every admitted stream's state resident in device memory (frame slot, edge
+// map, edge list, accumulator, peak buffers, and for the pruned path the
+// proposal logits and tile mask) and runs one worker thread:
+//
+//   wait for requests -> take the oldest request of every stream (one per
+//   stream) -> copy those frames into their slots -> write the per-slot flags
+//   -> one graph launch over all slots (proposal network and mask per size
+//   class when pruned, then clear, Sobel, vote, peaks; switched-off slots
+//   return at once) -> copy the peaks back -> complete the requests.
+//
+// Requests that arrive while a batch runs wait for the next refill.  Streams
+// with the same configuration form a class whose frame slots are contiguous,
+// so the network runs over a class as one batch.  Admission: streams are
+// taken in order while their device state fits the HBM budget.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string.h>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lane.h"
+#include "lane_internal.h"
+
+extern "C" {
+LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                          int64_t img_stride, int32_t batch, const void* packed,
+                                          void* act, float* logits, const uint8_t* active,
+                                          void* stream);
+LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
+                                               int32_t batch, float conf, uint8_t* mask,
+                                               const uint8_t* active, void* stream);
+}
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_stream(const lane_stream_cfg& c, int pruned) {
+    if (c.W < 1 || c.H < 1 || c.n_theta < 1 || c.k < 1 || c.threshold < 0 || c.threshold > 255)
+        return LANE_E_ARG;
+    if (c.W > LANE_MAX_DIM || c.H > LANE_MAX_DIM || c.n_theta > 8192) return LANE_E_SIZE;
+    if (c.k > LANE_SERVE_MAX_K) return LANE_E_ARG;
+    if (c.border_mode != LANE_BORDER_ZERO && c.border_mode != LANE_BORDER_ZERO_MASKRING)
+        return LANE_E_UNSUPPORTED;
+    if (pruned && (c.n_theta % 4) != 0) return LANE_E_UNSUPPORTED;
+    return LANE_OK;
+}
+
+int check_cfg(const lane_server_cfg& c) {
+    if (c.max_pending < 1) return LANE_E_ARG;
+    if (c.vote_rows < 0 || (c.vote_rows & (c.vote_rows - 1)) != 0) return LANE_E_ARG;
+    if (c.sobel_strip_rows < 0 || (c.sobel_strip_rows % 8) != 0) return LANE_E_ARG;
+    if (c.pruned && (!c.cnn_params || !(c.conf > 0.5f && c.conf < 1.f))) return LANE_E_ARG;
+    return LANE_OK;
+}
+
+using ClassKey = std::tuple<int, int, int, int, int, int>;
+ClassKey key_of(const lane_stream_cfg& c) {
+    return ClassKey(c.W, c.H, c.n_theta, c.k, c.threshold, c.border_mode);
+}
+
+// Device bytes of one stream's own buffers (the class's proposal activations
+// are counted separately because they grow with the class size).
+struct StreamSizes {
+    size_t img, edges, list, acc, peaks, peaks_ws, counters, mask, logits;
+    size_t total() const {
+        return img + edges + list + acc + peaks + peaks_ws + counters + mask + logits;
+    }
+};
+
+StreamSizes stream_sizes(const lane_stream_cfg& c, int pruned) {
+    StreamSizes z;
+    const int pitch = (c.W + 15) / 16 * 16;
+    int32_t D = 0;
+    lane_r_offset(c.W, c.H, &D);
+    const size_t n_r = 2 * (size_t)D + 1;
+    const size_t th = (c.H + 7) / 8, tw = (c.W + 7) / 8;
+    z.img = al256((size_t)pitch * c.H);
+    z.edges = al256((size_t)c.W * c.H);
+    size_t lb = 0;
+    lane_edge_list_size(c.W, c.H, &lb);
+    z.list = al256(lb);
+    z.acc = al256(sizeof(int32_t) * (size_t)c.n_theta * n_r);
+    z.peaks = al256(sizeof(int32_t) * (3 * (size_t)c.k + 1));
+    size_t ws = 0;
+    lane_hough_peaks_workspace_size(c.n_theta, (int32_t)n_r, &ws);
+    z.peaks_ws = al256(ws);
+    z.counters = 256;
+    z.mask = pruned ? al256(th * tw) : 0;
+    z.logits = pruned ? al256(sizeof(float) * 9 * th * tw) : 0;
+    return z;
+}
+
+size_t act_bytes(const lane_stream_cfg& c, int n) {
+    if (n <= 0) return 0;
+    size_t a = 0;
+    lane_cnn_sizes(c.W, c.H, n, nullptr, &a, nullptr);
+    return al256(a);
+}
+
+// Admission in stream order; returns the device bytes of everything the
+// server allocates for the admitted streams (tables and weights included).
+size_t plan_admission(const lane_stream_cfg* s, int n, const lane_server_cfg& cfg,
+                      uint8_t* admitted, size_t* stream_bytes) {
+    std::map<ClassKey, int> count;
+    std::map<int, int> thetas;
+    size_t shared = 0;
+    if (cfg.pruned) {
+        size_t pk = 0;
+        lane_cnn_sizes(16, 16, 1, &pk, nullptr, nullptr);
+        shared += al256(pk) + al256(sizeof(float) * LANE_CNN_PARAMS);
+    }
+    size_t total = shared;
+    for (int i = 0; i < n; ++i) {
+        const StreamSizes z = stream_sizes(s[i], cfg.pruned);
+        const ClassKey k = key_of(s[i]);
+        const int c = count.count(k) ? count[k] : 0;
+        size_t add = z.total();
+        if (cfg.pruned) add += act_bytes(s[i], c + 1) - act_bytes(s[i], c);
+        if (!thetas.count(s[i].n_theta)) add += al256(sizeof(int16_t) * 2 * (size_t)s[i].n_theta);
+        if (stream_bytes) stream_bytes[i] = add;
+        const bool ok = total + add <= cfg.hbm_budget;
+        if (admitted) admitted[i] = ok ? 1 : 0;
+        if (ok) {
+            total += add;
+            count[k] = c + 1;
+            thetas[s[i].n_theta] = 1;
+        }
+    }
+    return total;
+}
+
+struct Req {
+    int stream;
+    int pitch;
+    const uint8_t* frame;
+    uint64_t frame_id;
+    int64_t t_submit;
+    int64_t tag;  // >= 0: index in the running replay
+};
+
+}  // namespace
+
+struct lane_server {
+    lane_server_cfg cfg;
+    int dev = 0;
+    std::vector<lane_stream_cfg> streams;  // admitted, in slot order
+    std::vector<int> slot_of;              // caller's stream index -> slot (-1: not admitted)
+    std::vector<int> stream_of;            // slot -> caller's stream index
+    struct Class {
+        lane_stream_cfg cfg;
+        int first_slot, n;
+        int pitch;
+        uint8_t* img;
+        uint8_t* mask;
+        float* logits;
+        void* act;
+    };
+    std::vector<Class> classes;
+    std::vector<int> class_of;             // slot -> class
+    std::vector<uint8_t*> slot_img;
+    std::vector<int32_t*> slot_peaks;
+    void* dmem = nullptr;
+    size_t dbytes = 0;
+    int32_t* h_peaks = nullptr;            // pinned, per slot (3k+1) at h_peak_off[slot]
+    std::vector<size_t> h_peak_off;
+    uint8_t* h_flags = nullptr;            // pinned, one per slot
+    uint8_t* d_flags = nullptr;            // the plan's flags
+    lane_batch* plan = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::vector<std::deque<Req>> pending;
+    std::deque<lane_result> done;
+    lane_result* replay_out = nullptr;
+    int64_t replay_left = 0;
+    bool stop = false;
+    int error = LANE_OK;
+    lane_server_stats stats;
+    std::thread worker;
+};
+
+namespace {
+
+void fill_result(lane_result& r, const Req& q, int status) {
+    memset(&r, 0, sizeof(r));
+    r.stream = q.stream;
+    r.status = status;
+    r.frame_id = q.frame_id;
+    r.t_submit_ns = q.t_submit;
+    r.count = 0;
+}
+
+// caller holds s->mu
+void complete(lane_server* s, lane_result& r, int64_t tag) {
+    if (tag >= 0 && s->replay_out) {
+        s->replay_out[tag] = r;
+        --s->replay_left;
+    } else {
+        s->done.push_back(r);
+    }
+    s->cv_done.notify_all();
+}
+
+int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_result>& out) {
+    const int n_slots = (int)s->streams.size();
+    memset(s->h_flags, 0, (size_t)n_slots);
+    for (const Req& q : batch) s->h_flags[s->slot_of[q.stream]] = 1;
+    hipError_t e = hipMemcpyAsync(s->d_flags, s->h_flags, (size_t)n_slots, hipMemcpyHostToDevice,
+                                  s->stream);
+    for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
+        const Req& q = batch[i];
+        const int slot = s->slot_of[q.stream];
+        const lane_server::Class& c = s->classes[s->class_of[slot]];
+        e = hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch,
+                             (size_t)c.cfg.W, (size_t)c.cfg.H, hipMemcpyHostToDevice, s->stream);
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(s->exec, s->stream);
+    for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
+        const int slot = s->slot_of[batch[i].stream];
+        const int k = s->streams[slot].k;
+        e = hipMemcpyAsync(s->h_peaks + s->h_peak_off[slot], s->slot_peaks[slot],
+                           sizeof(int32_t) * (3 * (size_t)k + 1), hipMemcpyDeviceToHost, s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    const int64_t t_done = now_ns();
+    const int status = e == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+    out.resize(batch.size());
+    for (size_t i = 0; i < batch.size(); ++i) {
+        const Req& q = batch[i];
+        lane_result& r = out[i];
+        fill_result(r, q, status);
+        r.t_done_ns = t_done;
+        r.batch_frames = (int32_t)batch.size();
+        if (status != LANE_OK) continue;
+        const int slot = s->slot_of[q.stream];
+        const int k = s->streams[slot].k;
+        const int32_t* p = s->h_peaks + s->h_peak_off[slot];
+        r.count = p[3 * k];
+        for (int j = 0; j < k; ++j) {
+            r.theta_idx[j] = p[j];
+            r.r_idx[j] = p[k + j];
+            r.votes[j] = p[2 * k + j];
+        }
+    }
+    return status;
+}
+
+void worker_main(lane_server* s) {
+    hipSetDevice(s->dev);
+    std::vector<Req> batch;
+    std::vector<lane_result> out;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        auto any = [&] {
+            for (auto& d : s->pending)
+                if (!d.empty()) return true;
+            return false;
+        };
+        s->cv_work.wait(lk, [&] { return s->stop || any(); });
+        if (s->stop) break;
+        batch.clear();
+        for (auto& d : s->pending) {
+            if (d.empty()) continue;
+            batch.push_back(d.front());
+            d.pop_front();
+        }
+        const int64_t t_start = now_ns();
+        const bool failed = s->error != LANE_OK;
+        lk.unlock();
+        int st = LANE_E_DEVICE;
+        if (!failed) st = run_batch(s, batch, out);
+        lk.lock();
+        if (failed) {
+            out.resize(batch.size());
+            for (size_t i = 0; i < batch.size(); ++i) fill_result(out[i], batch[i], LANE_E_DEVICE);
+        }
+        if (st != LANE_OK) s->error = st;
+        s->stats.batches += 1;
+        s->stats.frames_in_batches += (int64_t)batch.size();
+        for (size_t i = 0; i < batch.size(); ++i) {
+            out[i].t_start_ns = t_start;
+            s->stats.completed += 1;
+            complete(s, out[i], batch[i].tag);
+        }
+    }
+}
+
+int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, uint64_t frame_id,
+                  int64_t tag) {
+    Req q;
+    q.stream = stream;
+    q.pitch = pitch;
+    q.frame = frame;
+    q.frame_id = frame_id;
+    q.t_submit = now_ns();
+    q.tag = tag;
+    s->stats.submitted += 1;
+    auto& d = s->pending[s->slot_of[stream]];
+    if ((int)d.size() >= s->cfg.max_pending) {
+        s->stats.dropped += 1;
+        lane_result r;
+        fill_result(r, q, LANE_E_BUSY);
+        r.t_done_ns = q.t_submit;
+        complete(s, r, tag);
+        return LANE_E_BUSY;
+    }
+    d.push_back(q);
+    s->cv_work.notify_one();
+    return LANE_OK;
+}
+
+int check_submit(lane_server* s, int32_t stream, const uint8_t* frame, int32_t pitch) {
+    if (!s || !frame || stream < 0 || stream >= (int)s->slot_of.size()) return LANE_E_ARG;
+    const int slot = s->slot_of[stream];
+    if (slot < 0) return LANE_E_ARG;
+    if (pitch < s->streams[slot].W) return LANE_E_ARG;
+    return LANE_OK;
+}
+
+void free_server(lane_server* s) {
+    if (s->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        s->worker.join();
+    }
+    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->exec) hipGraphExecDestroy(s->exec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->plan) lane_batch_destroy(s->plan);
+    if (s->stream) hipStreamDestroy(s->stream);
+    if (s->dmem) hipFree(s->dmem);
+    if (s->h_peaks) hipHostFree(s->h_peaks);
+    if (s->h_flags) hipHostFree(s->h_flags);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lane_server_plan(const lane_stream_cfg* streams, int32_t n, const lane_server_cfg* cfg,
+                     uint8_t* admitted, size_t* stream_bytes, size_t* total_bytes) {
+    if (!streams || n < 1 || !cfg) return LANE_E_ARG;
+    int st = check_cfg(*cfg);
+    if (st != LANE_OK) return st;
+    for (int i = 0; i < n; ++i)
+        if ((st = check_stream(streams[i], cfg->pruned)) != LANE_OK) return st;
+    const size_t t = plan_admission(streams, n, *cfg, admitted, stream_bytes);
+    if (total_bytes) *total_bytes = t;
+    return LANE_OK;
+}
+
+int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_server_cfg* cfg,
+                       lane_server** out, uint8_t* admitted_opt) {
+    if (!streams || n < 1 || !cfg || !out) return LANE_E_ARG;
+    *out = nullptr;
+    int st = check_cfg(*cfg);
+    if (st != LANE_OK) return st;
+    for (int i = 0; i < n; ++i)
+        if ((st = check_stream(streams[i], cfg->pruned)) != LANE_OK) return st;
+    std::vector<uint8_t> adm(n, 0);
+    plan_admission(streams, n, *cfg, adm.data(), nullptr);
+    if (admitted_opt) memcpy(admitted_opt, adm.data(), (size_t)n);
+    int n_adm = 0;
+    for (int i = 0; i < n; ++i) n_adm += adm[i];
+    if (n_adm == 0) return LANE_E_WS;
+
+    lane_server* s = new (std::nothrow) lane_server();
+    if (!s) return LANE_E_DEVICE;
+    s->cfg = *cfg;
+    memset(&s->stats, 0, sizeof(s->stats));
+    if (hipGetDevice(&s->dev) != hipSuccess) {
+        free_server(s);
+        return LANE_E_DEVICE;
+    }
+    // classes in order of first appearance; slots grouped by class
+    std::map<ClassKey, int> cidx;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < n; ++i) {
+        if (!adm[i]) continue;
+        const ClassKey k = key_of(streams[i]);
+        if (!cidx.count(k)) {
+            cidx[k] = (int)members.size();
+            members.emplace_back();
+        }
+        members[cidx[k]].push_back(i);
+    }
+    s->slot_of.assign(n, -1);
+    for (size_t c = 0; c < members.size(); ++c) {
+        lane_server::Class cl;
+        memset(&cl, 0, sizeof(cl));
+        cl.cfg = streams[members[c][0]];
+        cl.first_slot = (int)s->streams.size();
+        cl.n = (int)members[c].size();
+        cl.pitch = (cl.cfg.W + 15) / 16 * 16;
+        for (int i : members[c]) {
+            s->slot_of[i] = (int)s->streams.size();
+            s->stream_of.push_back(i);
+            s->streams.push_back(streams[i]);
+            s->class_of.push_back((int)c);
+        }
+        s->classes.push_back(cl);
+    }
+    const int n_slots = (int)s->streams.size();
+    s->pending.resize(n_slots);
+
+    // one device allocation: per class the frame slots (contiguous), masks,
+    // logits and activations; per slot the path's buffers; shared tables
+    std::vector<StreamSizes> sz(n_slots);
+    for (int i = 0; i < n_slots; ++i) sz[i] = stream_sizes(s->streams[i], cfg->pruned);
+    std::map<int, size_t> trig_off;
+    size_t off = 0;
+    std::vector<size_t> o_img(s->classes.size()), o_mask(s->classes.size()), o_log(s->classes.size()),
+        o_act(s->classes.size());
+    for (size_t c = 0; c < s->classes.size(); ++c) {
+        const auto& cl = s->classes[c];
+        const StreamSizes& z = sz[cl.first_slot];
+        o_img[c] = off;
+        off += z.img * cl.n;
+        o_mask[c] = off;
+        off += z.mask * cl.n;
+        o_log[c] = off;
+        off += z.logits * cl.n;
+        o_act[c] = off;
+        off += cfg->pruned ? act_bytes(cl.cfg, cl.n) : 0;
+    }
+    std::vector<size_t> o_slot(n_slots);
+    for (int i = 0; i < n_slots; ++i) {
+        o_slot[i] = off;
+        off += sz[i].total() - sz[i].img - sz[i].mask - sz[i].logits;
+        if (!trig_off.count(s->streams[i].n_theta)) {
+            trig_off[s->streams[i].n_theta] = off;
+            off += al256(sizeof(int16_t) * 2 * (size_t)s->streams[i].n_theta);
+        }
+    }
+    size_t o_pk = off, o_par = off;
+    if (cfg->pruned) {
+        size_t pk = 0;
+        lane_cnn_sizes(16, 16, 1, &pk, nullptr, nullptr);
+        o_pk = off;
+        off += al256(pk);
+        o_par = off;
+        off += al256(sizeof(float) * LANE_CNN_PARAMS);
+    }
+    s->dbytes = off;
+    s->stats.device_bytes = (int64_t)off;
+    s->stats.streams_admitted = n_slots;
+    bool ok = hipMalloc(&s->dmem, off) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    size_t hp = 0;
+    s->h_peak_off.resize(n_slots);
+    for (int i = 0; i < n_slots; ++i) {
+        s->h_peak_off[i] = hp;
+        hp += 3 * (size_t)s->streams[i].k + 1;
+    }
+    ok = ok && hipHostMalloc((void**)&s->h_peaks, sizeof(int32_t) * hp, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->h_flags, (size_t)n_slots, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        free_server(s);
+        return LANE_E_DEVICE;
+    }
+    char* base = (char*)s->dmem;
+    // zeroed state first: every slot starts with an empty frame and no peaks
+    ok = ok && hipMemsetAsync(s->dmem, 0, off, s->stream) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+    // trig tables (host helper, then one copy each)
+    for (auto& t : trig_off) {
+        std::vector<int16_t> cs(2 * (size_t)t.first);
+        lane_make_trig_q14(t.first, cs.data(), cs.data() + t.first);
+        ok = ok && hipMemcpy(base + t.second, cs.data(), sizeof(int16_t) * cs.size(),
+                             hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (cfg->pruned) {
+        ok = ok && hipMemcpy(base + o_par, cfg->cnn_params, sizeof(float) * LANE_CNN_PARAMS,
+                             hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && lane_cnn_pack((const float*)(base + o_par), base + o_pk, s->stream) == LANE_OK;
+    }
+    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+    std::vector<lane_frame> frames(n_slots);
+    s->slot_img.resize(n_slots);
+    s->slot_peaks.resize(n_slots);
+    for (size_t c = 0; c < s->classes.size() && ok; ++c) {
+        auto& cl = s->classes[c];
+        cl.img = (uint8_t*)(base + o_img[c]);
+        cl.mask = (uint8_t*)(base + o_mask[c]);
+        cl.logits = (float*)(base + o_log[c]);
+        cl.act = base + o_act[c];
+        for (int j = 0; j < cl.n; ++j) {
+            const int i = cl.first_slot + j;
+            const lane_stream_cfg& sc = s->streams[i];
+            const StreamSizes& z = sz[i];
+            int32_t D = 0;
+            lane_r_offset(sc.W, sc.H, &D);
+            char* p = base + o_slot[i];
+            lane_frame& f = frames[i];
+            memset(&f, 0, sizeof(f));
+            s->slot_img[i] = cl.img + z.img * j;
+            f.img = s->slot_img[i];
+            f.W = sc.W;
+            f.H = sc.H;
+            f.pitch = cl.pitch;
+            f.threshold = sc.threshold;
+            f.border_mode = sc.border_mode;
+            f.edges = (uint8_t*)p;
+            p += z.edges;
+            f.list = (uint32_t*)p;
+            p += z.list;
+            f.cos_q14 = (const int16_t*)(base + trig_off[sc.n_theta]);
+            f.sin_q14 = f.cos_q14 + sc.n_theta;
+            f.n_theta = sc.n_theta;
+            f.r_offset = D;
+            f.n_r = 2 * D + 1;
+            // the mask kernel writes a class's masks back to back, [n][th][tw]
+            const size_t tiles = (size_t)((sc.H + 7) / 8) * (size_t)((sc.W + 7) / 8);
+            f.tile_mask_opt = cfg->pruned ? cl.mask + tiles * j : nullptr;
+            f.acc = (int32_t*)p;
+            p += z.acc;
+            f.k = sc.k;
+            f.h_theta = std::max(1, (sc.n_theta + 99) / 100);
+            f.h_r = std::max(1, (f.n_r + 99) / 100);
+            f.min_votes = 1;
+            f.peaks = (int32_t*)p;
+            s->slot_peaks[i] = f.peaks;
+            p += z.peaks;
+            f.peaks_ws = p;
+            f.peaks_ws_bytes = z.peaks_ws;
+            p += z.peaks_ws;
+            f.counters_opt = (uint32_t*)p;
+        }
+    }
+    lane_tune tune = {cfg->vote_rows > 0 ? cfg->vote_rows : 1, 1, 0,
+                      cfg->sobel_strip_rows > 0 ? cfg->sobel_strip_rows : 8};
+    if (ok && lane_batch_create(frames.data(), n_slots, &tune, &s->plan) != LANE_OK) ok = false;
+    ok = ok && lane_batch_active_flags(s->plan, &s->d_flags) == LANE_OK;
+    if (!ok) {
+        free_server(s);
+        return LANE_E_DEVICE;
+    }
+    // the whole refill as one graph: proposal per class (pruned), then the path
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        free_server(s);
+        return LANE_E_DEVICE;
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int cst = LANE_OK;
+    if (e == hipSuccess && cfg->pruned) {
+        for (auto& cl : s->classes) {
+            const uint8_t* fl = s->d_flags + cl.first_slot;
+            cst = lane_cnn_forward_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
+                                          (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
+                                          cl.act, cl.logits, fl, cs);
+            if (cst == LANE_OK)
+                cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
+                                                   cl.mask, fl, cs);
+            if (cst != LANE_OK) break;
+        }
+    }
+    for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg)
+        cst = lane_batch_launch_stage(s->plan, stg, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && cst == LANE_OK) {
+        s->graph = g;
+        e = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
+    } else if (g) {
+        hipGraphDestroy(g);
+    }
+    hipStreamDestroy(cs);
+    if (e != hipSuccess || cst != LANE_OK) {
+        free_server(s);
+        return LANE_E_DEVICE;
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return LANE_OK;
+}
+
+int lane_server_submit(lane_server* s, int32_t stream, const uint8_t* frame, int32_t pitch,
+                       uint64_t frame_id) {
+    const int st = check_submit(s, stream, frame, pitch);
+    if (st != LANE_OK) return st;
+    std::lock_guard<std::mutex> g(s->mu);
+    return submit_locked(s, stream, frame, pitch, frame_id, -1);
+}
+
+int lane_server_poll(lane_server* s, lane_result* out, int32_t max, int32_t wait_ms, int32_t* n_out) {
+    if (!s || !out || max < 1 || !n_out) return LANE_E_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && wait_ms != 0) {
+        auto ready = [&] { return !s->done.empty(); };
+        if (wait_ms < 0) s->cv_done.wait(lk, ready);
+        else s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+    }
+    int n = 0;
+    while (n < max && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = n;
+    return LANE_OK;
+}
+
+int lane_server_replay(lane_server* s, const lane_request* reqs, int32_t n, lane_result* results) {
+    if (!s || !reqs || n < 1 || !results) return LANE_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const int st = check_submit(s, reqs[i].stream, reqs[i].frame, reqs[i].pitch);
+        if (st != LANE_OK) return st;
+        if (reqs[i].t_offset_ns < 0 || (i > 0 && reqs[i].t_offset_ns < reqs[i - 1].t_offset_ns))
+            return LANE_E_ARG;
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->replay_out) return LANE_E_BUSY;  // one replay at a time
+        s->replay_out = results;
+        s->replay_left = n;
+    }
+    const int64_t t0 = now_ns();
+    for (int i = 0; i < n; ++i) {
+        const int64_t target = t0 + reqs[i].t_offset_ns;
+        // sleep to just before the arrival time, then spin the rest
+        const int64_t early = target - now_ns() - 200000;
+        if (early > 0) std::this_thread::sleep_for(std::chrono::nanoseconds(early));
+        while (now_ns() < target) {
+        }
+        std::lock_guard<std::mutex> g(s->mu);
+        submit_locked(s, reqs[i].stream, reqs[i].frame, reqs[i].pitch, reqs[i].frame_id, i);
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->replay_left == 0; });
+    s->replay_out = nullptr;
+    return LANE_OK;
+}
+
+int lane_server_stats_get(lane_server* s, lane_server_stats* out) {
+    if (!s || !out) return LANE_E_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    out->error = s->error;
+    return LANE_OK;
+}
+
+int lane_server_destroy(lane_server* s) {
+    if (!s) return LANE_E_ARG;
+    free_server(s);
+    return LANE_OK;
+}
+
+}  // extern "C"

@@ -335,6 +335,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
         const int2 w = items[it];
         if (w.x < 0) continue;
         const SobelDesc d = descs[w.x];
+        if (!frame_on(d.active)) continue;
         sobel_item<FAST, kModeSobel>(d, w.y);
     }
 }

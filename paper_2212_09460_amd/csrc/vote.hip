@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(kVoteThreads)
         const int2 w = items[it];
         if (w.x >= 0) {
             const VoteDesc d = descs[w.x];
-            vote_item(sm, d, w.y);
+            if (frame_on(d.active)) vote_item(sm, d, w.y);
         }
         __syncthreads();
         if (!queue) it += gridDim.x;

@@ -53,7 +53,9 @@ EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_of
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
-           "lane_mask_from_logits")
+           "lane_mask_from_logits", "lane_batch_active_flags", "lane_server_plan",
+           "lane_server_create", "lane_server_submit", "lane_server_poll", "lane_server_replay",
+           "lane_server_stats_get", "lane_server_destroy")
 
 
 class LaneError(RuntimeError):
@@ -218,6 +220,7 @@ _batch_create = _sig("lane_batch_create", [ctypes.POINTER(LaneFrame), _i32,
 _batch_launch = _sig("lane_batch_launch", [_vp, _vp])
 _batch_stage = _sig("lane_batch_launch_stage", [_vp, _i32, _vp])
 _batch_destroy = _sig("lane_batch_destroy", [_vp])
+_batch_flags = _sig("lane_batch_active_flags", [_vp, ctypes.POINTER(_vp)])
 _tune_run = _sig("lane_tune_run", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32,
                                    ctypes.POINTER(LaneTune), ctypes.POINTER(ctypes.c_float)])
 
@@ -326,6 +329,12 @@ class Batch:
     def launch_stage(self, stage: int, stream=None):
         _check(_batch_stage(self._h, stage, _stream(stream)), "lane_batch_launch_stage")
 
+    def active_flags_ptr(self) -> int:
+        """Device address of the plan's per-frame switches (uint8 [n])."""
+        p = _vp()
+        _check(_batch_flags(self._h, ctypes.byref(p)), "lane_batch_active_flags")
+        return int(p.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             torch.cuda.synchronize()
@@ -416,3 +425,158 @@ def tile_labels(fb: "FrameBuffers", keep, bands, stream=None):
 def mask_from_logits(logits, W: int, H: int, batch: int, conf: float, mask, stream=None):
     _check(_mask(_p(logits), W, H, batch, float(conf), _p(mask), _stream(stream)),
            "lane_mask_from_logits")
+
+
+# ---------------------------------------------------------------- serving --
+
+LANE_E_BUSY = -7
+SERVE_MAX_K = 64
+
+
+class StreamCfg(ctypes.Structure):
+    _fields_ = [("W", _i32), ("H", _i32), ("n_theta", _i32), ("k", _i32), ("threshold", _i32),
+                ("border_mode", _i32)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", _sz), ("pruned", _i32), ("conf", ctypes.c_float),
+                ("cnn_params", _vp), ("max_pending", _i32), ("vote_rows", _i32),
+                ("sobel_strip_rows", _i32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("stream", _i32), ("status", _i32), ("frame_id", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("batch_frames", _i32), ("count", _i32),
+                ("theta_idx", _i32 * SERVE_MAX_K), ("r_idx", _i32 * SERVE_MAX_K),
+                ("votes", _i32 * SERVE_MAX_K)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("stream", _i32), ("pitch", _i32), ("t_offset_ns", ctypes.c_int64),
+                ("frame", _vp), ("frame_id", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("dropped", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("frames_in_batches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("streams_admitted", _i32), ("error", _i32)]
+
+
+_srv_plan = _sig("lane_server_plan", [ctypes.POINTER(StreamCfg), _i32, ctypes.POINTER(ServerCfg),
+                                      _vp, _vp, ctypes.POINTER(_sz)])
+_srv_create = _sig("lane_server_create", [ctypes.POINTER(StreamCfg), _i32,
+                                          ctypes.POINTER(ServerCfg), ctypes.POINTER(_vp), _vp])
+_srv_submit = _sig("lane_server_submit", [_vp, _i32, _vp, _i32, ctypes.c_uint64])
+_srv_poll = _sig("lane_server_poll", [_vp, ctypes.POINTER(Result), _i32, _i32,
+                                      ctypes.POINTER(_i32)])
+_srv_replay = _sig("lane_server_replay", [_vp, ctypes.POINTER(Request), _i32,
+                                          ctypes.POINTER(Result)])
+_srv_stats = _sig("lane_server_stats_get", [_vp, ctypes.POINTER(ServerStats)])
+_srv_destroy = _sig("lane_server_destroy", [_vp])
+
+
+def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, sobel_strip_rows):
+    import numpy as np
+
+    keep = None
+    if cnn_params is not None:
+        keep = np.ascontiguousarray(np.asarray(cnn_params, dtype=np.float32))
+    cfg = ServerCfg(int(hbm_budget), int(pruned), float(conf),
+                    None if keep is None else keep.ctypes.data, int(max_pending), int(vote_rows),
+                    int(sobel_strip_rows))
+    return cfg, keep
+
+
+def _stream_cfgs(streams):
+    arr = (StreamCfg * len(streams))()
+    for i, st in enumerate(streams):
+        d = dict(n_theta=360, k=8, threshold=128, border_mode=LANE_BORDER_ZERO_MASKRING)
+        d.update(st)
+        arr[i] = StreamCfg(d["W"], d["H"], d["n_theta"], d["k"], d["threshold"], d["border_mode"])
+    return arr
+
+
+def server_plan(streams, hbm_budget: int, pruned: bool = False, conf: float = 0.9,
+                cnn_params=None, max_pending: int = 4, vote_rows: int = 0, sobel_strip_rows: int = 0):
+    """Host-only admission plan: (admitted list of bool, per-stream bytes, total bytes)."""
+    import numpy as np
+
+    arr = _stream_cfgs(streams)
+    cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
+                            sobel_strip_rows)
+    adm = np.zeros(len(streams), np.uint8)
+    sb = np.zeros(len(streams), np.uint64)
+    tot = _sz(0)
+    _check(_srv_plan(arr, len(streams), ctypes.byref(cfg), adm.ctypes.data, sb.ctypes.data,
+                     ctypes.byref(tot)), "lane_server_plan")
+    return [bool(a) for a in adm], [int(b) for b in sb], int(tot.value)
+
+
+class Server:
+    """Continuous-batching server over camera streams (lane_server_*).
+
+    streams: list of dicts with W, H and optionally n_theta, k, threshold,
+    border_mode."""
+
+    def __init__(self, streams, hbm_budget: int = 8 << 30, pruned: bool = False,
+                 conf: float = 0.9, cnn_params=None, max_pending: int = 4, vote_rows: int = 0,
+                 sobel_strip_rows: int = 0):
+        import numpy as np
+
+        self.streams = [dict(s) for s in streams]
+        arr = _stream_cfgs(streams)
+        cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
+                                sobel_strip_rows)
+        adm = np.zeros(len(streams), np.uint8)
+        h = _vp()
+        _check(_srv_create(arr, len(streams), ctypes.byref(cfg), ctypes.byref(h), adm.ctypes.data),
+               "lane_server_create")
+        self._h = h
+        self.admitted = [bool(a) for a in adm]
+        self._hold = {}
+
+    def submit(self, stream: int, frame, frame_id: int = 0) -> int:
+        """frame: host numpy uint8 [H][pitch]; kept alive until its result is polled."""
+        rc = _srv_submit(self._h, stream, frame.ctypes.data, frame.strides[0], frame_id)
+        if rc == LANE_OK:
+            self._hold[(stream, frame_id)] = frame
+        elif rc != LANE_E_BUSY:
+            _check(rc, "lane_server_submit")
+        return rc
+
+    def poll(self, max_n: int = 64, wait_ms: int = 0):
+        out = (Result * max_n)()
+        n = _i32(0)
+        _check(_srv_poll(self._h, out, max_n, wait_ms, ctypes.byref(n)), "lane_server_poll")
+        res = [out[i] for i in range(n.value)]
+        for r in res:
+            self._hold.pop((r.stream, r.frame_id), None)
+        return res
+
+    def replay(self, reqs):
+        """reqs: list of (stream, t_offset_s, frame ndarray, frame_id); returns results in order."""
+        arr = (Request * len(reqs))()
+        for i, (st, t, fr, fid) in enumerate(reqs):
+            arr[i] = Request(st, fr.strides[0], int(round(t * 1e9)), fr.ctypes.data, fid)
+        out = (Result * len(reqs))()
+        _check(_srv_replay(self._h, arr, len(reqs), out), "lane_server_replay")
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_srv_stats(self._h, ctypes.byref(st)), "lane_server_stats_get")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _srv_destroy(self._h)
+            self._h = None
+            self._hold.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@ plain .npz files (arrays only; loaded with allow_pickle=False).
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import torch
@@ -15,6 +16,20 @@ from .. import lane
 
 # (c_in, c_out) per layer, master layout: weights [c_out][c_in][3][3], biases [c_out]
 LAYERS = ((1, 16), (16, 16), (16, 16), (16, 9))
+
+
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def default_weights() -> str:
+    """The trained proposal weights shipped with the package."""
+    return os.path.join(WEIGHTS_DIR, "proposal.npz")
+
+
+def load_params(path: str | None = None) -> np.ndarray:
+    """FP32 master parameters from a checkpoint (host array)."""
+    z = np.load(default_weights() if path is None else path, allow_pickle=False)
+    return np.asarray(z["params"], np.float32)
 
 
 def he_uniform(seed: int) -> np.ndarray:

@@ -1,0 +1,159 @@
+"""Serving on the GPU: every frame's peaks through the continuous-batching
+server equal those of the same frame alone (single-frame entry points), for
+the plain and the pruned path, whatever else shares its batch; dropped
+requests are reported; the poll interface returns every result."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lane():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2212_09460_amd.lane as m
+
+    return m
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+STREAMS = [dict(W=320, H=240), dict(W=320, H=240), dict(W=640, H=480, n_theta=180, k=4),
+           dict(W=200, H=120, k=3), dict(W=1100, H=200)]
+
+
+def pools(synth, streams, n=3, seed=100):
+    return [np.stack([synth.road(s["W"], s["H"], seed + 10 * i + j) for j in range(n)])
+            for i, s in enumerate(streams)]
+
+
+def alone(lane, img, st, tile_mask=None):
+    n_theta, k = st.get("n_theta", 360), st.get("k", 8)
+    C, S = lane.make_trig_q14(n_theta)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    r = lane.pipeline(torch.from_numpy(img).cuda(), Cd, Sd, k, tile_mask=tile_mask)
+    torch.cuda.synchronize()
+    c = int(r["count"].item())
+    return c, r["theta_idx"].cpu().numpy(), r["r_idx"].cpu().numpy(), r["votes"].cpu().numpy()
+
+
+def same(res, ref, k):
+    c, t, r, v = ref
+    return (res.count == c and list(res.theta_idx[:k]) == list(t) and list(res.r_idx[:k]) == list(r)
+            and list(res.votes[:k]) == list(v))
+
+
+def schedule(n_streams, n, seed):
+    g = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for i in range(n):
+        if i % 7 == 0:
+            t += 0.004           # gaps let batches drain ...
+        else:
+            t += g.exponential(0.0002)  # ... and bursts make them fill up
+        reqs.append((int(g.integers(0, n_streams)), t))
+    return reqs
+
+
+def test_plain_server_matches_alone(lane, synth, oracle):
+    say("serve plain")
+    P = pools(synth, STREAMS)
+    refs = [[alone(lane, P[s][j], STREAMS[s]) for j in range(len(P[s]))] for s in range(len(STREAMS))]
+    # the oracle agrees with the alone path on two of the frames
+    for s in (0, 3):
+        st = STREAMS[s]
+        C, S = synth.trig_q14(st.get("n_theta", 360))
+        want = oracle.pipeline(P[s][0], C, S, st.get("k", 8))
+        c, t, r, v = refs[s][0]
+        assert c == want["count"] and (t == want["theta_idx"]).all() and (v == want["votes"]).all()
+    srv = lane.Server(STREAMS, hbm_budget=1 << 30, max_pending=64)
+    try:
+        for rep in range(2):
+            sched = schedule(len(STREAMS), 40, seed=rep)
+            reqs = [(s, t, P[s][i % len(P[s])], i) for i, (s, t) in enumerate(sched)]
+            out = srv.replay(reqs)
+            batched = 0
+            for i, (s, t, fr, fid) in enumerate(reqs):
+                r = out[i]
+                assert r.status == 0 and r.stream == s and r.frame_id == fid
+                assert r.t_done_ns >= r.t_start_ns >= r.t_submit_ns
+                assert same(r, refs[s][i % len(P[s])], STREAMS[s].get("k", 8)), (rep, i, s)
+                batched += r.batch_frames > 1
+            assert batched > 0  # some requests shared a batch
+        st = srv.stats()
+        assert st["completed"] == 80 and st["dropped"] == 0 and st["error"] == 0
+        assert st["frames_in_batches"] == 80 and st["batches"] < 80
+    finally:
+        srv.close()
+
+
+def test_pruned_server_matches_alone(lane, synth):
+    say("serve pruned")
+    from paper_2212_09460_amd.learned.model import ProposalNet, load_params
+
+    streams = [dict(W=320, H=240), dict(W=320, H=240), dict(W=640, H=480, n_theta=180, k=4),
+               dict(W=1100, H=200)]
+    P = pools(synth, streams, seed=300)
+    params = load_params()
+    net = ProposalNet(params)
+    refs = []
+    for s, st in enumerate(streams):
+        rs = []
+        for img in P[s]:
+            H, W = img.shape
+            lg = net.forward(torch.from_numpy(img[None].copy()).cuda())
+            m = torch.empty((1, (H + 7) // 8, (W + 7) // 8), dtype=torch.uint8, device="cuda")
+            lane.mask_from_logits(lg, W, H, 1, 0.9, m)
+            rs.append(alone(lane, img, st, tile_mask=m[0]))
+        refs.append(rs)
+    srv = lane.Server(streams, hbm_budget=1 << 30, pruned=True, conf=0.9, cnn_params=params,
+                      max_pending=64)
+    try:
+        sched = schedule(len(streams), 40, seed=7)
+        reqs = [(s, t, P[s][i % len(P[s])], i) for i, (s, t) in enumerate(sched)]
+        out = srv.replay(reqs)
+        for i, (s, t, fr, fid) in enumerate(reqs):
+            assert out[i].status == 0
+            assert same(out[i], refs[s][i % len(P[s])], streams[s].get("k", 8)), (i, s)
+    finally:
+        srv.close()
+
+
+def test_drops_and_poll(lane, synth):
+    say("serve drops + poll")
+    P = pools(synth, STREAMS[:2], seed=500)
+    refs = [[alone(lane, P[s][j], STREAMS[s]) for j in range(3)] for s in range(2)]
+    srv = lane.Server(STREAMS[:2], hbm_budget=1 << 30, max_pending=1)
+    try:
+        # six requests for stream 0 at once: one runs, one waits, the rest
+        # find the queue full
+        reqs = [(0, 0.0, P[0][i % 3], i) for i in range(6)]
+        out = srv.replay(reqs)
+        ok = [i for i in range(6) if out[i].status == 0]
+        dropped = [i for i in range(6) if out[i].status == lane.LANE_E_BUSY]
+        assert len(ok) + len(dropped) == 6 and len(ok) >= 1 and len(dropped) >= 1
+        for i in ok:
+            assert same(out[i], refs[0][i % 3], 8)
+        assert srv.stats()["dropped"] == len(dropped)
+        # poll interface
+        n = 0
+        for j in range(3):
+            assert srv.submit(1, P[1][j], frame_id=100 + j) == 0
+            got = srv.poll(8, wait_ms=5000)
+            for r in got:
+                assert r.status == 0 and same(r, refs[1][r.frame_id - 100], 8)
+                n += 1
+        while n < 3:
+            got = srv.poll(8, wait_ms=5000)
+            assert got, "poll timed out"
+            for r in got:
+                assert r.status == 0 and same(r, refs[1][r.frame_id - 100], 8)
+                n += 1
+    finally:
+        srv.close()
