@@ -8,8 +8,10 @@ The frames are resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput (Mpix/s; frames/s beside it), the
 roofline of the dominant kernel (the vote) measured live with HIP events on
-the launch stream, the Sobel pass's HBM roofline, single-frame latency, and
-the CPU oracle timed on a bounded sample of the same workload.
+the launch stream, the Sobel pass's HBM roofline, single-frame latency, the
+serving latency (p50/p99 over 16 camera streams with Poisson arrivals,
+continuous batching, plain and pruned path), and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -47,6 +49,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune-cache", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="length of each serving run, plain and pruned (0 = skip)")
+    ap.add_argument("--serve-pool", type=int, default=32, help="pre-generated frames per stream")
     return ap.parse_args()
 
 
@@ -103,6 +108,25 @@ def cpu_baseline(pool, C, S, budget_s):
                       f"{dt:.1f} s", "frames_per_s": round(n / dt, 4)}
 
 
+def serving(args):
+    """p50 / p99 latency (arrival to peaks in host memory) of the 16-stream
+    mix through the continuous-batching server, plain then pruned."""
+    from paper_2212_09460_amd import serve
+
+    res = {"streams": "8x1280x720 + 6x1920x1080 + 2x3840x2160, Poisson arrivals 30 Hz each",
+           "seconds": args.serve_seconds}
+    pools = None
+    for pruned in (False, True):
+        r, pools = serve.run(args.serve_seconds, pruned=pruned, pool=args.serve_pool, pools=pools,
+                             verbose=False)
+        res["pruned" if pruned else "plain"] = {
+            k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+            if k in ("p50_ms", "p99_ms", "max_ms", "frames_per_s", "gpx_per_s", "completed",
+                     "dropped", "mean_batch_frames", "per_size")}
+    res["p99_pruned_over_plain"] = round(res["pruned"]["p99_ms"] / res["plain"]["p99_ms"], 4)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -139,7 +163,7 @@ def main():
         frames.append(lane.FrameBuffers(img, W, N_THETA, TOPK, Cd, Sd))
     batch = lane.Batch(frames, tune=tune)
 
-    # correctness guard on one frame: edges and peaks against the oracle
+    # first launch outside the timed region
     batch.launch(stream)
     torch.cuda.synchronize()
 
@@ -174,10 +198,11 @@ def main():
     sobel_gbs = sobel_bytes / (t_sobel * 1e-3) / 1e9
     vote_gvotes = votes / (t_vote * 1e-3) / 1e9
 
-    # single-frame latency: a one-frame plan, each launch timed alone
+    # single-frame latency: a one-frame plan shaped for latency (one theta
+    # row per vote workgroup, 8-row Sobel strips), each launch timed alone
     lat = []
     if args.latency_iters > 0:
-        one = lane.Batch([frames[0]], tune=tune)
+        one = lane.Batch([frames[0]], vote_rows=1, vote_queue=1, sobel_strip_rows=8)
         for i in range(args.latency_iters + 5):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -231,11 +256,15 @@ def main():
                            "frac": round(sobel_gbs / HBM_PEAK_GBS, 4),
                            "traffic": profiled_traffic("k_sobel_batch", "sobel.hip") if B == 256 else None,
                            "bytes_per_launch": sobel_bytes},
-        "latency_ms_single_frame": {"p50": round(float(np.percentile(lat, 50)), 4),
-                                    "p99": round(float(np.percentile(lat, 99)), 4)},
+        "latency_ms_single_frame_gpu": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "wall_s_timed": round(wall, 3),
     }
     batch.close()
+    del frames, pool_d
+    torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        out["serving"] = serving(args)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(pool, C, S, args.cpu_seconds)
     print(json.dumps(out), flush=True)
