@@ -18,7 +18,8 @@
 // Compaction (the vote reads a list of edge coordinates, Sec. 4.3): after
 // every 8 rows each lane holds the 64-bit edge masks of its two 8x8 tiles.
 // Tile counts are prefix-summed across the wave (the segment offsets); each
-// lane then writes the coordinates of its two tiles' edge pixels in order.
+// lane places the coordinates of its two tiles' edge pixels in the wave's
+// LDS stage, and the wave writes the stage out with coalesced stores.
 #include "lane_internal.h"
 
 namespace lane {
@@ -200,8 +201,16 @@ __device__ __forceinline__ uint32_t raw_edge_bits(const RawRow& r, int x0, int W
 }
 
 // Writes one tile row (8 rows x this wave's 1024 columns) into the list.
+// Each lane first places its two tiles' coordinates in the wave's LDS
+// stage (at their final offsets), then the wave copies the stage out with
+// 128-bit stores, so every store instruction writes 1 KB of consecutive
+// entries instead of 64 scattered words.  A tile row with more than
+// kStageCap edges goes out in several passes.
+constexpr int kStageCap = 2048;
+
 __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListLayout& L, int chunk,
-                                                 int ty, uint64_t m0, uint64_t m1, int lane) {
+                                                 int ty, uint64_t m0, uint64_t m1, int lane,
+                                                 uint32_t* __restrict__ stage) {
     const uint32_t ca = (uint32_t)__popcll(m0);
     const uint32_t cb = (uint32_t)__popcll(m1);
     const uint32_t tot = ca + cb;
@@ -212,7 +221,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
         if (lane >= o) incl += t;
     }
     const uint32_t off = incl - tot;
-    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)incl, kWave - 1));
     const int seg = ty * L.nchunk + chunk;
     uint32_t* list = d.list;
     if (lane == 0) gst(list + seg, total);
@@ -221,24 +230,42 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     if (txa < L.tw) gst(info + txa, (ca << 16) | off);
     if (txa + 1 < L.tw) gst(info + txa + 1, (cb << 16) | (off + ca));
     if (total == 0) return;
-    // each lane writes its own run: tile a then tile b, row-major in a tile
-    uint32_t* dst = list + L.off_ent + (size_t)seg * kSegCap + off;
+    uint32_t* dst = list + L.off_ent + (size_t)seg * kSegCap;
     const uint32_t xa = (uint32_t)(txa * kTile);
     const uint32_t y0 = (uint32_t)(ty * kTile) << 16;
+    for (uint32_t p0 = 0; p0 < total; p0 += kStageCap) {
+        // this lane's run, tile a then tile b, row-major in a tile; only the
+        // entries of the current pass land in the stage
+        uint32_t e = off - p0;  // wraps for runs before the pass: then >= kStageCap
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
-        uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
-        const uint32_t base = y0 + ((uint32_t)((q & 1) * 4) << 16) + xa + (uint32_t)((q >> 1) * kTile);
-        while (m) {
-            const uint32_t b = (uint32_t)__builtin_ctz(m);
-            m &= m - 1u;
-            gst(dst++, base + ((b >> 3) << 16) + (b & 7u));
+        for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
+            uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
+            const uint32_t base = y0 + ((uint32_t)((q & 1) * 4) << 16) + xa + (uint32_t)((q >> 1) * kTile);
+            while (m) {
+                const uint32_t bit = (uint32_t)__builtin_ctz(m);
+                m &= m - 1u;
+                if (e < (uint32_t)kStageCap) stage[e] = base + ((bit >> 3) << 16) + (bit & 7u);
+                ++e;
+            }
         }
+        // the stage is read by other lanes of the same wave: order the LDS
+        // writes before the reads (one wave, so no workgroup barrier)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t n = min(total - p0, (uint32_t)kStageCap);
+        // whole 16-byte groups; the last may carry up to three stale words
+        // past the segment's count, inside the segment's capacity
+        for (uint32_t g = (uint32_t)lane * 4u; g < n; g += 4u * kWave)
+            gst4(dst + p0 + g, *reinterpret_cast<const u32x4*>(stage + g));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
 template <bool FAST, int MODE>
-__device__ void sobel_item(const SobelDesc& d, int item) {
+__device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ stage) {
     const int lane = threadIdx.x & (kWave - 1);
     const ListLayout L = list_layout(d.W, d.H);
     const int chunk = item % L.nchunk;
@@ -258,7 +285,7 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
         m1 |= (uint64_t)((bits >> 8) & 0xFFu) << (ly * 8);
     };
     auto flush = [&](int ty) {
-        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane);
+        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane, stage);
         m0 = 0;
         m1 = 0;
     };
@@ -318,9 +345,11 @@ __device__ void sobel_item(const SobelDesc& d, int item) {
 template <bool FAST, int MODE>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel(SobelDesc d, int n_items) {
-    const int item = blockIdx.x * kSobelWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int item = blockIdx.x * kSobelWaves + wave;
     if (item >= n_items) return;  // whole wave leaves; no barriers in this kernel
-    sobel_item<FAST, MODE>(d, item);
+    sobel_item<FAST, MODE>(d, item, s_stage + wave * kStageCap);
 }
 
 // Batched, persistent: each wave walks the (frame, item) table with a grid
@@ -329,6 +358,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
 template <bool FAST>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items, int n_items) {
+    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
     // wave-uniform indices, so the table and descriptor loads are scalar
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int it = blockIdx.x * kSobelWaves + wave; it < n_items; it += gridDim.x * kSobelWaves) {
@@ -336,7 +366,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
         if (w.x < 0) continue;
         const SobelDesc d = descs[w.x];
         if (!frame_on(d.active)) continue;
-        sobel_item<FAST, kModeSobel>(d, w.y);
+        sobel_item<FAST, kModeSobel>(d, w.y, s_stage + wave * kStageCap);
     }
 }
 
