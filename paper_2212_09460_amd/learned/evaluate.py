@@ -66,6 +66,20 @@ def lane_flags(segs, pt, pr, pn, n_theta, D, tol_px=8.0):
     return out
 
 
+def lanes_found(segs, pt, pr, pn, n_theta, D, k=4, tol_px=8.0):
+    """Per painted lane, whether one of the top-k peaks lies on it (both ends
+    of its centre segment within tol_px of the peak's line)."""
+    found = np.zeros(len(segs), bool)
+    for i in range(min(k, pn)):
+        th = pt[i] * math.pi / n_theta
+        c, s_ = math.cos(th), math.sin(th)
+        r = pr[i] - D
+        for j, (x0, y0, x1, y1) in enumerate(segs):
+            if max(abs(x0 * c + y0 * s_ - r), abs(x1 * c + y1 * s_ - r)) <= tol_px:
+                found[j] = True
+    return found
+
+
 class EvalPlans:
     def __init__(self, W, H, B, device="cuda"):
         self.W, self.H, self.B = W, H, B
@@ -97,7 +111,9 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
     rand_net = ProposalNet(seed=12345) if baselines else None
     gpool = ThreadPoolExecutor(max_workers=workers)
     stream = torch.cuda.current_stream()
-    agg = dict(m4=0, n4=0, m8=0, n8=0, l4=0, ln4=0, l8=0, ln8=0, votes_plain=0, votes_pruned=0, tiles=0, t_skip=0,
+    agg = dict(m4=0, n4=0, m8=0, n8=0, l4=0, ln4=0, l8=0, ln8=0, lanes=0, lanes_solid=0,
+               found_plain=0, found_pruned=0, found_plain_solid=0, found_pruned_solid=0,
+               votes_plain=0, votes_pruned=0, tiles=0, t_skip=0,
                t_fall=0, t_band=0, ms_plain=0.0, ms_pruned=0.0, ms_cnn=0.0, frames=0)
     rnd = dict(m4=0, n4=0, m8=0, n8=0, votes=0)
     heur_stats = []  # per frame: (tile counts, plain peaks) for the budget-matched heuristic
@@ -163,11 +179,22 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
             a, n = agreement_counts(pt, pr, pn, qt, qr, qn, 8, N_THETA, P.D, only=lf)
             agg["l8"] += a
             agg["ln8"] += n
+            fp = lanes_found(segs, pt, pr, pn, N_THETA, P.D)
+            fq = lanes_found(segs, qt, qr, qn, N_THETA, P.D)
+            solid = np.zeros(len(segs), bool)
+            solid[[0, len(segs) - 1]] = True
+            agg["lanes"] += len(segs)
+            agg["lanes_solid"] += int(solid.sum())
+            agg["found_plain"] += int(fp.sum())
+            agg["found_pruned"] += int(fq.sum())
+            agg["found_plain_solid"] += int((fp & solid).sum())
+            agg["found_pruned_solid"] += int((fq & solid).sum())
             agg["votes_plain"] += int(P.plain[b].counters[0].item()) * N_THETA
             agg["votes_pruned"] += int(P.pruned[b].acc.sum().item())
             agg["frames"] += 1
             if baselines and bi < max(1, nb // 4):
-                heur_stats.append((P.tile_counts(b).cpu().numpy(), (pt, pr, pn), frames[b]))
+                heur_stats.append((P.tile_counts(b).cpu().numpy(), (pt, pr, pn), frames[b],
+                                   synth.lane_segments(scene, seeds[b])))
         if baselines:
             rl = rand_net.forward(P.imgs, stream=stream)
             rm = torch.empty_like(P.mask)
@@ -197,6 +224,10 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
         lane_share_top8=agg["ln8"] / max(1, agg["n8"]),
         agreement_top4_lane_peaks=agg["l4"] / max(1, agg["ln4"]),
         agreement_top8_lane_peaks=agg["l8"] / max(1, agg["ln8"]),
+        lanes_found_top4_plain=agg["found_plain"] / max(1, agg["lanes"]),
+        lanes_found_top4_pruned=agg["found_pruned"] / max(1, agg["lanes"]),
+        solid_lanes_found_top4_plain=agg["found_plain_solid"] / max(1, agg["lanes_solid"]),
+        solid_lanes_found_top4_pruned=agg["found_pruned_solid"] / max(1, agg["lanes_solid"]),
         missed_top4=1 - agg["m4"] / max(1, agg["n4"]),
         missed_top8=1 - agg["m8"] / max(1, agg["n8"]),
         votes_fraction=frac,
@@ -230,6 +261,7 @@ def heuristic_at_budget(P, stats, frac):
         tau = 65
     m4 = n4 = m8 = n8 = 0
     votes = 0
+    found = lanes = 0
     B = P.B
     for i0 in range(0, len(stats), B):
         chunk = stats[i0:i0 + B]
@@ -252,9 +284,13 @@ def heuristic_at_budget(P, stats, frac):
             m8 += a
             n8 += n
             votes += int(P.pruned[b].acc.sum().item())
+            f = lanes_found(c[3], qt, qr, qn, N_THETA, P.D)
+            found += int(f.sum())
+            lanes += len(f)
     plain_votes = int(counts.sum()) * N_THETA
     return dict(tau=tau, agreement_top4=m4 / max(1, n4), agreement_top8=m8 / max(1, n8),
-                votes_fraction=votes / max(1, plain_votes), frames=len(stats))
+                votes_fraction=votes / max(1, plain_votes), frames=len(stats),
+                lanes_found_top4=found / max(1, lanes))
 
 
 def main():

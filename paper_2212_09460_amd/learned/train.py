@@ -61,7 +61,10 @@ def lr_at(step, total, lr0, lr_min):
 
 def train(n_frames=20000, batch=16, lr=2e-3, lr_min=1e-4, seed_base=1_000_000, out=None,
           resume=None, log_every=50, ckpt_every=250, workers=16, init_seed=0, max_seconds=None,
-          verbose=True):
+          verbose=True, epochs=1):
+    """Adam over `epochs` passes of the n_frames training frames (the same
+    seeds each pass, each seed always at the same size), cosine LR decay over
+    all steps."""
     dev = torch.device("cuda")
     if resume and os.path.exists(resume):
         net, meta = ProposalNet.load(resume)
@@ -69,7 +72,8 @@ def train(n_frames=20000, batch=16, lr=2e-3, lr_min=1e-4, seed_base=1_000_000, o
     else:
         net, start = ProposalNet(seed=init_seed), 0
     plans = {sz: LabelPlan(sz[0], sz[1], batch, dev) for sz in SIZES}
-    total = n_frames // batch
+    per_epoch = n_frames // batch
+    total = per_epoch * epochs
     pool = ThreadPoolExecutor(max_workers=workers)
     nxt = None
     t0 = time.time()
@@ -77,15 +81,15 @@ def train(n_frames=20000, batch=16, lr=2e-3, lr_min=1e-4, seed_base=1_000_000, o
     hist = []
 
     def submit(step):
-        W, H = SIZES[step % 2]
-        seeds = [seed_base + step * batch + i for i in range(batch)]
+        W, H = SIZES[(step % per_epoch) % 2]
+        seeds = [seed_base + (step % per_epoch) * batch + i for i in range(batch)]
         return pool.submit(gen_batch, pool_gen, W, H, seeds)
 
     pool_gen = ThreadPoolExecutor(max_workers=workers)
     if start < total:
         nxt = submit(start)
     for step in range(start, total):
-        W, H = SIZES[step % 2]
+        W, H = SIZES[(step % per_epoch) % 2]
         frames = nxt.result()
         nxt = submit(step + 1) if step + 1 < total else None
         p = plans[(W, H)]
@@ -125,9 +129,10 @@ def main():
     ap.add_argument("--resume", default=None)
     ap.add_argument("--max-seconds", type=float, default=None)
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=1)
     a = ap.parse_args()
     train(a.frames, a.batch, a.lr, out=a.out, resume=a.resume, max_seconds=a.max_seconds,
-          workers=a.workers)
+          workers=a.workers, epochs=a.epochs)
 
 
 if __name__ == "__main__":
