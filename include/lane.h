@@ -201,6 +201,12 @@ int lane_batch_launch_stage(lane_batch *b, int32_t stage, void *stream);
  * keeps its previous outputs and counters.  The caller may rewrite the
  * switches between launches with stream-ordered copies. */
 int lane_batch_active_flags(lane_batch *b, uint8_t **flags);
+/* Select the frames the next launches run (active: host uint8 [n], non-zero
+ * = run): enqueues on `stream` the copies of the switches and of work lists
+ * holding only those frames' items, so switched-off frames cost nothing.
+ * The copies come from page-locked staging owned by the plan: call again only
+ * after the launches this selection served have completed. */
+int lane_batch_select(lane_batch *b, const uint8_t *active, void *stream);
 /* Frees the plan's device table and graph (waits for nothing: the caller
  * must make sure no launch of this plan is still running). */
 int lane_batch_destroy(lane_batch *b);
@@ -241,6 +247,11 @@ int lane_cnn_pack(const float *params, void *packed, void *stream);
  * activations kept in `act` for the backward; logits device float. */
 int lane_cnn_forward(const uint8_t *img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
                      int32_t batch, const void *packed, void *act, float *logits, void *stream);
+/* Inference only, same logits as lane_cnn_forward (bit-identical): all
+ * four layers fused per 8x8 block of logits with the intermediate
+ * activations in LDS, so it needs no activation workspace. */
+int lane_cnn_infer(const uint8_t *img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                   int32_t batch, const void *packed, float *logits, void *stream);
 /* Per frame: loss = mean over tiles of BCE(keep) + mean over keep tiles of
  * the mean over bands of BCE(band) -> loss[b] (device float); writes
  * scale * dloss/dlogits into `act` for the backward.  keep: device uint8
@@ -338,8 +349,8 @@ typedef struct lane_server_stats {
 typedef struct lane_server lane_server;
 
 /* Host only, no device calls.  Admission: streams are taken in order and
- * admitted while the device bytes of the admitted ones (their state, their
- * share of the class's network activations, shared tables and weights) stay
+ * admitted while the device bytes of the admitted ones (their state, shared
+ * tables and network weights) stay
  * within hbm_budget.  admitted (host uint8 [n], 1/0), stream_bytes (host
  * size_t [n], each stream's added bytes) and total_bytes may be NULL. */
 int lane_server_plan(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,

@@ -22,13 +22,15 @@
 
 using namespace lane;
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
-                                              int fast, int grid, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items,
+                                                            const int* counts, int fast, int grid,
+                                                            hipStream_t s);
 extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy();
 extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows);
 extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode);
-extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
-                                             uint32_t* queue, int half_lds, int grid, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items,
+                                                           const int* n_items, uint32_t* queue,
+                                                           int half_lds, int grid, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
                                               int total_blocks, int grid_keys, int grid_select,
                                               hipStream_t s);
@@ -65,6 +67,13 @@ struct lane_batch {
     uint32_t** d_counters = nullptr;
     uint32_t* d_queue = nullptr;
     uint8_t* d_active = nullptr;   // one flag per frame, 1 after creation
+    int* d_counts = nullptr;       // items to run: Sobel aligned, Sobel other, vote
+    // host copies of the full work tables, for lane_batch_select
+    std::vector<int2> h_sitems, h_vitems;
+    std::vector<int> h_sfirst, h_scount;   // per frame: its Sobel items (contiguous)
+    std::vector<int> h_vfirst, h_vcount;   // per frame: its vote items, -1 first if interleaved
+    std::vector<int> h_sgroup;             // per frame: 0 aligned, 1 other
+    char* h_stage = nullptr;               // page-locked staging for the selection copies
     int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0, total_blocks = 0;
     int grid_sobel = 1, grid_sobel_slow = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
     bool vote_dynamic = false;
@@ -114,11 +123,12 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
             return hipGetLastError();
         case 1: {
             // aligned frames first (vector loads), then the rest
-            const hipError_t e = lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->n_sobel_fast, 1,
-                                                         b->grid_sobel, s);
-            if (e != hipSuccess) return e;
-            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items + b->n_sobel_fast,
-                                           b->n_sobel_items - b->n_sobel_fast, 0, b->grid_sobel_slow, s);
+            hipError_t e = hipSuccess;
+            if (b->n_sobel_fast > 0)
+                e = lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 1, b->grid_sobel, s);
+            if (e != hipSuccess || b->n_sobel_items == b->n_sobel_fast) return e;
+            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 0,
+                                           b->grid_sobel_slow, s);
         }
         case 2:
             if (b->vote_dynamic) {
@@ -127,7 +137,7 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
-            return lane_launch_vote_batch(b->d_vote, b->d_vote_items, b->n_vote_items,
+            return lane_launch_vote_batch(b->d_vote, b->d_vote_items, b->d_counts + 2,
                                           b->vote_dynamic ? b->d_queue : nullptr, b->vote_half_lds,
                                           b->grid_vote, s);
         case 3:
@@ -143,6 +153,7 @@ void free_plan(lane_batch* b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     if (b->dmem) hipFree(b->dmem);
+    if (b->h_stage) hipHostFree(b->h_stage);
     delete b;
 }
 
@@ -295,6 +306,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_cnt = off; off = al(off + sizeof(uint32_t*) * n);
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
     const size_t o_active = off; off = al(off + (size_t)n);
+    const size_t o_counts = off; off = al(off + sizeof(int) * 4);
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -309,6 +321,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->d_counters = (uint32_t**)(base + o_cnt);
     b->d_queue = (uint32_t*)(base + o_queue);
     b->d_active = (uint8_t*)(base + o_active);
+    b->d_counts = (int*)(base + o_counts);
     for (int i = 0; i < n; ++i) {
         sd[i].active = b->d_active + i;
         vd[i].active = b->d_active + i;
@@ -324,6 +337,36 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 4) == hipSuccess;
     ok = ok && hipMemset(b->d_active, 1, (size_t)n) == hipSuccess;
+    const int counts0[4] = {n_fast, b->n_sobel_items - n_fast, b->n_vote_items, 0};
+    ok = ok && hipMemcpy(b->d_counts, counts0, sizeof(counts0), hipMemcpyHostToDevice) == hipSuccess;
+    // host copies for lane_batch_select: per-frame item ranges
+    b->h_sitems = sitems;
+    b->h_vitems = vitems;
+    b->h_sfirst.assign(n, 0);
+    b->h_scount.assign(n, 0);
+    b->h_sgroup.assign(n, 0);
+    for (int i = (int)sitems.size() - 1; i >= 0; --i) {
+        const int f = sitems[i].x;
+        b->h_sfirst[f] = i;
+        b->h_scount[f] += 1;
+        b->h_sgroup[f] = i >= n_fast ? 1 : 0;
+    }
+    b->h_vfirst.assign(n, -1);
+    b->h_vcount.assign(n, 0);
+    for (int i = (int)vitems.size() - 1; i >= 0; --i) {
+        const int f = vitems[i].x;
+        if (f < 0) continue;
+        b->h_vfirst[f] = i;
+        b->h_vcount[f] += 1;
+    }
+    for (int f = 0; f < n; ++f) {  // a frame's vote items need not be contiguous (static layout)
+        const int a = b->h_vfirst[f], c = b->h_vcount[f];
+        if (a < 0) continue;
+        for (int i = a; i < a + c && b->h_vfirst[f] >= 0; ++i)
+            if (vitems[i].x != f) b->h_vfirst[f] = -2;
+    }
+    const size_t stage_bytes = (((size_t)n + 15) & ~(size_t)15) + 16 + sizeof(int2) * (sitems.size() + vitems.size());
+    ok = ok && hipHostMalloc((void**)&b->h_stage, al(stage_bytes), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -371,6 +414,56 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
 int lane_batch_launch(lane_batch* b, void* stream) {
     if (!b || !b->exec) return LANE_E_ARG;
     return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_batch_select(lane_batch* b, const uint8_t* active, void* stream) {
+    if (!b || !active) return LANE_E_ARG;
+    const int n = b->n;
+    // staging: flags | counts | Sobel items (aligned group, then the other) | vote items
+    uint8_t* fl = (uint8_t*)b->h_stage;
+    int* cnt = (int*)(b->h_stage + ((n + 15) & ~15));
+    int2* si = (int2*)(cnt + 4);
+    int2* vi = si + b->h_sitems.size();
+    int ns[2] = {0, 0};
+    for (int g = 0; g < 2; ++g) {
+        int* dst = &ns[g];
+        for (int f = 0; f < n; ++f) {
+            fl[f] = active[f] ? 1 : 0;
+            if (!fl[f] || b->h_sgroup[f] != g || b->h_scount[f] == 0) continue;
+            memcpy(si + ns[0] * (g == 1) + *dst, b->h_sitems.data() + b->h_sfirst[f],
+                   sizeof(int2) * b->h_scount[f]);
+            *dst += b->h_scount[f];
+        }
+    }
+    int nv = 0;
+    bool contiguous = true;
+    for (int f = 0; f < n; ++f) contiguous = contiguous && b->h_vfirst[f] != -2;
+    if (contiguous) {
+        // frames in table order (the table is sorted by cost; keep that order)
+        std::vector<std::pair<int, int>> order;
+        for (int f = 0; f < n; ++f)
+            if (fl[f] && b->h_vcount[f] > 0) order.push_back({b->h_vfirst[f], f});
+        std::sort(order.begin(), order.end());
+        for (auto& o : order) {
+            memcpy(vi + nv, b->h_vitems.data() + o.first, sizeof(int2) * b->h_vcount[o.second]);
+            nv += b->h_vcount[o.second];
+        }
+    } else {
+        for (const int2& it : b->h_vitems)
+            if (it.x >= 0 && fl[it.x]) vi[nv++] = it;
+    }
+    cnt[0] = ns[0];
+    cnt[1] = ns[1];
+    cnt[2] = nv;
+    cnt[3] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->d_active, fl, (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_counts, cnt, sizeof(int) * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && ns[0] + ns[1] > 0)
+        e = hipMemcpyAsync(b->d_sobel_items, si, sizeof(int2) * (ns[0] + ns[1]), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nv > 0)
+        e = hipMemcpyAsync(b->d_vote_items, vi, sizeof(int2) * nv, hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? LANE_OK : LANE_E_DEVICE;
 }
 
 int lane_batch_active_flags(lane_batch* b, uint8_t** flags) {

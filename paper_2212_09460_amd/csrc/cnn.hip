@@ -20,6 +20,8 @@
 // Master parameters are FP32 in the flat order: for each layer the weights
 // [c_out][c_in][3][3] then the biases [c_out] (6105 values).
 #include <math.h>
+
+#include <algorithm>
 #include <string.h>
 
 #include "lane_internal.h"
@@ -182,6 +184,242 @@ __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
             if (co < 9)
                 gst(p.logits + (((size_t)b * 9 + co) * Ho + oy) * Wo + ox, acc[j] + bias[co]);
         }
+    }
+}
+
+// ------------------------------------------------------- fused inference --
+// Forward only, all four layers in one workgroup per 8x8 block of head
+// outputs: the input window (87x87 bytes) and the conv1 / conv2 / conv3
+// activations the block needs (43x43, 21x21, 10x10 pixels, halo included)
+// stay in LDS, so nothing but the frame and the logits touches HBM.  Every
+// layer issues the same MFMA sequence on the same FP16 values as the
+// layer-by-layer kernels above, so the logits are bit-identical to theirs.
+// Positions outside a layer's output are stored as zero: they are the next
+// layer's zero padding.
+//
+// LDS: windows read at stride 2 (conv1 and conv2 outputs) keep even columns
+// before odd ones, so a 16-lane stride-2 read touches 16 consecutive pixels
+// (each bank four times for 64-bit reads, the minimum); the input window
+// shares its space with the conv2 window (it is dead by then).  76 KB per
+// workgroup: two workgroups per CU.  The next block's input bytes are
+// loaded into registers while the current block computes.
+constexpr int kFT = 8;                // head outputs per block side
+constexpr int kR3 = kFT + 2;          // conv3 window side
+constexpr int kR2 = 2 * kR3 + 1;      // conv2 window side
+constexpr int kR1 = 2 * kR2 + 1;      // conv1 window side
+constexpr int kR0 = 2 * kR1 + 1;      // input window side
+constexpr int kInferThreads = 512;
+constexpr int kR0PerThread = (kR0 * kR0 + kInferThreads - 1) / kInferThreads;
+
+struct CnnInfer {
+    const uint8_t* img;
+    int W, H, pitch;
+    long long img_stride;
+    const void* pk;
+    float* logits;             // [B][9][H3][W3]
+    int H1, W1, H2, W2, H3, W3;
+    int bx, by;                // blocks per frame along x / y
+    int batch;
+    const uint8_t* active;     // frame b runs iff active[b] != 0 (null = all)
+};
+
+// column of pixel x in a window of side n stored even columns first
+__device__ __forceinline__ int deint(int x, int n) { return (x & 1) ? ((n + 1) >> 1) + (x >> 1) : (x >> 1); }
+
+// The 9 weight tiles of a layer for this lane (A operands), kept in registers.
+struct Taps {
+    h4 a[9];
+};
+__device__ __forceinline__ Taps load_taps(const _Float16* __restrict__ w, int col, int grp) {
+    Taps t;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) t.a[tap] = ld_h4(w + (tap * 16 + col) * 16 + 4 * grp);
+    return t;
+}
+
+// One 16-pixel x 16-channel MFMA tile of a 16-channel layer from an LDS
+// window of side RIN.  `base` addresses input row STRIDE * ly, column
+// lx (stride 2: the window is de-interleaved, so tap kx = 0 / 2 read
+// columns lx / lx + 1 of the even half and kx = 1 column lx of the odd
+// half); every tap is then a constant offset from base.
+template <int STRIDE, int RIN>
+__device__ __forceinline__ f4 conv16_lds(const _Float16* __restrict__ in, int base, const Taps& w) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap % 3;
+        const int off = STRIDE == 2 ? (ky * RIN + ((kx & 1) ? (RIN + 1) / 2 : 0) + (kx >> 1)) * 16
+                                    : (ky * RIN + kx) * 16;
+        const h4 B = *reinterpret_cast<const h4*>(in + base + off);
+        acc = mfma16(w.a[tap], B, acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void put_relu(_Float16* __restrict__ out, int rout, bool de, int ly, int lx,
+                                         bool inside, f4 acc, const float* bias, int grp) {
+    h4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        o[j] = inside ? (_Float16)fmaxf(acc[j] + bias[4 * grp + j], 0.f) : (_Float16)0;
+    const int cx = de ? deint(lx, rout) : lx;
+    *reinterpret_cast<h4*>(out + (ly * rout + cx) * 16 + 4 * grp) = o;
+}
+
+__global__ void __launch_bounds__(kInferThreads) k_cnn_infer(CnnInfer p) {
+    __shared__ __align__(16) _Float16 r1[kR1 * kR1 * 16];
+    __shared__ __align__(16) _Float16 r2[kR2 * kR2 * 16];  // the input window lives here first
+    __shared__ __align__(16) _Float16 r3[kR3 * kR3 * 16];
+    uint8_t* r0 = reinterpret_cast<uint8_t*>(r2);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kInferThreads / 64;
+    const int col = lane & 15, grp = lane >> 4;
+    const int nblk = p.bx * p.by;
+    const _Float16* wk = pk_h(p.pk);
+    // the work: (frame, block) pairs of switched-on frames, grid stride
+    auto next = [&](int b, int blk, int& nb, int& nblk_out) {
+        int f = b, k = blk + (int)gridDim.x;
+        while (f < p.batch) {
+            if (k < nblk && (!p.active || gld(p.active + f) != 0)) break;
+            ++f;
+            k = blockIdx.x;
+        }
+        nb = f;
+        nblk_out = k;
+    };
+    // a block's input bytes, four per register
+    constexpr int kPacked = (kR0PerThread + 3) / 4;
+    auto fetch = [&](int b, int blk, uint32_t (&v)[kPacked]) {
+        const int TY = blk / p.bx, TX = blk - TY * p.bx;
+        // input window origin 2 Y1 - 1 = 8 Y4 - 15 (Y1 = 2 Y2 - 1, Y2 = 2 Y3 - 1, Y3 = Y4 - 1)
+        const int Y0 = 8 * TY * kFT - 15, X0 = 8 * TX * kFT - 15;
+        const uint8_t* img = p.img + (size_t)b * p.img_stride;
+        uint32_t t[kR0PerThread];
+#pragma unroll
+        for (int u = 0; u < kR0PerThread; ++u) {
+            const int i = tid + u * kInferThreads;
+            const int y = Y0 + i / kR0, x = X0 + i % kR0;
+            const bool in = i < kR0 * kR0 && y >= 0 && y < p.H && x >= 0 && x < p.W;
+            t[u] = gld(img + (in ? (size_t)y * p.pitch + x : 0));
+            if (!in) t[u] = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kPacked; ++q) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (4 * q + k < kR0PerThread) w |= t[4 * q + k] << (8 * k);
+            v[q] = w;
+        }
+    };
+    // conv1 taps of this lane: K index 4 grp + j is tap 4 grp + j (taps 9..15
+    // have zero weights, so whatever finite value they read adds nothing)
+    int off1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int tap = min(4 * grp + j, 8);
+        off1[j] = (tap / 3) * kR0 + tap % 3 + 2 * col;
+    }
+    const h4 A1 = ld_h4(wk + kPkW1 + col * 16 + 4 * grp);
+    const Taps T2 = load_taps(wk + kPkW2, col, grp);
+    int b, blk;
+    next(0, (int)blockIdx.x - (int)gridDim.x, b, blk);
+    uint32_t v[kPacked];
+    if (b < p.batch) fetch(b, blk, v);
+    while (b < p.batch) {
+        const int TY = blk / p.bx, TX = blk - TY * p.bx;
+        const int Y4 = TY * kFT, X4 = TX * kFT;
+        const int Y3 = Y4 - 1, X3 = X4 - 1;
+        const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1;
+        const int Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1;
+#pragma unroll
+        for (int u = 0; u < kR0PerThread; ++u)
+            if (tid + u * kInferThreads < kR0 * kR0)
+                r0[tid + u * kInferThreads] = (uint8_t)(v[u >> 2] >> (8 * (u & 3)));
+        int nb, nblk2;
+        next(b, blk, nb, nblk2);
+        __syncthreads();
+        {  // conv1: K = the 9 taps of the single input channel
+            const float* bias = pk_bias(p.pk, 0);
+            constexpr int nxg = (kR1 + 15) / 16;
+            for (int task = wave; task < kR1 * nxg; task += nw) {
+                const int ly = task / nxg, xg = task - ly * nxg;
+                const int lx = xg * 16 + col;
+                const int base = 2 * ly * kR0 + 32 * xg;
+                h4 B;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    B[j] = (_Float16)((float)r0[min(base + off1[j], kR0 * kR0 - 1)] * (1.0f / 255.0f));
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mfma16(A1, B, acc);
+                const int y1 = Y1 + ly, x1 = X1 + lx;
+                if (lx < kR1)
+                    put_relu(r1, kR1, true, ly, lx, y1 >= 0 && y1 < p.H1 && x1 >= 0 && x1 < p.W1, acc,
+                             bias, grp);
+            }
+        }
+        // the next block's input bytes travel while this one computes
+        if (nb < p.batch) fetch(nb, nblk2, v);
+        __syncthreads();
+        {  // conv2, two tiles per wave at a time (independent MFMA chains)
+            const float* bias = pk_bias(p.pk, 1);
+            constexpr int nxg = (kR2 + 15) / 16;
+            constexpr int ntask = kR2 * nxg;
+            for (int t0 = wave; t0 < ntask; t0 += 2 * nw) {
+                const int t1 = min(t0 + nw, ntask - 1);
+                const int ly0 = t0 / nxg, lx0 = (t0 - ly0 * nxg) * 16 + col;
+                const int ly1 = t1 / nxg, lx1 = (t1 - ly1 * nxg) * 16 + col;
+                // columns past the window read a clamped in-window pixel; their
+                // outputs are dropped (a lane's column only feeds its own output)
+                const int b0 = (2 * ly0 * kR1 + min(lx0, kR2 - 1)) * 16 + 4 * grp;
+                const int b1 = (2 * ly1 * kR1 + min(lx1, kR2 - 1)) * 16 + 4 * grp;
+                const f4 a0 = conv16_lds<2, kR1>(r1, b0, T2);
+                const f4 a1 = conv16_lds<2, kR1>(r1, b1, T2);
+                const int y20 = Y2 + ly0, x20 = X2 + lx0, y21 = Y2 + ly1, x21 = X2 + lx1;
+                if (lx0 < kR2)
+                    put_relu(r2, kR2, true, ly0, lx0, y20 >= 0 && y20 < p.H2 && x20 >= 0 && x20 < p.W2,
+                             a0, bias, grp);
+                if (t0 + nw < ntask && lx1 < kR2)
+                    put_relu(r2, kR2, true, ly1, lx1, y21 >= 0 && y21 < p.H2 && x21 >= 0 && x21 < p.W2,
+                             a1, bias, grp);
+            }
+        }
+        __syncthreads();
+        {  // conv3
+            const Taps T3 = load_taps(wk + kPkW3, col, grp);
+            const float* bias = pk_bias(p.pk, 2);
+            for (int ly = wave; ly < kR3; ly += nw) {
+                const int lx = col;
+                const int base = (2 * ly * kR2 + min(lx, kR3 - 1)) * 16 + 4 * grp;
+                const f4 acc = conv16_lds<2, kR2>(r2, base, T3);
+                const int y3 = Y3 + ly, x3 = X3 + lx;
+                if (lx < kR3)
+                    put_relu(r3, kR3, false, ly, lx, y3 >= 0 && y3 < p.H3 && x3 >= 0 && x3 < p.W3, acc,
+                             bias, grp);
+            }
+        }
+        __syncthreads();
+        {  // head: logits, no ReLU
+            const Taps T4 = load_taps(wk + kPkW4, col, grp);
+            const float* bias = pk_bias(p.pk, 3);
+            for (int ly = wave; ly < kFT; ly += nw) {
+                const int lx = col;
+                const int base = (ly * kR3 + min(lx, kFT - 1)) * 16 + 4 * grp;
+                const f4 acc = conv16_lds<1, kR3>(r3, base, T4);
+                const int y4 = Y4 + ly, x4 = X4 + lx;
+                if (lx < kFT && y4 < p.H3 && x4 < p.W3) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int co = 4 * grp + j;
+                        if (co < 9)
+                            gst(p.logits + (((size_t)b * 9 + co) * p.H3 + y4) * p.W3 + x4,
+                                acc[j] + bias[co]);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the windows are rewritten by the next block
+        b = nb;
+        blk = nblk2;
     }
 }
 
@@ -668,6 +906,47 @@ LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t
     hipLaunchKernelGGL(k_cnn_fwd16, dim3((waves(g.H3, g.W3) + 3) / 4), dim3(256), 0, s, p, 2);
     hipLaunchKernelGGL(k_cnn_fwd16, dim3((waves(g.H3, g.W3) + 3) / 4), dim3(256), 0, s, p, 3);
     return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+// Inference with per-frame switches (device uint8 [batch] or null): one
+// persistent launch of the fused kernel; switched-off frames are skipped
+// whole and keep their previous logits.
+LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                        int64_t img_stride, int32_t batch, const void* packed,
+                                        float* logits, const uint8_t* active, void* stream) {
+    if (!img || !packed || !logits || W < 1 || H < 1 || pitch < W || batch < 1 ||
+        img_stride < (int64_t)H * pitch || !a16(packed))
+        return LANE_E_ARG;
+    if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    const Geo g = geo(W, H);
+    CnnInfer p;
+    memset(&p, 0, sizeof(p));
+    p.img = img;
+    p.W = W;
+    p.H = H;
+    p.pitch = pitch;
+    p.img_stride = img_stride;
+    p.pk = packed;
+    p.logits = logits;
+    p.H1 = g.H1; p.W1 = g.W1; p.H2 = g.H2; p.W2 = g.W2; p.H3 = g.H3; p.W3 = g.W3;
+    p.bx = (g.W3 + kFT - 1) / kFT;
+    p.by = (g.H3 + kFT - 1) / kFT;
+    p.batch = batch;
+    p.active = active;
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // blocks of one frame spread over the chip (two workgroups per CU);
+    // frames run one after another
+    const int grid = std::max(1, std::min(p.bx * p.by, 2 * cus));
+    hipLaunchKernelGGL(k_cnn_infer, dim3(grid), dim3(kInferThreads), 0, (hipStream_t)stream, p);
+    return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+int lane_cnn_infer(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,
+                   int32_t batch, const void* packed, float* logits, void* stream) {
+    return lane_cnn_infer_active(img, W, H, pitch, img_stride, batch, packed, logits, nullptr,
+                                 stream);
 }
 
 int lane_cnn_loss(const float* logits, const uint8_t* keep, const uint8_t* bands, int32_t W,

@@ -34,10 +34,9 @@
 #include "lane_internal.h"
 
 extern "C" {
-LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
-                                          int64_t img_stride, int32_t batch, const void* packed,
-                                          void* act, float* logits, const uint8_t* active,
-                                          void* stream);
+LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                        int64_t img_stride, int32_t batch, const void* packed,
+                                        float* logits, const uint8_t* active, void* stream);
 LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
                                                int32_t batch, float conf, uint8_t* mask,
                                                const uint8_t* active, void* stream);
@@ -77,8 +76,8 @@ ClassKey key_of(const lane_stream_cfg& c) {
     return ClassKey(c.W, c.H, c.n_theta, c.k, c.threshold, c.border_mode);
 }
 
-// Device bytes of one stream's own buffers (the class's proposal activations
-// are counted separately because they grow with the class size).
+// Device bytes of one stream's buffers (the fused proposal network needs no
+// activation workspace).
 struct StreamSizes {
     size_t img, edges, list, acc, peaks, peaks_ws, counters, mask, logits;
     size_t total() const {
@@ -109,12 +108,6 @@ StreamSizes stream_sizes(const lane_stream_cfg& c, int pruned) {
     return z;
 }
 
-size_t act_bytes(const lane_stream_cfg& c, int n) {
-    if (n <= 0) return 0;
-    size_t a = 0;
-    lane_cnn_sizes(c.W, c.H, n, nullptr, &a, nullptr);
-    return al256(a);
-}
 
 // Admission in stream order; returns the device bytes of everything the
 // server allocates for the admitted streams (tables and weights included).
@@ -134,7 +127,6 @@ size_t plan_admission(const lane_stream_cfg* s, int n, const lane_server_cfg& cf
         const ClassKey k = key_of(s[i]);
         const int c = count.count(k) ? count[k] : 0;
         size_t add = z.total();
-        if (cfg.pruned) add += act_bytes(s[i], c + 1) - act_bytes(s[i], c);
         if (!thetas.count(s[i].n_theta)) add += al256(sizeof(int16_t) * 2 * (size_t)s[i].n_theta);
         if (stream_bytes) stream_bytes[i] = add;
         const bool ok = total + add <= cfg.hbm_budget;
@@ -172,7 +164,6 @@ struct lane_server {
         uint8_t* img;
         uint8_t* mask;
         float* logits;
-        void* act;
     };
     std::vector<Class> classes;
     std::vector<int> class_of;             // slot -> class
@@ -182,7 +173,7 @@ struct lane_server {
     size_t dbytes = 0;
     int32_t* h_peaks = nullptr;            // pinned, per slot (3k+1) at h_peak_off[slot]
     std::vector<size_t> h_peak_off;
-    uint8_t* h_flags = nullptr;            // pinned, one per slot
+    uint8_t* h_flags = nullptr;            // one per slot
     uint8_t* d_flags = nullptr;            // the plan's flags
     lane_batch* plan = nullptr;
     hipStream_t stream = nullptr;
@@ -227,14 +218,19 @@ int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_re
     const int n_slots = (int)s->streams.size();
     memset(s->h_flags, 0, (size_t)n_slots);
     for (const Req& q : batch) s->h_flags[s->slot_of[q.stream]] = 1;
-    hipError_t e = hipMemcpyAsync(s->d_flags, s->h_flags, (size_t)n_slots, hipMemcpyHostToDevice,
-                                  s->stream);
+    // switches and the work lists of exactly these slots
+    hipError_t e = lane_batch_select(s->plan, s->h_flags, s->stream) == LANE_OK ? hipSuccess
+                                                                                : hipErrorUnknown;
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const Req& q = batch[i];
         const int slot = s->slot_of[q.stream];
         const lane_server::Class& c = s->classes[s->class_of[slot]];
-        e = hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch,
-                             (size_t)c.cfg.W, (size_t)c.cfg.H, hipMemcpyHostToDevice, s->stream);
+        if (q.pitch == c.cfg.W && c.pitch == c.cfg.W)  // one contiguous copy
+            e = hipMemcpyAsync(s->slot_img[slot], q.frame, (size_t)c.cfg.W * c.cfg.H,
+                               hipMemcpyHostToDevice, s->stream);
+        else
+            e = hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch,
+                                 (size_t)c.cfg.W, (size_t)c.cfg.H, hipMemcpyHostToDevice, s->stream);
     }
     if (e == hipSuccess) e = hipGraphLaunch(s->exec, s->stream);
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
@@ -435,8 +431,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     for (int i = 0; i < n_slots; ++i) sz[i] = stream_sizes(s->streams[i], cfg->pruned);
     std::map<int, size_t> trig_off;
     size_t off = 0;
-    std::vector<size_t> o_img(s->classes.size()), o_mask(s->classes.size()), o_log(s->classes.size()),
-        o_act(s->classes.size());
+    std::vector<size_t> o_img(s->classes.size()), o_mask(s->classes.size()), o_log(s->classes.size());
     for (size_t c = 0; c < s->classes.size(); ++c) {
         const auto& cl = s->classes[c];
         const StreamSizes& z = sz[cl.first_slot];
@@ -446,8 +441,6 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         off += z.mask * cl.n;
         o_log[c] = off;
         off += z.logits * cl.n;
-        o_act[c] = off;
-        off += cfg->pruned ? act_bytes(cl.cfg, cl.n) : 0;
     }
     std::vector<size_t> o_slot(n_slots);
     for (int i = 0; i < n_slots; ++i) {
@@ -509,7 +502,6 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         cl.img = (uint8_t*)(base + o_img[c]);
         cl.mask = (uint8_t*)(base + o_mask[c]);
         cl.logits = (float*)(base + o_log[c]);
-        cl.act = base + o_act[c];
         for (int j = 0; j < cl.n; ++j) {
             const int i = cl.first_slot + j;
             const lane_stream_cfg& sc = s->streams[i];
@@ -572,9 +564,9 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     if (e == hipSuccess && cfg->pruned) {
         for (auto& cl : s->classes) {
             const uint8_t* fl = s->d_flags + cl.first_slot;
-            cst = lane_cnn_forward_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
-                                          (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
-                                          cl.act, cl.logits, fl, cs);
+            cst = lane_cnn_infer_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
+                                        (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
+                                        cl.logits, fl, cs);
             if (cst == LANE_OK)
                 cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
                                                    cl.mask, fl, cs);

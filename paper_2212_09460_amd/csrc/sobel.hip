@@ -357,7 +357,13 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
 // 16-byte aligned go to the vector-load instance, the rest to the byte one.
 template <bool FAST>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
-    k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items, int n_items) {
+    k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items,
+                  const int* __restrict__ counts, int group) {
+    // items of group 0 (aligned frames) come first, then group 1; the counts
+    // live in device memory so a launch can run any selection of frames
+    const int first = group == 0 ? 0 : gld(counts);
+    const int n_items = gld(counts + group);
+    items += first;
     __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
     // wave-uniform indices, so the table and descriptor loads are scalar
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -399,15 +405,15 @@ extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
             (((uintptr_t)d.edges % 16 == 0) && ((uintptr_t)d.mag % 16 == 0)));
 }
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items, int n_items,
-                                              int fast, int grid, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
+extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items,
+                                                            const int* counts, int fast, int grid,
+                                                            hipStream_t s) {
     if (fast)
         hipLaunchKernelGGL(k_sobel_batch<true>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
-                           items, n_items);
+                           items, counts, 0);
     else
         hipLaunchKernelGGL(k_sobel_batch<false>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
-                           items, n_items);
+                           items, counts, 1);
     return hipGetLastError();
 }
 

@@ -373,8 +373,9 @@ __global__ void __launch_bounds__(kVoteThreads) k_vote(VoteDesc d) {
 template <int LDSW>
 __global__ void __launch_bounds__(kVoteThreads)
     __attribute__((amdgpu_waves_per_eu(LDSW == kVoteLdsWordsHalf ? 8 : 4)))
-    k_vote_batch(const VoteDesc* __restrict__ descs, const int2* __restrict__ items, int n_items,
-                 uint32_t* queue) {
+    k_vote_batch(const VoteDesc* __restrict__ descs, const int2* __restrict__ items,
+                 const int* __restrict__ n_items_ptr, uint32_t* queue) {
+    const int n_items = gld(n_items_ptr);  // in device memory: any selection of frames
     __shared__ VoteLds<LDSW> sm;
     int it = blockIdx.x;
     for (;;) {
@@ -403,8 +404,9 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* dp, hipStre
     return hipGetLastError();
 }
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items, int n_items,
-                                             uint32_t* queue, int half_lds, int grid, hipStream_t s) {
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items,
+                                                           const int* n_items, uint32_t* queue,
+                                                           int half_lds, int grid, hipStream_t s) {
     if (half_lds)
         hipLaunchKernelGGL(k_vote_batch<kVoteLdsWordsHalf>, dim3(grid), dim3(kVoteThreads), 0, s,
                            descs, items, n_items, queue);

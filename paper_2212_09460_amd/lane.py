@@ -53,7 +53,7 @@ EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_of
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
-           "lane_mask_from_logits", "lane_batch_active_flags", "lane_server_plan",
+           "lane_mask_from_logits", "lane_cnn_infer", "lane_batch_active_flags", "lane_batch_select", "lane_server_plan",
            "lane_server_create", "lane_server_submit", "lane_server_poll", "lane_server_replay",
            "lane_server_stats_get", "lane_server_destroy")
 
@@ -221,6 +221,7 @@ _batch_launch = _sig("lane_batch_launch", [_vp, _vp])
 _batch_stage = _sig("lane_batch_launch_stage", [_vp, _i32, _vp])
 _batch_destroy = _sig("lane_batch_destroy", [_vp])
 _batch_flags = _sig("lane_batch_active_flags", [_vp, ctypes.POINTER(_vp)])
+_batch_select = _sig("lane_batch_select", [_vp, _vp, _vp])
 _tune_run = _sig("lane_tune_run", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32,
                                    ctypes.POINTER(LaneTune), ctypes.POINTER(ctypes.c_float)])
 
@@ -329,6 +330,16 @@ class Batch:
     def launch_stage(self, stage: int, stream=None):
         _check(_batch_stage(self._h, stage, _stream(stream)), "lane_batch_launch_stage")
 
+    def select(self, active, stream=None):
+        """Run only the frames whose entry of `active` is true in the next
+        launches (their work lists are rebuilt on the host and copied in on
+        `stream`).  Call again only after those launches have completed."""
+        import numpy as np
+
+        a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8))
+        assert a.size == len(self.frames)
+        _check(_batch_select(self._h, a.ctypes.data, _stream(stream)), "lane_batch_select")
+
     def active_flags_ptr(self) -> int:
         """Device address of the plan's per-frame switches (uint8 [n])."""
         p = _vp()
@@ -356,6 +367,7 @@ _cnn_sizes = _sig("lane_cnn_sizes", [_i32, _i32, _i32, ctypes.POINTER(_sz), ctyp
                                      ctypes.POINTER(_sz)])
 _cnn_pack = _sig("lane_cnn_pack", [_vp, _vp, _vp])
 _cnn_fwd = _sig("lane_cnn_forward", [_vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp])
+_cnn_infer = _sig("lane_cnn_infer", [_vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp])
 _cnn_loss = _sig("lane_cnn_loss", [_vp, _vp, _vp, _i32, _i32, _i32, _f32, _vp, _vp, _vp])
 _cnn_bwd = _sig("lane_cnn_backward", [_vp, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _sz, _vp,
                                       _vp])
@@ -392,6 +404,14 @@ def cnn_forward(imgs: torch.Tensor, packed, act, logits, W: int | None = None, s
     W = pitch if W is None else W
     _check(_cnn_fwd(_p(imgs), W, H, pitch, H * pitch, B, _p(packed), _p(act), _p(logits),
                     _stream(stream)), "lane_cnn_forward")
+
+
+def cnn_infer(imgs: torch.Tensor, packed, logits, W: int | None = None, stream=None):
+    """Forward only (fused, no activation workspace); imgs uint8 [B][H][pitch]."""
+    B, H, pitch = imgs.shape
+    W = pitch if W is None else W
+    _check(_cnn_infer(_p(imgs), W, H, pitch, H * pitch, B, _p(packed), _p(logits),
+                      _stream(stream)), "lane_cnn_infer")
 
 
 def cnn_loss(logits, keep, bands, W: int, H: int, batch: int, scale: float, act, loss,

@@ -74,8 +74,20 @@ class ProposalNet:
         return self._ws[key]
 
     def forward(self, imgs: torch.Tensor, W: int | None = None, stream=None) -> torch.Tensor:
-        """imgs uint8 [B][H][pitch] -> logits float32 [B][9][th][tw] (a view of
-        a reused workspace buffer)."""
+        """imgs uint8 [B][H][pitch] -> logits float32 [B][9][th][tw] (a reused
+        buffer), by the fused inference kernel."""
+        B, H, pitch = imgs.shape
+        W = pitch if W is None else W
+        key = ("infer", W, H, B)
+        if key not in self._ws:
+            th, tw = (H + 7) // 8, (W + 7) // 8
+            self._ws[key] = torch.empty((B, 9, th, tw), dtype=torch.float32, device=self.device)
+        lane.cnn_infer(imgs, self.packed, self._ws[key], W, stream)
+        return self._ws[key]
+
+    def forward_layers(self, imgs: torch.Tensor, W: int | None = None, stream=None) -> torch.Tensor:
+        """The same logits through the layer-by-layer kernels the training
+        uses (activations kept in the workspace for a backward pass)."""
         B, H, pitch = imgs.shape
         W = pitch if W is None else W
         ws = self.workspace(W, H, B)

@@ -153,3 +153,44 @@ def test_sobel_strip_heights(lane, synth, oracle, strip):
     b.launch()
     check(frames, wants)
     b.close()
+
+
+@pytest.mark.parametrize("queue", [1, 0])
+def test_select_runs_only_selected_frames(lane, synth, oracle, queue):
+    """lane_batch_select: selected frames are computed from their current
+    images, the others keep every output and counter untouched; a later
+    selection of all frames computes everything again (graph replays)."""
+    say("select", queue)
+    specs = [(640, 480, 640, 21, False), (1280, 720, 1280, 22, False), (333, 211, 352, 23, True),
+             (1920, 1080, 1920, 24, False), (640, 480, 640, 25, True)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, vote_rows=2, vote_queue=queue, sobel_strip_rows=8)
+    b.launch()
+    check(frames, wants)
+    # new images for the selected frames 0, 2, 3; sentinels in the others
+    sel = [1, 0, 1, 1, 0]
+    new_wants = list(wants)
+    C, S = synth.trig_q14(360)
+    for i in (0, 2, 3):
+        Wf, Hf, pitch, seed, masked = specs[i]
+        img = synth.gen_frame(synth.scene_road(Wf, Hf), seed + 100, pitch=pitch)
+        frames[i].img.copy_(torch.from_numpy(img))
+        mask = frames[i].tile_mask.cpu().numpy() if masked else None
+        new_wants[i] = oracle.pipeline(img[:, :Wf].copy(), C, S, 8, tile_mask=mask)
+    for i in (1, 4):
+        frames[i].edges.fill_(3)
+        frames[i].acc.fill_(-7)
+        frames[i].peaks.fill_(-5)
+        frames[i].counters.fill_(11)
+    b.select(sel)
+    for rep in range(2):
+        b.launch()
+        torch.cuda.synchronize()
+        check([frames[i] for i in (0, 2, 3)], [new_wants[i] for i in (0, 2, 3)])
+        for i in (1, 4):
+            assert (frames[i].edges == 3).all() and (frames[i].acc == -7).all()
+            assert (frames[i].peaks == -5).all() and (frames[i].counters == 11).all()
+    b.select([1] * 5)
+    b.launch()
+    check(frames, new_wants)
+    b.close()

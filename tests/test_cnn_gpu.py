@@ -62,6 +62,20 @@ def test_forward_matches_oracle(lane, synth, ocnn, W, H, B):
         assert err <= 2e-2 * np.abs(ref).max(), (b, err, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("W,H,B", [(136, 72, 2), (97, 43, 3), (1100, 200, 2), (1920, 1080, 2),
+                                   (3840, 2160, 1), (8, 8, 1), (65, 130, 1)])
+def test_fused_inference_equals_layers(lane, synth, W, H, B):
+    """The fused inference kernel issues the layer kernels' MFMA sequence on
+    the same FP16 values: identical logits."""
+    say("cnn fused == layers", W, H, B)
+    net, _ = make_net(7, bias_scale=0.5)
+    imgs = torch.from_numpy(frames(synth, max(W, 16), max(H, 16), B, 40)[:, :H, :W].copy()).cuda()
+    a = net.forward(imgs).clone()
+    b = net.forward_layers(imgs).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def _labels(rng, th, tw):
     keep = (rng.random((th, tw)) < 0.3).astype(np.uint8)
     keep[0, 0] = 1
