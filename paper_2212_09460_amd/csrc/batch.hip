@@ -169,9 +169,11 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         const int st = validate(frames[i]);
         if (st != LANE_OK) return st;
     }
-    lane_tune tune = {0, -1, 0, 0};
+    lane_tune tune = {0, -1, 0, 0, 0};
     if (tune_opt) tune = *tune_opt;
     if (tune.vote_rows < 0 || (tune.vote_rows & (tune.vote_rows - 1)) != 0) return LANE_E_ARG;
+    if (tune.vote_split < 0 || tune.vote_split > 64) return LANE_E_ARG;
+    const int E = tune.vote_split > 1 ? tune.vote_split : 1;
     if (tune.sobel_strip_rows < 0 || (tune.sobel_strip_rows % 8) != 0 || tune.sobel_strip_rows > 1024)
         return LANE_E_ARG;
 
@@ -227,6 +229,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.T = tune.vote_rows > 0 ? std::min(tmax, std::min(tune.vote_rows, pow2_floor(f.n_theta))) : tmax;
         v.log2T = ilog2_floor((unsigned)v.T);
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
+        v.E = E;
+        v.part_stride = v.T * lane_vote_row_cap(f.W, f.H, f.n_r);
         if ((long)v.T * lane_vote_row_cap(f.W, f.H, f.n_r) > kVoteLdsWordsHalf) all_half = false;
 
         if (f.k > 0) {
@@ -262,8 +266,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     if (dynamic) {
         std::vector<std::pair<double, int2>> all;
         for (int i = 0; i < n; ++i) {
-            const double cost = (double)vd[i].T * frames[i].W * frames[i].H;
-            for (int s = 0; s < vd[i].n_slices; ++s) all.push_back({cost, make_int2(i, s)});
+            const double cost = (double)vd[i].T * frames[i].W * frames[i].H / E;
+            for (int s = 0; s < vd[i].n_slices * E; ++s) all.push_back({cost, make_int2(i, s)});
         }
         std::stable_sort(all.begin(), all.end(),
                          [](const std::pair<double, int2>& a, const std::pair<double, int2>& b) {
@@ -273,7 +277,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     } else {
         std::vector<std::vector<int2>> per(8);
         for (int i = 0; i < n; ++i)
-            for (int s = 0; s < vd[i].n_slices; ++s) per[i % 8].push_back(make_int2(i, s));
+            for (int s = 0; s < vd[i].n_slices * E; ++s) per[i % 8].push_back(make_int2(i, s));
         size_t longest = 0;
         for (auto& p : per) longest = std::max(longest, p.size());
         vitems.assign(longest * 8, make_int2(-1, -1));
@@ -307,6 +311,16 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
     const size_t o_active = off; off = al(off + (size_t)n);
     const size_t o_counts = off; off = al(off + sizeof(int) * 4);
+    // edge split: per frame E partial rows per slice and the arrival counters
+    std::vector<size_t> o_part(n, 0), o_arr(n, 0);
+    if (E > 1) {
+        for (int i = 0; i < n; ++i) {
+            o_part[i] = off;
+            off = al(off + sizeof(int32_t) * (size_t)E * vd[i].n_slices * vd[i].part_stride);
+            o_arr[i] = off;
+            off = al(off + sizeof(uint32_t) * (size_t)vd[i].n_slices);
+        }
+    }
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -325,6 +339,10 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     for (int i = 0; i < n; ++i) {
         sd[i].active = b->d_active + i;
         vd[i].active = b->d_active + i;
+        if (E > 1) {
+            vd[i].partials = (int32_t*)(base + o_part[i]);
+            vd[i].arrivals = (uint32_t*)(base + o_arr[i]);
+        }
     }
     for (auto& p : pd) p.active = b->d_active + p.active_index;
     bool ok = hipMemcpy(b->d_sobel, sd.data(), sizeof(SobelDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
@@ -337,6 +355,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 4) == hipSuccess;
     ok = ok && hipMemset(b->d_active, 1, (size_t)n) == hipSuccess;
+    for (int i = 0; i < n && E > 1; ++i)
+        ok = ok && hipMemset(vd[i].arrivals, 0, sizeof(uint32_t) * vd[i].n_slices) == hipSuccess;
     const int counts0[4] = {n_fast, b->n_sobel_items - n_fast, b->n_vote_items, 0};
     ok = ok && hipMemcpy(b->d_counts, counts0, sizeof(counts0), hipMemcpyHostToDevice) == hipSuccess;
     // host copies for lane_batch_select: per-frame item ranges
@@ -570,13 +590,13 @@ int lane_tune_run(const uint8_t* sample, int32_t W, int32_t H, int32_t pitch, in
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     const int tmax = lane_vote_rows_per_group(W, H, n_theta, n_r);
-    lane_tune best = {tmax, -1, 0, 0};
+    lane_tune best = {tmax, -1, 0, 0, 0};
     float best_vote = 1e30f, best_sobel = 1e30f;
     int status = LANE_OK;
     // theta rows per vote workgroup x work distribution
     for (int T = tmax; T >= 1 && T * 16 >= tmax; T >>= 1) {
         for (int q = 0; q <= 1; ++q) {
-            lane_tune t = {T, q, 0, 0};
+            lane_tune t = {T, q, 0, 0, 0};
             lane_batch* b = nullptr;
             status = lane_batch_create(frames.data(), n_frames, &t, &b);
             if (status != LANE_OK) break;

@@ -34,6 +34,8 @@
 #include "lane_internal.h"
 
 extern "C" {
+LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
+LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
 LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
                                         int64_t img_stride, int32_t batch, const void* packed,
                                         float* logits, const uint8_t* active, void* stream);
@@ -67,6 +69,7 @@ int check_cfg(const lane_server_cfg& c) {
     if (c.max_pending < 1) return LANE_E_ARG;
     if (c.vote_rows < 0 || (c.vote_rows & (c.vote_rows - 1)) != 0) return LANE_E_ARG;
     if (c.sobel_strip_rows < 0 || (c.sobel_strip_rows % 8) != 0) return LANE_E_ARG;
+    if (c.vote_split < 0 || c.vote_split > 64) return LANE_E_ARG;
     if (c.pruned && (!c.cnn_params || !(c.conf > 0.5f && c.conf < 1.f))) return LANE_E_ARG;
     return LANE_OK;
 }
@@ -79,13 +82,29 @@ ClassKey key_of(const lane_stream_cfg& c) {
 // Device bytes of one stream's buffers (the fused proposal network needs no
 // activation workspace).
 struct StreamSizes {
-    size_t img, edges, list, acc, peaks, peaks_ws, counters, mask, logits;
+    size_t img, edges, list, acc, peaks, peaks_ws, counters, mask, logits, split;
     size_t total() const {
-        return img + edges + list + acc + peaks + peaks_ws + counters + mask + logits;
+        return img + edges + list + acc + peaks + peaks_ws + counters + mask + logits + split;
     }
 };
 
-StreamSizes stream_sizes(const lane_stream_cfg& c, int pruned) {
+int serve_vote_rows(const lane_server_cfg& cfg) { return cfg.vote_rows > 0 ? cfg.vote_rows : 1; }
+
+// device bytes the plan holds for a stream's edge-split partial rows
+size_t split_bytes(const lane_stream_cfg& c, const lane_server_cfg& cfg, int n_r) {
+    const int E = cfg.vote_split > 1 ? cfg.vote_split : 1;
+    if (E == 1) return 0;
+    int p2 = 1;
+    while (p2 * 2 <= c.n_theta) p2 *= 2;
+    const int T = std::min(lane_vote_rows_per_group(c.W, c.H, c.n_theta, n_r),
+                           std::min(serve_vote_rows(cfg), p2));
+    const size_t n_slices = (size_t)(c.n_theta + T - 1) / T;
+    const size_t stride = (size_t)T * lane_vote_row_cap(c.W, c.H, n_r);
+    return al256(sizeof(int32_t) * E * n_slices * stride) + al256(sizeof(uint32_t) * n_slices);
+}
+
+StreamSizes stream_sizes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
+    const int pruned = cfg.pruned;
     StreamSizes z;
     const int pitch = (c.W + 15) / 16 * 16;
     int32_t D = 0;
@@ -105,6 +124,7 @@ StreamSizes stream_sizes(const lane_stream_cfg& c, int pruned) {
     z.counters = 256;
     z.mask = pruned ? al256(th * tw) : 0;
     z.logits = pruned ? al256(sizeof(float) * 9 * th * tw) : 0;
+    z.split = split_bytes(c, cfg, (int)n_r);
     return z;
 }
 
@@ -123,7 +143,7 @@ size_t plan_admission(const lane_stream_cfg* s, int n, const lane_server_cfg& cf
     }
     size_t total = shared;
     for (int i = 0; i < n; ++i) {
-        const StreamSizes z = stream_sizes(s[i], cfg.pruned);
+        const StreamSizes z = stream_sizes(s[i], cfg);
         const ClassKey k = key_of(s[i]);
         const int c = count.count(k) ? count[k] : 0;
         size_t add = z.total();
@@ -428,7 +448,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     // one device allocation: per class the frame slots (contiguous), masks,
     // logits and activations; per slot the path's buffers; shared tables
     std::vector<StreamSizes> sz(n_slots);
-    for (int i = 0; i < n_slots; ++i) sz[i] = stream_sizes(s->streams[i], cfg->pruned);
+    for (int i = 0; i < n_slots; ++i) sz[i] = stream_sizes(s->streams[i], *cfg);
     std::map<int, size_t> trig_off;
     size_t off = 0;
     std::vector<size_t> o_img(s->classes.size()), o_mask(s->classes.size()), o_log(s->classes.size());
@@ -445,7 +465,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     std::vector<size_t> o_slot(n_slots);
     for (int i = 0; i < n_slots; ++i) {
         o_slot[i] = off;
-        off += sz[i].total() - sz[i].img - sz[i].mask - sz[i].logits;
+        off += sz[i].total() - sz[i].img - sz[i].mask - sz[i].logits - sz[i].split;
         if (!trig_off.count(s->streams[i].n_theta)) {
             trig_off[s->streams[i].n_theta] = off;
             off += al256(sizeof(int16_t) * 2 * (size_t)s->streams[i].n_theta);
@@ -545,8 +565,8 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
             f.counters_opt = (uint32_t*)p;
         }
     }
-    lane_tune tune = {cfg->vote_rows > 0 ? cfg->vote_rows : 1, 1, 0,
-                      cfg->sobel_strip_rows > 0 ? cfg->sobel_strip_rows : 8};
+    lane_tune tune = {serve_vote_rows(*cfg), 1, 0, cfg->sobel_strip_rows > 0 ? cfg->sobel_strip_rows : 8,
+                      cfg->vote_split};
     if (ok && lane_batch_create(frames.data(), n_slots, &tune, &s->plan) != LANE_OK) ok = false;
     ok = ok && lane_batch_active_flags(s->plan, &s->d_flags) == LANE_OK;
     if (!ok) {

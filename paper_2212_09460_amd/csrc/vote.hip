@@ -51,7 +51,7 @@ template <int LDSW>
 struct VoteLds {
     int32_t acc[LDSW];
     int lo[kMaxT], win[kMaxT], base[kMaxT];
-    int fast, total, item;
+    int fast, total, item, last;
     uint32_t dropped;
 };
 
@@ -67,7 +67,13 @@ __device__ __forceinline__ void lds_vote(VoteLds<LDSW>& L, uint32_t v) {
 constexpr int kSlotsPerSegment = 8;
 
 template <int LDSW>
-__device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
+__device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
+    // code = slice * E + part: with an edge split, E workgroups share a
+    // slice, each voting a contiguous 1/E share of the segments into its own
+    // LDS rows; the last to finish adds the others' rows to its own and
+    // writes the result
+    const int E = d.E > 1 ? d.E : 1;
+    const int slice = code / E, part = code - slice * E;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
@@ -111,10 +117,14 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
             base += sm.win[q];
         }
         sm.total = base;
-        if (base > LDSW) sm.fast = 0;
+        if (base > LDSW || (E > 1 && base > d.part_stride)) sm.fast = 0;
     }
     __syncthreads();
     const bool fast = sm.fast != 0;
+    // the exact fallback runs unsplit, in part 0 (the same decision in every part)
+    if (!fast && part != 0) return;
+    const int seg_lo = fast ? (int)(((long long)L.nseg * part) / E) : 0;
+    const int seg_hi = fast ? (int)(((long long)L.nseg * (part + 1)) / E) : L.nseg;
     const int kk = k0 + j;
     const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
     const bool masked = d.tile_mask != nullptr;
@@ -175,7 +185,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
                 }
             };
             if (G <= kSlotsPerSegment) {
-                for (int seg = wave; seg < L.nseg; seg += nwaves) {
+                for (int seg = seg_lo + wave; seg < seg_hi; seg += nwaves) {
                     const int n = min((int)gld(list + seg), kSegCap);
                     run_segment(list + L.off_ent + (size_t)seg * kSegCap, n, G, g);
                 }
@@ -185,10 +195,10 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
                 // pipeline instead of a few per segment
                 const int P = G / kSlotsPerSegment;
                 const int sub = g / kSlotsPerSegment, gs = g - sub * kSlotsPerSegment;
-                for (int seg0 = wave * P; seg0 < L.nseg; seg0 += nwaves * P) {
+                for (int seg0 = seg_lo + wave * P; seg0 < seg_hi; seg0 += nwaves * P) {
                     const int seg = seg0 + sub;
-                    const int n = seg < L.nseg ? min((int)gld(list + seg), kSegCap) : 0;
-                    run_segment(list + L.off_ent + (size_t)min(seg, L.nseg - 1) * kSegCap, n,
+                    const int n = seg < seg_hi ? min((int)gld(list + seg), kSegCap) : 0;
+                    run_segment(list + L.off_ent + (size_t)min(seg, seg_hi - 1) * kSegCap, n,
                                 kSlotsPerSegment, gs);
                 }
             }
@@ -199,7 +209,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
             // entries are contiguous in the segment, so each run is voted
             // like the unmasked stream, with the lane predicate "this lane's
             // angle lies in a band of the run's mask".
-            for (int seg = wave; seg < L.nseg; seg += nwaves) {
+            for (int seg = seg_lo + wave; seg < seg_hi; seg += nwaves) {
                 const int ty = seg / L.nchunk, chunk = seg - ty * L.nchunk;
                 const int n = min((int)gld(list + seg), kSegCap);
                 if (n == 0) continue;
@@ -269,6 +279,29 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int slice) {
             }
         }
         __syncthreads();
+        if (E > 1) {
+            // publish this part's rows; the last part to arrive merges
+            const int total = sm.total;
+            int32_t* mine = d.partials + ((size_t)part * d.n_slices + slice) * d.part_stride;
+            for (int c = tid; c < total; c += blockDim.x) gst(mine + c, sm.acc[c]);
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) {
+                const uint32_t seen = atomicAdd(d.arrivals + slice, 1u);
+                sm.last = seen == (uint32_t)(E - 1);
+                if (sm.last) d.arrivals[slice] = 0;  // ready for the next launch
+            }
+            __syncthreads();
+            if (!sm.last) return;
+            __threadfence();
+            for (int c = tid; c < total; c += blockDim.x) {
+                int v = sm.acc[c];
+                for (int e = 0; e < E; ++e)
+                    if (e != part) v += gld(d.partials + ((size_t)e * d.n_slices + slice) * d.part_stride + c);
+                sm.acc[c] = v;
+            }
+            __syncthreads();
+        }
         const int q0 = own_from - k0;  // first owned row of the slice
         if (d.keys) {
             // write the rows and, block by block, the peak-search keys

@@ -212,7 +212,7 @@ class LaneFrame(ctypes.Structure):
 
 class LaneTune(ctypes.Structure):
     _fields_ = [("vote_rows", _i32), ("vote_queue", _i32), ("sobel_groups_per_cu", _i32),
-                ("sobel_strip_rows", _i32)]
+                ("sobel_strip_rows", _i32), ("vote_split", _i32)]
 
 
 _batch_create = _sig("lane_batch_create", [ctypes.POINTER(LaneFrame), _i32,
@@ -240,7 +240,8 @@ def tune_run(sample: torch.Tensor, n_theta: int, n_frames: int, W: int | None = 
 
 def tune_dict(t: LaneTune) -> dict:
     return {"vote_rows": t.vote_rows, "vote_queue": t.vote_queue,
-            "sobel_groups_per_cu": t.sobel_groups_per_cu, "sobel_strip_rows": t.sobel_strip_rows}
+            "sobel_groups_per_cu": t.sobel_groups_per_cu, "sobel_strip_rows": t.sobel_strip_rows,
+            "vote_split": t.vote_split}
 
 
 class FrameBuffers:
@@ -313,11 +314,12 @@ class Batch:
     every frame as one graph launch."""
 
     def __init__(self, frames, vote_rows: int = 0, vote_queue: int = -1,
-                 sobel_groups_per_cu: int = 0, sobel_strip_rows: int = 0, tune=None):
+                 sobel_groups_per_cu: int = 0, sobel_strip_rows: int = 0, tune=None,
+                 vote_split: int = 0):
         self.frames = list(frames)
         arr = (LaneFrame * len(self.frames))(*[f.desc() for f in self.frames])
         if tune is None:
-            tune = LaneTune(vote_rows, vote_queue, sobel_groups_per_cu, sobel_strip_rows)
+            tune = LaneTune(vote_rows, vote_queue, sobel_groups_per_cu, sobel_strip_rows, vote_split)
         self.tune = tune
         h = _vp()
         _check(_batch_create(arr, len(self.frames), ctypes.byref(tune), ctypes.byref(h)),
@@ -461,7 +463,7 @@ class StreamCfg(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", _sz), ("pruned", _i32), ("conf", ctypes.c_float),
                 ("cnn_params", _vp), ("max_pending", _i32), ("vote_rows", _i32),
-                ("sobel_strip_rows", _i32)]
+                ("sobel_strip_rows", _i32), ("vote_split", _i32)]
 
 
 class Result(ctypes.Structure):
@@ -497,7 +499,8 @@ _srv_stats = _sig("lane_server_stats_get", [_vp, ctypes.POINTER(ServerStats)])
 _srv_destroy = _sig("lane_server_destroy", [_vp])
 
 
-def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, sobel_strip_rows):
+def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, sobel_strip_rows,
+                vote_split=0):
     import numpy as np
 
     keep = None
@@ -505,7 +508,7 @@ def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, so
         keep = np.ascontiguousarray(np.asarray(cnn_params, dtype=np.float32))
     cfg = ServerCfg(int(hbm_budget), int(pruned), float(conf),
                     None if keep is None else keep.ctypes.data, int(max_pending), int(vote_rows),
-                    int(sobel_strip_rows))
+                    int(sobel_strip_rows), int(vote_split))
     return cfg, keep
 
 
@@ -519,13 +522,14 @@ def _stream_cfgs(streams):
 
 
 def server_plan(streams, hbm_budget: int, pruned: bool = False, conf: float = 0.9,
-                cnn_params=None, max_pending: int = 4, vote_rows: int = 0, sobel_strip_rows: int = 0):
+                cnn_params=None, max_pending: int = 4, vote_rows: int = 0, sobel_strip_rows: int = 0,
+                vote_split: int = 0):
     """Host-only admission plan: (admitted list of bool, per-stream bytes, total bytes)."""
     import numpy as np
 
     arr = _stream_cfgs(streams)
     cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
-                            sobel_strip_rows)
+                            sobel_strip_rows, vote_split)
     adm = np.zeros(len(streams), np.uint8)
     sb = np.zeros(len(streams), np.uint64)
     tot = _sz(0)
@@ -542,13 +546,13 @@ class Server:
 
     def __init__(self, streams, hbm_budget: int = 8 << 30, pruned: bool = False,
                  conf: float = 0.9, cnn_params=None, max_pending: int = 4, vote_rows: int = 0,
-                 sobel_strip_rows: int = 0):
+                 sobel_strip_rows: int = 0, vote_split: int = 0):
         import numpy as np
 
         self.streams = [dict(s) for s in streams]
         arr = _stream_cfgs(streams)
         cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
-                                sobel_strip_rows)
+                                sobel_strip_rows, vote_split)
         adm = np.zeros(len(streams), np.uint8)
         h = _vp()
         _check(_srv_create(arr, len(streams), ctypes.byref(cfg), ctypes.byref(h), adm.ctypes.data),

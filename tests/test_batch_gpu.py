@@ -194,3 +194,42 @@ def test_select_runs_only_selected_frames(lane, synth, oracle, queue):
     b.launch()
     check(frames, new_wants)
     b.close()
+
+
+@pytest.mark.parametrize("rows,split,queue", [(1, 2, 1), (4, 4, 1), (16, 3, 0), (2, 8, 1), (8, 64, 1)])
+def test_vote_split(lane, synth, oracle, rows, split, queue):
+    """Edge-split vote: several workgroups per slice, the last merges; exact
+    on every replay (the arrival counters restart themselves)."""
+    say("vote split", rows, split, queue)
+    specs = [(1280, 720, 1280, 31, False), (640, 480, 640, 32, True), (1100, 200, 1104, 33, False)]
+    frames, wants = make_frames(lane, synth, oracle, specs)
+    b = lane.Batch(frames, vote_rows=rows, vote_split=split, vote_queue=queue)
+    for rep in range(3):
+        scribble(frames)
+        b.launch()
+        check(frames, wants)
+    b.close()
+
+
+def test_vote_split_with_fallback_rows(lane, synth, oracle):
+    """A table whose row leaves the accumulator sends that slice down the
+    exact global-atomic path, which runs unsplit in the slice's first part."""
+    say("vote split + fallback")
+    W, H = 640, 480
+    img = synth.road(W, H, 61)
+    C, S = synth.trig_q14(360)
+    C = C.copy()
+    C[5] = 32767
+    D = synth.r_offset(W, H)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    fb = lane.FrameBuffers(torch.from_numpy(img).cuda(), W, 360, 8, Cd, Sd)
+    want = oracle.pipeline(img, C, S, 8)
+    b = lane.Batch([fb], vote_rows=4, vote_split=4, vote_queue=1)
+    for rep in range(2):
+        scribble([fb])
+        b.launch()
+        torch.cuda.synchronize()
+        assert (fb.acc.cpu().numpy() == want["acc"]).all()
+        assert int(fb.counters.cpu().numpy()[1]) == want["dropped"] > 0
+        assert (fb.theta_idx().cpu().numpy() == want["theta_idx"]).all()
+    b.close()
