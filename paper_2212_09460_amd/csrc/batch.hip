@@ -36,6 +36,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* des
                                               hipStream_t s);
 extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
+extern "C" LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T);
 extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
@@ -231,7 +232,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
         v.E = E;
         v.part_stride = v.T * lane_vote_row_cap(f.W, f.H, f.n_r);
-        if ((long)v.T * lane_vote_row_cap(f.W, f.H, f.n_r) > kVoteLdsWordsHalf) all_half = false;
+        if (lane_vote_slice_words(f.W, f.H, f.n_theta, f.n_r, v.T) > kVoteLdsWordsHalf) all_half = false;
 
         if (f.k > 0) {
             PeaksDesc p;

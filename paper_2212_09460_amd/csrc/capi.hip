@@ -126,9 +126,6 @@ int lane_edges_to_list(const uint8_t* edges, int32_t W, int32_t H, int32_t pitch
     return dev_status(lane_launch_sobel(&d, 1, s));
 }
 
-// Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
-// whose rows fit in LDS, each row holding up to D + 3 cells (the r range of
-// one angle across the frame, plus rounding).
 // LDS cells one theta row needs: the r range of one angle across the frame
 // (at most D + 1 cells, plus rounding), never more than n_r.
 LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r) {
@@ -137,12 +134,19 @@ LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r) {
     return D + 3 < n_r ? D + 3 : n_r;
 }
 
+// LDS words a vote workgroup needs for slices of T rows laid out back to
+// back (T x the row cap).  The kernel uses the interleaved layout instead
+// when the slice's r span times T also fits.
+LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T) {
+    (void)n_theta;
+    return (long)T * lane_vote_row_cap(W, H, n_r);
+}
+
 // Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
-// whose rows fit in LDS.
+// whose slices fit in LDS.
 LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
-    const int row = lane_vote_row_cap(W, H, n_r);
     int T = kMaxT;
-    while (T > 1 && (T > n_theta || (long)T * row > kVoteLdsWords)) T >>= 1;
+    while (T > 1 && (T > n_theta || lane_vote_slice_words(W, H, n_theta, n_r, T) > kVoteLdsWords)) T >>= 1;
     return T;
 }
 

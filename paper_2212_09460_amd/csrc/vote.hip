@@ -52,6 +52,7 @@ struct VoteLds {
     int32_t acc[LDSW];
     int lo[kMaxT], win[kMaxT], base[kMaxT];
     int fast, total, item, last;
+    int il, lo_min, span;  // interleaved layout: on/off, lowest r_idx of the slice, its r span
     uint32_t dropped;
 };
 
@@ -62,6 +63,26 @@ __device__ __forceinline__ void lds_vote(VoteLds<LDSW>& L, uint32_t v) {
                                __builtin_assume_aligned(reinterpret_cast<char*>(L.acc) + adr, 4)),
                            1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// Interleaved layout: cell u = r_idx - lo_min of row j sits in word u*T + j,
+// so within one pixel's T lanes (T rows) the banks differ (j + T u mod 32
+// with j < T); with back-to-back rows the banks of a wave's 64 votes are
+// effectively random.  The word's byte address is ((v >> 14) << (2 +
+// log2 T)) | 4j with v the biased dot product (floor(v / 2^14) = u): the
+// same three instructions per vote as the back-to-back layout.  It needs
+// T x (the slice's r span) words, used whenever that fits.
+template <int LDSW>
+__device__ __forceinline__ void lds_vote_il(VoteLds<LDSW>& L, uint32_t v, uint32_t jb, int sh) {
+    const uint32_t adr = ((v >> 14) << sh) | jb;
+    __hip_atomic_fetch_add(reinterpret_cast<int32_t*>(
+                               __builtin_assume_aligned(reinterpret_cast<char*>(L.acc) + adr, 4)),
+                           1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool B>
+struct Mode {
+    static constexpr bool value = B;
+};
 
 // slots of one wave that share a segment when the slice has few rows
 constexpr int kSlotsPerSegment = 8;
@@ -111,16 +132,27 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     }
     __syncthreads();
     if (tid == 0) {
-        int base = 0;
+        int base = 0, lo_min = 0x7FFFFFFF, hi_max = -1;
         for (int q = 0; q < T; ++q) {
             sm.base[q] = base;
             base += sm.win[q];
+            lo_min = min(lo_min, sm.lo[q]);
+            hi_max = max(hi_max, sm.lo[q] + sm.win[q] - 1);
         }
-        sm.total = base;
-        if (base > LDSW || (E > 1 && base > d.part_stride)) sm.fast = 0;
+        // interleaved whenever the slice's r span fits
+        const int span = hi_max - lo_min + 1;
+        const int il_words = span * T;
+        const bool il = il_words <= LDSW && (E == 1 || il_words <= d.part_stride);
+        const bool plain_fit = base <= LDSW && (E == 1 || base <= d.part_stride);
+        sm.il = il ? 1 : 0;
+        sm.lo_min = lo_min;
+        sm.span = span;
+        sm.total = il ? il_words : base;
+        if (!il && !plain_fit) sm.fast = 0;
     }
     __syncthreads();
     const bool fast = sm.fast != 0;
+    const bool il = sm.il != 0;
     // the exact fallback runs unsplit, in part 0 (the same decision in every part)
     if (!fast && part != 0) return;
     const int seg_lo = fast ? (int)(((long long)L.nseg * part) / E) : 0;
@@ -138,14 +170,24 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         const int total = sm.total;
         for (int c = tid; c < total; c += blockDim.x) sm.acc[c] = 0;
         const int lo = sm.lo[j], base = sm.base[j];
-        const int K = 8192 + (base - lo + d.r_offset) * 16384;
+        const int K = il ? 8192 + (d.r_offset - sm.lo_min) * 16384
+                         : 8192 + (base - lo + d.r_offset) * 16384;
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
+        const uint32_t jb = 4u * (uint32_t)j;
+        const int sh = 2 + d.log2T;
         __syncthreads();
+        auto body = [&](auto mode) {
+        constexpr bool kIL = decltype(mode)::value;
+        auto vote1 = [&](uint32_t xy) {
+            const uint32_t v = (uint32_t)dot2_i16((int)xy, CS, K);
+            if constexpr (kIL) lds_vote_il(sm, v, jb, sh);
+            else lds_vote(sm, v);
+        };
         auto vote4 = [&](u32x4 q) {
-            lds_vote(sm, (uint32_t)dot2_i16((int)q.x, CS, K));
-            lds_vote(sm, (uint32_t)dot2_i16((int)q.y, CS, K));
-            lds_vote(sm, (uint32_t)dot2_i16((int)q.z, CS, K));
-            lds_vote(sm, (uint32_t)dot2_i16((int)q.w, CS, K));
+            vote1(q.x);
+            vote1(q.y);
+            vote1(q.z);
+            vote1(q.w);
         };
         if (!masked) {
             // One segment's entries split over Gs slots (slot gs): each slot
@@ -181,7 +223,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 const int i0 = Gs * part + 4 * gs;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (i0 + q < n) lds_vote(sm, (uint32_t)dot2_i16((int)gld(ents + i0 + q), CS, K));
+                    if (i0 + q < n) vote1(gld(ents + i0 + q));
                 }
             };
             if (G <= kSlotsPerSegment) {
@@ -272,12 +314,15 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                         const int nl = nh + max(0, end - t0);
                         for (int t = g; t < nl; t += G) {
                             const int e = t < nh ? start + t : t0 + (t - nh);
-                            lds_vote(sm, (uint32_t)dot2_i16((int)gld(ents + e), CS, K));
+                            vote1(gld(ents + e));
                         }
                     }
                 }
             }
         }
+        };
+        if (il) body(Mode<true>{});
+        else body(Mode<false>{});
         __syncthreads();
         if (E > 1) {
             // publish this part's rows; the last part to arrive merges
@@ -303,6 +348,15 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
             __syncthreads();
         }
         const int q0 = own_from - k0;  // first owned row of the slice
+        const int lo_min = sm.lo_min, span = sm.span;
+        auto cell = [&](int q, int rlo, int rwin, int rbase, int i) -> int {
+            if (il) {
+                const int u = i - lo_min;
+                return (u >= 0 && u < span) ? sm.acc[u * T + q] : 0;
+            }
+            const int o = i - rlo;
+            return (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0;
+        };
         if (d.keys) {
             // write the rows and, block by block, the peak-search keys
             const int B = 1 << d.key_log2;
@@ -316,8 +370,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 const int i0 = jb * B, i1 = min(d.n_r, i0 + B);
                 unsigned long long best = 0;
                 for (int i = i0 + lane; i < i1; i += kWave) {
-                    const int o = i - rlo;
-                    const int v = (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0;
+                    const int v = cell(q, rlo, rwin, rbase, i);
                     gst(out + i, v);
                     const unsigned long long kk = make_key(v, rowc + (uint32_t)i);
                     best = kk > best ? kk : best;
@@ -330,10 +383,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 const int row = k0 + q;
                 const int rlo = sm.lo[q], rwin = sm.win[q], rbase = sm.base[q];
                 int32_t* out = d.acc + (size_t)row * d.n_r;
-                for (int i = tid; i < d.n_r; i += blockDim.x) {
-                    const int o = i - rlo;
-                    gst(out + i, (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0);
-                }
+                for (int i = tid; i < d.n_r; i += blockDim.x) gst(out + i, cell(q, rlo, rwin, rbase, i));
             }
         }
     } else {

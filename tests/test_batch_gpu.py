@@ -95,7 +95,7 @@ def test_same_size_static_and_stages(lane, synth, oracle):
     b.close()
 
 
-@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("rows", [1, 2, 4, 8, 16, 32, 64])
 def test_vote_rows_override(lane, synth, oracle, rows):
     say("vote rows", rows)
     specs = [(1280, 720, 1280, 7, False), (640, 480, 640, 8, True)]
