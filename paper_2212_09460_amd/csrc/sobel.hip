@@ -105,7 +105,7 @@ __device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
 // may be edges (inside the frame; not on the ring in border mode 1).
 struct ColMask {
     uint32_t bits;     // bit i: column x0 + i may be an edge
-    uint32_t bytes[4]; // 0xFF per allowed column, as the edge-map bytes
+    uint32_t bytes[4]; // 0x01 per allowed column, as the edge-map bytes
 };
 
 __device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
@@ -121,10 +121,20 @@ __device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
     for (int w = 0; w < 4; ++w) {
         uint32_t b = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) b |= ((c.bits >> (4 * w + i)) & 1u) ? (0xFFu << (8 * i)) : 0u;
+        for (int i = 0; i < 4; ++i) b |= ((c.bits >> (4 * w + i)) & 1u) << (8 * i);
         c.bytes[w] = b;
     }
     return c;
+}
+
+__device__ __forceinline__ u16x2 flag_above(u16x2 g, uint32_t tt) {
+    // both halves of every operand are registers (an inline constant would
+    // give the high half 0)
+    uint32_t r;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3"
+        : "=&v"(r)
+        : "v"(__builtin_bit_cast(uint32_t, g)), "v"(tt), "v"(0x00010001u));
+    return __builtin_bit_cast(u16x2, r);
 }
 
 // Vertical pass and output of row y.  X = hd(y-1) + 2 hd(y) and
@@ -134,7 +144,7 @@ template <bool FAST>
 __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool active,
                                          const ColMask& cm, const s16x2 (&X)[8],
                                          const u16x2 (&HU)[8], const HRow& D) {
-    const unsigned short T = (unsigned short)d.threshold;
+    const uint32_t TT = (uint32_t)d.threshold * 0x00010001u;
     u16x2 g[8], e16[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -143,22 +153,23 @@ __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool
         const s16x2 ax = __builtin_elementwise_max(gx, -gx);
         const s16x2 ay = __builtin_elementwise_max(gy, -gy);
         g[k] = __builtin_bit_cast(u16x2, ax + ay);
-        const u16x2 f = __builtin_elementwise_min(__builtin_elementwise_sub_sat(g[k], (u16x2)T),
-                                                  (u16x2)(unsigned short)1);
-        e16[k] = (f << (unsigned short)8) - f;  // 255 or 0
+        // 1 if |gx| + |gy| > T else 0: a saturating subtract and a min,
+        // both packed (written out: the compiler would turn the pair into a
+        // compare and select per half)
+        e16[k] = flag_above(g[k], TT);
     }
     uint32_t eb[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-        eb[w] = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, e16[2 * w + 1]),
-                                      __builtin_bit_cast(uint32_t, e16[2 * w]), 0x06040200u);
     const bool ring_row = (d.border_mode == 1) && (y == 0 || y == d.H - 1);
     uint32_t bits = 0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        eb[w] = ring_row ? 0u : (eb[w] & cm.bytes[w]);
-        // byte flags -> 4 bits: (b & 0x01010101) * 0x01020408 puts them in bits 24..27
-        bits |= (((eb[w] & 0x01010101u) * 0x01020408u) >> 24) << (4 * w);
+        // four 0/1 flags as bytes, masked to the allowed columns
+        uint32_t f = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, e16[2 * w + 1]),
+                                           __builtin_bit_cast(uint32_t, e16[2 * w]), 0x06040200u);
+        f = ring_row ? 0u : (f & cm.bytes[w]);
+        // byte flags -> 4 bits: f * 0x01020408 puts them in bits 24..27
+        bits |= ((f * 0x01020408u) >> 24) << (4 * w);
+        eb[w] = f * 255u;  // 0 / 255 per byte, no carries
     }
     if (active) {
         const size_t o = (size_t)y * d.W + x0;
