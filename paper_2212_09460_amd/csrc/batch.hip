@@ -35,6 +35,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* des
                                               int total_blocks, int grid_keys, int grid_select,
                                               hipStream_t s);
 extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
+extern "C" LANE_INTERNAL int lane_vote_rows_default(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
 extern "C" LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T);
 extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
@@ -227,7 +228,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.acc = f.acc;
         v.dropped = f.counters_opt ? f.counters_opt + 1 : nullptr;
         const int tmax = lane_vote_rows_per_group(f.W, f.H, f.n_theta, f.n_r);
-        v.T = tune.vote_rows > 0 ? std::min(tmax, std::min(tune.vote_rows, pow2_floor(f.n_theta))) : tmax;
+        v.T = tune.vote_rows > 0 ? std::min(tmax, std::min(tune.vote_rows, pow2_floor(f.n_theta)))
+                                 : lane_vote_rows_default(f.W, f.H, f.n_theta, f.n_r);
         v.log2T = ilog2_floor((unsigned)v.T);
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
         v.E = E;

@@ -134,12 +134,34 @@ LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r) {
     return D + 3 < n_r ? D + 3 : n_r;
 }
 
-// LDS words a vote workgroup needs for slices of T rows laid out back to
-// back (T x the row cap).  The kernel uses the interleaved layout instead
-// when the slice's r span times T also fits.
+// LDS words a vote workgroup needs for slices of T rows: the rows back to
+// back (T x the row cap) or, when the frame is small enough for the paired
+// counters, T x ceil(span / 2) with span the r range of a slice's rows --
+// from the exact corner values, widened by 4 for the table's rounding; the
+// kernel measures the real span and picks the layout that fits.
 LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T) {
-    (void)n_theta;
-    return (long)T * lane_vote_row_cap(W, H, n_r);
+    const long plain = (long)T * lane_vote_row_cap(W, H, n_r);
+    if (T > n_theta || 2 * (W + H + 2) > 16383) return plain;
+    const double pi = 3.14159265358979323846;
+    long worst = 0;
+    for (int s = 0; s * T < n_theta; ++s) {
+        const int k0 = s * T < n_theta - T ? s * T : n_theta - T;
+        double lo = 1e300, hi = -1e300;
+        for (int k = k0; k < k0 + T; ++k) {
+            const double c = cos(pi * k / n_theta), sn = sin(pi * k / n_theta);
+            const double xs[4] = {0.0, (double)(W - 1), 0.0, (double)(W - 1)};
+            const double ys[4] = {0.0, 0.0, (double)(H - 1), (double)(H - 1)};
+            for (int q = 0; q < 4; ++q) {
+                const double r = xs[q] * c + ys[q] * sn;
+                lo = r < lo ? r : lo;
+                hi = r > hi ? r : hi;
+            }
+        }
+        const long span = (long)(floor(hi + 0.5) - floor(lo + 0.5)) + 1 + 4;
+        const long words = (span + 1) / 2 * T;
+        worst = words > worst ? words : worst;
+    }
+    return worst < plain ? worst : plain;
 }
 
 // Rows per vote workgroup: the largest power of two <= 64 and <= n_theta
@@ -148,6 +170,16 @@ LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta
     int T = kMaxT;
     while (T > 1 && (T > n_theta || lane_vote_slice_words(W, H, n_theta, n_r, T) > kVoteLdsWords)) T >>= 1;
     return T;
+}
+
+// Default rows per batched vote workgroup: the largest T whose slices fit the
+// half-size LDS variant (two workgroups per CU hide each other's LDS latency),
+// unless the full-size maximum is more than twice that.
+LANE_INTERNAL int lane_vote_rows_default(int32_t W, int32_t H, int32_t n_theta, int32_t n_r) {
+    const int tmax = lane_vote_rows_per_group(W, H, n_theta, n_r);
+    int th = tmax;
+    while (th > 1 && lane_vote_slice_words(W, H, n_theta, n_r, th) > kVoteLdsWordsHalf) th >>= 1;
+    return 2 * th >= tmax ? th : tmax;
 }
 
 int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* cos_q14,
@@ -174,7 +206,11 @@ int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* c
     d.tile_mask = tile_mask_opt;
     d.acc = acc;
     d.dropped = dropped_opt;
+    // one frame: few rows per workgroup, so the slices fill the CUs
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     d.T = lane_vote_rows_per_group(W, H, n_theta, n_r);
+    while (d.T > 1 && (n_theta + d.T - 1) / d.T < cus) d.T >>= 1;
     d.log2T = ilog2_floor((unsigned)d.T);
     d.n_slices = (n_theta + d.T - 1) / d.T;
     if (dropped_opt) {

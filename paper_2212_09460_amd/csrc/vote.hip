@@ -52,7 +52,8 @@ struct VoteLds {
     int32_t acc[LDSW];
     int lo[kMaxT], win[kMaxT], base[kMaxT];
     int fast, total, item, last;
-    int il, lo_min, span;  // interleaved layout: on/off, lowest r_idx of the slice, its r span
+    int il, lo_min, span;  // layout (0 rows back to back, 1 interleaved, 2 interleaved pairs),
+                           // lowest r_idx of the slice, its r span
     uint32_t dropped;
 };
 
@@ -79,9 +80,26 @@ __device__ __forceinline__ void lds_vote_il(VoteLds<LDSW>& L, uint32_t v, uint32
                            1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool B>
+// Interleaved pairs: cells u = 2m and 2m + 1 of row j share word m*T + j;
+// a vote adds 1 to the word's low 14 bits and, for odd u, also 1 << 14, so
+// the low field counts both cells and the high field the odd one (even =
+// low - high).  Half the words of the interleaved layout for one more
+// instruction ((v & 2^14) | 1 is one v_and_or); with T = 32 rows every lane
+// of a pixel owns bank j and the wave's two pixels meet at most pairwise,
+// the fewest bank cycles a 64-lane atomic can take.  Needs every cell count
+// below 2^13 (a cell holds at most D + 2 pixels).
+template <int LDSW>
+__device__ __forceinline__ void lds_vote_il2(VoteLds<LDSW>& L, uint32_t v, uint32_t jb, int sh) {
+    const uint32_t adr = ((v >> 15) << sh) | jb;
+    const uint32_t inc = (v & 0x4000u) | 1u;
+    __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(
+                               __builtin_assume_aligned(reinterpret_cast<char*>(L.acc) + adr, 4)),
+                           inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int M>
 struct Mode {
-    static constexpr bool value = B;
+    static constexpr int value = M;
 };
 
 // slots of one wave that share a segment when the slice has few rows
@@ -139,20 +157,24 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
             lo_min = min(lo_min, sm.lo[q]);
             hi_max = max(hi_max, sm.lo[q] + sm.win[q] - 1);
         }
-        // interleaved whenever the slice's r span fits
+        // layout: pairs when 32 or more rows make them conflict-free, else
+        // interleaved, else pairs to fit, else rows back to back
         const int span = hi_max - lo_min + 1;
-        const int il_words = span * T;
-        const bool il = il_words <= LDSW && (E == 1 || il_words <= d.part_stride);
-        const bool plain_fit = base <= LDSW && (E == 1 || base <= d.part_stride);
-        sm.il = il ? 1 : 0;
+        auto fits = [&](int w) { return w <= LDSW && (E == 1 || w <= d.part_stride); };
+        const int il_words = span * T, il2_words = ((span + 1) >> 1) * T;
+        // a cell counts at most D + 2 pixels (D = the frame diagonal, below W + H)
+        const bool il2_ok = 2 * (d.W + d.H + 2) <= 16383 && fits(il2_words);
+        const int mode = (T >= 32 && il2_ok) ? 2 : fits(il_words) ? 1 : il2_ok ? 2 : 0;
+        sm.il = mode;
         sm.lo_min = lo_min;
         sm.span = span;
-        sm.total = il ? il_words : base;
-        if (!il && !plain_fit) sm.fast = 0;
+        sm.total = mode == 2 ? il2_words : mode == 1 ? il_words : base;
+        if (mode == 0 && !fits(base)) sm.fast = 0;
     }
     __syncthreads();
     const bool fast = sm.fast != 0;
-    const bool il = sm.il != 0;
+    const int layout = sm.il;
+    const bool il = layout != 0;
     // the exact fallback runs unsplit, in part 0 (the same decision in every part)
     if (!fast && part != 0) return;
     const int seg_lo = fast ? (int)(((long long)L.nseg * part) / E) : 0;
@@ -177,10 +199,11 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         const int sh = 2 + d.log2T;
         __syncthreads();
         auto body = [&](auto mode) {
-        constexpr bool kIL = decltype(mode)::value;
+        constexpr int kIL = decltype(mode)::value;
         auto vote1 = [&](uint32_t xy) {
             const uint32_t v = (uint32_t)dot2_i16((int)xy, CS, K);
-            if constexpr (kIL) lds_vote_il(sm, v, jb, sh);
+            if constexpr (kIL == 2) lds_vote_il2(sm, v, jb, sh);
+            else if constexpr (kIL == 1) lds_vote_il(sm, v, jb, sh);
             else lds_vote(sm, v);
         };
         auto vote4 = [&](u32x4 q) {
@@ -199,24 +222,37 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 const int nfull = part / 4;
                 const uint32_t* p = ents + gs * part;
                 // software pipeline: U 128-bit loads per lane stay in flight
-                // while the previous U are voted
+                // while the previous U are voted; two register sets take
+                // turns, so no copies between them
                 constexpr int U = 4;
                 int it = 0;
                 if (nfull >= U) {
-                    u32x4 cur[U];
+                    u32x4 a[U], b[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) cur[u] = gld4(p + 4 * u);
-                    for (it = U; it + U <= nfull; it += U) {
-                        u32x4 nxt[U];
+                    for (int u = 0; u < U; ++u) a[u] = gld4(p + 4 * u);
+                    for (it = U; it + 2 * U <= nfull; it += 2 * U) {
 #pragma unroll
-                        for (int u = 0; u < U; ++u) nxt[u] = gld4(p + 4 * (it + u));
+                        for (int u = 0; u < U; ++u) b[u] = gld4(p + 4 * (it + u));
 #pragma unroll
-                        for (int u = 0; u < U; ++u) vote4(cur[u]);
+                        for (int u = 0; u < U; ++u) vote4(a[u]);
 #pragma unroll
-                        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+                        for (int u = 0; u < U; ++u) a[u] = gld4(p + 4 * (it + U + u));
+#pragma unroll
+                        for (int u = 0; u < U; ++u) vote4(b[u]);
                     }
+                    // a holds entries [it - U, it); fewer than 2U groups remain
+                    if (it + U <= nfull) {
 #pragma unroll
-                    for (int u = 0; u < U; ++u) vote4(cur[u]);
+                        for (int u = 0; u < U; ++u) b[u] = gld4(p + 4 * (it + u));
+#pragma unroll
+                        for (int u = 0; u < U; ++u) vote4(a[u]);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) vote4(b[u]);
+                        it += U;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) vote4(a[u]);
+                    }
                 }
                 for (; it < nfull; ++it) vote4(gld4(p + 4 * it));
                 // remainder (fewer than 4 Gs entries), shared by all slots
@@ -321,8 +357,9 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
             }
         }
         };
-        if (il) body(Mode<true>{});
-        else body(Mode<false>{});
+        if (layout == 2) body(Mode<2>{});
+        else if (layout == 1) body(Mode<1>{});
+        else body(Mode<0>{});
         __syncthreads();
         if (E > 1) {
             // publish this part's rows; the last part to arrive merges
@@ -350,9 +387,16 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         const int q0 = own_from - k0;  // first owned row of the slice
         const int lo_min = sm.lo_min, span = sm.span;
         auto cell = [&](int q, int rlo, int rwin, int rbase, int i) -> int {
-            if (il) {
+            if (layout == 1) {
                 const int u = i - lo_min;
                 return (u >= 0 && u < span) ? sm.acc[u * T + q] : 0;
+            }
+            if (layout == 2) {
+                const int u = i - lo_min;
+                if (u < 0 || u >= span) return 0;
+                const uint32_t w = (uint32_t)sm.acc[(u >> 1) * T + q];
+                const uint32_t odd = w >> 14;
+                return (int)((u & 1) ? odd : (w & 0x3FFFu) - odd);
             }
             const int o = i - rlo;
             return (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0;
