@@ -65,6 +65,10 @@ __device__ __forceinline__ RawRow load_raw(const uint8_t* __restrict__ img, int 
     return o;
 }
 
+// DPP controls: every lane takes the value of lane - 1 / lane + 1
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+
 // Horizontal pass on packed pairs: pixel pair k = (a[2k], a[2k+1]).
 struct HRow {
     u16x2 hs[8];  // [1 2 1] smooth
@@ -75,9 +79,10 @@ template <bool FAST>
 __device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
     int left = (int)(r.lr & 0xFFu), right = (int)(r.lr >> 8);
     if (FAST) {
-        // neighbours from the adjacent lanes (lane 0 / 63 loaded theirs)
-        const uint32_t up = (uint32_t)__shfl((int)r.v.w, lane > 0 ? lane - 1 : 0);
-        const uint32_t dn = (uint32_t)__shfl((int)r.v.x, lane < kWave - 1 ? lane + 1 : kWave - 1);
+        // neighbours from the adjacent lanes by whole-wave DPP shifts by one
+        // lane (lane 0 / 63 loaded theirs)
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r.v.w, kDppWaveShr1, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)r.v.x, kDppWaveShl1, 0xF, 0xF, false);
         if (lane > 0) left = (int)(up >> 24);
         if (lane < kWave - 1) right = (int)(dn & 0xFFu);
     }
@@ -104,8 +109,8 @@ __device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
 // Per-lane constants of the output masking: which of the lane's 16 columns
 // may be edges (inside the frame; not on the ring in border mode 1).
 struct ColMask {
-    uint32_t bits;     // bit i: column x0 + i may be an edge
-    uint32_t bytes[4]; // 0x01 per allowed column, as the edge-map bytes
+    uint32_t bits;   // bit i: column x0 + i may be an edge
+    uint32_t sel[4]; // byte selectors of the edge-map dwords (below): sign of the pixel's half, or 0
 };
 
 __device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
@@ -117,24 +122,16 @@ __device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
         const bool ok = (x < d.W) && !(d.border_mode == 1 && (x == 0 || x == d.W - 1));
         c.bits |= (uint32_t)ok << i;
     }
+    // v_perm_b32 selectors 8..11 give 0xFF or 0x00 by bit 15 / 31 of the
+    // second and first source; 12 gives 0x00
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         uint32_t b = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) b |= ((c.bits >> (4 * w + i)) & 1u) << (8 * i);
-        c.bytes[w] = b;
+        for (int i = 0; i < 4; ++i) b |= (((c.bits >> (4 * w + i)) & 1u) ? (uint32_t)(8 + i) : 0x0Cu) << (8 * i);
+        c.sel[w] = b;
     }
     return c;
-}
-
-__device__ __forceinline__ u16x2 flag_above(u16x2 g, uint32_t tt) {
-    // both halves of every operand are registers (an inline constant would
-    // give the high half 0)
-    uint32_t r;
-    asm("v_pk_sub_u16 %0, %1, %2 clamp\n\tv_pk_min_u16 %0, %0, %3"
-        : "=&v"(r)
-        : "v"(__builtin_bit_cast(uint32_t, g)), "v"(tt), "v"(0x00010001u));
-    return __builtin_bit_cast(u16x2, r);
 }
 
 // Vertical pass and output of row y.  X = hd(y-1) + 2 hd(y) and
@@ -144,8 +141,8 @@ template <bool FAST>
 __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool active,
                                          const ColMask& cm, const s16x2 (&X)[8],
                                          const u16x2 (&HU)[8], const HRow& D) {
-    const uint32_t TT = (uint32_t)d.threshold * 0x00010001u;
-    u16x2 g[8], e16[8];
+    const u16x2 TT = (u16x2)(unsigned short)d.threshold;
+    u16x2 g[8], ef[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const s16x2 gx = X[k] + D.hd[k];
@@ -153,24 +150,30 @@ __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool
         const s16x2 ax = __builtin_elementwise_max(gx, -gx);
         const s16x2 ay = __builtin_elementwise_max(gy, -gy);
         g[k] = __builtin_bit_cast(u16x2, ax + ay);
-        // 1 if |gx| + |gy| > T else 0: a saturating subtract and a min,
-        // both packed (written out: the compiler would turn the pair into a
-        // compare and select per half)
-        e16[k] = flag_above(g[k], TT);
+        // threshold - g wraps below zero exactly when g > threshold (g <= 2040),
+        // so bit 15 of each half is the pixel's edge flag
+        ef[k] = TT - g[k];
     }
-    uint32_t eb[4];
     const bool ring_row = (d.border_mode == 1) && (y == 0 || y == d.H - 1);
-    uint32_t bits = 0;
+    uint32_t eb[4];
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        // four 0/1 flags as bytes, masked to the allowed columns
-        uint32_t f = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, e16[2 * w + 1]),
-                                           __builtin_bit_cast(uint32_t, e16[2 * w]), 0x06040200u);
-        f = ring_row ? 0u : (f & cm.bytes[w]);
-        // byte flags -> 4 bits: f * 0x01020408 puts them in bits 24..27
-        bits |= ((f * 0x01020408u) >> 24) << (4 * w);
-        eb[w] = f * 255u;  // 0 / 255 per byte, no carries
+        // pixels 4w .. 4w+3 are the halves of pairs 2w, 2w+1: one byte
+        // permute turns their flag bits into 0xFF / 0x00 and zeroes the
+        // columns that may not be edges
+        eb[w] = ring_row ? 0u
+                         : __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, ef[2 * w + 1]),
+                                                 __builtin_bit_cast(uint32_t, ef[2 * w]), cm.sel[w]);
     }
+    // 16 edge bits: each byte's low bit weighted 1, 2, 4, 8 (16 .. 128 for
+    // the next dword) by unsigned byte dot products
+    const uint32_t lo = __builtin_amdgcn_udot4(eb[1] & 0x01010101u, 0x80402010u,
+                                               __builtin_amdgcn_udot4(eb[0] & 0x01010101u, 0x08040201u, 0u, false),
+                                               false);
+    const uint32_t hi = __builtin_amdgcn_udot4(eb[3] & 0x01010101u, 0x80402010u,
+                                               __builtin_amdgcn_udot4(eb[2] & 0x01010101u, 0x08040201u, 0u, false),
+                                               false);
+    const uint32_t bits = lo | (hi << 8);
     if (active) {
         const size_t o = (size_t)y * d.W + x0;
         uint32_t mb[4] = {0u, 0u, 0u, 0u};
@@ -325,22 +328,39 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
             X[k] = Q1.hd[k] + Q0.hd[k] * (short)2;
             HU[k] = Q1.hs[k];
         }
-#define LANE_SOBEL_STEP(QC, QN, R_, dy)                                           \
+#define LANE_SOBEL_STEP(QC, QN, R_, dy, B_)                                       \
     if (y + (dy) < y_end) {                                                       \
         const int yy = y + (dy);                                                  \
         hfilter<FAST>(R_, lane, QN);                                              \
         R_ = load(yy + 5);                                                        \
-        account(yy, vout<FAST>(d, yy, x0, active, cm, X, HU, QN));                \
+        B_ = vout<FAST>(d, yy, x0, active, cm, X, HU, QN);                        \
         _Pragma("unroll") for (int k = 0; k < 8; ++k) {                           \
             X[k] = QC.hd[k] + QN.hd[k] * (short)2;                                \
             HU[k] = QC.hs[k];                                                     \
         }                                                                         \
     }
+        // strips start on a tile row, so each group of 4 rows is rows 0-3 or
+        // 4-7 of its tile row
         for (int y = y_begin; y < y_end; y += 4) {
-            LANE_SOBEL_STEP(Q0, Q1, R0, 0)
-            LANE_SOBEL_STEP(Q1, Q0, R1, 1)
-            LANE_SOBEL_STEP(Q0, Q1, R2, 2)
-            LANE_SOBEL_STEP(Q1, Q0, R3, 3)
+            uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+            LANE_SOBEL_STEP(Q0, Q1, R0, 0, b0)
+            LANE_SOBEL_STEP(Q1, Q0, R1, 1, b1)
+            LANE_SOBEL_STEP(Q0, Q1, R2, 2, b2)
+            LANE_SOBEL_STEP(Q1, Q0, R3, 3, b3)
+            // row r's bits: byte 0 tile a, byte 1 tile b; gather each tile's
+            // four row bytes into one dword (row r in byte r)
+            const uint32_t t01 = __builtin_amdgcn_perm(b1, b0, 0x05010400u);
+            const uint32_t t23 = __builtin_amdgcn_perm(b3, b2, 0x05010400u);
+            const uint32_t qa = __builtin_amdgcn_perm(t23, t01, 0x05040100u);
+            const uint32_t qb = __builtin_amdgcn_perm(t23, t01, 0x07060302u);
+            nedge += (uint32_t)__popc(qa) + (uint32_t)__popc(qb);
+            if (y & 4) {
+                m0 |= (uint64_t)qa << 32;
+                m1 |= (uint64_t)qb << 32;
+            } else {
+                m0 = qa;
+                m1 = qb;
+            }
             if (((y + 4) & (kTile - 1)) == 0 || y + 4 >= y_end) flush(y >> 3);
         }
 #undef LANE_SOBEL_STEP

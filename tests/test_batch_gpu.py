@@ -106,6 +106,29 @@ def test_vote_rows_override(lane, synth, oracle, rows):
     b.close()
 
 
+@pytest.mark.parametrize("rows", [4, 8])
+def test_vote_paired_cells_dense_edges(lane, synth, oracle, rows):
+    """Every interior pixel an edge (columns 0, 0, 255, 255 repeating) on a
+    4094 x 4094 frame, the largest square whose cell pairs the paired LDS
+    layout may count (2 (W + H + 2) <= 16383).  With 16 angles the slices
+    around 45 degrees span about 5800 r cells, too wide for one word per cell
+    at 4 or 8 rows, so the paired layout votes them; a cell pair there gets
+    about 11600 votes."""
+    W = H = 4094
+    say("paired cells, dense edges", W, H, "rows", rows)
+    img = np.tile(np.array([0, 0, 255, 255], np.uint8), (H, W // 4 + 1))[:, :W].copy()
+    C, S = synth.trig_q14(16)
+    want = oracle.pipeline(img, C, S, 4)
+    assert want["n_edges"] == (W - 2) * (H - 2)
+    assert want["acc"].max() > 5000
+    fb = lane.FrameBuffers(torch.from_numpy(img).cuda(), W, 16, 4, torch.from_numpy(C).cuda(),
+                           torch.from_numpy(S).cuda())
+    b = lane.Batch([fb], vote_rows=rows)
+    b.launch()
+    check([fb], [want])
+    b.close()
+
+
 def test_batch_matches_single_frame_calls(lane, synth):
     """A frame gives the same bytes alone (single-frame entry points) and in
     a batch."""
