@@ -222,9 +222,25 @@ __device__ __forceinline__ uint32_t raw_edge_bits(const RawRow& r, int x0, int W
 // kStageCap edges goes out in several passes.
 constexpr int kStageCap = 2048;
 
+static_assert(kWave * kSobelWaves == 256, "one table entry per thread");
+
+// lut[b]: the columns of the set bits of row byte b, in order, one per byte
+__device__ __forceinline__ uint2 row_byte_columns(uint32_t b) {
+    uint64_t v = 0;
+    int n = 0;
+    for (int c = 0; c < 8; ++c) {
+        if ((b >> c) & 1u) {
+            v |= (uint64_t)c << (8 * n);
+            ++n;
+        }
+    }
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
 __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListLayout& L, int chunk,
                                                  int ty, uint64_t m0, uint64_t m1, int lane,
-                                                 uint32_t* __restrict__ stage) {
+                                                 uint32_t* __restrict__ stage,
+                                                 const uint2* __restrict__ lut) {
     const uint32_t ca = (uint32_t)__popcll(m0);
     const uint32_t cb = (uint32_t)__popcll(m1);
     const uint32_t tot = ca + cb;
@@ -247,19 +263,59 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     uint32_t* dst = list + L.off_ent + (size_t)seg * kSegCap;
     const uint32_t xa = (uint32_t)(txa * kTile);
     const uint32_t y0 = (uint32_t)(ty * kTile) << 16;
+    const uint32_t end = off + tot;
     for (uint32_t p0 = 0; p0 < total; p0 += kStageCap) {
-        // this lane's run, tile a then tile b, row-major in a tile; only the
-        // entries of the current pass land in the stage
-        uint32_t e = off - p0;  // wraps for runs before the pass: then >= kStageCap
+        if (total <= (uint32_t)kStageCap) {
+            // One pass.  The lane's 16 row bytes (tile a rows 0-7, tile b
+            // rows 0-7) in order: each writes its entries as a block of 8
+            // (the row's columns from the table; the slots past its count
+            // hold junk that the next row byte overwrites), as long as the
+            // block ends inside the lane's run.  The row bytes after that
+            // (their entries are the run's last seven or fewer) go one
+            // entry at a time.
+            uint32_t p = off, nfull = 0;
+#pragma unroll 8  // fully unrolled, the table loads all hoist and spill
+            for (int j = 0; j < 16; ++j) {
+                const uint64_t m = j < 8 ? m0 : m1;
+                const uint32_t b = (uint32_t)(m >> (8 * (j & 7))) & 0xFFu;
+                const uint2 cols = lut[b];
+                const uint32_t rb = y0 + ((uint32_t)(j & 7) << 16) + xa + (j < 8 ? 0u : (uint32_t)kTile);
+                if (p + 8u <= end) {
+                    uint32_t* q = stage + p;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
-            uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
-            const uint32_t base = y0 + ((uint32_t)((q & 1) * 4) << 16) + xa + (uint32_t)((q >> 1) * kTile);
-            while (m) {
-                const uint32_t bit = (uint32_t)__builtin_ctz(m);
-                m &= m - 1u;
-                if (e < (uint32_t)kStageCap) stage[e] = base + ((bit >> 3) << 16) + (bit & 7u);
-                ++e;
+                    for (int i = 0; i < 4; ++i) q[i] = rb + ((cols.x >> (8 * i)) & 0xFFu);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[4 + i] = rb + ((cols.y >> (8 * i)) & 0xFFu);
+                    ++nfull;
+                }
+                p += (uint32_t)__popc(b);
+            }
+            // row bytes nfull .. 15
+            uint64_t t0 = nfull >= 8 ? 0ull : (m0 >> (8 * nfull)) << (8 * nfull);
+            uint64_t t1 = nfull <= 8 ? m1 : nfull >= 16 ? 0ull : (m1 >> (8 * (nfull - 8))) << (8 * (nfull - 8));
+            uint32_t e = end - (uint32_t)(__popcll(t0) + __popcll(t1));
+            while (t0 | t1) {
+                const bool in_a = t0 != 0;
+                const uint64_t m = in_a ? t0 : t1;
+                const uint32_t bit = (uint32_t)__builtin_ctzll(m);
+                stage[e++] = y0 + ((bit >> 3) << 16) + xa + (in_a ? 0u : (uint32_t)kTile) + (bit & 7u);
+                if (in_a) t0 &= t0 - 1ull;
+                else t1 &= t1 - 1ull;
+            }
+        } else {
+            // this lane's run, tile a then tile b, row-major in a tile; only
+            // the entries of the current pass land in the stage
+            uint32_t e = off - p0;  // wraps for runs before the pass: then >= kStageCap
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
+                uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
+                const uint32_t base = y0 + ((uint32_t)((q & 1) * 4) << 16) + xa + (uint32_t)((q >> 1) * kTile);
+                while (m) {
+                    const uint32_t bit = (uint32_t)__builtin_ctz(m);
+                    m &= m - 1u;
+                    if (e < (uint32_t)kStageCap) stage[e] = base + ((bit >> 3) << 16) + (bit & 7u);
+                    ++e;
+                }
             }
         }
         // the stage is read by other lanes of the same wave: order the LDS
@@ -279,7 +335,8 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
 }
 
 template <bool FAST, int MODE>
-__device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ stage) {
+__device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ stage,
+                           const uint2* __restrict__ lut) {
     const int lane = threadIdx.x & (kWave - 1);
     const ListLayout L = list_layout(d.W, d.H);
     const int chunk = item % L.nchunk;
@@ -299,7 +356,7 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         m1 |= (uint64_t)((bits >> 8) & 0xFFu) << (ly * 8);
     };
     auto flush = [&](int ty) {
-        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane, stage);
+        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane, stage, lut);
         m0 = 0;
         m1 = 0;
     };
@@ -377,10 +434,13 @@ template <bool FAST, int MODE>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel(SobelDesc d, int n_items) {
     __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
+    __shared__ uint2 s_lut[256];
+    s_lut[threadIdx.x] = row_byte_columns(threadIdx.x);  // 256 threads
+    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int item = blockIdx.x * kSobelWaves + wave;
-    if (item >= n_items) return;  // whole wave leaves; no barriers in this kernel
-    sobel_item<FAST, MODE>(d, item, s_stage + wave * kStageCap);
+    if (item >= n_items) return;  // whole wave leaves; no barriers after this
+    sobel_item<FAST, MODE>(d, item, s_stage + wave * kStageCap, s_lut);
 }
 
 // Batched, persistent: each wave walks the (frame, item) table with a grid
@@ -396,6 +456,9 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
     const int n_items = gld(counts + group);
     items += first;
     __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
+    __shared__ uint2 s_lut[256];
+    s_lut[threadIdx.x] = row_byte_columns(threadIdx.x);  // 256 threads
+    __syncthreads();
     // wave-uniform indices, so the table and descriptor loads are scalar
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int it = blockIdx.x * kSobelWaves + wave; it < n_items; it += gridDim.x * kSobelWaves) {
@@ -403,7 +466,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
         if (w.x < 0) continue;
         const SobelDesc d = descs[w.x];
         if (!frame_on(d.active)) continue;
-        sobel_item<FAST, kModeSobel>(d, w.y, s_stage + wave * kStageCap);
+        sobel_item<FAST, kModeSobel>(d, w.y, s_stage + wave * kStageCap, s_lut);
     }
 }
 

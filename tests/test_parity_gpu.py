@@ -123,6 +123,42 @@ def test_edges_to_list(lane, W, H, p):
     assert int(host(cnt)[0]) == int((e == 255).sum())
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_edges_to_list_tile_patterns(lane, seed):
+    """Edge maps built tile by tile from patterns that exercise the list
+    writer's cases: empty tiles, single pixels, full first / last rows (a
+    lane's run ending in a full row), full tiles, sparse and dense random
+    tiles, and tile rows above and below the one-pass stage size (2048)."""
+    rng = np.random.default_rng(100 + seed)
+    W, H = 2048 + 8 * seed + 16, 96
+    th, tw = H // 8, W // 8
+    e = np.zeros((H, W), np.uint8)
+    for ty in range(th):
+        dense_row = ty % 4 == 3  # more than 2048 edges in some segments
+        for tx in range(tw):
+            kind = rng.integers(0, 8)
+            t = np.zeros((8, 8), bool)
+            if kind == 1:
+                t[rng.integers(0, 8), rng.integers(0, 8)] = True
+            elif kind == 2:
+                t[7, :] = True
+            elif kind == 3:
+                t[0, :] = True
+            elif kind == 4 and (dense_row or rng.random() < 0.1):
+                t[:, :] = True
+            elif kind == 5:
+                t = rng.random((8, 8)) < 0.2
+            elif kind == 6:
+                t = rng.random((8, 8)) < (0.9 if dense_row else 0.4)
+            elif kind == 7:
+                t[7, rng.integers(0, 8):] = True
+            e[ty * 8:ty * 8 + 8, tx * 8:tx * 8 + 8] = np.where(t, 255, 0)
+    say("edges_to_list tile patterns", W, H, seed, int((e == 255).sum()))
+    lst, cnt = lane.edges_to_list(dev(e), W)
+    check_list_matches_edges(lst, e, W, H)
+    assert int(host(cnt)[0]) == int((e == 255).sum())
+
+
 def vote_both(lane, oracle, e, W, H, C, S, D, n_r, mask=None):
     lst, _ = lane.edges_to_list(dev(e), W)
     acc, dropped = lane.hough_vote(lst, W, H, dev(C), dev(S), D, n_r,
