@@ -33,35 +33,50 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 // from its own wave (lane 0's left, lane 63's right; others come by shuffle)
 struct RawRow {
     u32x4 v;
-    uint32_t lr;  // left | right << 8
+    uint32_t l, r;  // left and right neighbour bytes, kept as loaded (no
+                    // arithmetic on a load result here: that would make the
+                    // wave wait for every load in flight)
 };
 
+// Rows of a frame whose rows are 16-byte aligned are read with raw buffer
+// loads over the whole image (base, pitch x H bytes): a lane or row outside
+// the frame passes an offset past the end and the hardware returns zeros.
+// No branch and no merge of loaded and zero values, so the loads kept in
+// flight across the row loop never force a wait for all of them.
+constexpr uint32_t kBufOutside = 0x80000000u;
+constexpr int kBufConfig = 0x00020000;  // raw buffer, 32-bit format (gfx9 family)
+
 template <bool FAST>
-__device__ __forceinline__ RawRow load_raw(const uint8_t* __restrict__ img, int W, int H, int pitch,
-                                           int y, int x0, bool active, int lane) {
+__device__ __forceinline__ RawRow load_raw(const uint8_t* __restrict__ img, __amdgpu_buffer_rsrc_t rsrc,
+                                           int W, int H, int pitch, int y, int x0, bool active,
+                                           int lane) {
     RawRow o;
-    o.v = u32x4{0u, 0u, 0u, 0u};
-    o.lr = 0;
     const bool yin = (y >= 0) && (y < H);
+    if (FAST) {
+        const bool ok = active && yin;
+        const uint32_t off = ok ? (uint32_t)(y * pitch + x0) : kBufOutside;
+        o.v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0));
+        o.l = __builtin_amdgcn_raw_buffer_load_b8(rsrc, (ok && lane == 0 && x0 > 0) ? off - 1u : kBufOutside,
+                                                  0, 0);
+        o.r = __builtin_amdgcn_raw_buffer_load_b8(
+            rsrc, (ok && lane == kWave - 1 && x0 + 16 < W) ? off + 16u : kBufOutside, 0, 0);
+        return o;
+    }
+    o.v = u32x4{0u, 0u, 0u, 0u};
+    o.l = 0;
+    o.r = 0;
     if (!(active && yin)) return o;
     const uint8_t* row = img + (size_t)y * pitch;
-    if (FAST) {
-        o.v = gld4(row + x0);
-        if (lane == 0 && x0 > 0) o.lr = gld(row + x0 - 1);
-        if (lane == kWave - 1 && x0 + 16 < W) o.lr = (uint32_t)gld(row + x0 + 16) << 8;
-    } else {
-        uint32_t p[4] = {0u, 0u, 0u, 0u};
+    uint32_t p[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int x = x0 + i;
-            const uint32_t b = (x < W) ? (uint32_t)gld(row + x) : 0u;
-            p[i >> 2] |= b << ((i & 3) * 8);
-        }
-        o.v = u32x4{p[0], p[1], p[2], p[3]};
-        const uint32_t l = (x0 > 0) ? gld(row + x0 - 1) : 0u;
-        const uint32_t rr = (x0 + 16 < W) ? gld(row + x0 + 16) : 0u;
-        o.lr = l | (rr << 8);
+    for (int i = 0; i < 16; ++i) {
+        const int x = x0 + i;
+        const uint32_t b = (x < W) ? (uint32_t)gld(row + x) : 0u;
+        p[i >> 2] |= b << ((i & 3) * 8);
     }
+    o.v = u32x4{p[0], p[1], p[2], p[3]};
+    o.l = (x0 > 0) ? gld(row + x0 - 1) : 0u;
+    o.r = (x0 + 16 < W) ? gld(row + x0 + 16) : 0u;
     return o;
 }
 
@@ -77,7 +92,7 @@ struct HRow {
 
 template <bool FAST>
 __device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
-    int left = (int)(r.lr & 0xFFu), right = (int)(r.lr >> 8);
+    int left = (int)r.l, right = (int)r.r;
     if (FAST) {
         // neighbours from the adjacent lanes by whole-wave DPP shifts by one
         // lane (lane 0 / 63 loaded theirs)
@@ -360,8 +375,10 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         m0 = 0;
         m1 = 0;
     };
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)d.img, (short)0, (int)((uint32_t)d.pitch * (uint32_t)d.H), kBufConfig);
     auto load = [&](int y) {
-        return load_raw<FAST>(d.img, d.W, d.H, d.pitch, y, x0, active && y < y_load_end, lane);
+        return load_raw<FAST>(d.img, rsrc, d.W, d.H, d.pitch, y, x0, active && y < y_load_end, lane);
     };
 
     if (MODE == kModeFromEdges) {
@@ -373,24 +390,31 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         const ColMask cm = col_mask(d, x0);
         // raw rows y+1 .. y+4 in flight; Q0/Q1 alternate as "row y" and
         // "row y+1"; X = hd(y-1) + 2 hd(y) and HU = hs(y-1) carry over
+        // (the two rows needed first are issued first)
+        const RawRow Rm = load(y_begin - 1), Rc = load(y_begin);
         RawRow R0 = load(y_begin + 1), R1 = load(y_begin + 2);
         RawRow R2 = load(y_begin + 3), R3 = load(y_begin + 4);
         HRow Q0, Q1;
         s16x2 X[8];
         u16x2 HU[8];
-        hfilter<FAST>(load(y_begin - 1), lane, Q1);
-        hfilter<FAST>(load(y_begin), lane, Q0);
+        hfilter<FAST>(Rm, lane, Q1);
+        hfilter<FAST>(Rc, lane, Q0);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             X[k] = Q1.hd[k] + Q0.hd[k] * (short)2;
             HU[k] = Q1.hs[k];
         }
+    // Every step runs (rows past the strip's end are computed and dropped:
+    // no store, no bits), so no branch surrounds the loads and the waits
+    // for rows in flight stay partial.
 #define LANE_SOBEL_STEP(QC, QN, R_, dy, B_)                                       \
-    if (y + (dy) < y_end) {                                                       \
+    {                                                                             \
         const int yy = y + (dy);                                                  \
+        const bool row_in = yy < y_end;                                           \
         hfilter<FAST>(R_, lane, QN);                                              \
         R_ = load(yy + 5);                                                        \
-        B_ = vout<FAST>(d, yy, x0, active, cm, X, HU, QN);                        \
+        B_ = vout<FAST>(d, yy, x0, active && row_in, cm, X, HU, QN);              \
+        B_ = row_in ? B_ : 0u;                                                    \
         _Pragma("unroll") for (int k = 0; k < 8; ++k) {                           \
             X[k] = QC.hd[k] + QN.hd[k] * (short)2;                                \
             HU[k] = QC.hs[k];                                                     \
@@ -399,7 +423,7 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         // strips start on a tile row, so each group of 4 rows is rows 0-3 or
         // 4-7 of its tile row
         for (int y = y_begin; y < y_end; y += 4) {
-            uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+            uint32_t b0, b1, b2, b3;
             LANE_SOBEL_STEP(Q0, Q1, R0, 0, b0)
             LANE_SOBEL_STEP(Q1, Q0, R1, 1, b1)
             LANE_SOBEL_STEP(Q0, Q1, R2, 2, b2)
