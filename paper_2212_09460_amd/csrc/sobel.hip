@@ -12,8 +12,8 @@
 // bytes are in flight to cover HBM latency.  The 3x3 stencil is split into a
 // horizontal pass per row ([1 2 1] smooth, [-1 0 1] difference, the two
 // neighbour bytes come from the adjacent lanes) and a vertical pass over
-// three rows held in registers.  All of it runs on packed 16-bit pairs
-// (v_pk_* instructions, two pixels per operation): |gx| + |gy| <= 2040 fits.
+// three rows held in registers.  All of it runs on packed pairs (v_pk_*
+// instructions, two pixels per operation), exact (below).
 //
 // Compaction (the vote reads a list of edge coordinates, Sec. 4.3): after
 // every 8 rows each lane holds the 64-bit edge masks of its two 8x8 tiles.
@@ -26,8 +26,14 @@ namespace lane {
 
 enum { kModeSobel = 0, kModeFromEdges = 1 };
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef short s16x2 __attribute__((ext_vector_type(2)));
+// Stencil arithmetic runs on packed half-precision pairs holding the integer
+// values scaled by 2^-24: a pixel byte b in the low byte of a 16-bit half IS
+// the half-precision number b * 2^-24 (a subnormal), and every intermediate
+// (|values| <= 2040, integers) is an integer multiple of 2^-24 below 2^-13,
+// so each addition, doubling and difference is exact.  Packed half
+// instructions give fused 2a + b and an absolute value in one operation each,
+// which the 16-bit integer ones do not.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
 // 16 pixels of one row for one lane, plus the neighbours the lane cannot get
 // from its own wave (lane 0's left, lane 63's right; others come by shuffle)
@@ -86,8 +92,8 @@ constexpr int kDppWaveShl1 = 0x130;
 
 // Horizontal pass on packed pairs: pixel pair k = (a[2k], a[2k+1]).
 struct HRow {
-    u16x2 hs[8];  // [1 2 1] smooth
-    s16x2 hd[8];  // [-1 0 1] difference
+    h2 hs[8];  // [1 2 1] smooth
+    h2 hd[8];  // [-1 0 1] difference
 };
 
 template <bool FAST>
@@ -102,22 +108,22 @@ __device__ __forceinline__ void hfilter(const RawRow& r, int lane, HRow& h) {
         if (lane < kWave - 1) right = (int)(dn & 0xFFu);
     }
     const uint32_t dw[4] = {r.v.x, r.v.y, r.v.z, r.v.w};
-    u16x2 P[8], S[9];
+    h2 P[8], S[9];
     // P[k] = (a[2k], a[2k+1]);  S[k] = (a[2k-1], a[2k]) with a[-1] = left, a[16] = right
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        P[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, dw[k >> 1], (k & 1) ? 0x0c030c02u : 0x0c010c00u));
-    S[0] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(dw[0], (uint32_t)left, 0x0c040c00u));
+        P[k] = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0u, dw[k >> 1], (k & 1) ? 0x0c030c02u : 0x0c010c00u));
+    S[0] = __builtin_bit_cast(h2, __builtin_amdgcn_perm(dw[0], (uint32_t)left, 0x0c040c00u));
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
-        if (k & 1) S[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(0u, dw[k >> 1], 0x0c020c01u));
-        else S[k] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(dw[k >> 1], dw[(k >> 1) - 1], 0x0c040c03u));
+        if (k & 1) S[k] = __builtin_bit_cast(h2, __builtin_amdgcn_perm(0u, dw[k >> 1], 0x0c020c01u));
+        else S[k] = __builtin_bit_cast(h2, __builtin_amdgcn_perm(dw[k >> 1], dw[(k >> 1) - 1], 0x0c040c03u));
     }
-    S[8] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm((uint32_t)right, dw[3], 0x0c040c03u));
+    S[8] = __builtin_bit_cast(h2, __builtin_amdgcn_perm((uint32_t)right, dw[3], 0x0c040c03u));
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        h.hs[k] = S[k] + P[k] * (unsigned short)2 + S[k + 1];
-        h.hd[k] = __builtin_bit_cast(s16x2, S[k + 1]) - __builtin_bit_cast(s16x2, S[k]);
+        h.hs[k] = (S[k] + S[k + 1]) + P[k] * (_Float16)2;
+        h.hd[k] = S[k + 1] - S[k];
     }
 }
 
@@ -154,19 +160,17 @@ __device__ __forceinline__ ColMask col_mask(const SobelDesc& d, int x0) {
 // 16 edge bits.
 template <bool FAST>
 __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool active,
-                                         const ColMask& cm, const s16x2 (&X)[8],
-                                         const u16x2 (&HU)[8], const HRow& D) {
-    const u16x2 TT = (u16x2)(unsigned short)d.threshold;
-    u16x2 g[8], ef[8];
+                                         const ColMask& cm, const h2 (&X)[8],
+                                         const h2 (&HU)[8], const HRow& D) {
+    const h2 TT = __builtin_bit_cast(h2, (uint32_t)d.threshold * 0x00010001u);
+    h2 g[8], ef[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const s16x2 gx = X[k] + D.hd[k];
-        const s16x2 gy = __builtin_bit_cast(s16x2, D.hs[k]) - __builtin_bit_cast(s16x2, HU[k]);
-        const s16x2 ax = __builtin_elementwise_max(gx, -gx);
-        const s16x2 ay = __builtin_elementwise_max(gy, -gy);
-        g[k] = __builtin_bit_cast(u16x2, ax + ay);
-        // threshold - g wraps below zero exactly when g > threshold (g <= 2040),
-        // so bit 15 of each half is the pixel's edge flag
+        const h2 gx = X[k] + D.hd[k];
+        const h2 gy = D.hs[k] - HU[k];
+        g[k] = __builtin_elementwise_abs(gx) + __builtin_elementwise_abs(gy);
+        // threshold - g is negative exactly when g > threshold, so the sign
+        // (bit 15 of each half) is the pixel's edge flag
         ef[k] = TT - g[k];
     }
     const bool ring_row = (d.border_mode == 1) && (y == 0 || y == d.H - 1);
@@ -195,8 +199,10 @@ __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool
         if (d.mag) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const u16x2 m0 = __builtin_elementwise_min(g[2 * w], (u16x2)(unsigned short)255);
-                const u16x2 m1 = __builtin_elementwise_min(g[2 * w + 1], (u16x2)(unsigned short)255);
+                // min(g, 255): for values up to 255 the half's low byte is the value
+                const h2 c255 = __builtin_bit_cast(h2, 0x00FF00FFu);
+                const h2 m0 = __builtin_elementwise_min(g[2 * w], c255);
+                const h2 m1 = __builtin_elementwise_min(g[2 * w + 1], c255);
                 mb[w] = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, m1),
                                               __builtin_bit_cast(uint32_t, m0), 0x06040200u);
             }
@@ -395,13 +401,13 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         RawRow R0 = load(y_begin + 1), R1 = load(y_begin + 2);
         RawRow R2 = load(y_begin + 3), R3 = load(y_begin + 4);
         HRow Q0, Q1;
-        s16x2 X[8];
-        u16x2 HU[8];
+        h2 X[8];
+        h2 HU[8];
         hfilter<FAST>(Rm, lane, Q1);
         hfilter<FAST>(Rc, lane, Q0);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            X[k] = Q1.hd[k] + Q0.hd[k] * (short)2;
+            X[k] = Q1.hd[k] + Q0.hd[k] * (_Float16)2;
             HU[k] = Q1.hs[k];
         }
     // Every step runs (rows past the strip's end are computed and dropped:
@@ -416,7 +422,7 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         B_ = vout<FAST>(d, yy, x0, active && row_in, cm, X, HU, QN);              \
         B_ = row_in ? B_ : 0u;                                                    \
         _Pragma("unroll") for (int k = 0; k < 8; ++k) {                           \
-            X[k] = QC.hd[k] + QN.hd[k] * (short)2;                                \
+            X[k] = QC.hd[k] + QN.hd[k] * (_Float16)2;                             \
             HU[k] = QC.hs[k];                                                     \
         }                                                                         \
     }
