@@ -295,21 +295,26 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
             // (their entries are the run's last seven or fewer) go one
             // entry at a time.
             uint32_t p = off, nfull = 0;
-#pragma unroll 8  // fully unrolled, the table loads all hoist and spill
-            for (int j = 0; j < 16; ++j) {
-                const uint64_t m = j < 8 ? m0 : m1;
-                const uint32_t b = (uint32_t)(m >> (8 * (j & 7))) & 0xFFu;
-                const uint2 cols = lut[b];
-                const uint32_t rb = y0 + ((uint32_t)(j & 7) << 16) + xa + (j < 8 ? 0u : (uint32_t)kTile);
-                if (p + 8u <= end) {
-                    uint32_t* q = stage + p;
+#pragma unroll 1  // (unrolled, the table reads of all 16 hoist and spill)
+            for (int g = 0; g < 4; ++g) {  // four row bytes at a time: their table reads go out together
+                const uint32_t w = (uint32_t)((g < 2 ? m0 : m1) >> (32 * (g & 1)));
+                uint2 cols[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] = rb + ((cols.x >> (8 * i)) & 0xFFu);
+                for (int i = 0; i < 4; ++i) cols[i] = lut[(w >> (8 * i)) & 0xFFu];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) q[4 + i] = rb + ((cols.y >> (8 * i)) & 0xFFu);
-                    ++nfull;
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 4 * g + i;
+                    const uint32_t rb = y0 + ((uint32_t)(j & 7) << 16) + xa + (j < 8 ? 0u : (uint32_t)kTile);
+                    if (p + 8u <= end) {
+                        uint32_t* q = stage + p;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) q[c] = rb + ((cols[i].x >> (8 * c)) & 0xFFu);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) q[4 + c] = rb + ((cols[i].y >> (8 * c)) & 0xFFu);
+                        ++nfull;
+                    }
+                    p += (uint32_t)__popc((w >> (8 * i)) & 0xFFu);
                 }
-                p += (uint32_t)__popc(b);
             }
             // row bytes nfull .. 15
             uint64_t t0 = nfull >= 8 ? 0ull : (m0 >> (8 * nfull)) << (8 * nfull);
