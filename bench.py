@@ -214,6 +214,22 @@ def main():
                 lat.append(a.elapsed_time(b))
         one.close()
     lat = np.array(lat if lat else [float("nan")])
+
+    # practical reference for the Sobel pass: a plain device copy moving the
+    # same number of bytes (half read, half written), timed the same way
+    nb = sobel_bytes // 2
+    csrc = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        cdst.copy_(csrc)
+    c1.record(stream)
+    c1.synchronize()
+    copy_gbs = 2 * nb / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del csrc, cdst
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -255,7 +271,9 @@ def main():
                            "achieved": round(sobel_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(sobel_gbs / HBM_PEAK_GBS, 4),
                            "traffic": profiled_traffic("k_sobel_batch", "sobel.hip") if B == 256 else None,
-                           "bytes_per_launch": sobel_bytes},
+                           "bytes_per_launch": sobel_bytes,
+                           "device_copy_gbs": round(copy_gbs, 1),
+                           "frac_of_device_copy": round(sobel_gbs / copy_gbs, 4)},
         "latency_ms_single_frame_gpu": {"p50": round(float(np.percentile(lat, 50)), 4),
                                         "p99": round(float(np.percentile(lat, 99)), 4)},
         "wall_s_timed": round(wall, 3),
