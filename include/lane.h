@@ -177,7 +177,9 @@ typedef struct lane_frame {
 } lane_frame;
 
 typedef struct lane_tune {
-    int32_t vote_rows;        /* theta rows per vote workgroup, power of two; 0 = largest that fits LDS */
+    int32_t vote_rows;        /* theta rows per vote workgroup, power of two; 0 = the largest that
+                                 fits the half-size LDS variant (two workgroups per CU), unless
+                                 the full-size maximum is more than twice that */
     int32_t vote_queue;       /* 1 = dynamic ticket queue (longest items first), 0 = static stride
                                  with each frame's slices on one XCD, -1 = automatic */
     int32_t sobel_groups_per_cu; /* persistent Sobel workgroups per CU; 0 = occupancy limit */
