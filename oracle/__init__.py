@@ -5,8 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 or calls it; the oracle imports nothing from the product.
 
 ``lane_oracle.c`` holds the integer path (Sobel + binarize, Q14 vote, greedy
-NMS peaks) as plain nested loops; ``cnn.py`` the FP64 proposal network and its
-analytic backward; ``learned.py`` tile labels, masks and peak agreement.
+NMS peaks, line segments along the peaks) as plain nested loops; ``cnn.py``
+the FP64 proposal network and its analytic backward, tile labels, masks and
+peak agreement.
 """
 from __future__ import annotations
 
@@ -49,6 +50,9 @@ def _load():
         lib.oracle_hough_peaks.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp]
         lib.oracle_band_bits.restype = i32
         lib.oracle_band_bits.argtypes = [i32, i32]
+        lib.oracle_hough_lines.restype = i32
+        lib.oracle_hough_lines.argtypes = [vp, i32, i32, i32, vp, vp, i32, i32, vp, vp, i32, i32,
+                                           i32, i32, vp, vp, vp]
         lib.oracle_r_offset.restype = i32
         lib.oracle_r_offset.argtypes = [i32, i32]
         _lib = lib
@@ -115,6 +119,30 @@ def hough_peaks(acc: np.ndarray, r_offset: int, k: int, h_theta: int | None = No
     if n < 0:
         raise ValueError("bad peak arguments")
     return t, r, v, n
+
+
+def hough_lines(edges: np.ndarray, cos_q14, sin_q14, r_offset: int, theta_idx, r_idx,
+                fill_gap: int = 20, min_length: int = 40, max_seg: int = 16, W: int | None = None):
+    """Line segments along peaks (see oracle_hough_lines).  Returns
+    (segs[k][max_seg][4] int32 -1 padded, counts[k], npts[k])."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint8)
+    H, epitch = edges.shape
+    W = epitch if W is None else W
+    C = np.ascontiguousarray(cos_q14, dtype=np.int16)
+    S = np.ascontiguousarray(sin_q14, dtype=np.int16)
+    t = np.ascontiguousarray(theta_idx, dtype=np.int32)
+    r = np.ascontiguousarray(r_idx, dtype=np.int32)
+    k = t.shape[0]
+    segs = np.zeros((k, max_seg, 4), np.int32)
+    counts = np.zeros(k, np.int32)
+    npts = np.zeros(k, np.int32)
+    st = _load().oracle_hough_lines(_ptr(edges), W, H, epitch, _ptr(C), _ptr(S), C.shape[0],
+                                    int(r_offset), _ptr(t), _ptr(r), k, int(fill_gap),
+                                    int(min_length), int(max_seg), _ptr(segs), _ptr(counts),
+                                    _ptr(npts))
+    if st != 0:
+        raise ValueError("bad line arguments")
+    return segs, counts, npts
 
 
 def band_bits(n_theta: int) -> np.ndarray:

@@ -18,6 +18,9 @@
  *   oracle_hough_peaks     Sec. 2.3: the line with the largest count is the
  *                          line with the most pixels ("Hough peak"; the paper
  *                          delegates it to MATLAB and gives no algorithm).
+ *   oracle_hough_lines     Sec. 1 step 4 and Sec. 5 ("Hough lines", Fig. 12):
+ *                          the lane lines drawn from the peaks; again MATLAB
+ *                          in the paper, no algorithm given (reading below).
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes):
@@ -31,6 +34,8 @@
  *     r = floor((x*C[k] + y*S[k] + 2^13) / 2^14), stored at r + r_offset;
  *     votes whose index falls outside [0, n_r) are counted as dropped.
  *   - peaks: greedy non-maximum suppression, see oracle_hough_peaks.
+ *   - lines: the pixels that voted into a peak's cell, ordered along the
+ *     line, split at gaps, short pieces dropped; see oracle_hough_lines.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -175,6 +180,91 @@ int oracle_hough_peaks(const int32_t *acc, int n_theta, int n_r, int r_offset, i
     }
     free(A);
     return found;
+}
+
+/* Line segments along peaks.  For peak j with theta_idx t >= 0 and r_idx i:
+ *   points: the 255 pixels (x, y) whose vote for bin t lands in cell i, i.e.
+ *           floor((x*C[t] + y*S[t] + 2^13) / 2^14) + r_offset == i;
+ *   order:  by (y, x) when |C[t]| >= |S[t]| (line nearer the vertical), else
+ *           by (x, y), ascending;
+ *   split:  two consecutive points more than fill_gap apart (squared
+ *           distance > fill_gap^2) end one segment and start the next;
+ *   keep:   a segment whose first and last point are at least min_length
+ *           apart (squared distance >= min_length^2);
+ *   output: segs[j][s] = (x1, y1, x2, y2), its first and last point, for the
+ *           first max_seg kept segments in order; counts[j] = number kept
+ *           (may exceed max_seg); npts[j] (nullable) = number of points.
+ * A peak with theta_idx < 0 (padding) has no points.  Unused slots are -1.
+ * Returns 0, or -1 on bad arguments. */
+typedef struct { int32_t a, b, x, y; } LinePoint;
+
+static int line_point_cmp(const void *p, const void *q)
+{
+    const LinePoint *u = (const LinePoint *)p, *v = (const LinePoint *)q;
+    if (u->a != v->a) return u->a < v->a ? -1 : 1;
+    if (u->b != v->b) return u->b < v->b ? -1 : 1;
+    return 0;
+}
+
+static int64_t dist2(const LinePoint *u, const LinePoint *v)
+{
+    int64_t dx = (int64_t)u->x - v->x, dy = (int64_t)u->y - v->y;
+    return dx * dx + dy * dy;
+}
+
+int oracle_hough_lines(const uint8_t *edges, int W, int H, int epitch, const int16_t *C,
+                       const int16_t *S, int n_theta, int r_offset, const int32_t *theta_idx,
+                       const int32_t *r_idx, int k, int fill_gap, int min_length, int max_seg,
+                       int32_t *segs, int32_t *counts, int32_t *npts)
+{
+    if (W <= 0 || H <= 0 || n_theta <= 0 || k < 0 || fill_gap < 0 || min_length < 0 || max_seg < 1)
+        return -1;
+    LinePoint *pts = (LinePoint *)malloc(sizeof(LinePoint) * (size_t)W * (size_t)H);
+    if (!pts) return -1;
+    const int64_t gap2 = (int64_t)fill_gap * fill_gap, len2 = (int64_t)min_length * min_length;
+    for (int j = 0; j < k; ++j) {
+        for (int s = 0; s < 4 * max_seg; ++s) segs[(size_t)j * 4 * max_seg + s] = -1;
+        counts[j] = 0;
+        if (npts) npts[j] = 0;
+        int t = theta_idx[j];
+        if (t < 0 || t >= n_theta) continue;
+        int by_y = abs(C[t]) >= abs(S[t]);
+        size_t n = 0;
+        for (int y = 0; y < H; ++y) {
+            for (int x = 0; x < W; ++x) {
+                if (edges[(size_t)y * epitch + x] != 255) continue;
+                int64_t v = (int64_t)x * C[t] + (int64_t)y * S[t];
+                if (floor_div(v + 8192, 16384) + r_offset != r_idx[j]) continue;
+                pts[n].a = by_y ? y : x;
+                pts[n].b = by_y ? x : y;
+                pts[n].x = x;
+                pts[n].y = y;
+                ++n;
+            }
+        }
+        if (npts) npts[j] = (int32_t)n;
+        qsort(pts, n, sizeof(LinePoint), line_point_cmp);
+        int kept = 0;
+        size_t first = 0;
+        for (size_t m = 1; m <= n; ++m) {
+            if (m < n && dist2(&pts[m - 1], &pts[m]) <= gap2) continue;
+            /* segment [first, m) */
+            if (n > 0 && dist2(&pts[first], &pts[m - 1]) >= len2) {
+                if (kept < max_seg) {
+                    int32_t *o = segs + ((size_t)j * max_seg + kept) * 4;
+                    o[0] = pts[first].x;
+                    o[1] = pts[first].y;
+                    o[2] = pts[m - 1].x;
+                    o[3] = pts[m - 1].y;
+                }
+                ++kept;
+            }
+            first = m;
+        }
+        counts[j] = kept;
+    }
+    free(pts);
+    return 0;
 }
 
 /* D = ceil(sqrt((W-1)^2 + (H-1)^2)) by integer search. */

@@ -357,3 +357,84 @@ def test_r_offset_matches_integer_sqrt(oracle, synth):
         d = oracle.r_offset(W, H)
         q = (W - 1) ** 2 + (H - 1) ** 2
         assert d * d >= q and (d - 1) * (d - 1) < q or q == 0
+
+
+# ------------------------------------------------- line segments (Sec. 1 step 4, Sec. 5)
+# Drawn segments with known end points: the expected output is the drawing,
+# not a re-typed formula.
+
+def _trig(n_theta):
+    from paper_2212_09460_amd import synth as s
+
+    return s.trig_q14(n_theta)
+
+
+def _lines(oracle, e, n_theta, t, r, **kw):
+    C, S = _trig(n_theta)
+    H, W = e.shape
+    D = oracle.r_offset(W, H)
+    segs, counts, npts = oracle.hough_lines(e, C, S, D, np.array([t], np.int32),
+                                            np.array([r + D], np.int32), **kw)
+    got = [tuple(int(v) for v in segs[0, s]) for s in range(min(int(counts[0]), segs.shape[1]))]
+    return got, int(counts[0]), int(npts[0])
+
+
+def test_lines_horizontal_and_vertical_runs(oracle):
+    e = np.zeros((48, 64), np.uint8)
+    e[17, 5:51] = 255          # row 17, x = 5..50
+    e[3:40, 33] = 255          # column 33, y = 3..39 (crosses the row)
+    # theta = 90 deg (bin 90 of 180): r = y; the row plus the column's pixel on it
+    got, n, npts = _lines(oracle, e, 180, 90, 17, fill_gap=20, min_length=10)
+    assert got == [(5, 17, 50, 17)] and n == 1 and npts == 46
+    # theta = 0: r = x; ordered by y
+    got, n, npts = _lines(oracle, e, 180, 0, 33, fill_gap=20, min_length=10)
+    assert got == [(33, 3, 33, 39)] and npts == 37
+
+
+def test_lines_gap_fill_and_min_length(oracle):
+    e = np.zeros((32, 96), np.uint8)
+    e[10, 2:21] = 255          # x = 2..20
+    e[10, 31:61] = 255         # x = 31..60: gap of 11 between 20 and 31
+    e[10, 80:84] = 255         # x = 80..83: a 3-px piece 20 away from 60
+    got, n, _ = _lines(oracle, e, 180, 90, 10, fill_gap=20, min_length=10)
+    assert got == [(2, 10, 83, 10)]                           # every gap <= 20 joins
+    got, n, _ = _lines(oracle, e, 180, 90, 10, fill_gap=10, min_length=10)
+    assert got == [(2, 10, 20, 10), (31, 10, 60, 10)] and n == 2   # the 3-px piece is dropped
+    got, n, _ = _lines(oracle, e, 180, 90, 10, fill_gap=10, min_length=3)
+    assert got == [(2, 10, 20, 10), (31, 10, 60, 10), (80, 10, 83, 10)]
+    got, n, _ = _lines(oracle, e, 180, 90, 10, fill_gap=10, min_length=3, max_seg=2)
+    assert got == [(2, 10, 20, 10), (31, 10, 60, 10)] and n == 3   # count beyond the slots
+
+
+def test_lines_diagonal_and_off_line_pixels(oracle):
+    e = np.zeros((64, 64), np.uint8)
+    for x in range(10, 41):
+        e[x, x] = 255          # y = x
+    e[30, 20] = 255            # 10 px off the line
+    e[25, 27] = 255            # distance 2/sqrt(2) off the line
+    # theta = 135 deg: x cos + y sin = (y - x)/sqrt(2) = 0 on the diagonal
+    got, n, npts = _lines(oracle, e, 180, 135, 0, fill_gap=5, min_length=5)
+    assert got == [(10, 10, 40, 40)] and npts == 31
+    assert _lines(oracle, e, 180, 135, 7, fill_gap=5, min_length=0)[2] == 1   # (20, 30): r = 10/sqrt(2)
+
+
+def test_lines_points_are_the_peak_voters(oracle):
+    rng = np.random.default_rng(5)
+    e = np.where(rng.random((40, 56)) < 0.2, 255, 0).astype(np.uint8)
+    n_theta = 64
+    C, S = _trig(n_theta)
+    D = oracle.r_offset(56, 40)
+    acc, _, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    t = np.repeat(np.arange(n_theta, dtype=np.int32), 3)
+    r = np.array([D, D + 7, D - 11] * n_theta, np.int32)
+    _, counts, npts = oracle.hough_lines(e, C, S, D, t, r, fill_gap=1000, min_length=0)
+    assert (npts == acc[t, r]).all()                  # exactly the cell's voters
+    assert (counts == (npts > 0)).all()               # one segment when no gap splits
+
+
+def test_lines_padding_peak_is_empty(oracle):
+    e = np.full((8, 8), 255, np.uint8)
+    C, S = _trig(16)
+    segs, counts, npts = oracle.hough_lines(e, C, S, oracle.r_offset(8, 8), np.array([-1], np.int32),
+                                            np.array([-1], np.int32))
+    assert counts[0] == 0 and npts[0] == 0 and (segs == -1).all()
