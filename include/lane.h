@@ -149,6 +149,41 @@ int lane_hough_peaks(const int32_t *acc, int32_t n_theta, int32_t n_r, int32_t r
                      int32_t *theta_idx, int32_t *r_idx, int32_t *votes, int32_t *count,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Line segments along peaks: the lane lines drawn from the Hough peaks
+ * (Sec. 1 step 4; Sec. 5, "Hough lines" and Fig. 12; the paper leaves the
+ * step to MATLAB without an algorithm, so it is specified here).  For peak j
+ * (theta_idx[j] = t, r_idx[j] = i):
+ *   points  the 255 pixels whose vote for bin t lands in cell i, i.e.
+ *           floor((x*C[t] + y*S[t] + 2^13) / 2^14) + r_offset == i
+ *           (exactly the pixels counted in acc[t][i]);
+ *   order   by (y, x) when |C[t]| >= |S[t]| (line nearer the vertical), else
+ *           by (x, y), ascending;
+ *   split   two consecutive points more than fill_gap apart (squared
+ *           Euclidean distance > fill_gap^2) end a segment;
+ *   keep    a segment whose first and last points are at least min_length
+ *           apart (squared distance >= min_length^2).
+ *   edges      device uint8 [H][W] (255 = edge), W, H <= LANE_MAX_DIM
+ *   cos_q14, sin_q14  device int16 [n_theta]; a row must be a rotation
+ *              (max(|C|, |S|) >= 11585), else that peak's count is -1
+ *   theta_idx, r_idx  device int32 [k] (lane_hough_peaks output); entries
+ *              with theta_idx < 0, or j >= *count_opt, have no segments
+ *   count_opt  device int32 scalar (peaks found) or NULL (all k)
+ *   k in [1, 4096]; fill_gap, min_length in [0, 65535];
+ *   max_segments in [1, 1024]; r_offset in [0, 131072]
+ *   segments   device int32 [k][max_segments][4]: (x1, y1, x2, y2), the first
+ *              and last point of each kept segment in line order; -1 in
+ *              unused slots
+ *   seg_count  device int32 [k]: kept segments (may exceed max_segments:
+ *              only the first max_segments are written)
+ *   npts_opt   device int32 [k] or NULL: points of each peak
+ * One workgroup per peak; no workspace.  Argument errors are returned before
+ * anything is enqueued. */
+int lane_hough_lines(const uint8_t *edges, int32_t W, int32_t H, const int16_t *cos_q14,
+                     const int16_t *sin_q14, int32_t n_theta, int32_t r_offset,
+                     const int32_t *theta_idx, const int32_t *r_idx, const int32_t *count_opt,
+                     int32_t k, int32_t fill_gap, int32_t min_length, int32_t max_segments,
+                     int32_t *segments, int32_t *seg_count, int32_t *npts_opt, void *stream);
+
 /* ------------------------------------------------------------------ batch
  * Many frames of mixed sizes through the whole path (Sobel + binarize +
  * compaction, vote, peaks) in one HIP graph launch.  A plan is built once

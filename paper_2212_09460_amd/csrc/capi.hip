@@ -13,6 +13,12 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int W, int H, const int16_t* C,
+                                                      const int16_t* S, int n_theta, int r_offset,
+                                                      const int32_t* theta_idx, const int32_t* r_idx,
+                                                      const int32_t* count, int k, int fill_gap,
+                                                      int min_length, int max_seg, int32_t* segs,
+                                                      int32_t* seg_count, int32_t* npts, hipStream_t s);
 
 namespace {
 
@@ -274,6 +280,22 @@ int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r
     d.nbr = lane_peaks_blocks_per_row(n_r, d.block_log2);
     d.n_blocks = n_theta * d.nbr;
     return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));
+}
+
+int lane_hough_lines(const uint8_t* edges, int32_t W, int32_t H, const int16_t* cos_q14,
+                     const int16_t* sin_q14, int32_t n_theta, int32_t r_offset,
+                     const int32_t* theta_idx, const int32_t* r_idx, const int32_t* count_opt,
+                     int32_t k, int32_t fill_gap, int32_t min_length, int32_t max_segments,
+                     int32_t* segments, int32_t* seg_count, int32_t* npts_opt, void* stream) {
+    if (!edges || !cos_q14 || !sin_q14 || !theta_idx || !r_idx || !segments || !seg_count ||
+        !dims_ok(W, H) || n_theta <= 0 || k < 1 || k > 4096 || fill_gap < 0 || fill_gap > 65535 ||
+        min_length < 0 || min_length > 65535 || max_segments < 1 || max_segments > 1024)
+        return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    if (r_offset < 0 || r_offset > 131072) return LANE_E_RANGE;
+    return dev_status(lane_launch_lines(edges, W, H, cos_q14, sin_q14, n_theta, r_offset, theta_idx,
+                                        r_idx, count_opt, k, fill_gap, min_length, max_segments,
+                                        segments, seg_count, npts_opt, (hipStream_t)stream));
 }
 
 }  // extern "C"

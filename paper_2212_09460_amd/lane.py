@@ -41,6 +41,8 @@ _vote = _sig("lane_hough_vote", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _v
 _peaks_ws = _sig("lane_hough_peaks_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _peaks = _sig("lane_hough_peaks", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
                                     _vp, _vp, _sz, _vp])
+_lines = _sig("lane_hough_lines", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i32, _i32,
+                                    _i32, _i32, _vp, _vp, _vp, _vp])
 
 LANE_OK = 0
 LANE_BORDER_ZERO = 0
@@ -49,7 +51,8 @@ LANE_BORDER_ZERO_MASKRING = 1
 # Exported entry points of the C ABI (also checked by the CPU tests).
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
-           "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_batch_create",
+           "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_lines",
+           "lane_batch_create",
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
@@ -179,6 +182,27 @@ def hough_peaks(acc: torch.Tensor, r_offset: int, k: int, h_theta: int | None = 
                   int(min_votes), _p(t), _p(r), _p(v), _p(c), _p(ws), ws.numel() * 8,
                   _stream(stream)), "lane_hough_peaks")
     return t, r, v, c
+
+
+def hough_lines(edges: torch.Tensor, cos_q14: torch.Tensor, sin_q14: torch.Tensor, r_offset: int,
+                theta_idx: torch.Tensor, r_idx: torch.Tensor, count: torch.Tensor | None = None,
+                fill_gap: int = 20, min_length: int = 40, max_segments: int = 16, W: int | None = None,
+                stream=None):
+    """Line segments along peaks.  edges: device uint8 [H][W].  Returns
+    (segments [k][max_segments][4], seg_count [k], npts [k]) int32 device tensors."""
+    H, pitch = edges.shape
+    W = pitch if W is None else W
+    assert W == pitch, "the edge map must be [H][W]"
+    k = int(theta_idx.numel())
+    dev = edges.device
+    segs = torch.empty((k, max_segments, 4), dtype=torch.int32, device=dev)
+    cnt = torch.empty((k,), dtype=torch.int32, device=dev)
+    npts = torch.empty((k,), dtype=torch.int32, device=dev)
+    _check(_lines(_p(edges), W, H, _p(cos_q14), _p(sin_q14), int(cos_q14.numel()), int(r_offset),
+                  _p(theta_idx), _p(r_idx), None if count is None else _p(count), k, int(fill_gap),
+                  int(min_length), int(max_segments), _p(segs), _p(cnt), _p(npts), _stream(stream)),
+           "lane_hough_lines")
+    return segs, cnt, npts
 
 
 def pipeline(img: torch.Tensor, cos_q14: torch.Tensor, sin_q14: torch.Tensor, k: int,

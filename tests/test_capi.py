@@ -106,3 +106,22 @@ def test_argument_errors_before_launch(lib):
     assert pk(P, 180, 11, 5, 0, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_ARG   # k < 1
     assert pk(P, 180, 12, 5, 2, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_RANGE  # n_r != 2D+1
     assert pk(P, 180, 11, 5, 2, 1, 1, 1, P, P, P, P, P, 8, None) == E_WS
+    ln = lib.lane_hough_lines
+    ln.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p]
+    ok = (P, 64, 48, P, P, 180, 79, P, P, None, 8, 20, 40, 16, P, P, None, None)
+    def lines_with(i, val):
+        a = list(ok)
+        a[i] = val
+        return ln(*a)
+    assert lines_with(0, None) == E_ARG            # no edge map
+    assert lines_with(10, 0) == E_ARG              # k < 1
+    assert lines_with(10, 5000) == E_ARG           # k > 4096
+    assert lines_with(11, -1) == E_ARG             # fill_gap
+    assert lines_with(12, 70000) == E_ARG          # min_length
+    assert lines_with(13, 0) == E_ARG              # max_segments
+    assert lines_with(1, 9000) == E_SIZE
+    assert lines_with(6, 200000) == E_RANGE        # r_offset
