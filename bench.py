@@ -215,6 +215,21 @@ def main():
         one.close()
     lat = np.array(lat if lat else [float("nan")])
 
+    # line segments along each frame's peaks (one launch per frame, one
+    # workgroup per peak): average over 64 frames launched back to back
+    lines_us = None
+    if args.latency_iters > 0:
+        nl = min(64, B)
+
+        def lines_all():
+            for f in frames[:nl]:
+                lane.hough_lines(f.edges, Cd, Sd, f.D, f.theta_idx(), f.r_idx(), f.count(),
+                                 stream=stream)
+
+        lines_all()
+        torch.cuda.synchronize()
+        lines_us = event_time(torch, lines_all, 5, stream) / nl * 1000
+
     # practical reference for the Sobel pass: a plain device copy moving the
     # same number of bytes (half read, half written), timed the same way
     nb = sobel_bytes // 2
@@ -276,6 +291,7 @@ def main():
                            "frac_of_device_copy": round(sobel_gbs / copy_gbs, 4)},
         "latency_ms_single_frame_gpu": {"p50": round(float(np.percentile(lat, 50)), 4),
                                         "p99": round(float(np.percentile(lat, 99)), 4)},
+        "lines_us_per_frame": None if lines_us is None else round(lines_us, 2),
         "wall_s_timed": round(wall, 3),
     }
     batch.close()
