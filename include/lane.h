@@ -186,7 +186,8 @@ int lane_hough_lines(const uint8_t *edges, int32_t W, int32_t H, const int16_t *
 
 /* ------------------------------------------------------------------ batch
  * Many frames of mixed sizes through the whole path (Sobel + binarize +
- * compaction, vote, peaks) in one HIP graph launch.  A plan is built once
+ * compaction, vote, peaks, and line segments where a frame asks for them) in
+ * one HIP graph launch.  A plan is built once
  * per set of buffers (creation allocates a small device descriptor table and
  * instantiates the graph; launching allocates nothing).  Each stage is a
  * persistent kernel that walks a work table covering every frame; the
@@ -209,6 +210,13 @@ typedef struct lane_frame {
     void *peaks_ws;           /* device, lane_hough_peaks_workspace_size() bytes, 16-byte aligned */
     size_t peaks_ws_bytes;
     uint32_t *counters_opt;   /* device uint32 [2] or NULL: edge pixels, dropped votes */
+    /* line segments along the peaks (lane_hough_lines), run after the peak
+     * step when lines_opt != NULL and k > 0 */
+    int32_t lines_max_seg;    /* segments per peak, [1, 1024] */
+    int32_t lines_fill_gap;   /* [0, 65535] */
+    int32_t lines_min_length; /* [0, 65535] */
+    int32_t *lines_opt;       /* device int32 [k*lines_max_seg*4 + 2k]: segments [k][max_seg][4],
+                                 then seg_count [k], then npts [k]; or NULL */
 } lane_frame;
 
 typedef struct lane_tune {
@@ -233,7 +241,8 @@ int lane_batch_create(const lane_frame *frames, int32_t n, const lane_tune *tune
 /* Enqueue the whole path for every frame: one hipGraphLaunch on `stream`. */
 int lane_batch_launch(lane_batch *b, void *stream);
 /* Enqueue one stage without the graph (0 = clear counters, 1 = Sobel,
- * 2 = vote, 3 = peaks), e.g. to time the stages separately. */
+ * 2 = vote, 3 = peaks, 4 = line segments of the frames that ask for them),
+ * e.g. to time the stages separately. */
 int lane_batch_launch_stage(lane_batch *b, int32_t stage, void *stream);
 /* Device address (*flags) of the plan's per-frame switches, uint8 [n] in
  * frame order, owned by the plan and all 1 after creation.  A launch (graph

@@ -38,6 +38,8 @@ extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int3
 extern "C" LANE_INTERNAL int lane_vote_rows_default(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
 extern "C" LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T);
+extern "C" LANE_INTERNAL hipError_t lane_launch_lines_batch(const LinesDesc* descs, int n, int max_k,
+                                                            int max_side, hipStream_t s);
 extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
 extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
@@ -63,6 +65,8 @@ struct lane_batch {
     SobelDesc* d_sobel = nullptr;
     VoteDesc* d_vote = nullptr;
     PeaksDesc* d_peaks = nullptr;
+    LinesDesc* d_lines = nullptr;
+    int n_lines_frames = 0, lines_max_k = 0, lines_max_side = 0;
     int2* d_sobel_items = nullptr;
     int2* d_vote_items = nullptr;
     int* d_prefix = nullptr;
@@ -108,6 +112,13 @@ int validate(const lane_frame& f) {
         lane_hough_peaks_workspace_size(f.n_theta, f.n_r, &need);
         if (f.peaks_ws_bytes < need) return LANE_E_WS;
     }
+    if (f.lines_opt) {
+        if (f.k < 1) return LANE_E_ARG;
+        if (f.lines_max_seg < 1 || f.lines_max_seg > 1024 || f.lines_fill_gap < 0 ||
+            f.lines_fill_gap > 65535 || f.lines_min_length < 0 || f.lines_min_length > 65535)
+            return LANE_E_ARG;
+        if (f.r_offset < 0) return LANE_E_RANGE;
+    }
     return LANE_OK;
 }
 
@@ -146,6 +157,10 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
             if (b->n_peak_frames == 0) return hipSuccess;
             return lane_launch_peaks_batch(b->d_peaks, b->d_prefix, b->n_peak_frames, b->total_blocks,
                                            0, b->grid_select, s);
+        case 4:
+            if (b->n_lines_frames == 0) return hipSuccess;
+            return lane_launch_lines_batch(b->d_lines, b->n_lines_frames, b->lines_max_k,
+                                           b->lines_max_side, s);
         default:
             return hipErrorInvalidValue;
     }
@@ -187,6 +202,9 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     std::vector<SobelDesc> sd(n);
     std::vector<VoteDesc> vd(n);
     std::vector<PeaksDesc> pd;
+    std::vector<LinesDesc> ld;
+    std::vector<int> ld_frame;
+    int lines_max_k = 0, lines_max_side = 0;
     std::vector<int2> sitems, sitems_slow, vitems;
     std::vector<int> prefix(1, 0);
     std::vector<uint32_t*> counters(n, nullptr);
@@ -257,6 +275,31 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
             p.n_blocks = f.n_theta * p.nbr;
             p.active_index = i;
             pd.push_back(p);
+            if (f.lines_opt) {
+                LinesDesc l;
+                memset(&l, 0, sizeof(l));
+                l.edges = f.edges;
+                l.W = f.W;
+                l.H = f.H;
+                l.cos_q14 = f.cos_q14;
+                l.sin_q14 = f.sin_q14;
+                l.n_theta = f.n_theta;
+                l.r_offset = f.r_offset;
+                l.theta_idx = f.peaks;
+                l.r_idx = f.peaks + f.k;
+                l.count = f.peaks + 3 * f.k;
+                l.k = f.k;
+                l.fill_gap = f.lines_fill_gap;
+                l.min_length = f.lines_min_length;
+                l.max_seg = f.lines_max_seg;
+                l.segs = f.lines_opt;
+                l.seg_count = f.lines_opt + (size_t)f.k * f.lines_max_seg * 4;
+                l.npts = l.seg_count + f.k;
+                ld.push_back(l);
+                ld_frame.push_back(i);
+                lines_max_k = std::max(lines_max_k, f.k);
+                lines_max_side = std::max(lines_max_side, std::max(f.W, f.H));
+            }
             // the vote writes the block keys while its rows are still in LDS
             v.keys = p.keys;
             v.key_log2 = p.block_log2;
@@ -295,6 +338,9 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->n = n;
     b->n_sobel_fast = n_fast;
     b->n_peak_frames = (int)pd.size();
+    b->n_lines_frames = (int)ld.size();
+    b->lines_max_k = lines_max_k;
+    b->lines_max_side = lines_max_side;
     b->n_sobel_items = (int)sitems.size();
     b->n_vote_items = (int)vitems.size();
     b->total_blocks = prefix.back();
@@ -307,6 +353,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_sobel = off; off = al(off + sizeof(SobelDesc) * n);
     const size_t o_vote = off; off = al(off + sizeof(VoteDesc) * n);
     const size_t o_peaks = off; off = al(off + sizeof(PeaksDesc) * std::max<size_t>(pd.size(), 1));
+    const size_t o_lines = off; off = al(off + sizeof(LinesDesc) * std::max<size_t>(ld.size(), 1));
     const size_t o_sitems = off; off = al(off + sizeof(int2) * sitems.size());
     const size_t o_vitems = off; off = al(off + sizeof(int2) * vitems.size());
     const size_t o_prefix = off; off = al(off + sizeof(int) * prefix.size());
@@ -332,6 +379,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->d_sobel = (SobelDesc*)(base + o_sobel);
     b->d_vote = (VoteDesc*)(base + o_vote);
     b->d_peaks = (PeaksDesc*)(base + o_peaks);
+    b->d_lines = (LinesDesc*)(base + o_lines);
     b->d_sobel_items = (int2*)(base + o_sitems);
     b->d_vote_items = (int2*)(base + o_vitems);
     b->d_prefix = (int*)(base + o_prefix);
@@ -348,10 +396,13 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         }
     }
     for (auto& p : pd) p.active = b->d_active + p.active_index;
+    for (size_t q = 0; q < ld.size(); ++q) ld[q].active = b->d_active + ld_frame[q];
     bool ok = hipMemcpy(b->d_sobel, sd.data(), sizeof(SobelDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_vote, vd.data(), sizeof(VoteDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
     if (!pd.empty())
         ok = ok && hipMemcpy(b->d_peaks, pd.data(), sizeof(PeaksDesc) * pd.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ld.empty())
+        ok = ok && hipMemcpy(b->d_lines, ld.data(), sizeof(LinesDesc) * ld.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_sobel_items, sitems.data(), sizeof(int2) * sitems.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_vote_items, vitems.data(), sizeof(int2) * vitems.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -408,14 +459,14 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->grid_keys = std::max(1, std::min((b->total_blocks + 3) / 4, cus * 8));
     b->grid_select = std::max(1, std::min(b->n_peak_frames, cus));
 
-    // capture the four stages into one graph
+    // capture the stages into one graph
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int st = 0; st < 4 && e == hipSuccess; ++st) e = enqueue_stage(b, st, cs);
+    for (int st = 0; st < 5 && e == hipSuccess; ++st) e = enqueue_stage(b, st, cs);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
@@ -496,7 +547,7 @@ int lane_batch_active_flags(lane_batch* b, uint8_t** flags) {
 }
 
 int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {
-    if (!b || stage < 0 || stage > 3) return LANE_E_ARG;
+    if (!b || stage < 0 || stage > 4) return LANE_E_ARG;
     return enqueue_stage(b, stage, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
 }
 

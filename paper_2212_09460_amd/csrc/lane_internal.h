@@ -108,6 +108,28 @@ struct PeaksDesc {
     const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
 };
 
+// One frame for the line segments along its peaks.
+struct LinesDesc {
+    const uint8_t* edges;  // [H][W], 255 = edge
+    int W, H;
+    const int16_t* cos_q14;
+    const int16_t* sin_q14;
+    int n_theta, r_offset;
+    const int32_t* theta_idx;  // [k]
+    const int32_t* r_idx;      // [k]
+    const int32_t* count;      // device scalar or null: peaks j >= *count are empty
+    int k;
+    int fill_gap, min_length, max_seg;
+    int32_t* segs;       // [k][max_seg][4]
+    int32_t* seg_count;  // [k]
+    int32_t* npts;       // [k] or null
+    const uint8_t* active;  // batched path: the frame runs iff *active != 0 (null = always)
+};
+
+// LDS of one line workgroup: points (4 B) and segment starts (2 B) for up to
+// two points per step of the frame's longer side.
+inline size_t lines_lds_bytes(int W, int H) { return (size_t)6 * 2 * (size_t)(W > H ? W : H); }
+
 // Peak-search key of a cell: one unsigned max picks the largest count and,
 // among equal counts, the smallest theta-major index.
 __device__ __forceinline__ unsigned long long make_key(int v, uint32_t idx) {

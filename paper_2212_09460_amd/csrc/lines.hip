@@ -25,25 +25,8 @@
 namespace lane {
 
 constexpr int kLinesThreads = 256;
-// A cell's voters: at most two per step of the walked axis (A >= 2^14/sqrt 2),
-// so at most 2 * 8192 points for the largest frame.
-constexpr int kLinesMaxPts = 2 * 8192;
-
-struct LinesDesc {
-    const uint8_t* edges;  // [H][W], 255 = edge
-    int W, H;
-    const int16_t* cos_q14;
-    const int16_t* sin_q14;
-    int n_theta, r_offset;
-    const int32_t* theta_idx;  // [k]
-    const int32_t* r_idx;      // [k]
-    const int32_t* count;      // device scalar or null: peaks j >= *count are empty
-    int k;
-    int fill_gap, min_length, max_seg;
-    int32_t* segs;      // [k][max_seg][4]
-    int32_t* seg_count; // [k]
-    int32_t* npts;      // [k] or null
-};
+// A cell's voters: at most two per step of the walked axis (|A| >= 2^14/sqrt 2),
+// so a frame with longer side L needs room for 2L points (lines_lds_bytes).
 
 __device__ __forceinline__ int floor_div_i(int a, int b) {  // b != 0, any signs
     int q = a / b;
@@ -81,11 +64,8 @@ __device__ __forceinline__ long long dist2(uint32_t p, uint32_t q) {
     return dx * dx + dy * dy;
 }
 
-__global__ void __launch_bounds__(kLinesThreads) k_lines(LinesDesc d) {
-    __shared__ uint32_t s_pts[kLinesMaxPts];     // x | y << 16, in line order
-    __shared__ uint16_t s_start[kLinesMaxPts];   // segment start indices
-    __shared__ int s_wave[kLinesThreads / kWave];
-    const int j = blockIdx.x;
+// Peak j of frame d; s_pts / s_start hold 2 * max(W, H) entries.
+__device__ void lines_item(const LinesDesc& d, int j, uint32_t* s_pts, uint16_t* s_start, int* s_wave) {
     const int tid = threadIdx.x;
     int32_t* out = d.segs + (size_t)j * d.max_seg * 4;
     for (int s = tid; s < 4 * d.max_seg; s += kLinesThreads) gst(out + s, -1);
@@ -181,6 +161,22 @@ __global__ void __launch_bounds__(kLinesThreads) k_lines(LinesDesc d) {
     if (tid == 0) gst(d.seg_count + j, kept_total);
 }
 
+__global__ void __launch_bounds__(kLinesThreads) k_lines(LinesDesc d, int cap) {
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    __shared__ int s_wave[kLinesThreads / kWave];
+    lines_item(d, blockIdx.x, s_dyn, (uint16_t*)(s_dyn + cap), s_wave);
+}
+
+// Batched: blockIdx.y = frame (a frame switched off keeps its outputs),
+// blockIdx.x = peak.
+__global__ void __launch_bounds__(kLinesThreads) k_lines_batch(const LinesDesc* __restrict__ descs, int cap) {
+    extern __shared__ __align__(16) uint32_t s_dyn[];
+    __shared__ int s_wave[kLinesThreads / kWave];
+    const LinesDesc d = descs[blockIdx.y];
+    if ((int)blockIdx.x >= d.k || !frame_on(d.active)) return;
+    lines_item(d, blockIdx.x, s_dyn, (uint16_t*)(s_dyn + cap), s_wave);
+}
+
 }  // namespace lane
 
 using namespace lane;
@@ -209,6 +205,15 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int 
     d.segs = segs;
     d.seg_count = seg_count;
     d.npts = npts;
-    hipLaunchKernelGGL(k_lines, dim3(k), dim3(kLinesThreads), 0, s, d);
+    d.active = nullptr;
+    const int cap = 2 * (W > H ? W : H);
+    hipLaunchKernelGGL(k_lines, dim3(k), dim3(kLinesThreads), lines_lds_bytes(W, H), s, d, cap);
+    return hipGetLastError();
+}
+
+extern "C" LANE_INTERNAL hipError_t lane_launch_lines_batch(const LinesDesc* descs, int n, int max_k,
+                                                            int max_side, hipStream_t s) {
+    const int cap = 2 * max_side;
+    hipLaunchKernelGGL(k_lines_batch, dim3(max_k, n), dim3(kLinesThreads), (size_t)6 * cap, s, descs, cap);
     return hipGetLastError();
 }

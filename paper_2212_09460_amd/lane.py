@@ -231,7 +231,8 @@ class LaneFrame(ctypes.Structure):
                 ("tile_mask_opt", _vp), ("acc", _vp),
                 ("k", _i32), ("h_theta", _i32), ("h_r", _i32), ("min_votes", _i32),
                 ("peaks", _vp), ("peaks_ws", _vp), ("peaks_ws_bytes", _sz),
-                ("counters_opt", _vp)]
+                ("counters_opt", _vp), ("lines_max_seg", _i32), ("lines_fill_gap", _i32),
+                ("lines_min_length", _i32), ("lines_opt", _vp)]
 
 
 class LaneTune(ctypes.Structure):
@@ -274,7 +275,8 @@ class FrameBuffers:
     def __init__(self, img: torch.Tensor, W: int | None = None, n_theta: int = 360, k: int = 8,
                  cos_q14=None, sin_q14=None, threshold: int = 128,
                  border_mode: int = LANE_BORDER_ZERO_MASKRING, tile_mask=None,
-                 want_mag: bool = False, h_theta=None, h_r=None, min_votes: int = 1):
+                 want_mag: bool = False, h_theta=None, h_r=None, min_votes: int = 1,
+                 lines_max_seg: int = 0, lines_fill_gap: int = 20, lines_min_length: int = 40):
         H, pitch = img.shape
         W = pitch if W is None else W
         dev = img.device
@@ -300,6 +302,11 @@ class FrameBuffers:
         nws = peaks_workspace_size(self.n_theta, self.n_r)
         self.peaks_ws = torch.empty(nws // 8 + 2, dtype=torch.int64, device=dev)
         self.counters = torch.empty(2, dtype=torch.int32, device=dev)
+        # line segments along the peaks (the batch runs them after the peaks)
+        self.lines_max_seg = lines_max_seg if k > 0 else 0
+        self.lines_fill_gap, self.lines_min_length = lines_fill_gap, lines_min_length
+        self.lines = (torch.empty(k * self.lines_max_seg * 4 + 2 * k, dtype=torch.int32, device=dev)
+                      if self.lines_max_seg > 0 else None)
 
     def desc(self) -> LaneFrame:
         f = LaneFrame()
@@ -318,6 +325,10 @@ class FrameBuffers:
         f.peaks_ws = self.peaks_ws.data_ptr()
         f.peaks_ws_bytes = self.peaks_ws.numel() * 8
         f.counters_opt = self.counters.data_ptr()
+        if self.lines is not None:
+            f.lines_max_seg = self.lines_max_seg
+            f.lines_fill_gap, f.lines_min_length = self.lines_fill_gap, self.lines_min_length
+            f.lines_opt = self.lines.data_ptr()
         return f
 
     def theta_idx(self):
@@ -331,6 +342,19 @@ class FrameBuffers:
 
     def count(self):
         return self.peaks[3 * self.k]
+
+    def segments(self):
+        """[k][lines_max_seg][4] int32 view (x1, y1, x2, y2)."""
+        n = self.k * self.lines_max_seg * 4
+        return self.lines[:n].view(self.k, self.lines_max_seg, 4)
+
+    def seg_count(self):
+        n = self.k * self.lines_max_seg * 4
+        return self.lines[n:n + self.k]
+
+    def line_npts(self):
+        n = self.k * self.lines_max_seg * 4
+        return self.lines[n + self.k:n + 2 * self.k]
 
 
 class Batch:

@@ -153,3 +153,58 @@ def test_lines_largest_frame(lane, synth, oracle):
     g, o = both(lane, oracle, e, C, S, D, t, r, fill_gap=20, min_length=40)
     check(g, o)
     assert g[2].max() > 8000
+
+
+def test_lines_in_batch_graph(lane, synth, oracle):
+    """The batch's fifth stage: frames that ask for segments get them after
+    their peaks, in the same graph launch, equal to the oracle on every
+    replay; frames switched off by select keep their previous outputs."""
+    say("lines in the batch graph")
+    n_theta, k = 360, 8
+    C, S = synth.trig_q14(n_theta)
+    Cd, Sd = dev(C), dev(S)
+    specs = [(640, 480, 640, 21, 16), (1280, 720, 1280, 22, 4), (1920, 1080, 1920, 23, 16),
+             (997, 41, 1000, 24, 2), (3840, 2160, 3840, 25, 16), (640, 480, 640, 26, 0)]
+    frames, wants = [], []
+    for (Wf, Hf, pitch, seed, ms) in specs:
+        img = synth.gen_frame(synth.scene_road(Wf, Hf), seed, pitch=pitch)
+        fb = lane.FrameBuffers(dev(img), Wf, n_theta, k, Cd, Sd, lines_max_seg=ms,
+                               lines_fill_gap=15, lines_min_length=30)
+        frames.append(fb)
+        w = oracle.pipeline(img[:, :Wf].copy(), C, S, k)
+        if ms:
+            w["lines"] = oracle.hough_lines(w["edges"], C, S, w["D"], w["theta_idx"], w["r_idx"],
+                                            fill_gap=15, min_length=30, max_seg=ms)
+        wants.append(w)
+
+    def check_all(which):
+        torch.cuda.synchronize()
+        for i in which:
+            f, w = frames[i], wants[i]
+            assert (host(f.theta_idx()) == w["theta_idx"]).all(), i
+            if f.lines is None:
+                continue
+            so, co, no = w["lines"]
+            assert (host(f.seg_count()) == co).all(), i
+            assert (host(f.line_npts()) == no).all(), i
+            assert (host(f.segments()) == so).all(), i
+
+    b = lane.Batch(frames)
+    for rep in range(3):
+        say("replay", rep)
+        b.launch()
+        check_all(range(len(frames)))
+        for f in frames:
+            if f.lines is not None:
+                f.lines.fill_(-9)
+        torch.cuda.synchronize()
+    # only frames 1 and 4 run: their segments come back, the others keep -9
+    b.select([0, 1, 0, 0, 1, 0])
+    b.launch()
+    check_all([1, 4])
+    for i in (0, 2, 3):
+        assert (host(frames[i].lines) == -9).all(), i
+    b.select([1] * len(frames))
+    b.launch_stage(4)   # the stage alone recomputes the segments from the kept peaks
+    check_all(range(len(frames)))
+    b.close()
