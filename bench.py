@@ -246,10 +246,13 @@ def main():
     copy_gbs = 2 * nb / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
     del csrc, cdst
     if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        # counter calibration for the traffic figures: an ordinary elementwise
+        # kernel reading 1 GiB and writing 1 GiB (a device copy_ goes to the
+        # runtime's blit kernel, whose counters behave differently)
+        src = torch.zeros(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(2):
-            dst.copy_(src)
+            torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
