@@ -405,6 +405,7 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         const RawRow Rm = load(y_begin - 1), Rc = load(y_begin);
         RawRow R0 = load(y_begin + 1), R1 = load(y_begin + 2);
         RawRow R2 = load(y_begin + 3), R3 = load(y_begin + 4);
+        __builtin_amdgcn_sched_barrier(0);  // all six rows go out before the first one is used
         HRow Q0, Q1;
         h2 X[8];
         h2 HU[8];
