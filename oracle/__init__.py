@@ -5,7 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 or calls it; the oracle imports nothing from the product.
 
 ``lane_oracle.c`` holds the integer path (Sobel + binarize, Q14 vote, greedy
-NMS peaks, line segments along the peaks) as plain nested loops; ``cnn.py``
+NMS peaks, line segments along the peaks, and the Canny detector) as plain
+nested loops; ``cnn.py``
 the FP64 proposal network and its analytic backward, tile labels, masks and
 peak agreement.
 """
@@ -53,6 +54,8 @@ def _load():
         lib.oracle_hough_lines.restype = i32
         lib.oracle_hough_lines.argtypes = [vp, i32, i32, i32, vp, vp, i32, i32, vp, vp, i32, i32,
                                            i32, i32, vp, vp, vp]
+        lib.oracle_canny.restype = ctypes.c_int64
+        lib.oracle_canny.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
         lib.oracle_r_offset.restype = i32
         lib.oracle_r_offset.argtypes = [i32, i32]
         _lib = lib
@@ -75,6 +78,22 @@ def sobel_binarize(img: np.ndarray, W: int | None = None, threshold: int = 128,
     mag = np.zeros((H, W), np.uint8)
     n = _load().oracle_sobel_binarize(_ptr(img), W, H, pitch, int(threshold), int(border_mode),
                                       _ptr(edges), _ptr(mag))
+    return edges, mag, int(n)
+
+
+def canny(img: np.ndarray, W: int | None = None, t_low: int = 64, t_high: int = 128,
+          border_mode: int = 1):
+    """Canny edges (see oracle_canny).  Returns (edges[H][W] 0/255,
+    mag[H][W] = min(|gx|+|gy|, 255) of the blurred image, n_edges)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, pitch = img.shape
+    W = pitch if W is None else W
+    edges = np.zeros((H, W), np.uint8)
+    mag = np.zeros((H, W), np.uint8)
+    n = _load().oracle_canny(_ptr(img), W, H, pitch, int(t_low), int(t_high), int(border_mode),
+                             _ptr(edges), _ptr(mag))
+    if n < 0:
+        raise ValueError("bad Canny arguments")
     return edges, mag, int(n)
 
 

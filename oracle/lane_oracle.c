@@ -21,6 +21,8 @@
  *   oracle_hough_lines     Sec. 1 step 4 and Sec. 5 ("Hough lines", Fig. 12):
  *                          the lane lines drawn from the peaks; again MATLAB
  *                          in the paper, no algorithm given (reading below).
+ *   oracle_canny           Sec. 7: the Canny detector the paper proposes in
+ *                          place of Sobel + binarization (specified below).
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes):
@@ -265,6 +267,117 @@ int oracle_hough_lines(const uint8_t *edges, int W, int H, int epitch, const int
     }
     free(pts);
     return 0;
+}
+
+/* Canny edge detector (Sec. 7 proposes it instead of Sobel + binarization;
+ * the paper gives no parameters, so this is the definition used here, all in
+ * integers):
+ *   blur   B = (sum over i, j in [-2, 2] of w[i] w[j] I(clamp x+i, clamp y+j)
+ *          + 128) >> 8 with w = (1, 4, 6, 4, 1) (binomial, sum 256; the frame
+ *          edge is replicated);
+ *   grad   gx, gy: the Sobel operator of oracle_sobel_binarize applied to B,
+ *          edge replicated; m = |gx| + |gy|;
+ *   sector the gradient direction to the nearest multiple of 45 degrees with
+ *          tan(22.5 deg) = 13573 / 2^15:
+ *            32768 |gy| <= 13573 |gx|  -> along x   (neighbours (x-1,y), (x+1,y))
+ *            32768 |gx| <= 13573 |gy|  -> along y   ((x,y-1), (x,y+1))
+ *            else gx gy > 0            -> diagonal  ((x-1,y-1), (x+1,y+1))
+ *            else                      -> anti-diag ((x+1,y-1), (x-1,y+1));
+ *   thin   keep m iff m > m(first neighbour) and m >= m(second), m = 0
+ *          outside the frame;
+ *   class  a kept pixel with m > t_high is strong, with t_low < m <= t_high
+ *          weak; with border_mode 1 the one-pixel ring is neither;
+ *   link   edge = 255 for the strong pixels and the weak pixels joined to a
+ *          strong one by a chain of 8-neighbouring strong or weak pixels.
+ * edges[H][W] gets 0/255; mag (nullable) gets min(m, 255) of the blurred
+ * image.  Returns the number of edge pixels, or -1 on bad arguments. */
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int64_t oracle_canny(const uint8_t *img, int W, int H, int pitch, int t_low, int t_high,
+                     int border_mode, uint8_t *edges, uint8_t *mag)
+{
+    if (W <= 0 || H <= 0 || pitch < W || t_low < 0 || t_high < t_low) return -1;
+    static const int w5[5] = {1, 4, 6, 4, 1};
+    size_t n = (size_t)W * H;
+    int *B = (int *)malloc(sizeof(int) * n);
+    int *M = (int *)malloc(sizeof(int) * n);
+    int *GX = (int *)malloc(sizeof(int) * n);
+    int *GY = (int *)malloc(sizeof(int) * n);
+    uint8_t *cls = (uint8_t *)malloc(n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * n);
+    if (!B || !M || !GX || !GY || !cls || !queue) {
+        free(B); free(M); free(GX); free(GY); free(cls); free(queue);
+        return -1;
+    }
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int acc = 0;
+            for (int j = -2; j <= 2; ++j)
+                for (int i = -2; i <= 2; ++i)
+                    acc += w5[i + 2] * w5[j + 2] *
+                           img[(size_t)clampi(y + j, 0, H - 1) * pitch + clampi(x + i, 0, W - 1)];
+            B[(size_t)y * W + x] = (acc + 128) >> 8;
+        }
+#define BB(u, v) B[(size_t)clampi((v), 0, H - 1) * W + clampi((u), 0, W - 1)]
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int gx = BB(x + 1, y - 1) + 2 * BB(x + 1, y) + BB(x + 1, y + 1) - BB(x - 1, y - 1) -
+                     2 * BB(x - 1, y) - BB(x - 1, y + 1);
+            int gy = BB(x - 1, y + 1) + 2 * BB(x, y + 1) + BB(x + 1, y + 1) - BB(x - 1, y - 1) -
+                     2 * BB(x, y - 1) - BB(x + 1, y - 1);
+            size_t o = (size_t)y * W + x;
+            GX[o] = gx;
+            GY[o] = gy;
+            M[o] = iabs(gx) + iabs(gy);
+            if (mag) mag[o] = (uint8_t)(M[o] > 255 ? 255 : M[o]);
+        }
+#undef BB
+#define MM(u, v) (((u) < 0 || (v) < 0 || (u) >= W || (v) >= H) ? 0 : M[(size_t)(v) * W + (u)])
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t o = (size_t)y * W + x;
+            int ax = iabs(GX[o]), ay = iabs(GY[o]), m = M[o];
+            int m1, m2;
+            if ((int64_t)32768 * ay <= (int64_t)13573 * ax) {
+                m1 = MM(x - 1, y); m2 = MM(x + 1, y);
+            } else if ((int64_t)32768 * ax <= (int64_t)13573 * ay) {
+                m1 = MM(x, y - 1); m2 = MM(x, y + 1);
+            } else if ((int64_t)GX[o] * GY[o] > 0) {
+                m1 = MM(x - 1, y - 1); m2 = MM(x + 1, y + 1);
+            } else {
+                m1 = MM(x + 1, y - 1); m2 = MM(x - 1, y + 1);
+            }
+            int c = 0;
+            if (m > m1 && m >= m2) c = m > t_high ? 2 : (m > t_low ? 1 : 0);
+            if (border_mode == 1 && (x == 0 || y == 0 || x == W - 1 || y == H - 1)) c = 0;
+            cls[o] = (uint8_t)c;
+            edges[o] = 0;
+        }
+#undef MM
+    /* breadth-first search from every strong pixel through strong/weak ones */
+    size_t head = 0, tail = 0;
+    for (size_t o = 0; o < n; ++o)
+        if (cls[o] == 2) {
+            edges[o] = 255;
+            queue[tail++] = (int32_t)o;
+        }
+    while (head < tail) {
+        int o = queue[head++];
+        int x = o % W, y = o / W;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int u = x + dx, v = y + dy;
+                if (u < 0 || v < 0 || u >= W || v >= H) continue;
+                size_t q = (size_t)v * W + u;
+                if (cls[q] != 0 && edges[q] == 0) {
+                    edges[q] = 255;
+                    queue[tail++] = (int32_t)q;
+                }
+            }
+    }
+    int64_t count = (int64_t)tail;
+    free(B); free(M); free(GX); free(GY); free(cls); free(queue);
+    return count;
 }
 
 /* D = ceil(sqrt((W-1)^2 + (H-1)^2)) by integer search. */

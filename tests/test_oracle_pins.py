@@ -438,3 +438,77 @@ def test_lines_padding_peak_is_empty(oracle):
     segs, counts, npts = oracle.hough_lines(e, C, S, oracle.r_offset(8, 8), np.array([-1], np.int32),
                                             np.array([-1], np.int32))
     assert counts[0] == 0 and npts[0] == 0 and (segs == -1).all()
+
+
+# --------------------------------------------------------------- Canny (Sec. 7)
+# The detector the paper proposes instead of Sobel + binarization.  Pinned by
+# library routines (blur and gradient by scipy correlation, the hysteresis by
+# scipy connected-component labelling) and by drawn steps whose thinned edge
+# is known.
+
+W5 = np.array([1, 4, 6, 4, 1], np.int64)
+
+
+def lib_canny_mag(img):
+    a = img.astype(np.int64)
+    b = (ndimage.correlate(a, np.outer(W5, W5), mode="nearest") + 128) >> 8
+    gx = ndimage.correlate(b, KX, mode="nearest")
+    gy = ndimage.correlate(b, KY, mode="nearest")
+    return np.abs(gx) + np.abs(gy)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_canny_gradient_matches_library(oracle, seed):
+    rng = np.random.default_rng(seed)
+    H, W = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    img = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    _, mag, _ = oracle.canny(img, t_low=50, t_high=100)
+    assert (mag == np.minimum(lib_canny_mag(img), 255)).all()
+
+
+def test_canny_constant_and_steps(oracle):
+    H, W = 30, 40
+    assert oracle.canny(np.full((H, W), 77, np.uint8))[2] == 0
+    img = np.full((H, W), 50, np.uint8)
+    img[:, 20:] = 200                      # vertical step between columns 19 and 20
+    e, _, n = oracle.canny(img, t_low=64, t_high=128)
+    want = np.zeros((H, W), np.uint8)
+    want[1:H - 1, 19] = 255                # one column: the left of the two equal maxima
+    assert (e == want).all() and n == H - 2
+    e, _, _ = oracle.canny(img.T.copy(), t_low=64, t_high=128)
+    assert (e == want.T).all()             # horizontal step: one row
+    # a step below the high threshold and above the low one has no strong pixel
+    weak = np.full((H, W), 100, np.uint8)
+    weak[:, 20:] = 118
+    _, mag, _ = oracle.canny(weak, t_low=10, t_high=200)
+    assert 10 < mag[5, 19] <= 200
+    assert oracle.canny(weak, t_low=10, t_high=200)[2] == 0
+
+
+def test_canny_diagonal_step_is_thin_and_continuous(oracle):
+    H = W = 48
+    yy, xx = np.mgrid[0:H, 0:W]
+    img = np.where(xx + yy > 47, 210, 60).astype(np.uint8)
+    e, _, _ = oracle.canny(img, t_low=64, t_high=128)
+    ys, xs = np.nonzero(e)
+    assert len(ys) > 0
+    assert set((xs + ys).tolist()) <= {47, 48}      # within half a pixel of the boundary
+    for y in range(3, H - 3):                       # an unbroken 8-connected line
+        assert e[y].any()
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_canny_hysteresis_is_connected_components(oracle, seed):
+    rng = np.random.default_rng(50 + seed)
+    H, W = 60, 80
+    img = ndimage.gaussian_filter(rng.integers(0, 256, (H, W)).astype(float), 2.0)
+    img = np.clip((img - img.mean()) * 6 + 128, 0, 255).astype(np.uint8)
+    lo, hi = 40, 120
+    cand = oracle.canny(img, t_low=lo, t_high=lo)[0] == 255     # kept and above low
+    strong = oracle.canny(img, t_low=hi, t_high=hi)[0] == 255   # kept and above high
+    assert strong.any() and (cand & ~strong).any()
+    lab, _ = ndimage.label(cand, structure=np.ones((3, 3), int))
+    keep = np.unique(lab[strong])
+    want = np.isin(lab, keep[keep > 0])
+    got = oracle.canny(img, t_low=lo, t_high=hi)[0] == 255
+    assert (got == want).all()
