@@ -103,6 +103,38 @@ int lane_sobel_binarize(const uint8_t *img, int32_t W, int32_t H, int32_t pitch,
                         uint8_t *mag_opt, uint32_t *list_opt, uint32_t *edge_count_opt,
                         void *stream);
 
+/* Workspace bytes of lane_canny for a W x H frame (6 bytes per pixel). */
+int lane_canny_workspace_size(int32_t W, int32_t H, size_t *bytes);
+
+/* Canny edge detector, the replacement for Sobel + binarization that Sec. 7
+ * proposes (the paper gives no parameters; this is the definition used):
+ *   blur   B = (sum_{i,j in [-2,2]} w_i w_j I(clamp(x+i), clamp(y+j)) + 128) >> 8,
+ *          w = (1, 4, 6, 4, 1), the frame edge replicated;
+ *   grad   gx, gy: the Sobel operator of lane_sobel_binarize on B (edge
+ *          replicated), m = |gx| + |gy|;
+ *   sector along x if 32768|gy| <= 13573|gx|, along y if 32768|gx| <= 13573|gy|,
+ *          else the diagonal (gx gy > 0) or the anti-diagonal;
+ *   thin   a pixel is kept iff m > m(neighbour at -1 along the sector) and
+ *          m >= m(neighbour at +1), m = 0 outside the frame;
+ *   class  kept and m > t_high: strong; kept and t_low < m <= t_high: weak;
+ *          border_mode 1 excludes the one-pixel ring;
+ *   link   edge = 255 for strong pixels and weak pixels 8-connected to a
+ *          strong one through strong or weak pixels; else 0.
+ *   img       device uint8 [H][pitch]; W, H <= LANE_MAX_DIM
+ *   t_low <= t_high in [0, 65535]
+ *   edges     device uint8 [H][W]
+ *   mag_opt   device uint8 [H][W] or NULL: min(m, 255)
+ *   list_opt  device edge list (as lane_sobel_binarize) or NULL, 16-byte aligned
+ *   edge_count_opt device uint32 scalar or NULL: edge pixels
+ *   ws        device, >= lane_canny_workspace_size() bytes, 16-byte aligned
+ *             (per-pixel classes, union-find labels, component flags)
+ * Results are exact (integer arithmetic; the linked set does not depend on
+ * the order in which components are merged). */
+int lane_canny(const uint8_t *img, int32_t W, int32_t H, int32_t pitch, int32_t t_low,
+               int32_t t_high, int32_t border_mode, uint8_t *edges, uint8_t *mag_opt,
+               uint32_t *list_opt, uint32_t *edge_count_opt, void *ws, size_t ws_bytes,
+               void *stream);
+
 /* Compaction alone: builds the edge list from an existing edge map (a pixel
  * is an edge iff it equals 255, Sec. 3.3).  edges: device uint8 [H][pitch]. */
 int lane_edges_to_list(const uint8_t *edges, int32_t W, int32_t H, int32_t pitch,

@@ -13,6 +13,11 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
+extern "C" LANE_INTERNAL size_t lane_canny_ws_bytes(int W, int H);
+extern "C" LANE_INTERNAL hipError_t lane_launch_canny(const uint8_t* img, int W, int H, int pitch, int t_low,
+                                                      int t_high, int border_mode, uint8_t* edges,
+                                                      uint8_t* mag, uint32_t* edge_count, void* ws,
+                                                      hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int W, int H, const int16_t* C,
                                                       const int16_t* S, int n_theta, int r_offset,
                                                       const int32_t* theta_idx, const int32_t* r_idx,
@@ -280,6 +285,42 @@ int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r
     d.nbr = lane_peaks_blocks_per_row(n_r, d.block_log2);
     d.n_blocks = n_theta * d.nbr;
     return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));
+}
+
+int lane_canny_workspace_size(int32_t W, int32_t H, size_t* bytes) {
+    if (!bytes || !dims_ok(W, H)) return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    *bytes = lane_canny_ws_bytes(W, H);
+    return LANE_OK;
+}
+
+int lane_canny(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int32_t t_low, int32_t t_high,
+               int32_t border_mode, uint8_t* edges, uint8_t* mag_opt, uint32_t* list_opt,
+               uint32_t* edge_count_opt, void* ws, size_t ws_bytes, void* stream) {
+    if (!img || !edges || !ws || !dims_ok(W, H) || pitch < W || t_low < 0 || t_high < t_low ||
+        t_high > 65535)
+        return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    if (border_mode != LANE_BORDER_ZERO && border_mode != LANE_BORDER_ZERO_MASKRING)
+        return LANE_E_UNSUPPORTED;
+    if ((list_opt && !aligned16(list_opt)) || !aligned16(ws)) return LANE_E_ARG;
+    if (ws_bytes < lane_canny_ws_bytes(W, H)) return LANE_E_WS;
+    hipStream_t s = (hipStream_t)stream;
+    if (edge_count_opt && lane_launch_fill_u32(edge_count_opt, 1, 0u, s) != hipSuccess) return LANE_E_DEVICE;
+    hipError_t e = lane_launch_canny(img, W, H, pitch, t_low, t_high, border_mode, edges, mag_opt,
+                                     list_opt ? nullptr : edge_count_opt, ws, s);
+    if (e != hipSuccess || !list_opt) return dev_status(e);
+    // the edge list, as lane_edges_to_list builds it (counting the edges)
+    SobelDesc d;
+    memset(&d, 0, sizeof(d));
+    d.img = edges;
+    d.W = W;
+    d.H = H;
+    d.pitch = W;
+    d.list = list_opt;
+    d.edge_count = edge_count_opt;
+    d.strip_rows = kStripRows;
+    return dev_status(lane_launch_sobel(&d, 1, s));
 }
 
 int lane_hough_lines(const uint8_t* edges, int32_t W, int32_t H, const int16_t* cos_q14,

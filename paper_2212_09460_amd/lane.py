@@ -41,6 +41,9 @@ _vote = _sig("lane_hough_vote", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _v
 _peaks_ws = _sig("lane_hough_peaks_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _peaks = _sig("lane_hough_peaks", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
                                     _vp, _vp, _sz, _vp])
+_canny_ws = _sig("lane_canny_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
+_canny = _sig("lane_canny", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
+                              _vp])
 _lines = _sig("lane_hough_lines", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i32, _i32,
                                     _i32, _i32, _vp, _vp, _vp, _vp])
 
@@ -52,7 +55,7 @@ LANE_BORDER_ZERO_MASKRING = 1
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
            "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_lines",
-           "lane_batch_create",
+           "lane_canny_workspace_size", "lane_canny", "lane_batch_create",
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
@@ -182,6 +185,31 @@ def hough_peaks(acc: torch.Tensor, r_offset: int, k: int, h_theta: int | None = 
                   int(min_votes), _p(t), _p(r), _p(v), _p(c), _p(ws), ws.numel() * 8,
                   _stream(stream)), "lane_hough_peaks")
     return t, r, v, c
+
+
+def canny_workspace_size(W: int, H: int) -> int:
+    n = _sz(0)
+    _check(_canny_ws(W, H, ctypes.byref(n)), "lane_canny_workspace_size")
+    return int(n.value)
+
+
+def canny(img: torch.Tensor, W: int | None = None, t_low: int = 64, t_high: int = 128,
+          border_mode: int = LANE_BORDER_ZERO_MASKRING, want_mag: bool = False,
+          want_list: bool = True, ws=None, stream=None):
+    """Canny edges (see lane_canny).  Returns (edges, mag or None, edge list or
+    None, edge count) as device tensors."""
+    H, pitch = img.shape
+    W = pitch if W is None else W
+    dev = img.device
+    edges = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    mag = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_mag else None
+    lst = new_edge_list(W, H, dev) if want_list else None
+    cnt = torch.empty((1,), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = torch.empty(canny_workspace_size(W, H) // 8 + 2, dtype=torch.int64, device=dev)
+    _check(_canny(_p(img), W, H, pitch, int(t_low), int(t_high), int(border_mode), _p(edges),
+                  _p(mag), _p(lst), _p(cnt), _p(ws), ws.numel() * 8, _stream(stream)), "lane_canny")
+    return edges, mag, lst, cnt
 
 
 def hough_lines(edges: torch.Tensor, cos_q14: torch.Tensor, sin_q14: torch.Tensor, r_offset: int,
