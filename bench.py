@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="length of each serving run, plain and pruned (0 = skip)")
     ap.add_argument("--serve-pool", type=int, default=32, help="pre-generated frames per stream")
+    ap.add_argument("--edge-frames", type=int, default=64,
+                    help="frames of the Sobel vs Canny comparison (0 = skip)")
     return ap.parse_args()
 
 
@@ -106,6 +108,69 @@ def cpu_baseline(pool, C, S, budget_s):
             "sample": f"{n} frames of the 1920x1080 workload (full path: Sobel, binarize, "
                       f"vote over 360 theta, top-8 peaks), single-threaded C oracle, "
                       f"{dt:.1f} s", "frames_per_s": round(n / dt, 4)}
+
+
+def edge_detectors(n_frames):
+    """Sobel + binarization (the paper's detector) against Canny (its
+    proposed replacement) on the same seeded 1080p frames, each through the
+    single-frame entry points (detector -> vote -> peaks): GPU time per frame,
+    edge fraction, and the share of painted lanes found among the top-4
+    peaks.  Frames come from seeds disjoint from the throughput pool."""
+    import torch
+
+    import paper_2212_09460_amd.lane as lane
+    from paper_2212_09460_amd import synth
+    from paper_2212_09460_amd.learned.evaluate import lanes_found
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sc = synth.scene_road(W, H)
+    seeds = [synth.frame_seed(0, synth.CONFIG_PLAIN_1080, 100000 + i) for i in range(n_frames)]
+    imgs = [torch.from_numpy(synth.gen_frame(sc, sd)).to(dev) for sd in seeds]
+    C, S = synth.trig_q14(N_THETA)
+    Cd, Sd = torch.from_numpy(C).to(dev), torch.from_numpy(S).to(dev)
+    D = lane.r_offset(W, H)
+    n_r = 2 * D + 1
+    ws = torch.empty(lane.canny_workspace_size(W, H) // 8 + 2, dtype=torch.int64, device=dev)
+    T_LOW, T_HIGH = 64, 128
+
+    def detect(kind, img):
+        if kind == "sobel":
+            _, _, lst, cnt = lane.sobel_binarize(img, W, 128, 1, stream=stream)
+        else:
+            _, _, lst, cnt = lane.canny(img, W, T_LOW, T_HIGH, 1, ws=ws, stream=stream)
+        return lst, cnt
+
+    out = {"frames": n_frames, "canny_thresholds": [T_LOW, T_HIGH], "sobel_threshold": 128}
+    for kind in ("sobel", "canny"):
+        # warm-up, then the detector alone and the whole path, back to back
+        for img in imgs[:2]:
+            detect(kind, img)
+        torch.cuda.synchronize()
+        t_det = event_time(torch, lambda: [detect(kind, im) for im in imgs], 1, stream) / n_frames
+        results = []
+
+        def path():
+            results.clear()
+            for im in imgs:
+                lst, cnt = detect(kind, im)
+                acc, _ = lane.hough_vote(lst, W, H, Cd, Sd, D, n_r, stream=stream)
+                results.append((cnt, lane.hough_peaks(acc, D, TOPK, stream=stream)))
+
+        t_path = event_time(torch, path, 1, stream) / n_frames
+        found = total = 0
+        edges = 0
+        for sd, (cnt, (t, r, v, c)) in zip(seeds, results):
+            n = int(c.cpu()[0])
+            f = lanes_found(synth.lane_segments(sc, sd), t.cpu().numpy(), r.cpu().numpy(), n,
+                            N_THETA, D, k=4)
+            found += int(f.sum())
+            total += len(f)
+            edges += int(cnt.cpu()[0])
+        out[kind] = {"detector_ms_per_frame": round(t_det, 4), "path_ms_per_frame": round(t_path, 4),
+                     "edge_fraction": round(edges / (n_frames * W * H), 4),
+                     "lanes_found_top4": round(found / max(total, 1), 4)}
+    return out
 
 
 def serving(args):
@@ -300,6 +365,8 @@ def main():
     batch.close()
     del frames, pool_d
     torch.cuda.empty_cache()
+    if args.edge_frames > 0:
+        out["edge_detectors"] = edge_detectors(args.edge_frames)
     if args.serve_seconds > 0:
         out["serving"] = serving(args)
     if args.cpu_seconds > 0:

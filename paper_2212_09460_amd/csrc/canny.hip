@@ -14,12 +14,15 @@
 //
 // k_canny_thin does blur, gradient, thinning and classes for a 64 x 16 tile in
 // LDS (the image tile with a 4-pixel apron, separable blur, gradient with a
-// 1-pixel apron).  The linking is connected-component labelling by lock-free
-// union-find over the candidate pixels (a root always hangs under a smaller
-// index, so every chain strictly decreases and ends): init with the classes,
-// union with the four already-visited neighbours, flatten and flag the
-// components holding a strong pixel, then write 0/255.  A fixed number of
-// kernels, no host loop, so it can sit in a graph.
+// 1-pixel apron), then labels the tile's candidate pixels (strong or weak)
+// by union-find in LDS and stores each pixel's label as the global index of
+// its tile-local root.  The linking across tiles is lock-free union-find over
+// those labels (a root always hangs under a smaller index, so every chain
+// strictly decreases and ends): only the pixels of each tile's top row and
+// left column unite with their neighbours across the boundary; then every
+// candidate takes its root, the components holding a strong pixel are
+// flagged, and the edge map is written.  A fixed number of kernels, no host
+// loop, so it can sit in a graph.
 #include "lane_internal.h"
 
 namespace lane {
@@ -42,6 +45,35 @@ struct CannyDesc {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Union-find in LDS over a tile's pixels (parents have smaller indices).
+__device__ __forceinline__ int lds_find(const int* lab, int i) {
+    int r = i;
+    for (int hops = 0; hops <= i; ++hops) {
+        const int p = __hip_atomic_load(lab + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (p == r) return r;
+        r = p;
+    }
+    return r;
+}
+
+__device__ __forceinline__ void lds_unite(int* lab, int a, int b) {
+    for (int tries = 0; tries <= a + b + 1; ++tries) {
+        a = lds_find(lab, a);
+        b = lds_find(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        int expected = a;
+        if (__hip_atomic_compare_exchange_strong(lab + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = expected;
+    }
+}
+
 __global__ void __launch_bounds__(kCannyThreads) k_canny_thin(CannyDesc d) {
     // tile coordinates are image coordinates; aprons: image 4, blur 2, grad 1
     constexpr int IW = kCannyTW + 8, IH = kCannyTH + 8;   // image, clamped
@@ -52,6 +84,8 @@ __global__ void __launch_bounds__(kCannyThreads) k_canny_thin(CannyDesc d) {
     __shared__ uint8_t s_b[BH][BW];
     __shared__ int16_t s_m[GH][GW];
     __shared__ int16_t s_gx[GH][GW], s_gy[GH][GW];
+    __shared__ uint8_t s_cls[kCannyTH][kCannyTW];
+    __shared__ int s_lab[kCannyTH * kCannyTW];
     const int X0 = blockIdx.x * kCannyTW, Y0 = blockIdx.y * kCannyTH;
     const int tid = threadIdx.x;
     const int W = d.W, H = d.H;
@@ -101,32 +135,59 @@ __global__ void __launch_bounds__(kCannyThreads) k_canny_thin(CannyDesc d) {
     for (int i = tid; i < kCannyTW * kCannyTH; i += kCannyThreads) {
         const int v = i / kCannyTW, u = i - v * kCannyTW;
         const int x = X0 + u, y = Y0 + v;
-        if (x >= W || y >= H) continue;
-        const int gu = u + 1, gv = v + 1;
-        const int gx = s_gx[gv][gu], gy = s_gy[gv][gu], m = s_m[gv][gu];
-        const int ax = gx < 0 ? -gx : gx, ay = gy < 0 ? -gy : gy;
-        int m1, m2;
-        if (32768 * ay <= kCTanQ15 * ax) {
-            m1 = s_m[gv][gu - 1];
-            m2 = s_m[gv][gu + 1];
-        } else if (32768 * ax <= kCTanQ15 * ay) {
-            m1 = s_m[gv - 1][gu];
-            m2 = s_m[gv + 1][gu];
-        } else if ((gx > 0) == (gy > 0)) {
-            m1 = s_m[gv - 1][gu - 1];
-            m2 = s_m[gv + 1][gu + 1];
-        } else {
-            m1 = s_m[gv - 1][gu + 1];
-            m2 = s_m[gv + 1][gu - 1];
-        }
         int c = 0;
-        if (m > m1 && m >= m2) c = m > d.t_high ? 2 : (m > d.t_low ? 1 : 0);
-        if (d.border_mode == 1 && (x == 0 || y == 0 || x == W - 1 || y == H - 1)) c = 0;
+        if (x < W && y < H) {
+            const int gu = u + 1, gv = v + 1;
+            const int gx = s_gx[gv][gu], gy = s_gy[gv][gu], m = s_m[gv][gu];
+            const int ax = gx < 0 ? -gx : gx, ay = gy < 0 ? -gy : gy;
+            int m1, m2;
+            if (32768 * ay <= kCTanQ15 * ax) {
+                m1 = s_m[gv][gu - 1];
+                m2 = s_m[gv][gu + 1];
+            } else if (32768 * ax <= kCTanQ15 * ay) {
+                m1 = s_m[gv - 1][gu];
+                m2 = s_m[gv + 1][gu];
+            } else if ((gx > 0) == (gy > 0)) {
+                m1 = s_m[gv - 1][gu - 1];
+                m2 = s_m[gv + 1][gu + 1];
+            } else {
+                m1 = s_m[gv - 1][gu + 1];
+                m2 = s_m[gv + 1][gu - 1];
+            }
+            if (m > m1 && m >= m2) c = m > d.t_high ? 2 : (m > d.t_low ? 1 : 0);
+            if (d.border_mode == 1 && (x == 0 || y == 0 || x == W - 1 || y == H - 1)) c = 0;
+            if (d.mag) gst(d.mag + (size_t)y * W + x, (uint8_t)(m > 255 ? 255 : m));
+        }
+        s_cls[v][u] = (uint8_t)c;
+        s_lab[i] = c ? i : -1;
+    }
+    __syncthreads();
+    // the tile's components: union with the already-visited neighbours
+    for (int i = tid; i < kCannyTW * kCannyTH; i += kCannyThreads) {
+        const int v = i / kCannyTW, u = i - v * kCannyTW;
+        if (!s_cls[v][u]) continue;
+        if (u > 0 && s_cls[v][u - 1]) lds_unite(s_lab, i, i - 1);
+        if (v > 0) {
+            if (u > 0 && s_cls[v - 1][u - 1]) lds_unite(s_lab, i, i - kCannyTW - 1);
+            if (s_cls[v - 1][u]) lds_unite(s_lab, i, i - kCannyTW);
+            if (u + 1 < kCannyTW && s_cls[v - 1][u + 1]) lds_unite(s_lab, i, i - kCannyTW + 1);
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < kCannyTW * kCannyTH; i += kCannyThreads) {
+        const int v = i / kCannyTW, u = i - v * kCannyTW;
+        const int x = X0 + u, y = Y0 + v;
+        if (x >= W || y >= H) continue;
+        const int c = s_cls[v][u];
         const size_t o = (size_t)y * W + x;
+        int32_t lab = -1;
+        if (c) {
+            const int r = lds_find(s_lab, i);  // the tile's smallest index of the component
+            lab = (int32_t)((size_t)(Y0 + r / kCannyTW) * W + X0 + r % kCannyTW);
+        }
         gst(d.cls + o, (uint8_t)c);
-        gst(d.label + o, c ? (int32_t)o : -1);
+        gst(d.label + o, lab);
         gst(d.flag + o, (uint8_t)0);
-        if (d.mag) gst(d.mag + o, (uint8_t)(m > 255 ? 255 : m));
     }
 }
 
@@ -164,18 +225,38 @@ __device__ __forceinline__ void unite(int32_t* label, int a, int b) {
     }
 }
 
+// One workgroup per tile: its top row unites with the row above (N, NW, NE),
+// its left column with the column to the left (W, NW, SW); inside a tile the
+// labels already point at the tile-local roots.
 __global__ void k_canny_merge(CannyDesc d) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= d.W) return;
+    const int X0 = blockIdx.x * kCannyTW, Y0 = blockIdx.y * kCannyTH;
+    const int t = threadIdx.x;
+    int x, y;
+    bool top;
+    if (t < kCannyTW) {
+        x = X0 + t;
+        y = Y0;
+        top = true;
+    } else if (t < kCannyTW + kCannyTH) {
+        x = X0;
+        y = Y0 + (t - kCannyTW);
+        top = false;
+    } else {
+        return;
+    }
+    if (x >= d.W || y >= d.H) return;
     const int o = y * d.W + x;
     if (gld(d.cls + o) == 0) return;
-    // the neighbours already visited in row-major order: W, NW, N, NE
-    if (x > 0 && gld(d.cls + o - 1)) unite(d.label, o, o - 1);
-    if (y > 0) {
+    if (top && y > 0) {
         const int u = o - d.W;
         if (x > 0 && gld(d.cls + u - 1)) unite(d.label, o, u - 1);
         if (gld(d.cls + u)) unite(d.label, o, u);
         if (x + 1 < d.W && gld(d.cls + u + 1)) unite(d.label, o, u + 1);
+    }
+    if (!top && x > 0) {
+        if (gld(d.cls + o - 1)) unite(d.label, o, o - 1);
+        if (y > 0 && gld(d.cls + o - d.W - 1)) unite(d.label, o, o - d.W - 1);
+        if (y + 1 < d.H && gld(d.cls + o + d.W - 1)) unite(d.label, o, o + d.W - 1);
     }
 }
 
@@ -240,7 +321,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_canny(const uint8_t* img, int W,
     const dim3 tiles((W + kCannyTW - 1) / kCannyTW, (H + kCannyTH - 1) / kCannyTH);
     hipLaunchKernelGGL(k_canny_thin, tiles, dim3(kCannyThreads), 0, s, d);
     const dim3 rows((W + 255) / 256, H);
-    hipLaunchKernelGGL(k_canny_merge, rows, dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_canny_merge, tiles, dim3(kCannyTW + kCannyTH), 0, s, d);
     hipLaunchKernelGGL(k_canny_flatten, rows, dim3(256), 0, s, d);
     hipLaunchKernelGGL(k_canny_link, rows, dim3(256), 0, s, d);
     return hipGetLastError();
