@@ -5,8 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 or calls it; the oracle imports nothing from the product.
 
 ``lane_oracle.c`` holds the integer path (Sobel + binarize, Q14 vote, greedy
-NMS peaks, line segments along the peaks, and the Canny detector) as plain
-nested loops; ``cnn.py``
+NMS peaks, line segments along the peaks, the Canny detector and the
+coarse-to-fine Hough transform) as plain nested loops; ``cnn.py``
 the FP64 proposal network and its analytic backward, tile labels, masks and
 peak agreement.
 """
@@ -56,6 +56,8 @@ def _load():
                                            i32, i32, vp, vp, vp]
         lib.oracle_canny.restype = ctypes.c_int64
         lib.oracle_canny.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
+        lib.oracle_hough_progressive.restype = i32
+        lib.oracle_hough_progressive.argtypes = [vp, i32, i32, i32, vp, vp, i32, i32, vp] + [vp] * 9
         lib.oracle_r_offset.restype = i32
         lib.oracle_r_offset.argtypes = [i32, i32]
         _lib = lib
@@ -162,6 +164,51 @@ def hough_lines(edges: np.ndarray, cos_q14, sin_q14, r_offset: int, theta_idx, r
     if st != 0:
         raise ValueError("bad line arguments")
     return segs, counts, npts
+
+
+PROGRESSIVE_FIELDS = ("theta_step", "r_width", "k_coarse", "h_theta_coarse", "h_r_coarse",
+                      "min_votes_coarse", "margin_theta", "margin_r", "k", "h_theta", "h_r",
+                      "min_votes")
+
+
+def hough_progressive(edges: np.ndarray, cos_q14, sin_q14, r_offset: int, W: int | None = None,
+                      **params):
+    """Coarse-to-fine Hough (see oracle_hough_progressive).  ``params`` holds
+    every name of PROGRESSIVE_FIELDS.  Returns a dict with the geometry
+    (n_c, n_rc, Dc, R, Wc), the coarse accumulator, the coarse peaks, the
+    windows, the candidates and the final peaks (theta_idx, r_idx, votes,
+    count)."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint8)
+    H, epitch = edges.shape
+    W = epitch if W is None else W
+    C = np.ascontiguousarray(cos_q14, dtype=np.int16)
+    S = np.ascontiguousarray(sin_q14, dtype=np.int16)
+    n_theta = C.shape[0]
+    missing = [f for f in PROGRESSIVE_FIELDS if f not in params]
+    if missing or len(params) != len(PROGRESSIVE_FIELDS):
+        raise ValueError(f"progressive parameters: missing {missing}, got {sorted(params)}")
+    p = np.array([int(params[f]) for f in PROGRESSIVE_FIELDS], np.int32)
+    f, w, kc, m_t, m_r, k = (int(p[0]), int(p[1]), int(p[2]), int(p[6]), int(p[7]), int(p[8]))
+    if f < 1 or n_theta % f or w < 1 or w % 2 == 0 or kc < 1 or not 1 <= k <= kc:
+        raise ValueError("bad progressive arguments")
+    q = (w - 1) // 2
+    D = int(r_offset)
+    n_c, Dc = n_theta // f, (D + q) // w
+    n_rc, R, Wc = 2 * Dc + 1, f + 2 * m_t, w + 2 * m_r
+    coarse = np.zeros((n_c, n_rc), np.int32)
+    ct, cr, cv = (np.zeros(kc, np.int32) for _ in range(3))
+    win = np.zeros((kc, R, Wc), np.int32)
+    cand = np.zeros((kc, 3), np.int32)
+    t, r, v = (np.zeros(k, np.int32) for _ in range(3))
+    n = _load().oracle_hough_progressive(_ptr(edges), W, H, epitch, _ptr(C), _ptr(S), n_theta, D,
+                                         _ptr(p), _ptr(coarse), _ptr(ct), _ptr(cr), _ptr(cv),
+                                         _ptr(win), _ptr(cand), _ptr(t), _ptr(r), _ptr(v))
+    if n < 0:
+        raise ValueError("bad progressive arguments")
+    n_coarse = int((ct >= 0).sum())
+    return dict(n_c=n_c, n_rc=n_rc, Dc=Dc, R=R, Wc=Wc, coarse_acc=coarse, coarse_theta=ct,
+                coarse_r=cr, coarse_votes=cv, coarse_count=n_coarse, windows=win, cand=cand,
+                theta_idx=t, r_idx=r, votes=v, count=n)
 
 
 def band_bits(n_theta: int) -> np.ndarray:

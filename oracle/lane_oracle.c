@@ -23,6 +23,10 @@
  *                          in the paper, no algorithm given (reading below).
  *   oracle_canny           Sec. 7: the Canny detector the paper proposes in
  *                          place of Sobel + binarization (specified below).
+ *   oracle_hough_progressive  the coarse-to-fine Hough transform of the
+ *                          multiresolution method the paper cites for its
+ *                          GPU vote (Sec. 4.3, reference [9]); the paper
+ *                          gives no algorithm, so it is specified below.
  *
  * Readings where the paper is silent (each one is listed with its reason in
  * the design notes):
@@ -378,6 +382,129 @@ int64_t oracle_canny(const uint8_t *img, int W, int H, int pitch, int t_low, int
     int64_t count = (int64_t)tail;
     free(B); free(M); free(GX); free(GY); free(cls); free(queue);
     return count;
+}
+
+/* Progressive (coarse-to-fine) Hough transform.  The paper bases its GPU
+ * vote (Sec. 4.3) on a multiresolution progressive Hough method (its
+ * reference [9]) without stating one; this is the definition used here.
+ * p[12] = {f, w, kc, hc_t, hc_r, minc, m_t, m_r, k, h_t, h_r, min_votes}.
+ *
+ *   coarse table   row c in [0, n_c), n_c = n_theta / f, is the fine row
+ *                  t_c = c*f + f/2 (f divides n_theta);
+ *   coarse r bins  odd width w, q = (w-1)/2: bin b = floor((r + q) / w) holds
+ *                  r in [b*w - q, b*w + q], so r -> -r maps b -> -b;
+ *                  Dc = floor((D + q) / w), n_rc = 2*Dc + 1, index b + Dc;
+ *   coarse vote    every 255 pixel adds 1 to (c, bin of its Eq. (3) r at
+ *                  row t_c); an r outside [-D, D] is not counted;
+ *   coarse peaks   oracle_hough_peaks on the coarse accumulator (kc, hc_t,
+ *                  hc_r, minc, r_offset Dc);
+ *   windows        coarse peak j = (c, bi) opens R = f + 2*m_t fine rows
+ *                  u = c*f - m_t + a (a in [0, R)) by Wc = w + 2*m_r cells
+ *                  e in [0, Wc): cell (a, e) is the line at unfolded angle
+ *                  row u and r = (bi - Dc)*w - q - m_r + e; its count is the
+ *                  number of 255 pixels whose Eq. (3) r at fine row
+ *                  t = u mod n_theta equals r, or -r when u is an odd number
+ *                  of half turns away (the line (r, theta + 180) is (-r,
+ *                  theta)); cells whose fine index falls outside [0, 2D]
+ *                  count 0 and are never the candidate;
+ *   candidate j    the window's largest count, first in (a, e) order, as the
+ *                  fine cell (t, r_idx, count);
+ *   final peaks    oracle_hough_peaks (k, h_t, h_r, min_votes) on a fine
+ *                  accumulator that is zero except at the candidates' cells.
+ * Outputs: coarse_acc [n_c][n_rc]; cpk_theta/cpk_r/cpk_votes [kc] (the
+ * coarse peaks, -1 padded); windows [kc][R][Wc] (0 for absent peaks);
+ * cand [kc][3] (-1 for absent peaks); theta_idx/r_idx/votes [k].
+ * Returns the number of final peaks, or -1 on bad arguments. */
+int oracle_hough_progressive(const uint8_t *edges, int W, int H, int epitch,
+                             const int16_t *C, const int16_t *S, int n_theta, int D,
+                             const int32_t *p, int32_t *coarse_acc, int32_t *cpk_theta,
+                             int32_t *cpk_r, int32_t *cpk_votes, int32_t *windows,
+                             int32_t *cand, int32_t *theta_idx, int32_t *r_idx, int32_t *votes)
+{
+    int f = p[0], w = p[1], kc = p[2], m_t = p[6], m_r = p[7], k = p[8];
+    if (f < 1 || n_theta % f != 0 || w < 1 || (w % 2) == 0 || kc < 1 || k < 1 || k > kc ||
+        m_t < 0 || m_r < 0 || D < 0)
+        return -1;
+    int q = (w - 1) / 2;
+    int n_c = n_theta / f;
+    int Dc = (D + q) / w;
+    int n_rc = 2 * Dc + 1;
+    int n_r = 2 * D + 1;
+    int R = f + 2 * m_t, Wc = w + 2 * m_r;
+
+    /* coarse vote */
+    memset(coarse_acc, 0, sizeof(int32_t) * (size_t)n_c * (size_t)n_rc);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            if (edges[(size_t)y * epitch + x] != 255) continue;
+            for (int c = 0; c < n_c; ++c) {
+                int t = c * f + f / 2;
+                int64_t r = floor_div((int64_t)x * C[t] + (int64_t)y * S[t] + 8192, 16384);
+                if (r < -D || r > D) continue;
+                int64_t b = floor_div(r + q, w);
+                coarse_acc[(size_t)c * n_rc + (size_t)(b + Dc)] += 1;
+            }
+        }
+
+    /* coarse peaks */
+    int nc = oracle_hough_peaks(coarse_acc, n_c, n_rc, Dc, kc, p[3], p[4], p[5], cpk_theta, cpk_r,
+                                cpk_votes);
+    if (nc < 0) return -1;
+
+    /* windows around the coarse peaks */
+    memset(windows, 0, sizeof(int32_t) * (size_t)kc * (size_t)R * (size_t)Wc);
+    for (int j = 0; j < kc; ++j) cand[3 * j] = cand[3 * j + 1] = cand[3 * j + 2] = -1;
+    for (int j = 0; j < nc; ++j) {
+        int c = cpk_theta[j];
+        int64_t rlo = (int64_t)(cpk_r[j] - Dc) * w - q - m_r; /* r of cell e = 0 */
+        int32_t *win = windows + (size_t)j * R * Wc;
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                if (edges[(size_t)y * epitch + x] != 255) continue;
+                for (int a = 0; a < R; ++a) {
+                    int64_t u = (int64_t)c * f - m_t + a;
+                    int64_t h = floor_div(u, n_theta);
+                    int t = (int)(u - h * n_theta);
+                    int64_t r = floor_div((int64_t)x * C[t] + (int64_t)y * S[t] + 8192, 16384);
+                    if (r < -D || r > D) continue;
+                    int64_t ru = (h % 2 != 0) ? -r : r; /* the same line at row u */
+                    int64_t e = ru - rlo;
+                    if (e >= 0 && e < Wc) win[(size_t)a * Wc + (size_t)e] += 1;
+                }
+            }
+        /* candidate: largest count in (a, e) order over cells inside [0, 2D] */
+        int best = -1, bt = -1, bi = -1;
+        for (int a = 0; a < R; ++a) {
+            int64_t u = (int64_t)c * f - m_t + a;
+            int64_t h = floor_div(u, n_theta);
+            int t = (int)(u - h * n_theta);
+            for (int e = 0; e < Wc; ++e) {
+                int64_t ru = rlo + e;
+                int64_t r = (h % 2 != 0) ? -ru : ru;
+                if (r < -D || r > D) continue;
+                int v = win[(size_t)a * Wc + (size_t)e];
+                if (v > best) {
+                    best = v;
+                    bt = t;
+                    bi = (int)(r + D);
+                }
+            }
+        }
+        cand[3 * j] = bt;
+        cand[3 * j + 1] = bi;
+        cand[3 * j + 2] = best;
+    }
+
+    /* final peaks among the candidates */
+    size_t ncell = (size_t)n_theta * (size_t)n_r;
+    int32_t *A = (int32_t *)calloc(ncell, sizeof(int32_t));
+    if (!A) return -1;
+    for (int j = 0; j < nc; ++j)
+        if (cand[3 * j] >= 0 && cand[3 * j + 2] > 0)
+            A[(size_t)cand[3 * j] * n_r + (size_t)cand[3 * j + 1]] = cand[3 * j + 2];
+    int n = oracle_hough_peaks(A, n_theta, n_r, D, k, p[9], p[10], p[11], theta_idx, r_idx, votes);
+    free(A);
+    return n;
 }
 
 /* D = ceil(sqrt((W-1)^2 + (H-1)^2)) by integer search. */

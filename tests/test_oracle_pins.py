@@ -512,3 +512,164 @@ def test_canny_hysteresis_is_connected_components(oracle, seed):
     want = np.isin(lab, keep[keep > 0])
     got = oracle.canny(img, t_low=lo, t_high=hi)[0] == 255
     assert (got == want).all()
+
+
+# ------------------------------------------- coarse-to-fine Hough (Sec. 4.3, ref. [9])
+# The progressive transform is pinned against the plain vote and peaks
+# (themselves pinned above): with no coarsening it must reduce to them, its
+# coarse accumulator must be the binned fine rows it samples, its windows
+# must be cells of the fine accumulator (with the half-turn mirror), its
+# final peaks the brute-force greedy selection over the candidates, and it
+# must find drawn lines at their own cells.
+
+def _prog(f=4, w=9, kc=8, hct=1, hcr=2, minc=1, mt=2, mr=6, k=4, ht=1, hr=2, mv=1):
+    return dict(theta_step=f, r_width=w, k_coarse=kc, h_theta_coarse=hct, h_r_coarse=hcr,
+                min_votes_coarse=minc, margin_theta=mt, margin_r=mr, k=k, h_theta=ht, h_r=hr,
+                min_votes=mv)
+
+
+def _random_edges(seed, H, W, p):
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random((H, W)) < p, 255, 0).astype(np.uint8)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_progressive_without_coarsening_is_the_plain_hough(oracle, synth, seed):
+    """theta_step 1, r_width 1, no margins: the coarse accumulator is the
+    fine one, each window is its coarse peak's own cell, and the final
+    peaks are the brute-force greedy peaks of the fine accumulator."""
+    H, W, n_theta = 24 + seed, 30 + 3 * seed, [8, 12, 9, 16][seed]
+    e = _random_edges(seed, H, W, 0.15)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, _, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    for k, ht, hr in ((1, 0, 0), (3, 1, 1), (6, 2, 3)):
+        out = oracle.hough_progressive(e, C, S, D, **_prog(1, 1, k, ht, hr, 1, 0, 0, k, ht, hr, 1))
+        assert out["n_c"] == n_theta and out["n_rc"] == 2 * D + 1 and out["Dc"] == D
+        assert (out["coarse_acc"] == acc).all()
+        want = _brute_peaks(acc, D, k, ht, hr)
+        got = [(int(out["theta_idx"][j]), int(out["r_idx"][j]), int(out["votes"][j]))
+               for j in range(out["count"])]
+        assert got == want
+        for j in range(out["coarse_count"]):
+            assert out["windows"][j].shape == (1, 1)
+            assert out["windows"][j][0, 0] == acc[out["coarse_theta"][j], out["coarse_r"][j]]
+
+
+@pytest.mark.parametrize("f,w", [(2, 3), (4, 9), (3, 5), (6, 1), (1, 7), (12, 15)])
+def test_progressive_coarse_rows_are_binned_fine_rows(oracle, synth, f, w):
+    """Coarse row c is fine row c*f + f/2 with odd-width r bins centred on
+    r = 0: every coarse cell is the sum of w fine cells of that row."""
+    H, W, n_theta = 41, 57, 36
+    e = _random_edges(7 + f + w, H, W, 0.2)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, cast, dropped = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    assert dropped == 0
+    out = oracle.hough_progressive(e, C, S, D, **_prog(f, w))
+    q, Dc = (w - 1) // 2, out["Dc"]
+    assert Dc * w + q >= D and (Dc - 1) * w + q < D   # the outer bins reach +-D
+    want = np.zeros((n_theta // f, 2 * Dc + 1), np.int64)
+    for c in range(n_theta // f):
+        row = acc[c * f + f // 2]
+        for i in range(2 * D + 1):
+            r = i - D
+            b = math.floor((r + q) / w)
+            assert b * w - q <= r <= b * w + q
+            want[c, b + Dc] += row[i]
+    assert (out["coarse_acc"] == want).all()
+    assert (out["coarse_acc"].sum(axis=1) == int((e == 255).sum())).all()
+
+
+def _unfolded_cell(u, rr, n_theta, D):
+    """Fine accumulator cell of the line at unfolded row u and r = rr."""
+    h = u // n_theta
+    t = u - h * n_theta
+    r = -rr if h % 2 else rr
+    return t, r + D
+
+
+@pytest.mark.parametrize("case", ["vertical", "near_180", "random"])
+def test_progressive_windows_are_fine_cells(oracle, synth, case):
+    """Every window cell equals the fine accumulator at the cell's line,
+    including rows that run past 0 or 180 degrees (where the line's r is
+    mirrored), and the candidate is the first largest in window order."""
+    H, W, n_theta = 64, 80, 72
+    e = _random_edges(3, H, W, 0.02)
+    if case == "vertical":
+        e[:, 37] = 255                       # theta = 0, r = 37
+    elif case == "near_180":
+        yy, xx = np.mgrid[0:H, 0:W]
+        th = 70 * math.pi / 72               # 175 degrees
+        e[np.abs(xx * math.cos(th) + yy * math.sin(th) + 20) < 0.4] = 255
+    else:
+        e = _random_edges(4, H, W, 0.25)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, _, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    f, w, mt, mr = 4, 5, 3, 4
+    out = oracle.hough_progressive(e, C, S, D, **_prog(f, w, 6, 1, 1, 1, mt, mr, 3, 1, 2, 1))
+    q, Dc, R, Wc = (w - 1) // 2, out["Dc"], out["R"], out["Wc"]
+    wraps = 0
+    for j in range(out["coarse_count"]):
+        c, bi = int(out["coarse_theta"][j]), int(out["coarse_r"][j])
+        best, where = -1, None
+        for a in range(R):
+            u = c * f - mt + a
+            wraps += u < 0 or u >= n_theta
+            for ee in range(Wc):
+                t, i = _unfolded_cell(u, (bi - Dc) * w - q - mr + ee, n_theta, D)
+                inside = 0 <= i <= 2 * D
+                assert out["windows"][j, a, ee] == (acc[t, i] if inside else 0)
+                if inside and acc[t, i] > best:
+                    best, where = int(acc[t, i]), (t, i)
+        assert tuple(out["cand"][j]) == (where[0], where[1], best)
+    for j in range(out["coarse_count"], 6):
+        assert (out["windows"][j] == 0).all() and (out["cand"][j] == -1).all()
+    if case != "random":
+        assert wraps > 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_progressive_final_is_greedy_over_candidates(oracle, synth, seed):
+    H, W, n_theta = 50, 70, 36
+    e = _random_edges(20 + seed, H, W, 0.3)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    for k, ht, hr, mv in ((4, 1, 2, 1), (8, 3, 5, 1), (8, 0, 0, 60)):
+        out = oracle.hough_progressive(e, C, S, D, **_prog(3, 7, 12, 1, 1, 1, 1, 3, k, ht, hr, mv))
+        sparse = np.zeros((n_theta, 2 * D + 1), np.int32)
+        for j in range(out["coarse_count"]):
+            t, i, v = out["cand"][j]
+            sparse[t, i] = v
+        want = _brute_peaks(sparse, D, k, ht, hr, mv)
+        got = [(int(out["theta_idx"][j]), int(out["r_idx"][j]), int(out["votes"][j]))
+               for j in range(out["count"])]
+        assert got == want
+
+
+def test_progressive_finds_drawn_lines(oracle, synth):
+    """Three real lines drawn at angles between the coarse samples over
+    faint salt: the final peaks are exactly their own cells, with every
+    drawn pixel counted (Sec. 2.3: the peak cell is the line)."""
+    H, W, n_theta = 240, 320, 180
+    yy, xx = np.mgrid[0:H, 0:W]
+    e = _random_edges(5, H, W, 0.003)
+    lines = [(33, 60), (91, 150), (150, -40)]
+    on_all = []
+    for k0, r0 in lines:
+        th = k0 * math.pi / n_theta
+        on = np.abs(xx * math.cos(th) + yy * math.sin(th) - r0) < 0.3
+        e[on] = 255
+        on_all.append(on)
+    C, S = synth.trig_q14(n_theta)
+    D = synth.r_offset(W, H)
+    acc, _, _ = oracle.hough_vote(e, C, S, D, 2 * D + 1)
+    out = oracle.hough_progressive(e, C, S, D, **_prog(2, 5, 8, 1, 2, 1, 1, 6, 3, 2, 6, 1))
+    got = {(int(out["theta_idx"][j]), int(out["r_idx"][j])) for j in range(out["count"])}
+    assert got == {(k0, r0 + D) for k0, r0 in lines}
+    for j in range(out["count"]):
+        t, i = int(out["theta_idx"][j]), int(out["r_idx"][j])
+        assert out["votes"][j] == acc[t, i]
+    for (k0, r0), on in zip(lines, on_all):
+        assert acc[k0, r0 + D] >= on.sum()
