@@ -216,6 +216,74 @@ int lane_hough_lines(const uint8_t *edges, int32_t W, int32_t H, const int16_t *
                      int32_t k, int32_t fill_gap, int32_t min_length, int32_t max_segments,
                      int32_t *segments, int32_t *seg_count, int32_t *npts_opt, void *stream);
 
+/* ------------------------------------------------------- coarse-to-fine Hough
+ * The paper bases its GPU vote (Sec. 4.3) on a multiresolution progressive
+ * Hough method (its reference [9]) and states no algorithm; this is the one
+ * computed here (all integer, so exact):
+ *   coarse vote   coarse row c in [0, n_theta / theta_step) uses the fine
+ *                 table row c*theta_step + theta_step/2; with w = r_width
+ *                 (odd) and q = (w-1)/2, an edge's Eq. (3) r (as in
+ *                 lane_hough_vote) in [-r_offset, r_offset] adds 1 at column
+ *                 floor((r + q) / w) + Dc, Dc = floor((r_offset + q) / w),
+ *                 of a [n_theta/theta_step][2 Dc + 1] accumulator (bins of w
+ *                 cells centred on r = 0); any other r is not counted;
+ *   coarse peaks  lane_hough_peaks on it (k_coarse, h_theta_coarse,
+ *                 h_r_coarse, min_votes_coarse, r_offset Dc);
+ *   windows       coarse peak j = (c, b) opens R = theta_step + 2*margin_theta
+ *                 rows u = c*theta_step - margin_theta + a by Wc = w +
+ *                 2*margin_r cells; cell (a, e) counts the edges whose r at
+ *                 fine row u mod n_theta equals rr = (b - Dc)*w - q - margin_r
+ *                 + e, or -rr when u is an odd number of half turns away from
+ *                 [0, n_theta) (the line (r, theta + 180deg) is (-r, theta));
+ *                 cells with |rr| > r_offset are empty and never chosen;
+ *   candidate j   the window's largest count, first in (a, e) order, as the
+ *                 fine cell (theta_idx, r_idx = r + r_offset, count);
+ *   final peaks   lane_hough_peaks (k, h_theta, h_r, min_votes) on a fine
+ *                 accumulator that is zero except at the candidates.
+ * Limits: n_theta % theta_step == 0; r_width odd in [1, 63]; k_coarse in
+ * [1, 64]; k in [1, k_coarse]; 0 <= h_theta < n_theta; margin_theta in
+ * [0, 512]; margin_r in [0, 8192]; R*Wc + 2R + 5 <= 16384;
+ * 0 <= r_offset <= 16384; the coarse row (2 Dc + 2 cells of 4 bytes) at
+ * most 96 KB. */
+typedef struct lane_progressive {
+    int32_t theta_step, r_width;
+    int32_t k_coarse, h_theta_coarse, h_r_coarse, min_votes_coarse;
+    int32_t margin_theta, margin_r;
+    int32_t k, h_theta, h_r, min_votes;
+} lane_progressive;
+
+/* Geometry and workspace layout.  After lane_hough_progressive the
+ * workspace holds, at these byte offsets, the coarse accumulator (int32
+ * [n_coarse_theta][n_coarse_r]), the coarse peaks (int32 theta[k_coarse],
+ * r_idx[k_coarse], votes[k_coarse], count), the windows (int32
+ * [k_coarse][win_rows][win_cols], zero for absent peaks) and the candidates
+ * (int32 [k_coarse][3], -1 for absent peaks). */
+typedef struct lane_progressive_layout {
+    int32_t n_coarse_theta, n_coarse_r, coarse_r_offset, win_rows, win_cols;
+    size_t coarse_acc, coarse_peaks, windows, candidates, bytes;
+} lane_progressive_layout;
+
+/* Fills *out for a W x H frame; LANE_E_ARG / LANE_E_SIZE as the limits above. */
+int lane_hough_progressive_layout(int32_t W, int32_t H, int32_t n_theta, int32_t r_offset,
+                                  const lane_progressive *p, lane_progressive_layout *out);
+
+/* Coarse-to-fine Hough of one frame.
+ *   list      device edge list of a W x H frame (lane_sobel_binarize, lane_canny
+ *             or lane_edges_to_list), 16-byte aligned
+ *   cos_q14, sin_q14  device int16 [n_theta]; r_offset as for lane_hough_vote
+ *             (the fine accumulator has 2*r_offset + 1 columns)
+ *   p         host, read during the call
+ *   theta_idx, r_idx, votes  device int32 [p->k], -1 after the last peak
+ *   count     device int32 scalar: final peaks
+ *   ws        device, >= layout.bytes, 16-byte aligned; also holds the
+ *             intermediate results (see lane_progressive_layout)
+ * Argument errors are returned before anything is enqueued. */
+int lane_hough_progressive(const uint32_t *list, int32_t W, int32_t H, const int16_t *cos_q14,
+                           const int16_t *sin_q14, int32_t n_theta, int32_t r_offset,
+                           const lane_progressive *p, int32_t *theta_idx, int32_t *r_idx,
+                           int32_t *votes, int32_t *count, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* ------------------------------------------------------------------ batch
  * Many frames of mixed sizes through the whole path (Sobel + binarize +
  * compaction, vote, peaks, and line segments where a frame asks for them) in

@@ -18,6 +18,8 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_canny(const uint8_t* img, int W,
                                                       int t_high, int border_mode, uint8_t* edges,
                                                       uint8_t* mag, uint32_t* edge_count, void* ws,
                                                       hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_progressive(const ProgDesc* d, const PeaksDesc* pk,
+                                                            hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int W, int H, const int16_t* C,
                                                       const int16_t* S, int n_theta, int r_offset,
                                                       const int32_t* theta_idx, const int32_t* r_idx,
@@ -337,6 +339,150 @@ int lane_hough_lines(const uint8_t* edges, int32_t W, int32_t H, const int16_t* 
     return dev_status(lane_launch_lines(edges, W, H, cos_q14, sin_q14, n_theta, r_offset, theta_idx,
                                         r_idx, count_opt, k, fill_gap, min_length, max_segments,
                                         segments, seg_count, npts_opt, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Geometry, workspace layout and launch shape of the coarse-to-fine Hough;
+// LANE_OK or the error of the first limit broken.
+int prog_plan(int32_t W, int32_t H, int32_t n_theta, int32_t r_offset, const lane_progressive* p,
+              lane_progressive_layout* lay, ProgDesc* d) {
+    if (!p || !lay || !dims_ok(W, H) || n_theta <= 0) return LANE_E_ARG;
+    if (!dims_small(W, H)) return LANE_E_SIZE;
+    if (r_offset < 0 || r_offset > 16384) return LANE_E_RANGE;
+    const int f = p->theta_step, w = p->r_width, kc = p->k_coarse, k = p->k;
+    if (f < 1 || n_theta % f != 0 || w < 1 || w > 63 || (w % 2) == 0 || kc < 1 || kc > 64 || k < 1 ||
+        k > kc || p->h_theta_coarse < 0 || p->h_r_coarse < 0 || p->h_theta_coarse > 1000000 ||
+        p->h_r_coarse > 1000000 || p->margin_theta < 0 || p->margin_theta > 512 || p->margin_r < 0 ||
+        p->margin_r > 8192 || p->h_theta < 0 || p->h_theta >= n_theta || p->h_r < 0 ||
+        p->h_r > 1000000)
+        return LANE_E_ARG;
+    const int q = (w - 1) / 2;
+    const int n_c = n_theta / f, Dc = (r_offset + q) / w, n_rc = 2 * Dc + 1;
+    const int R = f + 2 * p->margin_theta, Wc = w + 2 * p->margin_r;
+    if (n_c > kPeaksMaxBlocksLds || n_theta > kPeaksMaxBlocksLds) return LANE_E_SIZE;
+    if ((size_t)(n_rc + 1) * sizeof(int32_t) > (size_t)kProgCoarseLdsMax) return LANE_E_SIZE;
+    if (lane_prog_refine_lds(1, R, Wc) > (size_t)kProgRefineLdsMax) return LANE_E_SIZE;
+    size_t keys = 0;
+    if (lane_hough_peaks_workspace_size(n_c, n_rc, &keys) != LANE_OK) return LANE_E_SIZE;
+
+    lay->n_coarse_theta = n_c;
+    lay->n_coarse_r = n_rc;
+    lay->coarse_r_offset = Dc;
+    lay->win_rows = R;
+    lay->win_cols = Wc;
+    lay->coarse_acc = 0;
+    lay->windows = align256((size_t)n_c * n_rc * sizeof(int32_t));
+    lay->coarse_peaks = align256(lay->windows + (size_t)kc * R * Wc * sizeof(int32_t));
+    lay->candidates = align256(lay->coarse_peaks + (size_t)(3 * kc + 1) * sizeof(int32_t));
+    const size_t off_keys = align256(lay->candidates + (size_t)3 * kc * sizeof(int32_t));
+    lay->bytes = off_keys + keys;
+    if (!d) return LANE_OK;
+
+    memset(d, 0, sizeof(*d));
+    d->W = W;
+    d->H = H;
+    d->n_theta = n_theta;
+    d->D = r_offset;
+    d->f = f;
+    d->w = w;
+    d->q = q;
+    d->kc = kc;
+    d->mt = p->margin_theta;
+    d->mr = p->margin_r;
+    d->k = k;
+    d->ht = p->h_theta;
+    d->hr = p->h_r;
+    d->min_votes = p->min_votes;
+    d->n_c = n_c;
+    d->n_rc = n_rc;
+    d->Dc = Dc;
+    d->R = R;
+    d->Wc = Wc;
+    d->inv_w = (float)(1.0 / (double)w);
+    // coarse: the most rows per workgroup whose LDS stays within 64 KB
+    d->T = 4;
+    while (d->T > 1 && (size_t)(n_rc + 1) * d->T * sizeof(int32_t) > 65536) d->T >>= 1;
+    d->n_slices = (n_c + d->T - 1) / d->T;
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const ListLayout L = list_layout(W, H);
+    const int n_groups = (L.nseg + 15) / 16;
+    int chunks = (2 * cus + d->n_slices - 1) / d->n_slices;
+    chunks = chunks < 1 ? 1 : (chunks > n_groups ? n_groups : chunks);
+    d->groups_per_chunk = (n_groups + chunks - 1) / chunks;
+    d->n_chunks = (n_groups + d->groups_per_chunk - 1) / d->groups_per_chunk;
+    // refine: as many windows per workgroup as fit 64 KB, edge chunks to fill the GPU
+    d->wpg = kc;
+    while (d->wpg > 1 && lane_prog_refine_lds(d->wpg, R, Wc) > (size_t)kProgRefineLdsMax) --d->wpg;
+    d->n_wgroups = (kc + d->wpg - 1) / d->wpg;
+    int rc = (2 * cus + d->n_wgroups - 1) / d->n_wgroups;
+    d->r_chunks = rc < 1 ? 1 : (rc > L.nseg ? L.nseg : rc);
+    return LANE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lane_hough_progressive_layout(int32_t W, int32_t H, int32_t n_theta, int32_t r_offset,
+                                  const lane_progressive* p, lane_progressive_layout* out) {
+    if (!out) return LANE_E_ARG;
+    lane_progressive_layout lay;
+    const int st = prog_plan(W, H, n_theta, r_offset, p, &lay, nullptr);
+    if (st == LANE_OK) *out = lay;
+    return st;
+}
+
+int lane_hough_progressive(const uint32_t* list, int32_t W, int32_t H, const int16_t* cos_q14,
+                           const int16_t* sin_q14, int32_t n_theta, int32_t r_offset,
+                           const lane_progressive* p, int32_t* theta_idx, int32_t* r_idx,
+                           int32_t* votes, int32_t* count, void* ws, size_t ws_bytes, void* stream) {
+    if (!list || !cos_q14 || !sin_q14 || !theta_idx || !r_idx || !votes || !count || !ws)
+        return LANE_E_ARG;
+    if (!aligned16(list) || !aligned16(ws)) return LANE_E_ARG;
+    lane_progressive_layout lay;
+    ProgDesc d;
+    const int st = prog_plan(W, H, n_theta, r_offset, p, &lay, &d);
+    if (st != LANE_OK) return st;
+    if (ws_bytes < lay.bytes) return LANE_E_WS;
+    char* base = (char*)ws;
+    d.list = list;
+    d.cos_q14 = cos_q14;
+    d.sin_q14 = sin_q14;
+    d.coarse_acc = (int32_t*)(base + lay.coarse_acc);
+    d.windows = (int32_t*)(base + lay.windows);
+    d.cpk = (int32_t*)(base + lay.coarse_peaks);
+    d.cand = (int32_t*)(base + lay.candidates);
+    d.theta_idx = theta_idx;
+    d.r_idx = r_idx;
+    d.votes = votes;
+    d.count = count;
+    PeaksDesc pk;
+    memset(&pk, 0, sizeof(pk));
+    pk.acc = d.coarse_acc;
+    pk.n_theta = d.n_c;
+    pk.n_r = d.n_rc;
+    pk.r_offset = d.Dc;
+    pk.k = d.kc;
+    pk.h_theta = p->h_theta_coarse;
+    pk.h_r = p->h_r_coarse;
+    pk.min_votes = p->min_votes_coarse;
+    pk.theta_idx = d.cpk;
+    pk.r_idx = d.cpk + d.kc;
+    pk.votes = d.cpk + 2 * d.kc;
+    pk.count = d.cpk + 3 * d.kc;
+    pk.keys = (unsigned long long*)(base + align256(lay.candidates + (size_t)3 * d.kc * sizeof(int32_t)));
+    pk.block_log2 = lane_peaks_block_log2(d.n_c, d.n_rc);
+    pk.nbr = lane_peaks_blocks_per_row(d.n_rc, pk.block_log2);
+    pk.n_blocks = d.n_c * pk.nbr;
+    return dev_status(lane_launch_progressive(&d, &pk, (hipStream_t)stream));
 }
 
 }  // extern "C"

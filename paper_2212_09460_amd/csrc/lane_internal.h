@@ -108,6 +108,38 @@ struct PeaksDesc {
     const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
 };
 
+// One frame for the coarse-to-fine Hough transform.
+struct ProgDesc {
+    const uint32_t* list;  // edge list of a W x H frame
+    int W, H;
+    const int16_t* cos_q14;
+    const int16_t* sin_q14;
+    int n_theta, D;            // fine accumulator: n_r = 2 D + 1
+    int f, w, q, kc, mt, mr;   // theta step, odd r width, (w - 1) / 2, coarse peaks, margins
+    int k, ht, hr, min_votes;  // final selection
+    int n_c, n_rc, Dc, R, Wc;  // coarse rows / columns / offset, window rows / columns
+    float inv_w;               // float(1 / w)
+    int T;                     // coarse rows per workgroup (1, 2 or 4)
+    int n_slices, n_chunks, groups_per_chunk;  // coarse grid
+    int r_chunks, wpg, n_wgroups;              // refine grid: edge chunks x window groups
+    int32_t* coarse_acc;  // [n_c][n_rc]
+    int32_t* cpk;         // coarse peaks: theta[kc], r[kc], votes[kc], count
+    int32_t* windows;     // [kc][R][Wc]
+    int32_t* cand;        // [kc][3]: fine theta, fine r_idx, count (-1: none)
+    int32_t* theta_idx;   // [k]
+    int32_t* r_idx;       // [k]
+    int32_t* votes;       // [k]
+    int32_t* count;       // scalar
+};
+
+// LDS bytes of a refine workgroup holding wpg windows of R x Wc cells:
+// the cells, two words per (window, row), five per window.
+inline size_t lane_prog_refine_lds(int wpg, int R, int Wc) {
+    return ((size_t)wpg * R * Wc + 2 * (size_t)wpg * R + 5 * (size_t)wpg) * sizeof(int32_t);
+}
+constexpr int kProgRefineLdsMax = 65536;  // bytes
+constexpr int kProgCoarseLdsMax = 98304;  // bytes
+
 // One frame for the line segments along its peaks.
 struct LinesDesc {
     const uint8_t* edges;  // [H][W], 255 = edge

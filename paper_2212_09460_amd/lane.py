@@ -47,6 +47,28 @@ _canny = _sig("lane_canny", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, 
 _lines = _sig("lane_hough_lines", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _i32, _i32,
                                     _i32, _i32, _vp, _vp, _vp, _vp])
 
+PROGRESSIVE_FIELDS = ("theta_step", "r_width", "k_coarse", "h_theta_coarse", "h_r_coarse",
+                      "min_votes_coarse", "margin_theta", "margin_r", "k", "h_theta", "h_r",
+                      "min_votes")
+
+
+class LaneProgressive(ctypes.Structure):
+    _fields_ = [(n, _i32) for n in PROGRESSIVE_FIELDS]
+
+
+class LaneProgressiveLayout(ctypes.Structure):
+    _fields_ = [("n_coarse_theta", _i32), ("n_coarse_r", _i32), ("coarse_r_offset", _i32),
+                ("win_rows", _i32), ("win_cols", _i32), ("coarse_acc", _sz), ("coarse_peaks", _sz),
+                ("windows", _sz), ("candidates", _sz), ("bytes", _sz)]
+
+
+_prog_layout = _sig("lane_hough_progressive_layout", [_i32, _i32, _i32, _i32,
+                                                       ctypes.POINTER(LaneProgressive),
+                                                       ctypes.POINTER(LaneProgressiveLayout)])
+_prog = _sig("lane_hough_progressive", [_vp, _i32, _i32, _vp, _vp, _i32, _i32,
+                                         ctypes.POINTER(LaneProgressive), _vp, _vp, _vp, _vp, _vp,
+                                         _sz, _vp])
+
 LANE_OK = 0
 LANE_BORDER_ZERO = 0
 LANE_BORDER_ZERO_MASKRING = 1
@@ -55,7 +77,8 @@ LANE_BORDER_ZERO_MASKRING = 1
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
            "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_lines",
-           "lane_canny_workspace_size", "lane_canny", "lane_batch_create",
+           "lane_canny_workspace_size", "lane_canny", "lane_hough_progressive_layout",
+           "lane_hough_progressive", "lane_batch_create",
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
@@ -185,6 +208,68 @@ def hough_peaks(acc: torch.Tensor, r_offset: int, k: int, h_theta: int | None = 
                   int(min_votes), _p(t), _p(r), _p(v), _p(c), _p(ws), ws.numel() * 8,
                   _stream(stream)), "lane_hough_peaks")
     return t, r, v, c
+
+
+def progressive_params(n_theta: int, n_r: int, **over) -> dict:
+    """Parameters of the coarse-to-fine Hough: 4-row coarse steps, 9-cell r
+    bins, 16 coarse peaks, windows widened by 2 rows and 6 cells, 8 final
+    peaks with the default windows of hough_peaks; keywords override."""
+    p = dict(theta_step=4, r_width=9, k_coarse=16, h_theta_coarse=1, h_r_coarse=2,
+             min_votes_coarse=1, margin_theta=2, margin_r=6, k=8,
+             h_theta=max(1, -(-n_theta // 100)), h_r=max(1, -(-n_r // 100)), min_votes=1)
+    unknown = set(over) - set(p)
+    if unknown:
+        raise TypeError(f"unknown progressive parameters {sorted(unknown)}")
+    p.update(over)
+    return p
+
+
+def _prog_struct(params: dict) -> LaneProgressive:
+    if set(params) != set(PROGRESSIVE_FIELDS):
+        raise TypeError(f"progressive parameters must be exactly {PROGRESSIVE_FIELDS}")
+    return LaneProgressive(*[int(params[n]) for n in PROGRESSIVE_FIELDS])
+
+
+def progressive_layout(W: int, H: int, n_theta: int, r_offset: int, params: dict) -> dict:
+    lay = LaneProgressiveLayout()
+    p = _prog_struct(params)
+    _check(_prog_layout(W, H, n_theta, int(r_offset), ctypes.byref(p), ctypes.byref(lay)),
+           "lane_hough_progressive_layout")
+    return {n: getattr(lay, n) for n, _ in LaneProgressiveLayout._fields_}
+
+
+def hough_progressive(lst: torch.Tensor, W: int, H: int, C: torch.Tensor, S: torch.Tensor,
+                      r_offset: int, params: dict, ws=None, out=None, stream=None):
+    """Coarse-to-fine Hough (see lane_hough_progressive).  Returns
+    (theta_idx, r_idx, votes, count, detail); detail holds device views of the
+    intermediate results in the workspace (coarse_acc, coarse_peaks, windows,
+    candidates)."""
+    n_theta = C.shape[0]
+    lay = progressive_layout(W, H, n_theta, r_offset, params)
+    k, kc = int(params["k"]), int(params["k_coarse"])
+    dev = lst.device
+    if out is None:
+        out = torch.empty((3 * k + 1,), dtype=torch.int32, device=dev)
+    t, r, v, c = out[0:k], out[k:2 * k], out[2 * k:3 * k], out[3 * k:3 * k + 1]
+    if ws is None:
+        ws = torch.empty(lay["bytes"] // 8 + 2, dtype=torch.int64, device=dev)
+    if ws.numel() * ws.element_size() < lay["bytes"]:
+        raise ValueError("progressive workspace too small")
+    p = _prog_struct(params)
+    _check(_prog(_p(lst), W, H, _p(C), _p(S), n_theta, int(r_offset), ctypes.byref(p), _p(t),
+                 _p(r), _p(v), _p(c), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "lane_hough_progressive")
+    b = ws.view(torch.uint8)
+
+    def i32(off, n):
+        return b[off:off + 4 * n].view(torch.int32)
+
+    n_c, n_rc, R, Wc = lay["n_coarse_theta"], lay["n_coarse_r"], lay["win_rows"], lay["win_cols"]
+    detail = dict(layout=lay, coarse_acc=i32(lay["coarse_acc"], n_c * n_rc).view(n_c, n_rc),
+                  coarse_peaks=i32(lay["coarse_peaks"], 3 * kc + 1),
+                  windows=i32(lay["windows"], kc * R * Wc).view(kc, R, Wc),
+                  candidates=i32(lay["candidates"], 3 * kc).view(kc, 3))
+    return t, r, v, c, detail
 
 
 def canny_workspace_size(W: int, H: int) -> int:

@@ -125,3 +125,81 @@ def test_argument_errors_before_launch(lib):
     assert lines_with(13, 0) == E_ARG              # max_segments
     assert lines_with(1, 9000) == E_SIZE
     assert lines_with(6, 200000) == E_RANGE        # r_offset
+
+
+def test_progressive_layout_geometry_and_limits(oracle):
+    """Layout of the coarse-to-fine Hough: geometry equal to the oracle's,
+    sections in order inside the reported size, and the documented limits
+    rejected (no device involved)."""
+    import paper_2212_09460_amd.lane as lane
+
+    for (W, H, n_theta, over) in [(1920, 1080, 360, {}), (1, 1, 8, dict(theta_step=2, k_coarse=2, k=1)),
+                                  (8192, 8192, 180, dict(r_width=1, margin_r=0)),
+                                  (640, 480, 180, dict(theta_step=6, r_width=15, margin_theta=0))]:
+        D = oracle.r_offset(W, H)
+        p = lane.progressive_params(n_theta, 2 * D + 1, **over)
+        lay = lane.progressive_layout(W, H, n_theta, D, p)
+        f, w = p["theta_step"], p["r_width"]
+        q = (w - 1) // 2
+        assert lay["n_coarse_theta"] == n_theta // f
+        assert lay["coarse_r_offset"] == (D + q) // w
+        assert lay["n_coarse_r"] == 2 * lay["coarse_r_offset"] + 1
+        assert lay["win_rows"] == f + 2 * p["margin_theta"]
+        assert lay["win_cols"] == w + 2 * p["margin_r"]
+        kc = p["k_coarse"]
+        assert lay["coarse_acc"] == 0
+        assert lay["windows"] >= 4 * lay["n_coarse_theta"] * lay["n_coarse_r"]
+        assert lay["coarse_peaks"] >= lay["windows"] + 4 * kc * lay["win_rows"] * lay["win_cols"]
+        assert lay["candidates"] >= lay["coarse_peaks"] + 4 * (3 * kc + 1)
+        assert lay["bytes"] > lay["candidates"] + 12 * kc
+    D = oracle.r_offset(1920, 1080)
+    good = lane.progressive_params(360, 2 * D + 1)
+    bad = [dict(theta_step=7), dict(theta_step=0), dict(r_width=8), dict(r_width=65),
+           dict(k_coarse=65), dict(k=17), dict(k=0), dict(h_theta=360), dict(h_theta=-1),
+           dict(margin_theta=513), dict(margin_r=-1), dict(h_r_coarse=-1)]
+    for over in bad:
+        with pytest.raises(lane.LaneError) as ei:
+            lane.progressive_layout(1920, 1080, 360, D, {**good, **over})
+        assert ei.value.code == E_ARG, over
+    with pytest.raises(lane.LaneError) as ei:   # window cells beyond the LDS budget
+        lane.progressive_layout(1920, 1080, 360, D, {**good, "margin_theta": 100, "margin_r": 200})
+    assert ei.value.code == E_SIZE
+    with pytest.raises(lane.LaneError) as ei:
+        lane.progressive_layout(1920, 1080, 360, 16385, good)
+    assert ei.value.code == E_RANGE
+
+
+def test_progressive_argument_errors_before_launch(lib):
+    import paper_2212_09460_amd.lane as lane
+
+    p = lane._prog_struct(lane.progressive_params(360, 4407))
+    buf = (ctypes.c_uint8 * 64)()
+    a16 = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
+    f = lib.lane_hough_progressive
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p] + [ctypes.c_void_p] * 5 + \
+                 [ctypes.c_size_t, ctypes.c_void_p]
+    args = [a16, 1920, 1080, a16, a16, 360, 2203, ctypes.addressof(p), a16, a16, a16, a16, a16, 1 << 30, None]
+    for i in (0, 3, 4, 7, 8, 9, 10, 11, 12):
+        bad = list(args)
+        bad[i] = None
+        assert f(*bad) == E_ARG, i
+    bad = list(args)
+    bad[0] = a16 + 4           # list not 16-byte aligned
+    assert f(*bad) == E_ARG
+    bad = list(args)
+    bad[13] = 16               # workspace too small
+    assert f(*bad) == E_WS
+
+
+def test_coarse_bin_division_by_float_reciprocal_is_exact():
+    """The coarse vote finds floor(n / w) as trunc(fma(n, float(1/w),
+    float(1/w) / 2)) in single precision; checked for every n in [0, 2^16)
+    and every odd w <= 63 (the products are exact in double, so rounding
+    the double sum to float is the one rounding of the fused multiply-add)."""
+    n = np.arange(0, 1 << 16, dtype=np.int64)
+    for w in range(1, 64, 2):
+        iw = np.float32(1.0 / w)
+        hiw = np.float32(0.5) * iw
+        t = (n.astype(np.float64) * np.float64(iw) + np.float64(hiw)).astype(np.float32)
+        assert (np.trunc(t).astype(np.int64) == n // w).all(), w
