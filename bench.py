@@ -170,7 +170,59 @@ def edge_detectors(n_frames):
         out[kind] = {"detector_ms_per_frame": round(t_det, 4), "path_ms_per_frame": round(t_path, 4),
                      "edge_fraction": round(edges / (n_frames * W * H), 4),
                      "lanes_found_top4": round(found / max(total, 1), 4)}
+        out[kind]["progressive"] = progressive_vs_plain(
+            torch, lane, [detect(kind, im)[0] for im in imgs], seeds, sc, Cd, Sd, D, stream)
     return out
+
+
+def progressive_vs_plain(torch, lane, lists, seeds, sc, Cd, Sd, D, stream):
+    """The coarse-to-fine Hough against the plain vote + peaks on the same
+    edge lists: GPU time per frame of each, agreement of the top-4 (same line
+    within one theta bin and one r cell), exact cells, and painted lanes
+    found among the progressive top-4."""
+    from paper_2212_09460_amd import synth
+    from paper_2212_09460_amd.learned.evaluate import agreement_counts, lanes_found
+
+    n = len(lists)
+    n_r = 2 * D + 1
+    params = lane.progressive_params(N_THETA, n_r)
+    pws = torch.empty(lane.progressive_layout(W, H, N_THETA, D, params)["bytes"] // 8 + 2,
+                      dtype=torch.int64, device=lists[0].device)
+    plain, prog = [], []
+
+    def run_plain():
+        plain.clear()
+        for lst in lists:
+            acc, _ = lane.hough_vote(lst, W, H, Cd, Sd, D, n_r, stream=stream)
+            plain.append(lane.hough_peaks(acc, D, TOPK, stream=stream))
+
+    def run_prog():
+        prog.clear()
+        for lst in lists:
+            prog.append(lane.hough_progressive(lst, W, H, Cd, Sd, D, params, ws=pws, stream=stream)[:4])
+
+    run_plain()
+    run_prog()
+    torch.cuda.synchronize()
+    t_plain = event_time(torch, run_plain, 1, stream) / n
+    t_prog = event_time(torch, run_prog, 1, stream) / n
+    agree = tot = same = found = lanes = 0
+    for sd, (pt, pr, pv, pc), (qt, qr, qv, qc) in zip(seeds, plain, prog):
+        pt, pr, qt, qr = (x.cpu().numpy() for x in (pt, pr, qt, qr))
+        pn, qn = int(pc.cpu()[0]), int(qc.cpu()[0])
+        m, k = agreement_counts(pt, pr, pn, qt, qr, qn, 4, N_THETA, D)
+        agree += m
+        tot += k
+        same += len({(int(a), int(b)) for a, b in zip(pt[:min(4, pn)], pr[:min(4, pn)])} &
+                    {(int(a), int(b)) for a, b in zip(qt[:min(4, qn)], qr[:min(4, qn)])})
+        f = lanes_found(synth.lane_segments(sc, sd), qt, qr, qn, N_THETA, D, k=4)
+        found += int(f.sum())
+        lanes += len(f)
+    return {"params": params, "hough_ms_per_frame": {"plain": round(t_plain, 4),
+                                                     "progressive": round(t_prog, 4)},
+            "speedup": round(t_plain / t_prog, 3), "agreement_top4": round(agree / max(tot, 1), 4),
+            "same_cell_top4": round(same / max(tot, 1), 4),
+            "lanes_found_top4": round(found / max(lanes, 1), 4)}
 
 
 def serving(args):
