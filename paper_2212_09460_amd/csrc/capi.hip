@@ -404,26 +404,38 @@ int prog_plan(int32_t W, int32_t H, int32_t n_theta, int32_t r_offset, const lan
     d->R = R;
     d->Wc = Wc;
     d->inv_w = (float)(1.0 / (double)w);
-    // coarse: the most rows per workgroup whose LDS stays within 64 KB
-    d->T = 4;
-    while (d->T > 1 && (size_t)(n_rc + 1) * d->T * sizeof(int32_t) > 65536) d->T >>= 1;
-    d->n_slices = (n_c + d->T - 1) / d->T;
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     const ListLayout L = list_layout(W, H);
+    // coarse: chunks of 16-segment groups, about kProgTargetGroups workgroups
+    // in total; the most rows per workgroup (4, 2, 1) whose LDS stays within
+    // 64 KB and whose grid still gives 2 workgroups per CU
     const int n_groups = (L.nseg + 15) / 16;
-    int chunks = (2 * cus + d->n_slices - 1) / d->n_slices;
-    chunks = chunks < 1 ? 1 : (chunks > n_groups ? n_groups : chunks);
+    auto chunks_for = [&](int T) {
+        const int slices = (n_c + T - 1) / T;
+        int c = (kProgTargetGroups + slices - 1) / slices;
+        return c < 1 ? 1 : (c > n_groups ? n_groups : c);
+    };
+    d->T = 4;
+    while (d->T > 1 && ((size_t)(n_rc + 1) * d->T * sizeof(int32_t) > 65536 ||
+                        ((n_c + d->T - 1) / d->T) * chunks_for(d->T) < 2 * cus))
+        d->T >>= 1;
+    d->n_slices = (n_c + d->T - 1) / d->T;
+    const int chunks = chunks_for(d->T);
     d->groups_per_chunk = (n_groups + chunks - 1) / chunks;
     d->n_chunks = (n_groups + d->groups_per_chunk - 1) / d->groups_per_chunk;
-    // refine: as many windows per workgroup as fit 64 KB, edge chunks to fill the GPU
+    // refine: as many windows per workgroup as fit 64 KB; the edges cut into
+    // units (parts of segments) so that about kProgRefineGroups workgroups run
     d->wpg = kc;
     while (d->wpg > 1 && lane_prog_refine_lds(d->wpg, R, Wc) > (size_t)kProgRefineLdsMax) --d->wpg;
     d->n_wgroups = (kc + d->wpg - 1) / d->wpg;
-    int rc = (2 * cus + d->n_wgroups - 1) / d->n_wgroups;
-    d->r_chunks = rc < 1 ? 1 : (rc > L.nseg ? L.nseg : rc);
+    const int want = (kProgRefineGroups + d->n_wgroups - 1) / d->n_wgroups;
+    int P = (want + L.nseg - 1) / L.nseg;
+    d->r_parts = P < 1 ? 1 : (P > 16 ? 16 : P);
+    const long units = (long)L.nseg * d->r_parts;
+    d->r_chunks = (int)(units < want ? units : want);
     return LANE_OK;
 }
 

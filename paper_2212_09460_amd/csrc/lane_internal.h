@@ -121,7 +121,8 @@ struct ProgDesc {
     float inv_w;               // float(1 / w)
     int T;                     // coarse rows per workgroup (1, 2 or 4)
     int n_slices, n_chunks, groups_per_chunk;  // coarse grid
-    int r_chunks, wpg, n_wgroups;              // refine grid: edge chunks x window groups
+    int r_chunks, r_parts, wpg, n_wgroups;     // refine grid: edge chunks x window groups;
+                                               // a segment is cut into r_parts parts
     int32_t* coarse_acc;  // [n_c][n_rc]
     int32_t* cpk;         // coarse peaks: theta[kc], r[kc], votes[kc], count
     int32_t* windows;     // [kc][R][Wc]
@@ -138,6 +139,8 @@ inline size_t lane_prog_refine_lds(int wpg, int R, int Wc) {
     return ((size_t)wpg * R * Wc + 2 * (size_t)wpg * R + 5 * (size_t)wpg) * sizeof(int32_t);
 }
 constexpr int kProgRefineLdsMax = 65536;  // bytes
+constexpr int kProgTargetGroups = 2048;    // coarse workgroups a launch aims at (8 per CU)
+constexpr int kProgRefineGroups = 512;     // refine workgroups a launch aims at
 constexpr int kProgCoarseLdsMax = 98304;  // bytes
 
 // One frame for the line segments along its peaks.

@@ -24,9 +24,12 @@
 // integer).  k_prog_refine: a workgroup holds a group of windows in LDS and
 // votes a chunk of edges; an edge is tested against a window's middle row
 // first and skips the window when the other rows cannot reach it (a bound
-// from the table differences).  k_prog_cand: one workgroup per window,
-// max-reduction.  k_prog_final: one wave, greedy selection over <= 64
-// candidates.
+// from the table differences); the pairs that pass queue up per wave and are
+// counted 64 at a time, each lane starting at its own row (the pairs of a
+// line are queued together and would add into one cell at once).  The edges
+// are cut into parts of segments to fill the GPU.  k_prog_cand: one
+// workgroup per window takes the maximum.
+// k_prog_final: one wave, greedy selection over <= 64 candidates.
 #include "lane_internal.h"
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
@@ -36,6 +39,14 @@ namespace lane {
 
 constexpr int kProgThreads = 256;
 constexpr int kProgGroup = 16;  // segments a coarse workgroup walks at once
+constexpr int kQueue = 128;     // per-wave ring of refine work (two 64-pair batches)
+
+// LDS written by some lanes of a wave, then read by others of the same wave
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ int prog_dot2(int a, int b, int c) {
     // a.lo*b.lo + a.hi*b.hi + c on signed 16-bit halves
@@ -100,25 +111,37 @@ __global__ void __launch_bounds__(kProgThreads) k_prog_coarse(ProgDesc d) {
             const int len = q1 - q0;
             const int phase = (g * len) / kProgGroup;
             const uint32_t* base = ents + (size_t)seg * kSegCap;
-            for (int i = 0; i < len; i += 4) {
-                u32x4 e[4];
-                int qi[4];
+            // two register sets take turns: one set of four 128-bit loads is
+            // in flight while the other is voted
+            u32x4 a[4], b[4];
+            int xa[4], xb[4];
+            auto load = [&](u32x4* v, int* xs, int i0) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    int x = q0 + i + u + phase;
+                    const int i = i0 + u;
+                    int x = q0 + i + phase;
                     x = x >= q1 ? x - len : x;
-                    qi[u] = x;
-                    e[u] = (i + u < len) ? gld4(base + 4 * x) : u32x4{0u, 0u, 0u, 0u};
+                    xs[u] = i < len ? x : -1;
+                    v[u] = i < len ? gld4(base + 4 * x) : u32x4{0u, 0u, 0u, 0u};
                 }
+            };
+            auto vote4 = [&](const u32x4* v, const int* xs) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const bool in = i + u < len;
-                    const int e0 = 4 * qi[u];
-                    vote(e[u].x, in && e0 + 0 < n);
-                    vote(e[u].y, in && e0 + 1 < n);
-                    vote(e[u].z, in && e0 + 2 < n);
-                    vote(e[u].w, in && e0 + 3 < n);
+                    const bool in = xs[u] >= 0;
+                    const int e0 = 4 * xs[u];
+                    vote(v[u].x, in && e0 + 0 < n);
+                    vote(v[u].y, in && e0 + 1 < n);
+                    vote(v[u].z, in && e0 + 2 < n);
+                    vote(v[u].w, in && e0 + 3 < n);
                 }
+            };
+            load(a, xa, 0);
+            for (int i = 0; i < len; i += 8) {
+                load(b, xb, i + 4);
+                vote4(a, xa);
+                load(a, xa, i + 8);
+                vote4(b, xb);
             }
         }
     }
@@ -193,45 +216,113 @@ __global__ void __launch_bounds__(kProgThreads) k_prog_refine(ProgDesc d) {
     }
     __syncthreads();
 
+    // this workgroup's share of the edges: units u0 .. u1 - 1, unit u being
+    // part u % P of segment u / P (P parts of equal quad counts)
     const ListLayout L = list_layout(d.W, d.H);
     const uint32_t* ents = d.list + L.off_ent;
-    const int s0 = (int)(((long long)L.nseg * blockIdx.x) / d.r_chunks);
-    const int s1 = (int)(((long long)L.nseg * (blockIdx.x + 1)) / d.r_chunks);
+    const int P = d.r_parts;
+    const long units = (long)L.nseg * P;
+    const int u0 = (int)((units * blockIdx.x) / d.r_chunks);
+    const int u1 = (int)((units * (blockIdx.x + 1)) / d.r_chunks);
     const uint32_t span = 2u * (uint32_t)d.D;
     const int nw = min(wpg, max(0, min(d.kc, n_coarse) - j0));
 
-    auto visit = [&](uint32_t xy) {
-        for (int jj = 0; jj < nw; ++jj) {
-            const RefineWin Wn = s_w[jj];
-            const int rm = prog_dot2((int)xy, Wn.cs_mid, 8192) >> 14;
-            const int em = (rm ^ Wn.m_mid) - Wn.m_mid - Wn.rlo;
-            if ((uint32_t)(em + Wn.reach) > (uint32_t)(Wc - 1 + 2 * Wn.reach)) continue;
+    // Pairs (edge, window) that pass the reach test go to a per-wave ring in
+    // LDS; every 64 of them are counted row by row with all lanes busy (a
+    // wave would otherwise run a window's rows whenever one lane needs them).
+    __shared__ uint32_t s_qxy[kProgThreads / kWave][kQueue];
+    __shared__ int s_qj[kProgThreads / kWave][kQueue];
+    const int lane = tid & (kWave - 1), wv = tid >> 6;
+    uint32_t* qxy = s_qxy[wv];
+    int* qj = s_qj[wv];
+    int qt = 0, qn = 0;  // ring tail and fill, the same in every lane of the wave
+
+    auto drain = [&](int nact) {
+        wave_sync();
+        if (lane < nact) {
+            const int slot = (qt + lane) & (kQueue - 1);
+            const uint32_t xy = qxy[slot];
+            const int jj = qj[slot];
             const RefineRow* rows = s_row + jj * R;
             int32_t* win = s_win + jj * R * Wc;
-            for (int a = 0; a < R; ++a) {
-                const RefineRow ra = rows[a];
-                const int r = prog_dot2((int)xy, ra.cs, 8192) >> 14;
-                if ((uint32_t)(r + d.D) > span) continue;
-                const int e = (r ^ ra.m) - ra.m - Wn.rlo;
-                if ((uint32_t)e < (uint32_t)Wc) atomicAdd(win + a * Wc + e, 1);
+            const int rlo = s_w[jj].rlo;
+            // lanes start at different rows (the pairs of a line are queued
+            // together and would add into one cell at once); the constants of
+            // eight rows are read before any is used
+            const int a0 = lane % R;
+            for (int k0 = 0; k0 < R; k0 += 8) {
+                RefineRow rr[8];
+                int ar[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k0 + u;
+                    const int a = a0 + k < R ? a0 + k : a0 + k - R;
+                    ar[u] = a;
+                    rr[u] = rows[k < R ? a : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int r = prog_dot2((int)xy, rr[u].cs, 8192) >> 14;
+                    const int e = (r ^ rr[u].m) - rr[u].m - rlo;
+                    if (k0 + u < R && (uint32_t)(r + d.D) <= span && (uint32_t)e < (uint32_t)Wc)
+                        atomicAdd(win + ar[u] * Wc + e, 1);
+                }
+            }
+        }
+        wave_sync();
+        qt = (qt + nact) & (kQueue - 1);
+        qn -= nact;
+    };
+
+    auto offer = [&](uint32_t xy, bool valid) {
+        for (int jb = 0; jb < nw; jb += 4) {
+            // four windows' constants read together, then four tests
+            RefineWin w4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w4[u] = s_w[jb + u < nw ? jb + u : nw - 1];
+            bool pass[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int rm = prog_dot2((int)xy, w4[u].cs_mid, 8192) >> 14;
+                const int em = (rm ^ w4[u].m_mid) - w4[u].m_mid - w4[u].rlo;
+                pass[u] = valid && jb + u < nw &&
+                          (uint32_t)(em + w4[u].reach) <= (uint32_t)(Wc - 1 + 2 * w4[u].reach);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned long long m = __ballot(pass[u]);
+                if (pass[u]) {
+                    const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const int pos = (qt + qn + before) & (kQueue - 1);
+                    qxy[pos] = xy;
+                    qj[pos] = jb + u;
+                }
+                qn += __popcll(m);
+                if (qn >= kWave) drain(kWave);
             }
         }
     };
 
     if (nw > 0) {
-        for (int sg = s0; sg < s1; ++sg) {
+        for (int un = u0; un < u1; ++un) {
+            const int sg = un / P, part = un - sg * P;
             const int n = (int)gld(d.list + sg);
             const uint32_t* base = ents + (size_t)sg * kSegCap;
             const int nq = (n + 3) >> 2;
-            for (int qi = tid; qi < nq; qi += kProgThreads) {
-                const u32x4 e = gld4(base + 4 * qi);
+            const int qa = (int)(((long)nq * part) / P), qb = (int)(((long)nq * (part + 1)) / P);
+            for (int q0 = qa + wv * kWave; q0 < qb; q0 += kProgThreads) {  // the same trips in every lane
+                const int qi = q0 + lane;
+                const bool okq = qi < qb;
+                const u32x4 e = okq ? gld4(base + 4 * qi) : u32x4{0u, 0u, 0u, 0u};
                 const int e0 = 4 * qi;
-                visit(e.x);
-                if (e0 + 1 < n) visit(e.y);
-                if (e0 + 2 < n) visit(e.z);
-                if (e0 + 3 < n) visit(e.w);
+                offer(e.x, okq);
+                offer(e.y, okq && e0 + 1 < n);
+                offer(e.z, okq && e0 + 2 < n);
+                offer(e.w, okq && e0 + 3 < n);
             }
         }
+        if (qn > 0) drain(qn);
     }
     __syncthreads();
     const int used = nw * R * Wc;
@@ -259,10 +350,10 @@ __global__ void __launch_bounds__(kProgThreads) k_prog_cand(ProgDesc d) {
     unsigned long long best = 0;  // (count << 32) | ~index; 0 = none
     for (int i = tid; i < cells; i += kProgThreads) {
         const int a = i / d.Wc, e = i - a * d.Wc;
+        const int v = gld(win + i);
         const int ru = rlo + e;
         if (ru < -d.D || ru > d.D) continue;
-        const unsigned long long key =
-            ((unsigned long long)(uint32_t)gld(win + i) << 32) | (uint32_t)~(uint32_t)i;
+        const unsigned long long key = ((unsigned long long)(uint32_t)v << 32) | (uint32_t)~(uint32_t)i;
         best = key > best ? key : best;
     }
 #pragma unroll
