@@ -11,11 +11,15 @@
 // per block of B cells writes the block's best key, key = (count, -index)
 // packed in 64 bits so that one unsigned max gives "largest count, then
 // smallest index".  Pass 2 (one workgroup per frame): the block keys sit in
-// LDS; each round is one block-wide max, and only the blocks touched by the
-// new window are rescanned (skipping every suppressed cell), the cells of
-// all touched blocks spread over the whole workgroup with their loads
-// issued together, so a round costs O(window) and one memory round trip
-// instead of a pass over the accumulator.
+// LDS with one group key per 32 blocks; each round every wave finds the
+// maximum over the group keys by itself (a DPP reduction, no barrier), lists
+// the earlier peaks whose windows can reach the new window's rows (one
+// ballot), and only the blocks touched by the new window are rescanned
+// (skipping every suppressed cell), the cells of all touched blocks spread
+// over the whole workgroup with their loads issued together; the new block
+// keys go to a scratch array (two buffers taking turns) and the touched
+// groups are recomputed, so a round costs O(window), one memory round trip
+// and two barriers.
 #include "lane_internal.h"
 
 namespace lane {
@@ -85,13 +89,15 @@ __global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __res
     }
 }
 
+constexpr int kGroupLog2 = 5;                                  // 32 block keys per group key
+constexpr int kMaxGroups = kPeaksMaxBlocksLds >> kGroupLog2;
+constexpr int kTaskMax = 1024;                                 // rescan tasks of the two-buffer path
+constexpr int kSelWavesMax = 16;
 __shared__ unsigned long long s_keys[kPeaksMaxBlocksLds];
-__shared__ int s_tb[kPeaksMaxBlocksLds];  // rescan task -> (row | block column << 13), -1 if none
-constexpr int kIvTasks = 1024, kIvMax = 4;
-__shared__ uint32_t s_iv[kIvTasks][kIvMax];  // suppressed column ranges of a task's row (lo | hi << 16)
-__shared__ int s_niv[kIvTasks];
+__shared__ unsigned long long s_gkey[kMaxGroups];
+__shared__ unsigned long long s_new[2][kTaskMax];   // a round's rescanned block keys, by task
 __shared__ int s_sel_t[1024], s_sel_i[1024];
-__shared__ unsigned long long s_red[16];
+__shared__ int s_rel[kSelWavesMax][kWave];          // per wave: earlier peaks that reach the rows
 
 // in_window without divisions for the usual h_theta < n_theta, where a
 // cell's row can meet the window only unwrapped or wrapped once either way
@@ -105,11 +111,45 @@ __device__ __forceinline__ bool in_window_fast(int t, int i, int tp, int ip, con
     return false;
 }
 
+// max(v, v of the lane CTRL names); lanes whose source is outside the row
+// (or rows outside ROW_MASK) keep v
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_max(unsigned long long v) {
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+    const unsigned long long w = ((unsigned long long)hi2 << 32) | lo2;
+    return w > v ? w : v;
+}
+
+// Maximum over the 64 lanes, in every lane (all lanes active): row shifts
+// make lane 15 of each row its row's maximum, two row broadcasts carry
+// rows 0-1 and 2-3 into lane 63, which is read back.
+__device__ __forceinline__ unsigned long long wave_max_all(unsigned long long v) {
+    v = dpp_max<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_max<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_max<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_max<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_max<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_max<0x143, 0xC>(v);  // row_bcast:31
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ void peaks_select(const PeaksDesc& d) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
     const int nthreads = blockDim.x;
     const int floor_votes = d.min_votes > 1 ? d.min_votes : 1;
+    const int lg = d.block_log2, B = 1 << lg;
+    const int n_groups = (d.n_blocks + (1 << kGroupLog2) - 1) >> kGroupLog2;
     // block keys into LDS, eight loads in flight per thread (indices are
     // clamped so every load is in bounds and none waits on a branch)
     for (int b0 = tid; b0 < d.n_blocks; b0 += 8 * nthreads) {
@@ -120,27 +160,32 @@ __device__ void peaks_select(const PeaksDesc& d) {
         for (int u = 0; u < 8; ++u)
             if (b0 + u * nthreads < d.n_blocks) s_keys[b0 + u * nthreads] = v[u];
     }
+    for (int q = tid; q < 2 * kTaskMax; q += nthreads) s_new[q / kTaskMax][q % kTaskMax] = 0;
+    __syncthreads();
+    // group keys: the maximum of 32 consecutive block keys
+    for (int g = wave; g < n_groups; g += nwaves) {
+        const int b = (g << kGroupLog2) + (lane & 31);
+        const unsigned long long v = (lane < 32 && b < d.n_blocks) ? s_keys[b] : 0ull;
+        const unsigned long long m = wave_max_all(v);
+        if (lane == 0) s_gkey[g] = m;
+    }
     __syncthreads();
     // blocks a window can touch: 2 h_theta + 1 rows (all blocks when the
     // rows would repeat), each a contiguous column range of at most nbw
-    // blocks; at most n_blocks tasks either way
+    // blocks.  Few tasks: the rescanned keys go to s_new (two buffers taking
+    // turns), so a round needs two barriers; otherwise the touched blocks
+    // are cleared and rescanned in place (three).
     const bool all_rows = 2 * d.h_theta + 1 > d.n_theta;
-    const int nbw = min(d.nbr, ((2 * d.h_r) >> d.block_log2) + 2);
+    const int nbw = min(d.nbr, ((2 * d.h_r) >> lg) + 2);
     const int ntask = all_rows ? d.n_blocks : (2 * d.h_theta + 1) * nbw;
-    // per-row suppressed ranges replace the per-cell window tests when the
-    // windows do not wrap more than once and the tasks are few
-    const bool use_iv = !all_rows && ntask <= kIvTasks && d.n_r <= 0xFFFF;
-    const int lg = d.block_log2, B = 1 << lg;
+    const bool two_buf = !all_rows && ntask <= kTaskMax;
     int found = 0;
     for (int j = 0; j < d.k; ++j) {
+        // every wave finds the largest key itself: no barrier to share it
         unsigned long long best = 0;
-        for (int b = tid; b < d.n_blocks; b += nthreads) best = s_keys[b] > best ? s_keys[b] : best;
-        best = wave_max_u64(best);
-        if (lane == 0) s_red[wave] = best;
-        __syncthreads();
-        unsigned long long m = 0;
-        for (int w = 0; w < nwaves; ++w) m = s_red[w] > m ? s_red[w] : m;
-        if (m == 0 || key_value(m) < floor_votes) break;  // the same decision in every thread
+        for (int g = lane; g < n_groups; g += kWave) best = s_gkey[g] > best ? s_gkey[g] : best;
+        const unsigned long long m = wave_max_all(best);
+        if (m == 0 || key_value(m) < floor_votes) break;  // the same decision in every wave
         const uint32_t idx = key_index(m);
         const int t = (int)(idx / (uint32_t)d.n_r), i = (int)(idx % (uint32_t)d.n_r);
         if (tid == 0) {
@@ -152,57 +197,97 @@ __device__ void peaks_select(const PeaksDesc& d) {
         }
         found = j + 1;
         if (found == d.k) break;  // no further round reads the keys
-        __syncthreads();
-        // tasks -> blocks (the touched blocks restart from the empty key) and,
-        // per task row, the column ranges every selected window suppresses
-        for (int task = tid; task < ntask; task += nthreads) {
-            int row, jb;
+
+        // task -> (row, block column) of the new window, -1 if none
+        auto task_block = [&](int task, int& row) -> int {
             if (all_rows) {
                 row = task / d.nbr;
-                jb = task - row * d.nbr;
-            } else {
-                const int r = task / nbw, bi = task - r * nbw;
-                const int traw = t - d.h_theta + r;
-                const int q = floor_div_i(traw, d.n_theta);
-                row = traw - q * d.n_theta;
-                const int centre = (q & 1) ? 2 * d.r_offset - i : i;
-                const int ca = max(0, centre - d.h_r), cb = min(d.n_r - 1, centre + d.h_r);
-                jb = (ca > cb || (ca >> lg) + bi > (cb >> lg)) ? -1 : (ca >> lg) + bi;
+                return task - row * d.nbr;
             }
-            s_tb[task] = jb < 0 ? -1 : (row | (jb << 13));
-            if (jb >= 0) s_keys[row * d.nbr + jb] = 0;
-            if (use_iv) {
-                int n = 0;
-                for (int p = 0; p <= j && n <= kIvMax; ++p) {
-                    const int tp = s_sel_t[p], ip = s_sel_i[p];
-                    const int mir = 2 * d.r_offset - ip;
-                    int cs[3], nc = 0;
-                    if (abs(row - tp) <= d.h_theta) cs[nc++] = ip;
-                    if (row - d.n_theta >= tp - d.h_theta) cs[nc++] = mir;
-                    if (row + d.n_theta <= tp + d.h_theta) cs[nc++] = mir;
-                    for (int c = 0; c < nc; ++c) {
-                        const int lo = max(0, cs[c] - d.h_r), hi = min(d.n_r - 1, cs[c] + d.h_r);
-                        if (lo > hi) continue;
-                        if (n < kIvMax) s_iv[task][n] = (uint32_t)lo | ((uint32_t)hi << 16);
-                        ++n;
-                    }
-                }
-                s_niv[task] = n;  // more than kIvMax: the cells of this task use the full test
+            const int r = task / nbw, bi = task - r * nbw;
+            const int traw = t - d.h_theta + r;
+            const int q = floor_div_i(traw, d.n_theta);
+            row = traw - q * d.n_theta;
+            const int centre = (q & 1) ? 2 * d.r_offset - i : i;
+            const int ca = max(0, centre - d.h_r), cb = min(d.n_r - 1, centre + d.h_r);
+            return (ca > cb || (ca >> lg) + bi > (cb >> lg)) ? -1 : (ca >> lg) + bi;
+        };
+        // the task of block (row, jb) in this round, -1 if untouched (two-buffer path)
+        auto block_task = [&](int row, int jb) -> int {
+            int r = row - (t - d.h_theta);
+            r %= d.n_theta;
+            if (r < 0) r += d.n_theta;
+            if (r > 2 * d.h_theta) return -1;
+            const int traw = t - d.h_theta + r;
+            const int q = floor_div_i(traw, d.n_theta);
+            const int centre = (q & 1) ? 2 * d.r_offset - i : i;
+            const int ca = max(0, centre - d.h_r), cb = min(d.n_r - 1, centre + d.h_r);
+            if (ca > cb || jb < (ca >> lg) || jb > (cb >> lg)) return -1;
+            return r * nbw + (jb - (ca >> lg));
+        };
+
+        // earlier peaks whose windows reach the new window's rows (cyclic
+        // row distance <= 2 h_theta); each wave lists them for itself
+        int nrel = 0;
+        for (int p0 = 0; p0 < j; p0 += kWave) {
+            const int p = p0 + lane;
+            bool rel = false;
+            if (p < j) {
+                int dt = abs(t - s_sel_t[p]) % d.n_theta;
+                dt = min(dt, d.n_theta - dt);
+                rel = all_rows || dt <= 2 * d.h_theta;
             }
+            const unsigned long long mk = __ballot(rel);
+            if (rel) {
+                const int pos = nrel + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                if (pos < kWave) s_rel[wave][pos] = p;
+            }
+            nrel += __popcll(mk);
         }
-        __syncthreads();
+        wave_lds_sync();
+        const bool rel_all = nrel > kWave;  // too many to list: test every earlier peak
+        auto suppressed = [&](int row, int cell) {
+            if (in_window_fast(row, cell, t, i, d)) return true;
+            if (rel_all) {
+                for (int p = 0; p < j; ++p)
+                    if (in_window_fast(row, cell, s_sel_t[p], s_sel_i[p], d)) return true;
+                return false;
+            }
+            for (int q = 0; q < nrel; ++q) {
+                const int p = s_rel[wave][q];
+                if (in_window_fast(row, cell, s_sel_t[p], s_sel_i[p], d)) return true;
+            }
+            return false;
+        };
+
+        unsigned long long* snew = s_new[j & 1];
+        if (two_buf) {
+            // the other buffer was read in the previous round: clear it for the next
+            for (int q = tid; q < ntask; q += nthreads) s_new[(j & 1) ^ 1][q] = 0;
+        } else {
+            for (int task = tid; task < ntask; task += nthreads) {
+                int row;
+                const int jb = task_block(task, row);
+                if (jb >= 0) s_keys[row * d.nbr + jb] = 0;
+            }
+            __syncthreads();
+        }
         // rescan: every thread takes cells of the touched blocks, all loads
         // of a group of eight first, then the suppression tests and an LDS max
         const int ncell = ntask << lg;
         for (int c0 = tid; c0 < ncell; c0 += 8 * nthreads) {
-            int tk[8], ii[8], vv[8];
+            int tk[8], rw[8], ce[8], ii[8], vv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int c = c0 + u * nthreads;
-                const int e = c < ncell ? s_tb[c >> lg] : -1;
-                const int row = e & 0x1FFF, cell = ((e >> 13) << lg) + (c & (B - 1));
-                const bool ok = e >= 0 && cell < d.n_r;
+                int row = 0, jb = -1;
+                if (c < ncell) jb = task_block(c >> lg, row);
+                const int cell = (jb << lg) + (c & (B - 1));
+                const bool ok = jb >= 0 && cell < d.n_r;
                 tk[u] = ok ? (c >> lg) : -1;
+                rw[u] = row;
+                ce[u] = jb >= 0 ? jb : 0;
                 ii[u] = ok ? row * d.n_r + cell : 0;  // theta-major index
             }
 #pragma unroll
@@ -210,21 +295,39 @@ __device__ void peaks_select(const PeaksDesc& d) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 if (tk[u] < 0) continue;
-                const int e = s_tb[tk[u]];
-                const int row = e & 0x1FFF, cell = ((e >> 13) << lg) + ((c0 + u * nthreads) & (B - 1));
-                bool sup = false;
-                const int niv = use_iv ? s_niv[tk[u]] : kIvMax + 1;
-                if (niv <= kIvMax) {
-                    for (int q = 0; q < niv; ++q) {
-                        const uint32_t iv = s_iv[tk[u]][q];
-                        sup |= cell >= (int)(iv & 0xFFFFu) && cell <= (int)(iv >> 16);
-                    }
-                } else {
-                    for (int p = 0; p <= j && !sup; ++p)
-                        sup = in_window_fast(row, cell, s_sel_t[p], s_sel_i[p], d);
-                }
-                if (!sup) atomicMax(&s_keys[row * d.nbr + (e >> 13)], make_key(vv[u], (uint32_t)ii[u]));
+                const int cell = ii[u] - rw[u] * d.n_r;
+                if (suppressed(rw[u], cell)) continue;
+                unsigned long long* dst = two_buf ? &snew[tk[u]] : &s_keys[rw[u] * d.nbr + ce[u]];
+                atomicMax(dst, make_key(vv[u], (uint32_t)ii[u]));
             }
+        }
+        __syncthreads();
+        // group keys of the touched blocks (two-buffer path: a touched
+        // block's new key is read from s_new and copied into s_keys)
+        const int ngt = all_rows ? n_groups : ntask;
+        for (int task = wave; task < ngt; task += nwaves) {
+            int g;
+            if (all_rows) {
+                g = task;
+            } else {
+                int row;
+                const int jb = task_block(task, row);
+                if (jb < 0) continue;  // the same in every lane
+                g = (row * d.nbr + jb) >> kGroupLog2;
+            }
+            const int b = (g << kGroupLog2) + (lane & 31);
+            unsigned long long v = 0;
+            int tb = -1;
+            if (lane < 32 && b < d.n_blocks) {
+                if (two_buf) {
+                    const int brow = b / d.nbr;
+                    tb = block_task(brow, b - brow * d.nbr);
+                }
+                v = tb >= 0 ? snew[tb] : s_keys[b];
+            }
+            const unsigned long long gm = wave_max_all(v);
+            if (lane == 0) s_gkey[g] = gm;
+            if (tb >= 0) s_keys[b] = v;
         }
         __syncthreads();
     }
