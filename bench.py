@@ -170,9 +170,31 @@ def edge_detectors(n_frames):
         out[kind] = {"detector_ms_per_frame": round(t_det, 4), "path_ms_per_frame": round(t_path, 4),
                      "edge_fraction": round(edges / (n_frames * W * H), 4),
                      "lanes_found_top4": round(found / max(total, 1), 4)}
-        out[kind]["progressive"] = progressive_vs_plain(
-            torch, lane, [detect(kind, im)[0] for im in imgs], seeds, sc, Cd, Sd, D, stream)
+        lists = [detect(kind, im)[0] for im in imgs]
+        out[kind]["progressive"] = progressive_vs_plain(torch, lane, lists, seeds, sc, Cd, Sd, D, stream)
+        out[kind]["angle_pairing"] = paired_vote(torch, lane, lists, Cd, Sd, D, stream)
     return out
+
+
+def paired_vote(torch, lane, lists, Cd, Sd, D, stream):
+    """The angle pairing of the FPGA design (rows k and n - k from shared
+    products) against the same kernel without it and against the library's
+    single-frame vote, on the same edge lists: GPU time per frame of the
+    vote alone."""
+    n = len(lists)
+    n_r = 2 * D + 1
+
+    def run(fn):
+        fn()
+        torch.cuda.synchronize()
+        return round(event_time(torch, fn, 1, stream) / n, 4)
+
+    return {"vote_ms_per_frame": {
+        "library_vote": run(lambda: [lane.hough_vote(l, W, H, Cd, Sd, D, n_r, stream=stream) for l in lists]),
+        "pair_kernel_unpaired": run(lambda: [lane.hough_vote_paired(l, W, H, Cd, Sd, D, n_r, 0, stream=stream)
+                                             for l in lists]),
+        "pair_kernel_paired": run(lambda: [lane.hough_vote_paired(l, W, H, Cd, Sd, D, n_r, 1, stream=stream)
+                                           for l in lists])}}
 
 
 def progressive_vs_plain(torch, lane, lists, seeds, sc, Cd, Sd, D, stream):

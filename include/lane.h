@@ -159,6 +159,19 @@ int lane_hough_vote(const uint32_t *list, int32_t W, int32_t H, const int16_t *c
                     const uint8_t *tile_mask_opt, int32_t *acc, uint32_t *dropped_opt,
                     void *stream);
 
+/* Hough vote with the angle pairing of the FPGA design (Sec. 3.3 Eq. (4)-(5)):
+ * theta_{n-k} = 180deg - theta_k, so for a symmetric table (C[n-k] = -C[k],
+ * S[n-k] = S[k]) rows k and n-k follow from the same products x*C[k] and
+ * y*S[k].  One workgroup per row pair.  pairing = 1 shares the products
+ * wherever the table is symmetric (other pairs are voted row by row);
+ * pairing = 0 runs the same kernel with one dot product per row (the
+ * comparison).  The result is the accumulator of lane_hough_vote without a
+ * tile mask, for any table.  Arguments as lane_hough_vote; 0 <= r_offset <=
+ * 32768; acc is fully overwritten; dropped_opt counts votes outside [0, n_r). */
+int lane_hough_vote_paired(const uint32_t *list, int32_t W, int32_t H, const int16_t *cos_q14,
+                           const int16_t *sin_q14, int32_t n_theta, int32_t r_offset, int32_t n_r,
+                           int32_t pairing, int32_t *acc, uint32_t *dropped_opt, void *stream);
+
 /* Workspace bytes for lane_hough_peaks on an n_theta x n_r accumulator. */
 int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t *bytes);
 

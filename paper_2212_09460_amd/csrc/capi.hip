@@ -18,6 +18,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_canny(const uint8_t* img, int W,
                                                       int t_high, int border_mode, uint8_t* edges,
                                                       uint8_t* mag, uint32_t* edge_count, void* ws,
                                                       hipStream_t s);
+extern "C" LANE_INTERNAL hipError_t lane_launch_vote_pair(const VoteDesc* d, int pairing, hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_progressive(const ProgDesc* d, const PeaksDesc* pk,
                                                             hipStream_t s);
 extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int W, int H, const int16_t* C,
@@ -231,6 +232,35 @@ int lane_hough_vote(const uint32_t* list, int32_t W, int32_t H, const int16_t* c
         if (e != hipSuccess) return LANE_E_DEVICE;
     }
     return dev_status(lane_launch_vote(&d, s));
+}
+
+int lane_hough_vote_paired(const uint32_t* list, int32_t W, int32_t H, const int16_t* cos_q14,
+                           const int16_t* sin_q14, int32_t n_theta, int32_t r_offset, int32_t n_r,
+                           int32_t pairing, int32_t* acc, uint32_t* dropped_opt, void* stream) {
+    if (!list || !cos_q14 || !sin_q14 || !acc || !dims_ok(W, H) || n_theta <= 0 || n_r <= 0 ||
+        (pairing != 0 && pairing != 1))
+        return LANE_E_ARG;
+    if (!aligned16(list)) return LANE_E_ARG;
+    if (!dims_small(W, H) || (int64_t)n_theta * n_r > 0x7FFFFFFFll) return LANE_E_SIZE;
+    if (r_offset < 0 || r_offset > 32768) return LANE_E_RANGE;
+    hipStream_t s = (hipStream_t)stream;
+    VoteDesc d;
+    memset(&d, 0, sizeof(d));
+    d.list = list;
+    d.W = W;
+    d.H = H;
+    d.cos_q14 = cos_q14;
+    d.sin_q14 = sin_q14;
+    d.n_theta = n_theta;
+    d.r_offset = r_offset;
+    d.n_r = n_r;
+    d.acc = acc;
+    d.dropped = dropped_opt;
+    if (dropped_opt) {
+        hipError_t e = lane_launch_fill_u32(dropped_opt, 1, 0u, s);
+        if (e != hipSuccess) return LANE_E_DEVICE;
+    }
+    return dev_status(lane_launch_vote_pair(&d, pairing, s));
 }
 
 // Key blocks are row chunks of 1 << lg cells; the smallest lg >= 6 (one

@@ -38,6 +38,8 @@ _list_size = _sig("lane_edge_list_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _sobel = _sig("lane_sobel_binarize", [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp])
 _edges_to_list = _sig("lane_edges_to_list", [_vp, _i32, _i32, _i32, _vp, _vp, _vp])
 _vote = _sig("lane_hough_vote", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
+_vote_paired = _sig("lane_hough_vote_paired", [_vp, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _i32, _vp,
+                                                _vp, _vp])
 _peaks_ws = _sig("lane_hough_peaks_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _peaks = _sig("lane_hough_peaks", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
                                     _vp, _vp, _sz, _vp])
@@ -76,6 +78,7 @@ LANE_BORDER_ZERO_MASKRING = 1
 # Exported entry points of the C ABI (also checked by the CPU tests).
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
+           "lane_hough_vote_paired",
            "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_lines",
            "lane_canny_workspace_size", "lane_canny", "lane_hough_progressive_layout",
            "lane_hough_progressive", "lane_batch_create",
@@ -187,6 +190,23 @@ def hough_vote(edge_list: torch.Tensor, W: int, H: int, cos_q14: torch.Tensor,
         dropped = torch.empty(1, dtype=torch.int32, device=edge_list.device)
     _check(_vote(_p(edge_list), W, H, _p(cos_q14), _p(sin_q14), n_theta, int(r_offset), int(n_r),
                  _p(tile_mask), _p(acc), _p(dropped), _stream(stream)), "lane_hough_vote")
+    return acc, dropped
+
+
+def hough_vote_paired(edge_list: torch.Tensor, W: int, H: int, cos_q14: torch.Tensor,
+                      sin_q14: torch.Tensor, r_offset: int, n_r: int, pairing: int = 1, acc=None,
+                      dropped=None, stream=None):
+    """Vote with rows k and n - k sharing their products (pairing=1) or not
+    (pairing=0).  Returns (acc, dropped) device tensors."""
+    n_theta = cos_q14.shape[0]
+    dev = edge_list.device
+    if acc is None:
+        acc = torch.empty((n_theta, n_r), dtype=torch.int32, device=dev)
+    if dropped is None:
+        dropped = torch.empty((1,), dtype=torch.int32, device=dev)
+    _check(_vote_paired(_p(edge_list), W, H, _p(cos_q14), _p(sin_q14), n_theta, int(r_offset),
+                        int(n_r), int(pairing), _p(acc), _p(dropped), _stream(stream)),
+           "lane_hough_vote_paired")
     return acc, dropped
 
 
