@@ -337,11 +337,12 @@ def main():
     sobel_gbs = sobel_bytes / (t_sobel * 1e-3) / 1e9
     vote_gvotes = votes / (t_vote * 1e-3) / 1e9
 
-    # single-frame latency: a one-frame plan shaped for latency (one theta
-    # row per vote workgroup, 8-row Sobel strips), each launch timed alone
+    # single-frame latency: a one-frame plan shaped for latency (4 theta rows
+    # per vote workgroup, each slice split over 8 workgroups, 8-row Sobel
+    # strips), each launch timed alone
     lat = []
     if args.latency_iters > 0:
-        one = lane.Batch([frames[0]], vote_rows=1, vote_queue=1, sobel_strip_rows=8)
+        one = lane.Batch([frames[0]], vote_rows=4, vote_queue=1, sobel_strip_rows=8, vote_split=8)
         for i in range(args.latency_iters + 5):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)

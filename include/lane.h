@@ -341,8 +341,9 @@ typedef struct lane_tune {
     int32_t sobel_groups_per_cu; /* persistent Sobel workgroups per CU; 0 = occupancy limit */
     int32_t sobel_strip_rows; /* rows per Sobel work item, a multiple of 8; 0 = 32 */
     int32_t vote_split;       /* workgroups per theta slice, each voting a 1/vote_split share of
-                                 the edge list (1..64; 0 or 1 = none); the last to finish merges
-                                 the shares; the plan then holds vote_split partial rows per slice */
+                                 the edge list (1..64; 0 or 1 = none) and adding its rows into the
+                                 accumulator, which the plan then clears before each vote; the
+                                 peak keys are then found by a pass of their own */
 } lane_tune;
 
 typedef struct lane_batch lane_batch;
@@ -477,9 +478,9 @@ typedef struct lane_server_cfg {
     float conf;               /* pruned: mask confidence, 0.5 < conf < 1 */
     const float *cnn_params;  /* pruned: host float [LANE_CNN_PARAMS], copied at creation */
     int32_t max_pending;      /* per-stream queue bound, >= 1; a request beyond it is dropped */
-    int32_t vote_rows;        /* theta rows per vote workgroup (power of two); 0 = 1 */
+    int32_t vote_rows;        /* theta rows per vote workgroup (power of two); 0 = 4 */
     int32_t sobel_strip_rows; /* rows per Sobel work item (multiple of 8); 0 = 8 */
-    int32_t vote_split;       /* lane_tune.vote_split for the server's plan; 0 = 1 */
+    int32_t vote_split;       /* lane_tune.vote_split for the server's plan; 0 = 8 */
 } lane_server_cfg;
 
 typedef struct lane_result {

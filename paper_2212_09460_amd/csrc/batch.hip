@@ -55,6 +55,15 @@ __global__ void k_clear_counters(uint32_t* const* ptrs, const uint8_t* active, i
 
 __global__ void k_reset_queue(uint32_t* queue) { *queue = 0; }
 
+// blockIdx.y = frame: clear its accumulator (a frame switched off keeps it)
+__global__ void k_zero_acc(const VoteDesc* __restrict__ descs) {
+    const VoteDesc d = descs[blockIdx.y];
+    if (!frame_on(d.active)) return;
+    const size_t cells = (size_t)d.n_theta * d.n_r;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (size_t)gridDim.x * blockDim.x)
+        gst(d.acc + i, 0);
+}
+
 }  // namespace
 
 struct lane_batch {
@@ -83,6 +92,7 @@ struct lane_batch {
     int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0, total_blocks = 0;
     int grid_sobel = 1, grid_sobel_slow = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
     bool vote_dynamic = false;
+    int vote_split = 1;      // workgroups per theta slice (E)
     int vote_half_lds = 0;   // every slice fits half the LDS: two vote workgroups per CU
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -144,6 +154,13 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
                                            b->grid_sobel_slow, s);
         }
         case 2:
+            if (b->vote_split > 1) {
+                // the split parts add into the accumulators: clear them (a kernel,
+                // not a memset node, so every replay clears)
+                hipLaunchKernelGGL(k_zero_acc, dim3(256, b->n), dim3(256), 0, s, b->d_vote);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
             if (b->vote_dynamic) {
                 // a kernel, not a memset node: the ticket restarts on every replay
                 hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, b->d_queue);
@@ -155,8 +172,9 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
                                           b->grid_vote, s);
         case 3:
             if (b->n_peak_frames == 0) return hipSuccess;
+            // keys: written by the vote, or by a pass of their own after a split vote
             return lane_launch_peaks_batch(b->d_peaks, b->d_prefix, b->n_peak_frames, b->total_blocks,
-                                           0, b->grid_select, s);
+                                           b->vote_split > 1 ? b->grid_keys : 0, b->grid_select, s);
         case 4:
             if (b->n_lines_frames == 0) return hipSuccess;
             return lane_launch_lines_batch(b->d_lines, b->n_lines_frames, b->lines_max_k,
@@ -251,7 +269,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.log2T = ilog2_floor((unsigned)v.T);
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
         v.E = E;
-        v.part_stride = v.T * lane_vote_row_cap(f.W, f.H, f.n_r);
         if (lane_vote_slice_words(f.W, f.H, f.n_theta, f.n_r, v.T) > kVoteLdsWordsHalf) all_half = false;
 
         if (f.k > 0) {
@@ -301,9 +318,12 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
                 lines_max_side = std::max(lines_max_side, std::max(f.W, f.H));
             }
             // the vote writes the block keys while its rows are still in LDS
-            v.keys = p.keys;
-            v.key_log2 = p.block_log2;
-            v.nbr = p.nbr;
+            // (not with an edge split: no workgroup holds a whole row)
+            if (E == 1) {
+                v.keys = p.keys;
+                v.key_log2 = p.block_log2;
+                v.nbr = p.nbr;
+            }
             prefix.push_back(prefix.back() + p.n_blocks);
         }
     }
@@ -346,6 +366,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->total_blocks = prefix.back();
     b->vote_dynamic = dynamic;
     b->vote_half_lds = all_half ? 1 : 0;
+    b->vote_split = E;
 
     // one device allocation for every table
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -361,16 +382,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
     const size_t o_active = off; off = al(off + (size_t)n);
     const size_t o_counts = off; off = al(off + sizeof(int) * 4);
-    // edge split: per frame E partial rows per slice and the arrival counters
-    std::vector<size_t> o_part(n, 0), o_arr(n, 0);
-    if (E > 1) {
-        for (int i = 0; i < n; ++i) {
-            o_part[i] = off;
-            off = al(off + sizeof(int32_t) * (size_t)E * vd[i].n_slices * vd[i].part_stride);
-            o_arr[i] = off;
-            off = al(off + sizeof(uint32_t) * (size_t)vd[i].n_slices);
-        }
-    }
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
@@ -390,10 +401,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     for (int i = 0; i < n; ++i) {
         sd[i].active = b->d_active + i;
         vd[i].active = b->d_active + i;
-        if (E > 1) {
-            vd[i].partials = (int32_t*)(base + o_part[i]);
-            vd[i].arrivals = (uint32_t*)(base + o_arr[i]);
-        }
     }
     for (auto& p : pd) p.active = b->d_active + p.active_index;
     for (size_t q = 0; q < ld.size(); ++q) ld[q].active = b->d_active + ld_frame[q];
@@ -409,8 +416,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 4) == hipSuccess;
     ok = ok && hipMemset(b->d_active, 1, (size_t)n) == hipSuccess;
-    for (int i = 0; i < n && E > 1; ++i)
-        ok = ok && hipMemset(vd[i].arrivals, 0, sizeof(uint32_t) * vd[i].n_slices) == hipSuccess;
     const int counts0[4] = {n_fast, b->n_sobel_items - n_fast, b->n_vote_items, 0};
     ok = ok && hipMemcpy(b->d_counts, counts0, sizeof(counts0), hipMemcpyHostToDevice) == hipSuccess;
     // host copies for lane_batch_select: per-frame item ranges
@@ -456,7 +461,11 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         // a multiple of 8 keeps every table slot on its XCD
         b->grid_vote = std::max(8, std::min(b->n_vote_items, cus * vote_per_cu) / 8 * 8);
     }
-    b->grid_keys = std::max(1, std::min((b->total_blocks + 3) / 4, cus * 8));
+    // key pass (split votes): workgroups per frame, about 2048 in all
+    int max_blocks = 1;
+    for (const auto& p : pd) max_blocks = std::max(max_blocks, p.n_blocks);
+    b->grid_keys = std::max(1, std::min((max_blocks + 3) / 4,
+                                        std::max(64, 2048 / std::max(1, b->n_peak_frames))));
     b->grid_select = std::max(1, std::min(b->n_peak_frames, cus));
 
     // capture the stages into one graph

@@ -85,10 +85,8 @@ struct VoteDesc {
     int key_log2;              // cells per key block = 1 << key_log2
     int nbr;                   // key blocks per row
     const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
-    int E;                     // edge split: workgroups per slice, each a 1/E share of the segments
-    int part_stride;           // words per partial slice accumulator (E > 1)
-    int32_t* partials;         // [E][n_slices][part_stride] (E > 1)
-    uint32_t* arrivals;        // [n_slices], zero between launches (E > 1)
+    int E;                     // edge split: workgroups per slice, each a 1/E share of the segments,
+                               // adding into acc (cleared beforehand); keys must then be null
 };
 
 // One frame for the peak search.

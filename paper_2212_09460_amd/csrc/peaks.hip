@@ -71,22 +71,13 @@ __global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
     block_key(d, b, threadIdx.x & (kWave - 1));
 }
 
-// Batched: wave-granular grid stride over all blocks of all frames; the frame
-// of a global block index is found by binary search in the prefix table.
-__global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs,
-                                                          const int* __restrict__ prefix, int n_frames) {
-    const int total = prefix[n_frames];
-    for (int gb = blockIdx.x * 4 + (threadIdx.x >> 6); gb < total; gb += gridDim.x * 4) {
-        int lo = 0, hi = n_frames - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (prefix[mid] <= gb) lo = mid;
-            else hi = mid - 1;
-        }
-        const PeaksDesc d = descs[lo];
-        if (!frame_on(d.active)) continue;
-        block_key(d, gb - prefix[lo], threadIdx.x & (kWave - 1));
-    }
+// Batched: blockIdx.y = frame (a frame switched off leaves at once),
+// workgroups of a frame stride over its blocks, one wave per block.
+__global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs) {
+    const PeaksDesc d = descs[blockIdx.y];
+    if (!frame_on(d.active)) return;
+    for (int b = blockIdx.x * 4 + (threadIdx.x >> 6); b < d.n_blocks; b += gridDim.x * 4)
+        block_key(d, b, threadIdx.x & (kWave - 1));
 }
 
 constexpr int kGroupLog2 = 5;                                  // 32 block keys per group key
@@ -369,7 +360,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* des
                                               int total_blocks, int grid_keys, int grid_select,
                                               hipStream_t s) {
     if (grid_keys > 0) {  // 0: the vote already wrote the keys
-        hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys), dim3(256), 0, s, descs, prefix, n_frames);
+        hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys, n_frames), dim3(256), 0, s, descs);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

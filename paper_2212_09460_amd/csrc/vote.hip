@@ -109,8 +109,9 @@ template <int LDSW>
 __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     // code = slice * E + part: with an edge split, E workgroups share a
     // slice, each voting a contiguous 1/E share of the segments into its own
-    // LDS rows; the last to finish adds the others' rows to its own and
-    // writes the result
+    // LDS rows and adding them into the accumulator, which the caller clears
+    // before the launch (global atomic adds: no partial buffers, no arrival
+    // protocol, no device-scope fences)
     const int E = d.E > 1 ? d.E : 1;
     const int slice = code / E, part = code - slice * E;
     const int tid = threadIdx.x;
@@ -160,7 +161,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         // layout: pairs when 32 or more rows make them conflict-free, else
         // interleaved, else pairs to fit, else rows back to back
         const int span = hi_max - lo_min + 1;
-        auto fits = [&](int w) { return w <= LDSW && (E == 1 || w <= d.part_stride); };
+        auto fits = [&](int w) { return w <= LDSW; };
         const int il_words = span * T, il2_words = ((span + 1) >> 1) * T;
         // a cell counts at most D + 2 pixels (D = the frame diagonal, below W + H)
         const bool il2_ok = 2 * (d.W + d.H + 2) <= 16383 && fits(il2_words);
@@ -361,29 +362,6 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         else if (layout == 1) body(Mode<1>{});
         else body(Mode<0>{});
         __syncthreads();
-        if (E > 1) {
-            // publish this part's rows; the last part to arrive merges
-            const int total = sm.total;
-            int32_t* mine = d.partials + ((size_t)part * d.n_slices + slice) * d.part_stride;
-            for (int c = tid; c < total; c += blockDim.x) gst(mine + c, sm.acc[c]);
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) {
-                const uint32_t seen = atomicAdd(d.arrivals + slice, 1u);
-                sm.last = seen == (uint32_t)(E - 1);
-                if (sm.last) d.arrivals[slice] = 0;  // ready for the next launch
-            }
-            __syncthreads();
-            if (!sm.last) return;
-            __threadfence();
-            for (int c = tid; c < total; c += blockDim.x) {
-                int v = sm.acc[c];
-                for (int e = 0; e < E; ++e)
-                    if (e != part) v += gld(d.partials + ((size_t)e * d.n_slices + slice) * d.part_stride + c);
-                sm.acc[c] = v;
-            }
-            __syncthreads();
-        }
         const int q0 = own_from - k0;  // first owned row of the slice
         const int lo_min = sm.lo_min, span = sm.span;
         auto cell = [&](int q, int rlo, int rwin, int rbase, int i) -> int {
@@ -401,7 +379,19 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
             const int o = i - rlo;
             return (o >= 0 && o < rwin) ? sm.acc[rbase + o] : 0;
         };
-        if (d.keys) {
+        if (E > 1) {
+            // this part's share of the owned rows, over each row's window
+            // (cells outside it are zero); the peak keys come from a later pass
+            for (int q = q0; q < T; ++q) {
+                const int row = k0 + q;
+                const int rlo = sm.lo[q], rwin = sm.win[q], rbase = sm.base[q];
+                int32_t* out = d.acc + (size_t)row * d.n_r;
+                for (int o = tid; o < rwin; o += blockDim.x) {
+                    const int v = cell(q, rlo, rwin, rbase, rlo + o);
+                    if (v != 0) atomicAdd(out + rlo + o, v);
+                }
+            }
+        } else if (d.keys) {
             // write the rows and, block by block, the peak-search keys
             const int B = 1 << d.key_log2;
             const int ntask = (T - q0) * d.nbr;

@@ -103,7 +103,8 @@ def summarize(results, streams, seconds: float):
 
 def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_params=None,
         rate_hz: float = 30.0, seed: int = 0, pool: int = 64, hbm_budget: int = 8 << 30,
-        max_pending: int = 8, vote_rows: int = 0, pools=None, mix=MIX, verbose: bool = True):
+        max_pending: int = 8, vote_rows: int = 0, pools=None, mix=MIX, verbose: bool = True,
+        vote_split: int = 0):
     from . import lane
 
     streams = mix_streams(mix)
@@ -114,7 +115,8 @@ def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_para
 
         cnn_params = load_params()
     srv = lane.Server(streams, hbm_budget=hbm_budget, pruned=pruned, conf=conf,
-                      cnn_params=cnn_params, max_pending=max_pending, vote_rows=vote_rows)
+                      cnn_params=cnn_params, max_pending=max_pending, vote_rows=vote_rows,
+                      vote_split=vote_split)
     try:
         # warm-up: one frame per stream through the server
         warm = [(s, 0.0, pools[s].numpy()[0], s) for s in range(len(streams)) if srv.admitted[s]]
