@@ -141,7 +141,9 @@ def edge_detectors(n_frames):
             _, _, lst, cnt = lane.canny(img, W, T_LOW, T_HIGH, 1, ws=ws, stream=stream)
         return lst, cnt
 
-    out = {"frames": n_frames, "canny_thresholds": [T_LOW, T_HIGH], "sobel_threshold": 128}
+    out = {"frames": n_frames, "canny_thresholds": [T_LOW, T_HIGH], "sobel_threshold": 128,
+           "oracle_ms_per_frame": oracle_rows([synth.gen_frame(sc, sd) for sd in seeds[:2]], C, S, D,
+                                              T_LOW, T_HIGH)}
     for kind in ("sobel", "canny"):
         # warm-up, then the detector alone and the whole path, back to back
         for img in imgs[:2]:
@@ -174,6 +176,38 @@ def edge_detectors(n_frames):
         out[kind]["progressive"] = progressive_vs_plain(torch, lane, lists, seeds, sc, Cd, Sd, D, stream)
         out[kind]["angle_pairing"] = paired_vote(torch, lane, lists, Cd, Sd, D, stream)
     return out
+
+
+def oracle_rows(imgs, C, S, D, t_low, t_high):
+    """The CPU oracle (single-threaded C) on two of the same frames, step by
+    step, for comparison with the GPU times of each row."""
+    import oracle
+
+    from paper_2212_09460_amd import lane
+
+    n_r = 2 * D + 1
+    steps = {}
+
+    def timed(name, fn):
+        t0 = time.perf_counter()
+        res = [fn(im) for im in imgs]
+        steps[name] = round((time.perf_counter() - t0) / len(imgs) * 1000, 1)
+        return res
+
+    sob = timed("sobel_binarize", lambda im: oracle.sobel_binarize(im, W, 128, 1)[0])
+    can = timed("canny", lambda im: oracle.canny(im, W, t_low, t_high, 1)[0])
+    it = iter(sob)
+    accs = timed("vote", lambda im: oracle.hough_vote(next(it), C, S, D, n_r)[0])
+    it = iter(accs)
+    pk = timed("peaks", lambda im: oracle.hough_peaks(next(it), D, TOPK))
+    it, ip = iter(sob), iter(pk)
+    timed("line_segments", lambda im: oracle.hough_lines(next(it), C, S, D, *next(ip)[:2]))
+    prm = lane.progressive_params(N_THETA, n_r)
+    it = iter(sob)
+    timed("coarse_to_fine_hough", lambda im: oracle.hough_progressive(next(it), C, S, D, **prm))
+    it = iter(can)
+    timed("vote_canny_edges", lambda im: oracle.hough_vote(next(it), C, S, D, n_r)[0])
+    return steps
 
 
 def paired_vote(torch, lane, lists, Cd, Sd, D, stream):
