@@ -11,7 +11,10 @@ roofline of the dominant kernel (the vote) measured live with HIP events on
 the launch stream, the Sobel pass's HBM roofline, single-frame latency, the
 serving latency (p50/p99 over 16 camera streams with Poisson arrivals,
 continuous batching, plain and pruned path), and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  Beside it, on 64 other frames: Sobel
+against the Canny detector, the coarse-to-fine Hough and the angle-paired
+vote against the plain vote, and the oracle timed step by step on two of
+those frames.
 """
 from __future__ import annotations
 
