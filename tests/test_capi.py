@@ -203,3 +203,29 @@ def test_coarse_bin_division_by_float_reciprocal_is_exact():
         hiw = np.float32(0.5) * iw
         t = (n.astype(np.float64) * np.float64(iw) + np.float64(hiw)).astype(np.float32)
         assert (np.trunc(t).astype(np.int64) == n // w).all(), w
+
+
+def test_paired_vote_argument_errors_before_launch(lib):
+    f = lib.lane_hough_vote_paired
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    f.argtypes = [vp, i32, i32, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+    buf = (ctypes.c_uint8 * 64)()
+    a16 = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
+    good = [a16, 1920, 1080, a16, a16, 360, 2203, 4407, 1, a16, None, None]
+    for i in (0, 3, 4, 9):
+        bad = list(good)
+        bad[i] = None
+        assert f(*bad) == E_ARG, i
+    for i, v in ((8, 2), (8, -1), (5, 0), (7, 0), (1, 0)):
+        bad = list(good)
+        bad[i] = v
+        assert f(*bad) == E_ARG, (i, v)
+    bad = list(good)
+    bad[0] = a16 + 4
+    assert f(*bad) == E_ARG
+    bad = list(good)
+    bad[6] = -1
+    assert f(*bad) == E_RANGE
+    bad = list(good)
+    bad[1] = 8193
+    assert f(*bad) == E_SIZE
