@@ -72,12 +72,51 @@ __global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
 }
 
 // Batched: blockIdx.y = frame (a frame switched off leaves at once),
-// workgroups of a frame stride over its blocks, one wave per block.
+// workgroups of a frame stride over its blocks, one wave per block; blocks
+// of up to 256 cells go four at a time, every load of the four issued
+// before the first maximum (a wave walks many blocks: one memory round trip
+// per four instead of one per block).
 __global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs) {
     const PeaksDesc d = descs[blockIdx.y];
     if (!frame_on(d.active)) return;
-    for (int b = blockIdx.x * 4 + (threadIdx.x >> 6); b < d.n_blocks; b += gridDim.x * 4)
-        block_key(d, b, threadIdx.x & (kWave - 1));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int stride = gridDim.x * 4;
+    int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (d.block_log2 <= 8) {
+        constexpr int U = 4, Q = 4;  // blocks per round, cells per lane and block
+        const int B = 1 << d.block_log2;
+        for (; b < d.n_blocks; b += U * stride) {
+            int v[U][Q];
+            uint32_t idx[U][Q];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int bb = min(b + u * stride, d.n_blocks - 1);
+                const int t = bb / d.nbr, j = bb - t * d.nbr;
+                const uint32_t rowc = (uint32_t)t * (uint32_t)d.n_r;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int i = j * B + q * kWave + lane;
+                    const bool ok = q * kWave + lane < B && i < d.n_r;
+                    idx[u][q] = ok ? rowc + (uint32_t)i : 0xFFFFFFFFu;
+                    v[u][q] = gld(d.acc + (ok ? rowc + (uint32_t)i : rowc));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                unsigned long long best = 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (idx[u][q] == 0xFFFFFFFFu) continue;
+                    const unsigned long long k = make_key(v[u][q], idx[u][q]);
+                    best = k > best ? k : best;
+                }
+                best = wave_max_u64(best);
+                if (lane == 0 && b + u * stride < d.n_blocks) gst(d.keys + b + u * stride, best);
+            }
+        }
+        return;
+    }
+    for (; b < d.n_blocks; b += stride) block_key(d, b, lane);
 }
 
 constexpr int kGroupLog2 = 5;                                  // 32 block keys per group key

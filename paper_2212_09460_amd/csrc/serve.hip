@@ -574,22 +574,43 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         free_server(s);
         return LANE_E_DEVICE;
     }
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    // pruned: the network and the masks need only the frames, so they form a
+    // branch of their own beside the counter clear and the Sobel pass (a side
+    // stream forked and joined with events inside the capture), joined
+    // before the vote
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipError_t e = hipSuccess;
+    if (cfg->pruned) {
+        e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int cst = LANE_OK;
     if (e == hipSuccess && cfg->pruned) {
+        e = hipEventRecord(ev_fork, cs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
         for (auto& cl : s->classes) {
+            if (e != hipSuccess) break;
             const uint8_t* fl = s->d_flags + cl.first_slot;
             cst = lane_cnn_infer_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
                                         (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
-                                        cl.logits, fl, cs);
+                                        cl.logits, fl, side);
             if (cst == LANE_OK)
                 cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
-                                                   cl.mask, fl, cs);
+                                                   cl.mask, fl, side);
             if (cst != LANE_OK) break;
         }
+        if (e == hipSuccess) e = hipEventRecord(ev_join, side);
     }
-    for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg)
+    for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
+        if (stg == 2 && cfg->pruned) {
+            e = hipStreamWaitEvent(cs, ev_join, 0);
+            if (e != hipSuccess) break;
+        }
         cst = lane_batch_launch_stage(s->plan, stg, cs);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
@@ -600,6 +621,9 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         hipGraphDestroy(g);
     }
     hipStreamDestroy(cs);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (e != hipSuccess || cst != LANE_OK) {
         free_server(s);
         return LANE_E_DEVICE;
