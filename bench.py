@@ -11,7 +11,8 @@ roofline of the dominant kernel (the vote) measured live with HIP events on
 the launch stream, the Sobel pass's HBM roofline, single-frame latency, the
 serving latency (p50/p99 over 16 camera streams with Poisson arrivals,
 continuous batching, plain and pruned path), and the CPU oracle timed on a
-bounded sample of the same workload.  Beside it, on 64 other frames: Sobel
+bounded sample of the same workload, single-threaded and in one process per
+usable core.  Beside it, on 64 other frames: Sobel
 against the Canny detector, the coarse-to-fine Hough and the angle-paired
 vote against the plain vote, and the oracle timed step by step on two of
 those frames.
@@ -45,7 +46,9 @@ def parse():
     ap.add_argument("--frames", type=int, default=256, help="frames per step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU-oracle budget for the baseline sample (0 = skip)")
-    ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="processes of the all-cores oracle leg (capped at the usable cores; 0 = skip)")
+    ap.add_argument("--latency-iters", type=int, default=1000)
     ap.add_argument("--vote-rows", type=int, default=0,
                     help="theta rows per vote workgroup (0 = tuned default)")
     ap.add_argument("--vote-queue", type=int, default=-1)
@@ -98,7 +101,78 @@ def profiled_traffic(kernel: str, src: str):
     return float(m.group(1)) if cur == m.group(3) else None
 
 
-def cpu_baseline(pool, C, S, budget_s):
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def usable_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_worker(budget_s, first_seed):
+    """One process of the all-cores oracle leg (no torch, no GPU): makes two
+    frames of the workload, reports ready, waits for the go line on stdin,
+    runs the single-threaded oracle over them for budget_s seconds and prints
+    its frame count and time as JSON."""
+    import oracle
+    from paper_2212_09460_amd import synth
+
+    sc = synth.scene_road(W, H)
+    imgs = [synth.gen_frame(sc, synth.frame_seed(0, synth.CONFIG_PLAIN_1080, first_seed + i))
+            for i in range(2)]
+    C, S = synth.trig_q14(N_THETA)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.pipeline(imgs[n % 2], C, S, TOPK)
+        n += 1
+    print(json.dumps({"frames": n, "seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_all_cores(procs, budget_s):
+    """The same untuned oracle, one frame per process at a time, in `procs`
+    processes started together: the host's throughput over independent
+    frames.  Frame generation happens before the start."""
+    import subprocess
+
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--oracle-worker", str(budget_s)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    ps = [subprocess.Popen(cmd + [str(1000 + 2 * i)], stdin=subprocess.PIPE,
+                           stdout=subprocess.PIPE, text=True, env=env) for i in range(procs)]
+    try:
+        for p in ps:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker failed to start")
+        for p in ps:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        res = [json.loads(p.stdout.readline()) for p in ps]
+        for p in ps:
+            if p.wait(timeout=120) != 0:
+                raise RuntimeError("oracle worker failed")
+    finally:
+        for p in ps:
+            if p.poll() is None:
+                p.kill()
+    frames = sum(r["frames"] for r in res)
+    span = max(r["seconds"] for r in res)
+    return {"value": round(frames * W * H / span / 1e6, 3), "unit": "Mpix/s", "cores": procs,
+            "frames_per_s": round(frames / span, 3),
+            "sample": f"{frames} frames of the same workload in {procs} single-threaded oracle "
+                      f"processes started together, {span:.1f} s"}
+
+
+def cpu_baseline(pool, C, S, budget_s, procs):
     import oracle
 
     n, px, t0 = 0, 0, time.perf_counter()
@@ -107,10 +181,15 @@ def cpu_baseline(pool, C, S, budget_s):
         n += 1
         px += W * H
     dt = time.perf_counter() - t0
-    return {"value": round(px / dt / 1e6, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames of the 1920x1080 workload (full path: Sobel, binarize, "
-                      f"vote over 360 theta, top-8 peaks), single-threaded C oracle, "
-                      f"{dt:.1f} s", "frames_per_s": round(n / dt, 4)}
+    out = {"value": round(px / dt / 1e6, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n} frames of the 1920x1080 workload (full path: Sobel, binarize, "
+                     f"vote over 360 theta, top-8 peaks), single-threaded C oracle, "
+                     f"{dt:.1f} s", "frames_per_s": round(n / dt, 4),
+           "host_cpu": host_cpu_model(), "host_usable_cores": usable_cores()}
+    procs = min(procs, usable_cores())
+    if procs > 1:
+        out["all_cores"] = cpu_all_cores(procs, budget_s)
+    return out
 
 
 def edge_detectors(n_frames):
@@ -306,9 +385,9 @@ def serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not "
-                                   "supported (frames shard across GPUs with no exchange, "
-                                   "see the design notes)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py runs on one GPU; multi-GPU runs are not "
+                                   "supported (frames would shard across GPUs with no "
+                                   "exchange)", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -470,7 +549,8 @@ def main():
                            "device_copy_gbs": round(copy_gbs, 1),
                            "frac_of_device_copy": round(sobel_gbs / copy_gbs, 4)},
         "latency_ms_single_frame_gpu": {"p50": round(float(np.percentile(lat, 50)), 4),
-                                        "p99": round(float(np.percentile(lat, 99)), 4)},
+                                        "p99": round(float(np.percentile(lat, 99)), 4),
+                                        "max": round(float(np.max(lat)), 4), "runs": int(lat.size)},
         "lines_us_per_frame": None if lines_us is None else round(lines_us, 2),
         "wall_s_timed": round(wall, 3),
     }
@@ -482,9 +562,12 @@ def main():
     if args.serve_seconds > 0:
         out["serving"] = serving(args)
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(pool, C, S, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(pool, C, S, args.cpu_seconds, args.cpu_procs)
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-worker":
+        oracle_worker(float(sys.argv[2]), int(sys.argv[3]))
+    else:
+        main()
