@@ -10,9 +10,19 @@
 // Design.  Pass 1 (many workgroups, reads the accumulator once): one wave
 // per block of B cells writes the block's best key, key = (count, -index)
 // packed in 64 bits so that one unsigned max gives "largest count, then
-// smallest index".  Pass 2 (one workgroup per frame): the block keys sit in
-// LDS with one group key per 32 blocks; each round every wave finds the
-// maximum over the group keys by itself (a DPP reduction, no barrier), lists
+// smallest index".  Pass 2 (one workgroup per frame) first tries a
+// candidate set: a histogram of the block maxima gives the lowest count tau
+// such that at most 256 blocks of at most 16384 cells in all (65536 for
+// k > 16) reach it, the
+// cells >= tau of those blocks (every cell >= tau in the frame) are loaded
+// into LDS once, and the greedy rounds run over them alone, one barrier per
+// round and no memory access.  A pick among the candidates is the frame's
+// pick as long as one is left: every cell outside the set counts less than
+// tau.  If the set runs out before k peaks while tau is above the vote
+// floor (or does not fit), the frame is redone by the general search: the
+// block keys sit in LDS with one group key per 32 blocks; each round every
+// wave finds the maximum over the group keys by itself (a DPP reduction, no
+// barrier), lists
 // the earlier peaks whose windows can reach the new window's rows (one
 // ballot), and only the blocks touched by the new window are rescanned
 // (skipping every suppressed cell), the cells of all touched blocks spread
@@ -128,6 +138,19 @@ __shared__ unsigned long long s_gkey[kMaxGroups];
 __shared__ unsigned long long s_new[2][kTaskMax];   // a round's rescanned block keys, by task
 __shared__ int s_sel_t[1024], s_sel_i[1024];
 __shared__ int s_rel[kSelWavesMax][kWave];          // per wave: earlier peaks that reach the rows
+// candidate path
+constexpr int kCandSlots = 4;                                  // candidates per thread (1024 threads)
+constexpr int kCandMax = kCandSlots * 1024;
+constexpr int kSelBlocksMax = 256;                             // blocks whose cells are gathered
+constexpr int kGatherSmallK = 16384;   // cells gathered at most for k <= 16
+constexpr int kGatherLargeK = 65536;   // and for larger k
+__shared__ unsigned long long s_cand[kCandMax];
+__shared__ uint32_t s_bbase[kSelBlocksMax];  // gathered blocks: first cell (theta-major index)
+__shared__ int s_bcnt[kSelBlocksMax];        // and cell count
+__shared__ uint32_t s_hist[256];
+__shared__ unsigned long long s_wbest[2][kSelWavesMax];
+__shared__ int s_wv[kSelWavesMax];
+__shared__ int s_nsel, s_ncand;
 
 // in_window without divisions for the usual h_theta < n_theta, where a
 // cell's row can meet the window only unwrapped or wrapped once either way
@@ -167,31 +190,196 @@ __device__ __forceinline__ unsigned long long wave_max_all(unsigned long long v)
     return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ void peaks_select(const PeaksDesc& d) {
+// Candidate search (see the top of the file).  Returns the number of peaks
+// found, or -1 if the general search has to run.  Block keys are in s_keys,
+// vmax >= floor_votes is the largest block count, s_hist and the counters
+// are zero.
+__device__ int peaks_candidates(const PeaksDesc& d, int floor_votes, int vmax) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
     const int nthreads = blockDim.x;
-    const int floor_votes = d.min_votes > 1 ? d.min_votes : 1;
+    const int lg = d.block_log2, B = 1 << lg;
+    int found = 0;
+    // histogram of the block maxima >= floor, 256 bins of 2^s counts
+    const uint32_t span = (uint32_t)(vmax - floor_votes);
+    const int s = max(0, (span ? 32 - __builtin_clz(span) : 0) - 8);
+    for (int b = tid; b < d.n_blocks; b += nthreads) {
+        const unsigned long long kb = s_keys[b];
+        const int v = kb ? key_value(kb) : INT_MIN;
+        if (v >= floor_votes) atomicAdd(&s_hist[(uint32_t)(v - floor_votes) >> s], 1u);
+    }
+    __syncthreads();
+    // beta = the lowest bin such that at most NB blocks lie in it or
+    // above (every wave works it out for itself): lane l holds bins
+    // 4l .. 4l + 3, suffix sums over the lanes
+    const int NB = min(kSelBlocksMax, max(1, (d.k <= 16 ? kGatherSmallK : kGatherLargeK) >> lg));
+    uint32_t h[4], lsum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = s_hist[4 * lane + q];
+        lsum += h[q];
+    }
+    uint32_t suf = lsum;  // sum over lanes >= lane
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_down((int)suf, o);
+        if (lane + o < kWave) suf += t;
+    }
+    int qmin = 4;
+    uint32_t sq = suf;  // suffix from bin 4 lane + q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (qmin == 4 && sq <= (uint32_t)NB) qmin = q;
+        sq -= h[q];
+    }
+    const unsigned long long okm = __ballot(qmin < 4);
+    // the suffix only falls with the bin, so the lowest lane that
+    // qualifies holds beta; none: more than NB blocks in the top bin
+    if (okm == 0ull) return -1;
+    const int Lq = __builtin_ctzll(okm);
+    const int beta = 4 * Lq + __shfl(qmin, Lq);
+    const long long tau64 = (long long)floor_votes + ((long long)beta << s);
+    // beta past the top bin: more than NB blocks share it
+    if (tau64 > (long long)vmax) return -1;
+    const int tau = (int)tau64;
+    // the blocks that reach tau (at most NB)
+    for (int b0 = wave * kWave; b0 < d.n_blocks; b0 += nthreads) {
+        const int b = b0 + lane;
+        const unsigned long long kb = b < d.n_blocks ? s_keys[b] : 0ull;
+        const bool keep = kb != 0ull && key_value(kb) >= tau;
+        const unsigned long long mk = __ballot(keep);
+        if (mk == 0ull) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_nsel, __popcll(mk));
+        base = __shfl(base, 0);
+        if (keep) {
+            const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            const int t = b / d.nbr, c0 = (b - t * d.nbr) << lg;
+            s_bbase[pos] = (uint32_t)t * (uint32_t)d.n_r + (uint32_t)c0;
+            s_bcnt[pos] = min(B, d.n_r - c0);
+        }
+    }
+    __syncthreads();
+    // their cells >= tau into the candidate array: batches of four loads
+    // per lane, the next batch in flight while one is filtered, and one LDS
+    // atomic per batch and wave for the positions
+    const int nsel = s_nsel;
+    const int ncells = nsel << lg;
+    constexpr int U = 4;
+    const int step = U * nthreads;
+    auto load = [&](int c0, uint32_t* ii, int* vv) {  // ii = ~0u: no cell
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u * nthreads + lane;
+            const int q = min(c, ncells - 1) >> lg, w = c & (B - 1);
+            ii[u] = (c < ncells && w < s_bcnt[q]) ? s_bbase[q] + (uint32_t)w : ~0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = gld(d.acc + (ii[u] != ~0u ? ii[u] : 0u));
+    };
+    auto take = [&](const uint32_t* ii, const int* vv) {
+        unsigned long long mk[U];
+        int tot = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            mk[u] = __ballot(ii[u] != ~0u && vv[u] >= tau);
+            tot += __popcll(mk[u]);
+        }
+        if (tot == 0) return;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_ncand, tot);
+        base = __shfl(base, 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if ((mk[u] >> lane) & 1ull) {
+                const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk[u] >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mk[u], 0u));
+                if (pos < kCandMax) s_cand[pos] = make_key(vv[u], ii[u]);
+            }
+            base += __popcll(mk[u]);
+        }
+    };
+    {
+        uint32_t ia[U], ib[U];
+        int va[U], vb[U];
+        int c0 = wave * kWave;
+        if (c0 < ncells) load(c0, ia, va);
+        for (; c0 < ncells; c0 += 2 * step) {
+            if (c0 + step < ncells) load(c0 + step, ib, vb);
+            take(ia, va);
+            if (c0 + step < ncells) {
+                if (c0 + 2 * step < ncells) load(c0 + 2 * step, ia, va);
+                take(ib, vb);
+            }
+        }
+    }
+    __syncthreads();
+    const int nc = s_ncand;
+    if (nc > kCandMax || nthreads * kCandSlots < kCandMax) return -1;
+    unsigned long long ck[kCandSlots];
+    int ct[kCandSlots], ci[kCandSlots];
+#pragma unroll
+    for (int m = 0; m < kCandSlots; ++m) {
+        const int c = tid + m * nthreads;
+        ck[m] = c < nc ? s_cand[c] : 0ull;
+        const uint32_t idx = key_index(ck[m]);
+        ct[m] = ck[m] ? (int)(idx / (uint32_t)d.n_r) : 0;
+        ci[m] = ck[m] ? (int)(idx - (uint32_t)ct[m] * (uint32_t)d.n_r) : 0;
+    }
+    bool ran_out = false;
+    for (int j = 0; j < d.k; ++j) {
+        unsigned long long best = 0;
+#pragma unroll
+        for (int m = 0; m < kCandSlots; ++m) best = ck[m] > best ? ck[m] : best;
+        best = wave_max_all(best);
+        if (lane == 0) s_wbest[j & 1][wave] = best;
+        __syncthreads();
+        const unsigned long long mx = wave_max_all(lane < nwaves ? s_wbest[j & 1][lane] : 0ull);
+        if (mx == 0ull) {
+            ran_out = true;
+            break;
+        }
+        const uint32_t idx = key_index(mx);
+        const int t = (int)(idx / (uint32_t)d.n_r), i = (int)(idx % (uint32_t)d.n_r);
+        if (tid == 0) {
+            d.theta_idx[j] = t;
+            d.r_idx[j] = i;
+            d.votes[j] = key_value(mx);
+        }
+        found = j + 1;
+#pragma unroll
+        for (int m = 0; m < kCandSlots; ++m)
+            if (ck[m] && in_window_fast(ct[m], ci[m], t, i, d)) ck[m] = 0ull;
+    }
+    // out of candidates: every cell left counts less than tau, so the
+    // search is over if tau is the floor, else the general search redoes it
+    if (!ran_out || tau == floor_votes) return found;
+    return -1;
+}
+
+// General search (see the top of the file); block keys are in s_keys.
+// Returns the number of peaks found.
+__device__ int peaks_general(const PeaksDesc& d, int floor_votes) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
+    const int nthreads = blockDim.x;
     const int lg = d.block_log2, B = 1 << lg;
     const int n_groups = (d.n_blocks + (1 << kGroupLog2) - 1) >> kGroupLog2;
-    // block keys into LDS, eight loads in flight per thread (indices are
-    // clamped so every load is in bounds and none waits on a branch)
-    for (int b0 = tid; b0 < d.n_blocks; b0 += 8 * nthreads) {
-        unsigned long long v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = gld(d.keys + min(b0 + u * nthreads, d.n_blocks - 1));
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (b0 + u * nthreads < d.n_blocks) s_keys[b0 + u * nthreads] = v[u];
-    }
+    int found = 0;
     for (int q = tid; q < 2 * kTaskMax; q += nthreads) s_new[q / kTaskMax][q % kTaskMax] = 0;
-    __syncthreads();
     // group keys: the maximum of 32 consecutive block keys
     for (int g = wave; g < n_groups; g += nwaves) {
         const int b = (g << kGroupLog2) + (lane & 31);
@@ -209,7 +397,6 @@ __device__ void peaks_select(const PeaksDesc& d) {
     const int nbw = min(d.nbr, ((2 * d.h_r) >> lg) + 2);
     const int ntask = all_rows ? d.n_blocks : (2 * d.h_theta + 1) * nbw;
     const bool two_buf = !all_rows && ntask <= kTaskMax;
-    int found = 0;
     for (int j = 0; j < d.k; ++j) {
         // every wave finds the largest key itself: no barrier to share it
         unsigned long long best = 0;
@@ -360,6 +547,44 @@ __device__ void peaks_select(const PeaksDesc& d) {
             if (tb >= 0) s_keys[b] = v;
         }
         __syncthreads();
+    }
+    return found;
+}
+
+__device__ void peaks_select(const PeaksDesc& d) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6, nwaves = blockDim.x >> 6;
+    const int nthreads = blockDim.x;
+    const int floor_votes = d.min_votes > 1 ? d.min_votes : 1;
+    // block keys into LDS, eight loads in flight per thread (indices are
+    // clamped so every load is in bounds and none waits on a branch), and
+    // the largest block count
+    int vmax = INT_MIN;
+    for (int b0 = tid; b0 < d.n_blocks; b0 += 8 * nthreads) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = gld(d.keys + min(b0 + u * nthreads, d.n_blocks - 1));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (b0 + u * nthreads < d.n_blocks) {
+                s_keys[b0 + u * nthreads] = v[u];
+                if (v[u] != 0ull) vmax = max(vmax, key_value(v[u]));
+            }
+        }
+    }
+    vmax = wave_max_i32(vmax);
+    if (lane == 0) s_wv[wave] = vmax;
+    for (int q = tid; q < 256; q += nthreads) s_hist[q] = 0;
+    if (tid == 0) {
+        s_nsel = 0;
+        s_ncand = 0;
+    }
+    __syncthreads();
+    vmax = wave_max_i32(lane < nwaves ? s_wv[lane] : INT_MIN);
+    int found = 0;
+    if (vmax >= floor_votes) {  // else no cell reaches the floor
+        found = peaks_candidates(d, floor_votes, vmax);
+        if (found < 0) found = peaks_general(d, floor_votes);
     }
     __syncthreads();
     for (int j = found + tid; j < d.k; j += nthreads) {

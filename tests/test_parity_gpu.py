@@ -332,6 +332,50 @@ def test_peaks_large_blocks(lane, oracle):
     peaks_both(lane, oracle, acc, D, 10)
 
 
+@pytest.mark.parametrize("case", ["frame_k32", "frame_k200", "sparse", "flat", "dense_top",
+                                  "floor_above", "wide_window"])
+def test_peaks_candidate_branches(lane, synth, oracle, case):
+    """The peak search first works on the cells at or above a count tau
+    that only a few hundred blocks reach, and redoes the frame with the
+    general search when that set runs out above the vote floor or is too
+    large.  One case per way through: the set suffices (a 1080p frame,
+    k = 32); it runs out above the floor (k = 200); it runs out at the
+    floor (a few isolated cells); more blocks than allowed share the top
+    count (a flat accumulator); the set holds too many cells (a band of
+    rows at one high count); nothing reaches min_votes; a window wider
+    than the half-turn."""
+    say("peaks candidate branch", case)
+    n_theta = 360
+    if case.startswith("frame") or case == "wide_window":
+        img = synth.plain_1080(3)
+        C, S = synth.trig_q14(n_theta)
+        r = oracle.pipeline(img, C, S, 8)
+        acc, D = r["acc"], r["D"]
+    else:
+        D = 2202
+        acc = np.zeros((n_theta, 2 * D + 1), np.int32)
+    if case == "frame_k32":
+        assert peaks_both(lane, oracle, acc, D, 32) == 32
+    elif case == "frame_k200":
+        assert peaks_both(lane, oracle, acc, D, 200) == 200
+    elif case == "sparse":
+        for j, (t, i) in enumerate([(5, 100), (90, 2000), (200, 4000), (359, 7), (180, 2202)]):
+            acc[t, i] = 10 + j
+        assert peaks_both(lane, oracle, acc, D, 8) == 5
+    elif case == "flat":
+        acc[:] = 7
+        assert peaks_both(lane, oracle, acc, D, 8) == 8
+    elif case == "dense_top":
+        rng = np.random.default_rng(4)
+        acc[:] = rng.integers(0, 20, acc.shape)
+        acc[10:14, :] = 100
+        assert peaks_both(lane, oracle, acc, D, 8) == 8
+    elif case == "floor_above":
+        assert peaks_both(lane, oracle, acc + 5, D, 8, mv=6) == 0
+    else:
+        assert peaks_both(lane, oracle, acc, D, 12, 200, 30) >= 1
+
+
 @pytest.mark.parametrize("idx", [0, 16, 32, 48])
 def test_pipeline_mixed_sizes(lane, synth, oracle, idx):
     sc, seed = synth.mixed_batch_scene(idx)
