@@ -352,7 +352,10 @@ typedef struct lane_batch lane_batch;
  * Validation is the same as for the single-frame calls. */
 int lane_batch_create(const lane_frame *frames, int32_t n, const lane_tune *tune_opt,
                       lane_batch **out);
-/* Enqueue the whole path for every frame: one hipGraphLaunch on `stream`. */
+/* Enqueue the whole path for every frame: one hipGraphLaunch on `stream`.
+ * The graph runs the stages below in order, except that the vote's set-up
+ * (its work queue, the accumulators of a split vote) is done by the
+ * counter-clearing kernel at the start rather than before the vote. */
 int lane_batch_launch(lane_batch *b, void *stream);
 /* Enqueue one stage without the graph (0 = clear counters, 1 = Sobel,
  * 2 = vote, 3 = peaks, 4 = line segments of the frames that ask for them),

@@ -45,20 +45,23 @@ extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
 namespace {
 
-__global__ void k_clear_counters(uint32_t* const* ptrs, const uint8_t* active, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && ptrs[i] && active[i]) {
-        ptrs[i][0] = 0;
-        ptrs[i][1] = 0;
+// Set-up of a pass, one kernel (blockIdx.y = frame): clear the frame's
+// counters (ctrs non-null), reset the vote's ticket queue (queue non-null)
+// and clear the frame's accumulator for a split vote (zero_acc); a frame
+// switched off keeps its counters and accumulator.  A kernel rather than
+// memset nodes, so that every graph replay runs it.
+__global__ void k_setup(uint32_t* const* ctrs, const VoteDesc* __restrict__ descs,
+                        const uint8_t* active, uint32_t* queue, int zero_acc) {
+    const int f = blockIdx.y;
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (queue && f == 0 && first) gst(queue, 0u);
+    if (!active[f]) return;
+    if (ctrs && first && ctrs[f]) {
+        gst(ctrs[f], 0u);
+        gst(ctrs[f] + 1, 0u);
     }
-}
-
-__global__ void k_reset_queue(uint32_t* queue) { *queue = 0; }
-
-// blockIdx.y = frame: clear its accumulator (a frame switched off keeps it)
-__global__ void k_zero_acc(const VoteDesc* __restrict__ descs) {
-    const VoteDesc d = descs[blockIdx.y];
-    if (!frame_on(d.active)) return;
+    if (!zero_acc) return;
+    const VoteDesc d = descs[f];
     const size_t cells = (size_t)d.n_theta * d.n_r;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (size_t)gridDim.x * blockDim.x)
         gst(d.acc + i, 0);
@@ -138,12 +141,20 @@ int pow2_floor(int v) {
     return p;
 }
 
-hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
+// pass: the stage is part of a whole pass (the plan's graph, the serving
+// graph), where stage 0 also does the vote's set-up (its queue, split
+// accumulators) so that one kernel does all of it; otherwise every stage
+// stands alone.
+hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s, bool pass = false) {
+    const bool split = b->vote_split > 1;
     switch (stage) {
-        case 0:
-            hipLaunchKernelGGL(k_clear_counters, dim3((b->n + 255) / 256), dim3(256), 0, s,
-                               b->d_counters, b->d_active, b->n);
+        case 0: {
+            const bool zero = pass && split;
+            hipLaunchKernelGGL(k_setup, dim3(zero ? 256 : 1, b->n), dim3(256), 0, s, b->d_counters,
+                               b->d_vote, b->d_active, pass && b->vote_dynamic ? b->d_queue : nullptr,
+                               zero ? 1 : 0);
             return hipGetLastError();
+        }
         case 1: {
             // aligned frames first (vector loads), then the rest
             hipError_t e = hipSuccess;
@@ -154,16 +165,12 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s) {
                                            b->grid_sobel_slow, s);
         }
         case 2:
-            if (b->vote_split > 1) {
-                // the split parts add into the accumulators: clear them (a kernel,
-                // not a memset node, so every replay clears)
-                hipLaunchKernelGGL(k_zero_acc, dim3(256, b->n), dim3(256), 0, s, b->d_vote);
-                const hipError_t e = hipGetLastError();
-                if (e != hipSuccess) return e;
-            }
-            if (b->vote_dynamic) {
-                // a kernel, not a memset node: the ticket restarts on every replay
-                hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, b->d_queue);
+            if (!pass && (split || b->vote_dynamic)) {
+                // standing alone: the split parts add into cleared accumulators,
+                // and the ticket queue restarts
+                hipLaunchKernelGGL(k_setup, dim3(split ? 256 : 1, b->n), dim3(256), 0, s, nullptr,
+                                   b->d_vote, b->d_active, b->vote_dynamic ? b->d_queue : nullptr,
+                                   split ? 1 : 0);
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -475,7 +482,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         return LANE_E_DEVICE;
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int st = 0; st < 5 && e == hipSuccess; ++st) e = enqueue_stage(b, st, cs);
+    for (int st = 0; st < 5 && e == hipSuccess; ++st) e = enqueue_stage(b, st, cs, true);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
@@ -558,6 +565,13 @@ int lane_batch_active_flags(lane_batch* b, uint8_t** flags) {
 int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {
     if (!b || stage < 0 || stage > 4) return LANE_E_ARG;
     return enqueue_stage(b, stage, (hipStream_t)stream) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+// One stage of a whole pass (stage 0 also does the vote's set-up), for a
+// graph that puts other work between the stages (the serving loop).
+LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream) {
+    if (!b || stage < 0 || stage > 4) return LANE_E_ARG;
+    return enqueue_stage(b, stage, (hipStream_t)stream, true) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
 }
 
 int lane_batch_destroy(lane_batch* b) {

@@ -42,6 +42,7 @@ LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H
 LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
                                                int32_t batch, float conf, uint8_t* mask,
                                                const uint8_t* active, void* stream);
+LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream);
 }
 
 namespace {
@@ -609,7 +610,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
             e = hipStreamWaitEvent(cs, ev_join, 0);
             if (e != hipSuccess) break;
         }
-        cst = lane_batch_launch_stage(s->plan, stg, cs);
+        cst = lane_batch_enqueue_pass_stage(s->plan, stg, cs);
     }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
