@@ -41,6 +41,8 @@ extern "C" LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_
 extern "C" LANE_INTERNAL hipError_t lane_launch_lines_batch(const LinesDesc* descs, int n, int max_k,
                                                             int max_side, hipStream_t s);
 extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
+extern "C" LANE_INTERNAL hipError_t lane_launch_prune_batch(const PruneDesc* descs, int n, int max_nseg,
+                                                           hipStream_t s);
 extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
 namespace {
@@ -97,6 +99,10 @@ struct lane_batch {
     bool vote_dynamic = false;
     int vote_split = 1;      // workgroups per theta slice (E)
     int vote_half_lds = 0;   // every slice fits half the LDS: two vote workgroups per CU
+    // split vote with tile masks: pruned copies of those frames' edge lists
+    PruneDesc* d_prune = nullptr;
+    int n_prune = 0, prune_max_nseg = 0;
+    void* prune_mem = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -174,6 +180,11 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s, bool pass = fa
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
+            if (b->n_prune > 0) {
+                // masked frames of a split vote: their pruned lists first
+                const hipError_t e = lane_launch_prune_batch(b->d_prune, b->n_prune, b->prune_max_nseg, s);
+                if (e != hipSuccess) return e;
+            }
             return lane_launch_vote_batch(b->d_vote, b->d_vote_items, b->d_counts + 2,
                                           b->vote_dynamic ? b->d_queue : nullptr, b->vote_half_lds,
                                           b->grid_vote, s);
@@ -195,6 +206,7 @@ void free_plan(lane_batch* b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     if (b->dmem) hipFree(b->dmem);
+    if (b->prune_mem) hipFree(b->prune_mem);
     if (b->h_stage) hipHostFree(b->h_stage);
     delete b;
 }
@@ -233,6 +245,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     std::vector<int2> sitems, sitems_slow, vitems;
     std::vector<int> prefix(1, 0);
     std::vector<uint32_t*> counters(n, nullptr);
+    std::vector<PruneDesc> prd;  // masked frames of a split vote
+    std::vector<size_t> prune_bytes;
     std::vector<double> vcost;
     bool mixed = false;
     bool all_half = true;
@@ -277,6 +291,21 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         v.n_slices = (f.n_theta + v.T - 1) / v.T;
         v.E = E;
         if (lane_vote_slice_words(f.W, f.H, f.n_theta, f.n_r, v.T) > kVoteLdsWordsHalf) all_half = false;
+        if (E > 1 && f.tile_mask_opt) {
+            // the vote reads the pruned list (set below) with no mask
+            PruneDesc pr;
+            memset(&pr, 0, sizeof(pr));
+            pr.list = f.list;
+            pr.tile_mask = f.tile_mask_opt;
+            pr.W = f.W;
+            pr.H = f.H;
+            pr.vote = i;
+            prd.push_back(pr);
+            size_t lb = 0;
+            lane_edge_list_size(f.W, f.H, &lb);
+            prune_bytes.push_back((lb + 255) & ~(size_t)255);
+            v.pruned = 1;
+        }
 
         if (f.k > 0) {
             PeaksDesc p;
@@ -389,9 +418,25 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 4);
     const size_t o_active = off; off = al(off + (size_t)n);
     const size_t o_counts = off; off = al(off + sizeof(int) * 4);
+    const size_t o_prune = off; off = al(off + sizeof(PruneDesc) * std::max<size_t>(prd.size(), 1));
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
         return LANE_E_DEVICE;
+    }
+    if (!prd.empty()) {
+        size_t total = 0;
+        for (size_t q = 0; q < prd.size(); ++q) total += prune_bytes[q];
+        if (hipMalloc(&b->prune_mem, total) != hipSuccess) {
+            free_plan(b);
+            return LANE_E_DEVICE;
+        }
+        char* pm = (char*)b->prune_mem;
+        for (size_t q = 0; q < prd.size(); ++q) {
+            prd[q].pruned = (uint32_t*)pm;
+            vd[prd[q].vote].list = prd[q].pruned;
+            b->prune_max_nseg = std::max(b->prune_max_nseg, list_layout(prd[q].W, prd[q].H).nseg);
+            pm += prune_bytes[q];
+        }
     }
     char* base = (char*)b->dmem;
     b->d_sobel = (SobelDesc*)(base + o_sobel);
@@ -405,14 +450,19 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->d_queue = (uint32_t*)(base + o_queue);
     b->d_active = (uint8_t*)(base + o_active);
     b->d_counts = (int*)(base + o_counts);
+    b->d_prune = (PruneDesc*)(base + o_prune);
+    b->n_prune = (int)prd.size();
     for (int i = 0; i < n; ++i) {
         sd[i].active = b->d_active + i;
         vd[i].active = b->d_active + i;
     }
+    for (auto& pr : prd) pr.active = b->d_active + pr.vote;
     for (auto& p : pd) p.active = b->d_active + p.active_index;
     for (size_t q = 0; q < ld.size(); ++q) ld[q].active = b->d_active + ld_frame[q];
     bool ok = hipMemcpy(b->d_sobel, sd.data(), sizeof(SobelDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_vote, vd.data(), sizeof(VoteDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
+    if (!prd.empty())
+        ok = ok && hipMemcpy(b->d_prune, prd.data(), sizeof(PruneDesc) * prd.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (!pd.empty())
         ok = ok && hipMemcpy(b->d_peaks, pd.data(), sizeof(PeaksDesc) * pd.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (!ld.empty())

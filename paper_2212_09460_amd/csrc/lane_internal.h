@@ -87,6 +87,7 @@ struct VoteDesc {
     const uint8_t* active;     // batched path: the frame runs iff *active != 0 (null = always)
     int E;                     // edge split: workgroups per slice, each a 1/E share of the segments,
                                // adding into acc (cleared beforehand); keys must then be null
+    int pruned;                // list is a pruned list (PruneDesc) of a frame with tile_mask
 };
 
 // One frame for the peak search.
@@ -140,6 +141,33 @@ constexpr int kProgRefineLdsMax = 65536;  // bytes
 constexpr int kProgTargetGroups = 2048;    // coarse workgroups a launch aims at (8 per CU)
 constexpr int kProgRefineGroups = 512;     // refine workgroups a launch aims at
 constexpr int kProgCoarseLdsMax = 98304;  // bytes
+
+// One frame of a split vote with a tile mask: the pruned copy of its edge
+// list (same size and layout; word seg holds the count of segment seg's
+// entries from tiles that vote every row, word off_info + seg the count of
+// its band-restricted entries, which sit at the end of the segment's slot).
+struct PruneDesc {
+    const uint32_t* list;      // the frame's edge list
+    uint32_t* pruned;          // the pruned list
+    const uint8_t* tile_mask;  // [ceil(H/8)][ceil(W/8)] band bits
+    int W, H;
+    int vote;                  // index of the frame's VoteDesc in the plan
+    const uint8_t* active;     // the frame runs iff *active != 0 (null = always)
+};
+
+// Band bits of theta row k: bit b is set when k lies in band b, the
+// quarter turn of rows starting at row b * n_theta / 8 (cyclically).
+__device__ __forceinline__ int band_bits_dev(int n_theta, int k) {
+    int bits = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int start = (b * n_theta) / 8;
+        int dd = (k - start) % n_theta;
+        if (dd < 0) dd += n_theta;
+        if (dd < n_theta / 4) bits |= 1 << b;
+    }
+    return bits;
+}
 
 // One frame for the line segments along its peaks.
 struct LinesDesc {

@@ -33,18 +33,6 @@ __device__ __forceinline__ int dot2_i16(int a, int b, int c) {
     return d;
 }
 
-__device__ __forceinline__ int band_bits_dev(int n_theta, int k) {
-    int bits = 0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int start = (b * n_theta) / 8;
-        int dd = (k - start) % n_theta;
-        if (dd < 0) dd += n_theta;
-        if (dd < n_theta / 4) bits |= 1 << b;
-    }
-    return bits;
-}
-
 // Workgroup state.  The accumulator array is declared per LDS-size variant
 // (kVoteLdsWords: one workgroup per CU; kVoteLdsWordsHalf: two).
 template <int LDSW>
@@ -182,8 +170,12 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     const int seg_hi = fast ? (int)(((long long)L.nseg * (part + 1)) / E) : L.nseg;
     const int kk = k0 + j;
     const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
-    const bool masked = d.tile_mask != nullptr;
-    const int bb = masked ? band_bits_dev(d.n_theta, kk) : 0xFF;
+    // pruned: the list holds, per segment, the entries of tiles that vote
+    // every row (streamed like an unmasked list) and, at the end of the
+    // segment's slot, those of band-restricted tiles, tested entry by entry
+    const bool pruned = d.pruned != 0;
+    const bool masked = d.tile_mask != nullptr && !pruned;
+    const int bb = (masked || pruned) ? band_bits_dev(d.n_theta, kk) : 0xFF;
     int slice_bits = 0;
     if (masked) {
         for (int q = 0; q < T; ++q) slice_bits |= band_bits_dev(d.n_theta, k0 + q);
@@ -357,6 +349,30 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 }
             }
         }
+        if (pruned) {
+            // band-restricted entries of this wave's segments: the counts of
+            // 64 segments at once, then each segment that has any, its
+            // entries spread over the slots, each voting in this lane's row
+            // if its tile's mask meets the row's bands
+            for (int s0 = seg_lo + wave; s0 < seg_hi; s0 += nwaves * kWave) {
+                const int sj = s0 + lane * nwaves;
+                const int R = sj < seg_hi ? min((int)gld(list + L.off_info + sj), kSegCap) : 0;
+                unsigned long long mk = __ballot(R > 0);
+                while (mk) {
+                    const int l = __builtin_ctzll(mk);
+                    mk &= mk - 1ull;
+                    const int seg = s0 + l * nwaves;
+                    const int Rs = __builtin_amdgcn_readlane(R, l);
+                    const uint32_t* __restrict__ ents = list + L.off_ent + (size_t)seg * kSegCap + (kSegCap - Rs);
+                    for (int e = g; e < Rs; e += G) {
+                        const uint32_t xy = gld(ents + e);
+                        const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+                        if (x >= d.W || y >= d.H) continue;
+                        if (gld(d.tile_mask + (size_t)(y >> 3) * L.tw + (x >> 3)) & bb) vote1(xy);
+                    }
+                }
+            }
+        }
         };
         if (layout == 2) body(Mode<2>{});
         else if (layout == 1) body(Mode<1>{});
@@ -435,12 +451,15 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         uint32_t drop = 0;
         for (int seg = wave; seg < L.nseg; seg += nwaves) {
             const int n = min((int)list[seg], kSegCap);
+            // a pruned list's band-restricted entries follow, from the slot's end
+            const int R = pruned ? min((int)list[L.off_info + seg], kSegCap - n) : 0;
             const uint32_t* ents = list + L.off_ent + (size_t)seg * kSegCap;
-            for (int e = g; e < n; e += G) {
-                const uint32_t xy = ents[e];
+            for (int e = g; e < n + R; e += G) {
+                const bool res = e >= n;
+                const uint32_t xy = ents[res ? kSegCap - R + (e - n) : e];
                 const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
                 if (!own || x >= d.W || y >= d.H) continue;
-                if (masked) {
+                if (masked || res) {
                     const int m = d.tile_mask[(size_t)(y >> 3) * L.tw + (x >> 3)];
                     if ((m & bb) == 0) continue;
                 }

@@ -256,3 +256,61 @@ def test_vote_split_with_fallback_rows(lane, synth, oracle):
         assert int(fb.counters.cpu().numpy()[1]) == want["dropped"] > 0
         assert (fb.theta_idx().cpu().numpy() == want["theta_idx"]).all()
     b.close()
+
+
+def proposal_like_mask(rng, Hf, Wf, keep=0.07, restricted=0.01):
+    """Tile masks shaped like the proposal network's: most tiles skipped
+    (0), some voting every row (0xFF), a few restricted to some bands."""
+    th, tw = (Hf + 7) // 8, (Wf + 7) // 8
+    r = rng.random((th, tw))
+    m = np.zeros((th, tw), np.uint8)
+    m[r < keep] = 0xFF
+    sel = (r >= keep) & (r < keep + restricted)
+    m[sel] = rng.integers(1, 255, int(sel.sum()))
+    return m
+
+
+@pytest.mark.parametrize("rows,split,queue", [(4, 8, 1), (16, 2, 0), (1, 64, 1)])
+def test_split_vote_pruned_lists(lane, synth, oracle, rows, split, queue):
+    """Masked frames in a split plan vote from pruned copies of their edge
+    lists (tiles that vote every row) plus a pass over the band-restricted
+    tiles: exact on every replay, frames switched off keep their outputs,
+    and mask contents changed between launches take effect."""
+    say("split vote pruned lists", rows, split, queue)
+    rng = np.random.default_rng(rows * 100 + split)
+    C, S = synth.trig_q14(360)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    specs = [(1920, 1080, 1920, 81), (1280, 720, 1280, 82), (333, 211, 352, 83), (3840, 2160, 3840, 84)]
+    frames, wants, masks = [], [], []
+    for (Wf, Hf, pitch, seed) in specs:
+        img = synth.gen_frame(synth.scene_road(Wf, Hf), seed, pitch=pitch)
+        m = proposal_like_mask(rng, Hf, Wf)
+        masks.append(m)
+        frames.append(lane.FrameBuffers(torch.from_numpy(img).cuda(), Wf, 360, 8, Cd, Sd,
+                                        tile_mask=torch.from_numpy(m).cuda()))
+        wants.append(oracle.pipeline(img[:, :Wf].copy(), C, S, 8, tile_mask=m))
+    # one unmasked frame in the same plan
+    img = synth.gen_frame(synth.scene_road(640, 480), 85)
+    frames.append(lane.FrameBuffers(torch.from_numpy(img).cuda(), 640, 360, 8, Cd, Sd))
+    wants.append(oracle.pipeline(img, C, S, 8))
+    b = lane.Batch(frames, vote_rows=rows, vote_split=split, vote_queue=queue)
+    for rep in range(2):
+        scribble(frames)
+        b.launch()
+        check(frames, wants)
+    # new masks for frames 0 and 2 (every tile restricted in frame 2), frame 1 off
+    masks[0] = proposal_like_mask(rng, 1080, 1920, keep=0.2, restricted=0.05)
+    masks[2] = rng.integers(1, 255, masks[2].shape).astype(np.uint8)
+    for i in (0, 2):
+        frames[i].tile_mask.copy_(torch.from_numpy(masks[i]))
+        Wf, Hf, pitch, seed = specs[i]
+        img = frames[i].img.cpu().numpy()[:, :Wf].copy()
+        wants[i] = oracle.pipeline(img, C, S, 8, tile_mask=masks[i])
+    frames[1].acc.fill_(-7)
+    frames[1].peaks.fill_(-5)
+    b.select([1, 0, 1, 1, 1])
+    b.launch()
+    torch.cuda.synchronize()
+    check([frames[i] for i in (0, 2, 3, 4)], [wants[i] for i in (0, 2, 3, 4)])
+    assert (frames[1].acc == -7).all() and (frames[1].peaks == -5).all()
+    b.close()
