@@ -301,8 +301,9 @@ int lane_hough_progressive(const uint32_t *list, int32_t W, int32_t H, const int
  * Many frames of mixed sizes through the whole path (Sobel + binarize +
  * compaction, vote, peaks, and line segments where a frame asks for them) in
  * one HIP graph launch.  A plan is built once
- * per set of buffers (creation allocates a small device descriptor table and
- * instantiates the graph; launching allocates nothing).  Each stage is a
+ * per set of buffers (creation allocates a small device descriptor table,
+ * with a split vote also one edge-list-sized buffer per frame that has a tile
+ * mask, and instantiates the graph; launching allocates nothing).  Each stage is a
  * persistent kernel that walks a work table covering every frame; the
  * paper's GPU grid of one block per 16x16 pixels (Sec. 4.1 Eq. (6)) and of
  * one block per angle (Sec. 4.3) become these tables. */
@@ -343,7 +344,11 @@ typedef struct lane_tune {
     int32_t vote_split;       /* workgroups per theta slice, each voting a 1/vote_split share of
                                  the edge list (1..64; 0 or 1 = none) and adding its rows into the
                                  accumulator, which the plan then clears before each vote; the
-                                 peak keys are then found by a pass of their own */
+                                 peak keys are then found by a pass of their own.  A frame with
+                                 a tile mask then votes from a pruned copy of its edge list
+                                 (the entries of tiles that vote every row, then those of
+                                 band-restricted tiles, tested entry by entry), which the plan
+                                 writes before the vote and owns (lane_edge_list_size bytes) */
 } lane_tune;
 
 typedef struct lane_batch lane_batch;
