@@ -47,6 +47,10 @@ LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, vo
 
 namespace {
 
+// a pruned server with at most this many classes keeps one graph per
+// non-empty subset of classes (2^n - 1 graphs)
+constexpr int kSubsetClasses = 4;
+
 int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(
                std::chrono::steady_clock::now().time_since_epoch())
@@ -193,8 +197,12 @@ struct lane_server {
     uint8_t* d_flags = nullptr;            // the plan's flags
     lane_batch* plan = nullptr;
     hipStream_t stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // graphs[m]: the refill whose active slots lie in the classes of bit
+    // mask m (pruned, up to kSubsetClasses classes: only those classes run
+    // their network and masks); otherwise graphs[0] serves every refill
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
+    bool per_subset = false;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -248,7 +256,10 @@ int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_re
             e = hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch,
                                  (size_t)c.cfg.W, (size_t)c.cfg.H, hipMemcpyHostToDevice, s->stream);
     }
-    if (e == hipSuccess) e = hipGraphLaunch(s->exec, s->stream);
+    uint32_t cls_mask = 0;
+    if (s->per_subset)
+        for (const Req& q : batch) cls_mask |= 1u << s->class_of[s->slot_of[q.stream]];
+    if (e == hipSuccess) e = hipGraphLaunch(s->execs[s->per_subset ? cls_mask : 0], s->stream);
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const int slot = s->slot_of[batch[i].stream];
         const int k = s->streams[slot].k;
@@ -361,8 +372,10 @@ void free_server(lane_server* s) {
         s->worker.join();
     }
     if (s->stream) hipStreamSynchronize(s->stream);
-    if (s->exec) hipGraphExecDestroy(s->exec);
-    if (s->graph) hipGraphDestroy(s->graph);
+    for (auto x : s->execs)
+        if (x) hipGraphExecDestroy(x);
+    for (auto g : s->graphs)
+        if (g) hipGraphDestroy(g);
     if (s->plan) lane_batch_destroy(s->plan);
     if (s->stream) hipStreamDestroy(s->stream);
     if (s->dmem) hipFree(s->dmem);
@@ -587,39 +600,55 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int cst = LANE_OK;
-    if (e == hipSuccess && cfg->pruned) {
-        e = hipEventRecord(ev_fork, cs);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
-        for (auto& cl : s->classes) {
-            if (e != hipSuccess) break;
-            const uint8_t* fl = s->d_flags + cl.first_slot;
-            cst = lane_cnn_infer_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
-                                        (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
-                                        cl.logits, fl, side);
-            if (cst == LANE_OK)
-                cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
-                                                   cl.mask, fl, side);
-            if (cst != LANE_OK) break;
+    // one capture: the classes of cls_mask run their network and masks
+    auto capture = [&](uint32_t cls_mask, hipGraph_t* gout, hipGraphExec_t* xout) {
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return;
+        if (cfg->pruned) {
+            e = hipEventRecord(ev_fork, cs);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
+            for (size_t c = 0; c < s->classes.size() && e == hipSuccess; ++c) {
+                if (c < 32 && !((cls_mask >> c) & 1u)) continue;
+                auto& cl = s->classes[c];
+                const uint8_t* fl = s->d_flags + cl.first_slot;
+                cst = lane_cnn_infer_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
+                                            (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
+                                            cl.logits, fl, side);
+                if (cst == LANE_OK)
+                    cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
+                                                       cl.mask, fl, side);
+                if (cst != LANE_OK) break;
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev_join, side);
         }
-        if (e == hipSuccess) e = hipEventRecord(ev_join, side);
-    }
-    for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
-        if (stg == 2 && cfg->pruned) {
-            e = hipStreamWaitEvent(cs, ev_join, 0);
-            if (e != hipSuccess) break;
+        for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
+            if (stg == 2 && cfg->pruned) {
+                e = hipStreamWaitEvent(cs, ev_join, 0);
+                if (e != hipSuccess) break;
+            }
+            cst = lane_batch_enqueue_pass_stage(s->plan, stg, cs);
         }
-        cst = lane_batch_enqueue_pass_stage(s->plan, stg, cs);
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(cs, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess && cst == LANE_OK) {
-        s->graph = g;
-        e = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
-    } else if (g) {
-        hipGraphDestroy(g);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess && cst == LANE_OK) {
+            *gout = g;
+            e = hipGraphInstantiate(xout, g, nullptr, nullptr, 0);
+        } else if (g) {
+            hipGraphDestroy(g);
+        }
+    };
+    const size_t n_cls = s->classes.size();
+    s->per_subset = cfg->pruned && n_cls > 1 && n_cls <= (size_t)kSubsetClasses;
+    const size_t n_graphs = s->per_subset ? ((size_t)1 << n_cls) : 1;
+    s->graphs.assign(n_graphs, nullptr);
+    s->execs.assign(n_graphs, nullptr);
+    if (s->per_subset) {
+        for (size_t m = 1; m < n_graphs && e == hipSuccess && cst == LANE_OK; ++m)
+            capture((uint32_t)m, &s->graphs[m], &s->execs[m]);
+    } else {
+        capture(0xFFFFFFFFu, &s->graphs[0], &s->execs[0]);
     }
     hipStreamDestroy(cs);
     if (side) (void)hipStreamDestroy(side);
