@@ -221,8 +221,9 @@ def test_select_runs_only_selected_frames(lane, synth, oracle, queue):
 
 @pytest.mark.parametrize("rows,split,queue", [(1, 2, 1), (4, 4, 1), (16, 3, 0), (2, 8, 1), (8, 64, 1)])
 def test_vote_split(lane, synth, oracle, rows, split, queue):
-    """Edge-split vote: several workgroups per slice, the last merges; exact
-    on every replay (the arrival counters restart themselves)."""
+    """Edge-split vote: several workgroups per slice, each adding its share
+    of the rows into the accumulator the plan clears first; exact on every
+    replay (the clear and the vote's queue restart in every pass)."""
     say("vote split", rows, split, queue)
     specs = [(1280, 720, 1280, 31, False), (640, 480, 640, 32, True), (1100, 200, 1104, 33, False)]
     frames, wants = make_frames(lane, synth, oracle, specs)
