@@ -93,12 +93,22 @@ def test_plain_server_matches_alone(lane, synth, oracle):
         srv.close()
 
 
-def test_pruned_server_matches_alone(lane, synth):
-    say("serve pruned")
+PRUNED_STREAMS = {
+    # three size classes: one graph per non-empty subset of classes
+    "3 classes": [dict(W=320, H=240), dict(W=320, H=240), dict(W=640, H=480, n_theta=180, k=4),
+                  dict(W=1100, H=200)],
+    # five classes: one graph for every refill
+    "5 classes": [dict(W=320, H=240), dict(W=640, H=480, n_theta=180, k=4), dict(W=1100, H=200),
+                  dict(W=256, H=256, k=2), dict(W=400, H=120, n_theta=120), dict(W=320, H=240)],
+}
+
+
+@pytest.mark.parametrize("mix", sorted(PRUNED_STREAMS))
+def test_pruned_server_matches_alone(lane, synth, mix):
+    say("serve pruned", mix)
     from paper_2212_09460_amd.learned.model import ProposalNet, load_params
 
-    streams = [dict(W=320, H=240), dict(W=320, H=240), dict(W=640, H=480, n_theta=180, k=4),
-               dict(W=1100, H=200)]
+    streams = PRUNED_STREAMS[mix]
     P = pools(synth, streams, seed=300)
     params = load_params()
     net = ProposalNet(params)
