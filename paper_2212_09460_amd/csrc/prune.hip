@@ -16,7 +16,7 @@
 
 namespace lane {
 
-constexpr int kPruneWaves = 4;  // one wave per segment, four per workgroup
+constexpr int kPruneWaves = 4;  // a workgroup per segment, its waves on interleaved chunks
 
 __global__ void __launch_bounds__(kWave * kPruneWaves) k_prune_lists(const PruneDesc* __restrict__ descs) {
     const PruneDesc d = descs[blockIdx.y];
@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(kWave * kPruneWaves) k_prune_lists(const Prune
     __shared__ int s_delta[kPruneWaves][kTilesPerChunk];
     const ListLayout L = list_layout(d.W, d.H);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-    for (int seg = blockIdx.x * kPruneWaves + wave; seg < L.nseg; seg += gridDim.x * kPruneWaves) {
+    for (int seg = blockIdx.x; seg < L.nseg; seg += gridDim.x) {
         const int ty = seg / L.nchunk, chunk = seg - ty * L.nchunk;
         const int tx0 = chunk * kTilesPerChunk;
         const int ntx = min(L.tw - tx0, kTilesPerChunk);
@@ -72,12 +72,14 @@ __global__ void __launch_bounds__(kWave * kPruneWaves) k_prune_lists(const Prune
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // the entries, eight loads per lane in flight; an entry's tile is
-        // its x / 8 (entries of a segment lie in its own tiles)
+        // the entries, eight loads per lane in flight, chunks of 512 taken
+        // by the waves in turn (every wave has worked out the same table);
+        // an entry's tile is its x / 8 (entries of a segment lie in its own
+        // tiles)
         const int n = min((int)gld(d.list + seg), kSegCap);
         const uint32_t* src = d.list + L.off_ent + (size_t)seg * kSegCap;
         uint32_t* dst = d.pruned + L.off_ent + (size_t)seg * kSegCap;
-        for (int p0 = 0; p0 < n; p0 += 8 * kWave) {
+        for (int p0 = wave * 8 * kWave; p0 < n; p0 += kPruneWaves * 8 * kWave) {
             uint32_t e[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) e[u] = gld(src + min(p0 + u * kWave + lane, n - 1));
@@ -92,7 +94,7 @@ __global__ void __launch_bounds__(kWave * kPruneWaves) k_prune_lists(const Prune
                 if (dl != INT_MIN && (unsigned)(p + dl) < (unsigned)kSegCap) gst(dst + p + dl, e[u]);
             }
         }
-        if (lane == 0) {
+        if (wave == 0 && lane == 0) {
             gst(d.pruned + seg, (uint32_t)ftot);
             gst(d.pruned + L.off_info + seg, (uint32_t)rtot);
         }
@@ -106,10 +108,10 @@ __global__ void __launch_bounds__(kWave * kPruneWaves) k_prune_lists(const Prune
 
 using namespace lane;
 
-// grid: segments (max over the frames) x frames
+// grid: segments (max over the frames, at most 4096) x frames
 extern "C" LANE_INTERNAL hipError_t lane_launch_prune_batch(const PruneDesc* descs, int n, int max_nseg,
                                                            hipStream_t s) {
-    const int gx = (max_nseg + kPruneWaves - 1) / kPruneWaves;
+    const int gx = max(1, min(max_nseg, 4096));
     hipLaunchKernelGGL(k_prune_lists, dim3(gx, n), dim3(kWave * kPruneWaves), 0, s, descs);
     return hipGetLastError();
 }
