@@ -149,19 +149,27 @@ LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r) {
 }
 
 // LDS words a vote workgroup needs for slices of T rows: the rows back to
-// back (T x the row cap) or, when the frame is small enough for the paired
-// counters, T x ceil(span / 2) with span the r range of a slice's rows --
-// from the exact corner values, widened by 4 for the table's rounding; the
-// kernel measures the real span and picks the layout that fits.
+// back (T x the row cap) or, for a slice whose rows all bound their cell
+// pairs below 2^14 votes (vote_pair_bound on the lane_make_trig_q14 table),
+// T x ceil(span / 2) with span the r range of the slice's rows -- from the
+// exact corner values, widened by 4 for the table's rounding.  The kernel
+// measures the real span and the bound of the table it is given and picks
+// the layout that fits (another table may fall back to global memory).
 LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T) {
     const long plain = (long)T * lane_vote_row_cap(W, H, n_r);
-    if (T > n_theta || 2 * (W + H + 2) > 16383) return plain;
+    if (T > n_theta) return plain;
     const double pi = 3.14159265358979323846;
     long worst = 0;
     for (int s = 0; s * T < n_theta; ++s) {
         const int k0 = s * T < n_theta - T ? s * T : n_theta - T;
         double lo = 1e300, hi = -1e300;
+        bool pair_ok = true;
         for (int k = k0; k < k0 + T; ++k) {
+            const double a = (double)k * pi / (double)n_theta;
+            const double cq = cos(a) * 16384.0, sq = sin(a) * 16384.0;
+            const int Cq = (int)(cq >= 0 ? floor(cq + 0.5) : -floor(-cq + 0.5));
+            const int Sq = (int)(sq >= 0 ? floor(sq + 0.5) : -floor(-sq + 0.5));
+            if (vote_pair_bound(W, H, Cq, Sq) > kPairCountMax) pair_ok = false;
             const double c = cos(pi * k / n_theta), sn = sin(pi * k / n_theta);
             const double xs[4] = {0.0, (double)(W - 1), 0.0, (double)(W - 1)};
             const double ys[4] = {0.0, 0.0, (double)(H - 1), (double)(H - 1)};
@@ -172,7 +180,7 @@ LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, 
             }
         }
         const long span = (long)(floor(hi + 0.5) - floor(lo + 0.5)) + 1 + 4;
-        const long words = (span + 1) / 2 * T;
+        const long words = pair_ok && (span + 1) / 2 * T < plain ? (span + 1) / 2 * T : plain;
         worst = words > worst ? words : worst;
     }
     return worst < plain ? worst : plain;

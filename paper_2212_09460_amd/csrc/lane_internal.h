@@ -169,6 +169,32 @@ __device__ __forceinline__ int band_bits_dev(int n_theta, int k) {
     return bits;
 }
 
+// Most frame pixels (x, y) in [0, W) x [0, H) that two neighbouring r cells
+// of one theta row with table entries (C, S) can collect.  Cells u and u + 1
+// hold the pixels with x*C + y*S in one half-open interval of width 2^15:
+// on one image row y that is a run of at most ceil(2^15 / |C|) columns (all
+// W when C = 0), and only rows y with y*S inside an interval of width
+// 2^15 + (W - 1)|C| meet it, at most ceil((2^15 + (W - 1)|C|) / |S|) of them
+// (all H when S = 0).  The same holds with x and y exchanged; the smaller
+// product bounds the count.  For a rotation row (max(|C|, |S|) >= 2^14/sqrt 2)
+// this is at most 3 max(W, H).
+__host__ __device__ inline long long vote_pair_bound(int W, int H, int C, int S) {
+    const long long ac = C < 0 ? -(long long)C : C, as = S < 0 ? -(long long)S : S;
+    const long long w = W, h = H;
+    long long ym = as ? (32768 + (w - 1) * ac + as - 1) / as : h;
+    ym = ym < h ? ym : h;
+    long long per_y = ac ? (32768 + ac - 1) / ac : w;
+    ym *= per_y < w ? per_y : w;
+    long long xm = ac ? (32768 + (h - 1) * as + ac - 1) / ac : w;
+    xm = xm < w ? xm : w;
+    long long per_x = as ? (32768 + as - 1) / as : h;
+    xm *= per_x < h ? per_x : h;
+    return ym < xm ? ym : xm;
+}
+
+// The paired LDS counters keep the sum of a cell pair in 14 bits.
+constexpr long long kPairCountMax = 16383;
+
 // One frame for the line segments along its peaks.
 struct LinesDesc {
     const uint8_t* edges;  // [H][W], 255 = edge

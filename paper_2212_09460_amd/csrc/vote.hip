@@ -40,6 +40,7 @@ struct VoteLds {
     int32_t acc[LDSW];
     int lo[kMaxT], win[kMaxT], base[kMaxT];
     int fast, total, item, last;
+    int pair_ok;  // every row of the slice bounds its cell pairs below 2^14
     int il, lo_min, span;  // layout (0 rows back to back, 1 interleaved, 2 interleaved pairs),
                            // lowest r_idx of the slice, its r span
     uint32_t dropped;
@@ -74,8 +75,11 @@ __device__ __forceinline__ void lds_vote_il(VoteLds<LDSW>& L, uint32_t v, uint32
 // low - high).  Half the words of the interleaved layout for one more
 // instruction ((v & 2^14) | 1 is one v_and_or); with T = 32 rows every lane
 // of a pixel owns bank j and the wave's two pixels meet at most pairwise,
-// the fewest bank cycles a 64-lane atomic can take.  Needs every cell count
-// below 2^13 (a cell holds at most D + 2 pixels).
+// the fewest bank cycles a 64-lane atomic can take.  Exact while no cell
+// pair collects more than 2^14 - 1 votes: a slice takes this layout only
+// when every row's table entries bound its pairs below that
+// (vote_pair_bound), which holds for rotation tables on the frames the
+// paired slice sizes are planned for and fails for tables with small entries.
 template <int LDSW>
 __device__ __forceinline__ void lds_vote_il2(VoteLds<LDSW>& L, uint32_t v, uint32_t jb, int sh) {
     const uint32_t adr = ((v >> 15) << sh) | jb;
@@ -117,6 +121,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
 
     if (tid == 0) {
         sm.fast = 1;
+        sm.pair_ok = 1;
         sm.dropped = 0;
     }
     __syncthreads();
@@ -136,6 +141,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         sm.lo[tid] = lo;
         sm.win[tid] = hi - lo + 1;
         if (lo < 0 || hi >= d.n_r) sm.fast = 0;
+        if (vote_pair_bound(d.W, d.H, C, S) > kPairCountMax) sm.pair_ok = 0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -151,8 +157,8 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
         const int span = hi_max - lo_min + 1;
         auto fits = [&](int w) { return w <= LDSW; };
         const int il_words = span * T, il2_words = ((span + 1) >> 1) * T;
-        // a cell counts at most D + 2 pixels (D = the frame diagonal, below W + H)
-        const bool il2_ok = 2 * (d.W + d.H + 2) <= 16383 && fits(il2_words);
+        // paired counters only where no row's cell pair can reach 2^14 votes
+        const bool il2_ok = sm.pair_ok != 0 && fits(il2_words);
         const int mode = (T >= 32 && il2_ok) ? 2 : fits(il_words) ? 1 : il2_ok ? 2 : 0;
         sm.il = mode;
         sm.lo_min = lo_min;

@@ -109,11 +109,10 @@ def test_vote_rows_override(lane, synth, oracle, rows):
 @pytest.mark.parametrize("rows", [4, 8])
 def test_vote_paired_cells_dense_edges(lane, synth, oracle, rows):
     """Every interior pixel an edge (columns 0, 0, 255, 255 repeating) on a
-    4094 x 4094 frame, the largest square whose cell pairs the paired LDS
-    layout may count (2 (W + H + 2) <= 16383).  With 16 angles the slices
-    around 45 degrees span about 5800 r cells, too wide for one word per cell
-    at 4 or 8 rows, so the paired layout votes them; a cell pair there gets
-    about 11600 votes."""
+    4094 x 4094 frame.  With 16 angles the slices around 45 degrees span
+    about 5800 r cells, too wide for one word per cell at 4 or 8 rows, so the
+    paired layout votes them (the Q14 rows there bound a cell pair by
+    3 x 4094 = 12282 < 2^14 pixels); a cell pair gets about 11600 votes."""
     W = H = 4094
     say("paired cells, dense edges", W, H, "rows", rows)
     img = np.tile(np.array([0, 0, 255, 255], np.uint8), (H, W // 4 + 1))[:, :W].copy()
@@ -314,4 +313,42 @@ def test_split_vote_pruned_lists(lane, synth, oracle, rows, split, queue):
     torch.cuda.synchronize()
     check([frames[i] for i in (0, 2, 3, 4)], [wants[i] for i in (0, 2, 3, 4)])
     assert (frames[1].acc == -7).all() and (frames[1].peaks == -5).all()
+    b.close()
+
+
+def small_table(n, q):
+    """Rows of cos/sin rounded to q fractional bits (q = 0: C = S = 1)."""
+    if q == 0:
+        return np.ones(n, np.int16), np.ones(n, np.int16)
+    a = np.arange(n) * np.pi / n
+    return (np.round(np.cos(a) * 2 ** q).astype(np.int16),
+            np.round(np.sin(a) * 2 ** q).astype(np.int16))
+
+
+@pytest.mark.parametrize("rows", [32, 64])
+@pytest.mark.parametrize("q", [8, 6, 0])
+def test_vote_small_tables_many_rows(lane, synth, oracle, q, rows):
+    """Tables with small entries (Q8, Q6, C = S = 1) put thousands of pixels
+    in neighbouring r cells; at 32 and 64 rows per workgroup a slice must not
+    take the paired counters then (their 14-bit pair sum would wrap).  A road
+    frame at 640 x 480 and a dense 200 x 200 frame (every interior pixel an
+    edge), bit-exact against the oracle."""
+    say("small table q", q, "rows", rows)
+    n = 360
+    C, S = small_table(n, q)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    road = synth.road(640, 480, 7)
+    dense = np.tile(np.array([0, 0, 255, 255], np.uint8), (200, 50)).copy()
+    frames, wants = [], []
+    for img in (road, dense):
+        H, W = img.shape
+        frames.append(lane.FrameBuffers(torch.from_numpy(img).cuda(), W, n, 8, Cd, Sd))
+        wants.append(oracle.pipeline(img, C, S, 8))
+    pair = max(int((w["acc"][:, :-1].astype(np.int64) + w["acc"][:, 1:]).max()) for w in wants)
+    assert pair > 16383
+    b = lane.Batch(frames, vote_rows=rows)
+    for rep in range(2):
+        scribble(frames)
+        b.launch()
+        check(frames, wants)
     b.close()
