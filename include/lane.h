@@ -194,6 +194,25 @@ int lane_hough_peaks(const int32_t *acc, int32_t n_theta, int32_t n_r, int32_t r
                      int32_t *theta_idx, int32_t *r_idx, int32_t *votes, int32_t *count,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Peak search that allocates nothing and takes no workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that must not call the allocator, harnesses that forbid it).  Same
+ * arguments, results and error codes as lane_hough_peaks without ws /
+ * ws_bytes.  The block keys go to a fixed device array of the library, one
+ * copy per GPU, held until the process ends: at most
+ * lane_hough_peaks_noalloc_max_bytes() bytes (64 KiB, which every
+ * accumulator the peak search accepts fits; a larger need returns
+ * LANE_E_WS).  Its address on a device is looked up on the first call there
+ * (LANE_E_DEVICE if that fails).  Every call on one GPU shares that array:
+ * calls that overlap in time on one GPU (two streams, two threads) race and
+ * must be serialised by the caller; calls in order on one stream are safe
+ * (each call rewrites every key it reads). */
+size_t lane_hough_peaks_noalloc_max_bytes(void);
+int lane_hough_peaks_noalloc(const int32_t *acc, int32_t n_theta, int32_t n_r, int32_t r_offset,
+                             int32_t k, int32_t h_theta, int32_t h_r, int32_t min_votes,
+                             int32_t *theta_idx, int32_t *r_idx, int32_t *votes, int32_t *count,
+                             void *stream);
+
 /* Line segments along peaks: the lane lines drawn from the Hough peaks
  * (Sec. 1 step 4; Sec. 5, "Hough lines" and Fig. 12; the paper leaves the
  * step to MATLAB without an algorithm, so it is specified here).  For peak j

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "liblane.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["sobel.hip", "vote.hip", "prune.hip", "vote_pair.hip", "peaks.hip", "lines.hip", "canny.hip", "progressive.hip", "capi.hip",
+SOURCES = ["sobel.hip", "vote.hip", "prune.hip", "vote_pair.hip", "peaks.hip", "peaks_noalloc.hip", "lines.hip", "canny.hip", "progressive.hip", "capi.hip",
            "batch.hip",
            "cnn.hip", "serve.hip"]
 ARCH = "gfx950"

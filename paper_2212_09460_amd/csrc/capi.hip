@@ -291,39 +291,51 @@ int lane_hough_peaks_workspace_size(int32_t n_theta, int32_t n_r, size_t* bytes)
     return LANE_OK;
 }
 
-int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r_offset, int32_t k,
-                     int32_t h_theta, int32_t h_r, int32_t min_votes, int32_t* theta_idx,
-                     int32_t* r_idx, int32_t* votes, int32_t* count, void* ws, size_t ws_bytes,
-                     void* stream) {
-    if (!acc || !theta_idx || !r_idx || !votes || !count || !ws || n_theta <= 0 || n_r <= 0 ||
-        k < 1 || k > 1024 || h_theta < 0 || h_r < 0)
+// Validates the arguments of a peak search and fills *d (all but the
+// workspace pointer); *need receives the workspace bytes.
+LANE_INTERNAL int lane_peaks_prepare(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r_offset,
+                                     int32_t k, int32_t h_theta, int32_t h_r, int32_t min_votes,
+                                     int32_t* theta_idx, int32_t* r_idx, int32_t* votes, int32_t* count,
+                                     PeaksDesc* d, size_t* need) {
+    if (!acc || !theta_idx || !r_idx || !votes || !count || n_theta <= 0 || n_r <= 0 || k < 1 ||
+        k > 1024 || h_theta < 0 || h_r < 0)
         return LANE_E_ARG;
-    if (!aligned16(ws)) return LANE_E_ARG;
     if ((int64_t)n_theta * n_r > 0x7FFFFFFFll || h_theta > 1000000 || h_r > 1000000 ||
         n_theta > kPeaksMaxBlocksLds)
         return LANE_E_SIZE;
     if (n_r != 2 * r_offset + 1) return LANE_E_RANGE;
-    size_t need = 0;
-    lane_hough_peaks_workspace_size(n_theta, n_r, &need);
-    if (ws_bytes < need) return LANE_E_WS;
+    lane_hough_peaks_workspace_size(n_theta, n_r, need);
+    memset(d, 0, sizeof(*d));
+    d->acc = acc;
+    d->n_theta = n_theta;
+    d->n_r = n_r;
+    d->r_offset = r_offset;
+    d->k = k;
+    d->h_theta = h_theta;
+    d->h_r = h_r;
+    d->min_votes = min_votes;
+    d->theta_idx = theta_idx;
+    d->r_idx = r_idx;
+    d->votes = votes;
+    d->count = count;
+    d->block_log2 = lane_peaks_block_log2(n_theta, n_r);
+    d->nbr = lane_peaks_blocks_per_row(n_r, d->block_log2);
+    d->n_blocks = n_theta * d->nbr;
+    return LANE_OK;
+}
+
+int lane_hough_peaks(const int32_t* acc, int32_t n_theta, int32_t n_r, int32_t r_offset, int32_t k,
+                     int32_t h_theta, int32_t h_r, int32_t min_votes, int32_t* theta_idx,
+                     int32_t* r_idx, int32_t* votes, int32_t* count, void* ws, size_t ws_bytes,
+                     void* stream) {
+    if (!ws || !aligned16(ws)) return LANE_E_ARG;
     PeaksDesc d;
-    memset(&d, 0, sizeof(d));
-    d.acc = acc;
-    d.n_theta = n_theta;
-    d.n_r = n_r;
-    d.r_offset = r_offset;
-    d.k = k;
-    d.h_theta = h_theta;
-    d.h_r = h_r;
-    d.min_votes = min_votes;
-    d.theta_idx = theta_idx;
-    d.r_idx = r_idx;
-    d.votes = votes;
-    d.count = count;
+    size_t need = 0;
+    const int st = lane_peaks_prepare(acc, n_theta, n_r, r_offset, k, h_theta, h_r, min_votes,
+                                      theta_idx, r_idx, votes, count, &d, &need);
+    if (st != LANE_OK) return st;
+    if (ws_bytes < need) return LANE_E_WS;
     d.keys = (unsigned long long*)ws;
-    d.block_log2 = lane_peaks_block_log2(n_theta, n_r);
-    d.nbr = lane_peaks_blocks_per_row(n_r, d.block_log2);
-    d.n_blocks = n_theta * d.nbr;
     return dev_status(lane_launch_peaks(&d, (hipStream_t)stream));
 }
 

@@ -43,6 +43,10 @@ _vote_paired = _sig("lane_hough_vote_paired", [_vp, _i32, _i32, _vp, _vp, _i32, 
 _peaks_ws = _sig("lane_hough_peaks_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _peaks = _sig("lane_hough_peaks", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp,
                                     _vp, _vp, _sz, _vp])
+_peaks_noalloc = _sig("lane_hough_peaks_noalloc", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32,
+                                                  _vp, _vp, _vp, _vp, _vp])
+_lib.lane_hough_peaks_noalloc_max_bytes.restype = _sz
+_lib.lane_hough_peaks_noalloc_max_bytes.argtypes = []
 _canny_ws = _sig("lane_canny_workspace_size", [_i32, _i32, ctypes.POINTER(_sz)])
 _canny = _sig("lane_canny", [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
                               _vp])
@@ -79,7 +83,8 @@ LANE_BORDER_ZERO_MASKRING = 1
 EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_offset",
            "lane_edge_list_size", "lane_sobel_binarize", "lane_edges_to_list", "lane_hough_vote",
            "lane_hough_vote_paired",
-           "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_lines",
+           "lane_hough_peaks_workspace_size", "lane_hough_peaks", "lane_hough_peaks_noalloc",
+           "lane_hough_peaks_noalloc_max_bytes", "lane_hough_lines",
            "lane_canny_workspace_size", "lane_canny", "lane_hough_progressive_layout",
            "lane_hough_progressive", "lane_batch_create",
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
@@ -228,6 +233,28 @@ def hough_peaks(acc: torch.Tensor, r_offset: int, k: int, h_theta: int | None = 
                   int(min_votes), _p(t), _p(r), _p(v), _p(c), _p(ws), ws.numel() * 8,
                   _stream(stream)), "lane_hough_peaks")
     return t, r, v, c
+
+
+def hough_peaks_noalloc(acc: torch.Tensor, r_offset: int, k: int, h_theta: int | None = None,
+                        h_r: int | None = None, min_votes: int = 1, out=None, stream=None):
+    """lane_hough_peaks_noalloc: the peak search with the library's own fixed
+    device scratch (no workspace).  Returns (theta_idx, r_idx, votes, count)."""
+    n_theta, n_r = acc.shape
+    if h_theta is None:
+        h_theta = max(1, -(-n_theta // 100))
+    if h_r is None:
+        h_r = max(1, -(-n_r // 100))
+    if out is None:
+        out = torch.empty((3 * k + 1,), dtype=torch.int32, device=acc.device)
+    t, r, v, c = out[0:k], out[k:2 * k], out[2 * k:3 * k], out[3 * k:3 * k + 1]
+    _check(_peaks_noalloc(_p(acc), n_theta, n_r, int(r_offset), int(k), int(h_theta), int(h_r),
+                          int(min_votes), _p(t), _p(r), _p(v), _p(c), _stream(stream)),
+           "lane_hough_peaks_noalloc")
+    return t, r, v, c
+
+
+def peaks_noalloc_max_bytes() -> int:
+    return int(_lib.lane_hough_peaks_noalloc_max_bytes())
 
 
 def progressive_params(n_theta: int, n_r: int, **over) -> dict:

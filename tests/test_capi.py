@@ -18,7 +18,7 @@ E_ARG, E_SIZE, E_RANGE, E_WS, E_UNSUP = -1, -2, -3, -4, -6
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(lane_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(lane_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -106,6 +106,14 @@ def test_argument_errors_before_launch(lib):
     assert pk(P, 180, 11, 5, 0, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_ARG   # k < 1
     assert pk(P, 180, 12, 5, 2, 1, 1, 1, P, P, P, P, P, 1 << 20, None) == E_RANGE  # n_r != 2D+1
     assert pk(P, 180, 11, 5, 2, 1, 1, 1, P, P, P, P, P, 8, None) == E_WS
+    pn = lib.lane_hough_peaks_noalloc
+    pn.argtypes = pk.argtypes[:12] + [ctypes.c_void_p]
+    assert pn(P, 180, 11, 5, 0, 1, 1, 1, P, P, P, P, None) == E_ARG    # k < 1
+    assert pn(None, 180, 11, 5, 2, 1, 1, 1, P, P, P, P, None) == E_ARG  # no accumulator
+    assert pn(P, 180, 12, 5, 2, 1, 1, 1, P, P, P, P, None) == E_RANGE  # n_r != 2D+1
+    assert pn(P, 1 << 16, 11, 5, 2, 1, 1, 1, P, P, P, P, None) == E_SIZE
+    lib.lane_hough_peaks_noalloc_max_bytes.restype = ctypes.c_size_t
+    assert lib.lane_hough_peaks_noalloc_max_bytes() == 8192 * 8
     ln = lib.lane_hough_lines
     ln.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
