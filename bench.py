@@ -7,15 +7,24 @@ lanes with the inner two dashed, 200 clutter segments, 2 % salt, threshold
 The frames are resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput (Mpix/s; frames/s beside it), the
-roofline of the dominant kernel (the vote) measured live with HIP events on
-the launch stream, the Sobel pass's HBM roofline, single-frame latency, the
-serving latency (p50/p99 over 16 camera streams with Poisson arrivals,
-continuous batching, plain and pruned path), and the CPU oracle timed on a
-bounded sample of the same workload, single-threaded and in one process per
-usable core.  Beside it, on 64 other frames: Sobel
-against the Canny detector, the coarse-to-fine Hough and the angle-paired
-vote against the plain vote, and the oracle timed step by step on two of
-those frames.
+roofline of the dominant kernel (the vote, LDS-atomic bound) measured live
+with HIP events on the launch stream beside the rate of a conflict-free LDS
+increment probe, the Sobel pass's HBM roofline, single-frame latency, the
+mixed-resolution batch (64 frames, 16 each at 640x480, 1280x720, 1920x1080
+and 3840x2160, 2-6 lanes) in one autotuned graph launch, the serving latency
+(p50/p99 over 16 camera streams with Poisson arrivals, continuous batching,
+plain and pruned path, 60 s each), and the CPU oracle timed on a bounded
+sample of the same workload, single-threaded and in one process per usable
+core.  Beside it, on 64 other frames: Sobel against the Canny detector, the
+coarse-to-fine Hough and the angle-paired vote against the plain vote, and
+the oracle timed step by step on two of those frames.
+
+What is timed is also checked: the oracle runs of the CPU-baseline leg are
+compared with the GPU outputs of the timed plans (every peak of the 256-frame
+plan, the accumulators of its 16 distinct frames, every accumulator and peak
+of the 64-frame mixed plan), and every served result is compared with its
+frame alone through the single-frame entry points.  Any mismatch sets
+"parity": {"ok": false} and the exit status 1.
 """
 from __future__ import annotations
 
@@ -38,6 +47,11 @@ CUS, CLOCK_GHZ = 256, 2.4
 LDS_BANK_PEAK_GVOTES = CUS * 32 * CLOCK_GHZ
 
 
+def note(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,9 +69,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--no-tune-cache", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=15.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of each serving run, plain and pruned (0 = skip)")
-    ap.add_argument("--serve-pool", type=int, default=32, help="pre-generated frames per stream")
+    ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per stream")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="run the 64-frame mixed-resolution batch leg (0 = skip)")
     ap.add_argument("--edge-frames", type=int, default=64,
                     help="frames of the Sobel vs Canny comparison (0 = skip)")
     return ap.parse_args()
@@ -139,16 +155,39 @@ def oracle_worker(budget_s, first_seed):
     print(json.dumps({"frames": n, "seconds": time.perf_counter() - t0}), flush=True)
 
 
-def cpu_all_cores(procs, budget_s):
-    """The same untuned oracle, one frame per process at a time, in `procs`
-    processes started together: the host's throughput over independent
-    frames.  Frame generation happens before the start."""
+def oracle_mixed_worker(indices):
+    """One process of the mixed-batch oracle leg (no torch, no GPU): makes
+    frames `indices` of the 64-frame mixed batch, reports ready, waits for
+    the go line, runs the oracle over them and prints, per frame, its edge
+    count, dropped votes, peaks and the SHA-256 of its accumulator, with the
+    time taken."""
+    import hashlib
+
+    import oracle
+    from paper_2212_09460_amd import synth
+
+    imgs = [synth.mixed_batch(i) for i in indices]
+    C, S = synth.trig_q14(N_THETA)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    t0 = time.perf_counter()
+    res = [oracle.pipeline(im, C, S, TOPK) for im in imgs]
+    dt = time.perf_counter() - t0
+    out = [{"i": i, "px": int(im.shape[0] * im.shape[1]), "n_edges": r["n_edges"],
+            "dropped": r["dropped"], "count": r["count"], "theta_idx": r["theta_idx"].tolist(),
+            "r_idx": r["r_idx"].tolist(), "votes": r["votes"].tolist(),
+            "acc_sha": hashlib.sha256(r["acc"].tobytes()).hexdigest()}
+           for i, im, r in zip(indices, imgs, res)]
+    print(json.dumps({"frames": out, "seconds": dt}), flush=True)
+
+
+def run_workers(cmds, env):
+    """Starts the worker processes, waits until all are ready, starts them
+    together and returns their JSON results."""
     import subprocess
 
-    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--oracle-worker", str(budget_s)]
-    env = dict(os.environ, OMP_NUM_THREADS="1")
-    ps = [subprocess.Popen(cmd + [str(1000 + 2 * i)], stdin=subprocess.PIPE,
-                           stdout=subprocess.PIPE, text=True, env=env) for i in range(procs)]
+    ps = [subprocess.Popen(c, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+          for c in cmds]
     try:
         for p in ps:
             if p.stdout.readline().strip() != "ready":
@@ -158,12 +197,151 @@ def cpu_all_cores(procs, budget_s):
             p.stdin.flush()
         res = [json.loads(p.stdout.readline()) for p in ps]
         for p in ps:
-            if p.wait(timeout=120) != 0:
+            if p.wait(timeout=300) != 0:
                 raise RuntimeError("oracle worker failed")
     finally:
         for p in ps:
             if p.poll() is None:
                 p.kill()
+    return res
+
+
+def lds_probe():
+    """Rate of LDS atomic increments (ds_add_u32) on this GPU from the probe
+    library: conflict-free (the 64 lanes of an instruction on 64 consecutive
+    words) and hashed addresses over a 64 KB table, the best over 1, 2 and 4
+    workgroups of 1024 threads per CU; in G increments per second."""
+    import ctypes
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2212_09460_amd", "liblaneprobe.so"))
+    f = lib.lane_probe_lds_add
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_uint64)]
+    out = {}
+    for random, name in ((0, "conflict_free"), (1, "hashed")):
+        best = 0.0
+        for groups in (CUS, 2 * CUS, 4 * CUS):
+            steps = 1000
+            rate, chk = ctypes.c_double(0.0), ctypes.c_uint64(0)
+            if f(groups, steps, random, ctypes.byref(rate), ctypes.byref(chk)) != 0:
+                raise RuntimeError("LDS probe failed")
+            if chk.value != groups * 1024 * 16 * steps:
+                raise RuntimeError("LDS probe lost increments")
+            best = max(best, rate.value)
+        out[name] = round(best / 1e9, 1)
+    return out
+
+
+def mixed_leg(args, torch, lane, synth, stream):
+    """The mixed-resolution batch: 64 frames (16 each at 640x480, 1280x720,
+    1920x1080 and 3840x2160, 2..6 lanes, 360 theta, top-8) resident in HBM,
+    one graph launch per step, the plan's setting from the autotuner run on
+    these frames.  Returns the figures and the GPU outputs of one clean
+    launch (per frame: accumulator SHA-256, peaks, counters) for the check."""
+    import hashlib
+
+    dev = torch.device("cuda:0")
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        imgs = list(ex.map(synth.mixed_batch, range(64)))
+    C, S = synth.trig_q14(N_THETA)
+    Cd, Sd = torch.from_numpy(C).to(dev), torch.from_numpy(S).to(dev)
+    frames = [lane.FrameBuffers(torch.from_numpy(im).to(dev), im.shape[1], N_THETA, TOPK, Cd, Sd)
+              for im in imgs]
+    tune, vote_ms, sobel_ms = lane.tune_batch(frames)
+    b = lane.Batch(frames, tune=tune)
+    b.launch(stream)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        b.launch(stream)
+    torch.cuda.synchronize()
+    ms = event_time(torch, lambda: b.launch(stream), args.steps, stream)
+    for f in frames:  # the check reads one clean launch's outputs
+        f.acc.fill_(-1)
+        f.peaks.fill_(-2)
+    b.launch(stream)
+    torch.cuda.synchronize()
+    gpu = [{"acc_sha": hashlib.sha256(f.acc.cpu().numpy().tobytes()).hexdigest(),
+            "peaks": f.peaks.cpu().numpy(), "counters": f.counters.cpu().numpy()} for f in frames]
+    px = sum(im.shape[0] * im.shape[1] for im in imgs)
+    edges = sum(int(g["counters"][0]) for g in gpu)
+    out = {"workload": "64 seeded road frames, 16 each at 640x480, 1280x720, 1920x1080 and "
+                       "3840x2160 with 2-6 lanes, clutter and salt; threshold 128, ring masked; "
+                       "360 theta, Q14 trig, int32 accumulators; top-8 peaks",
+           "launch": "one HIP graph per step", "steps": args.steps,
+           "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpix/s",
+           "frames_per_s": round(64 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "megapixels_per_step": round(px / 1e6, 3), "edge_fraction": round(edges / px, 4),
+           "votes_per_step": edges * N_THETA,
+           "tuned": dict(lane.tune_dict(tune), vote_ms=round(vote_ms, 4), sobel_ms=round(sobel_ms, 4))}
+    b.close()
+    del frames
+    torch.cuda.empty_cache()
+    return out, gpu
+
+
+def check_plan_256(oracle_res, gpu256):
+    """Every frame's peaks, edge count and dropped votes of the timed
+    256-frame plan against the oracle's result for its pool frame, and the
+    full accumulators of the first POOL frames."""
+    bad = []
+    k = TOPK
+    for i in range(gpu256["peaks"].shape[0]):
+        w = oracle_res[i % POOL]
+        pk, cn = gpu256["peaks"][i], gpu256["counters"][i]
+        ok = (int(pk[3 * k]) == w["count"] and (pk[0:k] == w["theta_idx"]).all()
+              and (pk[k:2 * k] == w["r_idx"]).all() and (pk[2 * k:3 * k] == w["votes"]).all()
+              and int(cn[0]) == w["n_edges"] and int(cn[1]) == w["dropped"])
+        if ok and i < len(gpu256["acc"]):
+            ok = bool((gpu256["acc"][i] == w["acc"]).all())
+        if not ok:
+            bad.append(i)
+    return {"frames_peaks_checked": int(gpu256["peaks"].shape[0]),
+            "accumulators_checked": len(gpu256["acc"]), "mismatched_frames": bad[:16],
+            "ok": not bad}
+
+
+def check_mixed(oracle_frames, gpu):
+    bad = []
+    k = TOPK
+    for w in oracle_frames:
+        g = gpu[w["i"]]
+        pk, cn = g["peaks"], g["counters"]
+        ok = (g["acc_sha"] == w["acc_sha"] and int(pk[3 * k]) == w["count"]
+              and pk[0:k].tolist() == w["theta_idx"] and pk[k:2 * k].tolist() == w["r_idx"]
+              and pk[2 * k:3 * k].tolist() == w["votes"] and int(cn[0]) == w["n_edges"]
+              and int(cn[1]) == w["dropped"])
+        if not ok:
+            bad.append(w["i"])
+    return {"frames_checked": len(oracle_frames), "mismatched_frames": bad[:16],
+            "ok": not bad and len(oracle_frames) == len(gpu)}
+
+
+def cpu_mixed(procs, gpu):
+    """The oracle over the 64-frame mixed batch in `procs` processes (frame
+    i in process i mod procs, so each holds sizes of every kind), started
+    together: the host's time for the batch, and the check of the GPU plan."""
+    procs = max(1, min(procs, 64))
+    cmds = [[sys.executable, "-u", os.path.abspath(__file__), "--oracle-mixed-worker",
+             ",".join(str(i) for i in range(p, 64, procs))] for p in range(procs)]
+    res = run_workers(cmds, dict(os.environ, OMP_NUM_THREADS="1"))
+    frames = [f for r in res for f in r["frames"]]
+    span = max(r["seconds"] for r in res)
+    px = sum(f["px"] for f in frames)
+    return ({"value": round(px / span / 1e6, 3), "unit": "Mpix/s", "cores": procs,
+             "frames_per_s": round(len(frames) / span, 3),
+             "sample": f"the 64-frame mixed batch once, frame i in process i mod {procs} "
+                       f"(single-threaded oracle processes started together), {span:.1f} s"},
+            check_mixed(frames, gpu))
+
+
+def cpu_all_cores(procs, budget_s):
+    """The same untuned oracle, one frame per process at a time, in `procs`
+    processes started together: the host's throughput over independent
+    frames.  Frame generation happens before the start."""
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--oracle-worker", str(budget_s)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = run_workers([cmd + [str(1000 + 2 * i)] for i in range(procs)], env)
     frames = sum(r["frames"] for r in res)
     span = max(r["seconds"] for r in res)
     return {"value": round(frames * W * H / span / 1e6, 3), "unit": "Mpix/s", "cores": procs,
@@ -172,12 +350,18 @@ def cpu_all_cores(procs, budget_s):
                       f"processes started together, {span:.1f} s"}
 
 
-def cpu_baseline(pool, C, S, budget_s, procs):
+def cpu_baseline(pool, C, S, budget_s, procs, gpu256=None, mixed_gpu=None):
+    """The oracle timed on the host (single-threaded on the 1080p workload;
+    all cores on the same workload and on the mixed batch).  Its results are
+    also the reference the timed GPU plans are checked against."""
     import oracle
 
     n, px, t0 = 0, 0, time.perf_counter()
+    first = {}
     while time.perf_counter() - t0 < budget_s and n < 60:
-        oracle.pipeline(pool[n % len(pool)], C, S, TOPK)
+        j = n % len(pool)
+        r = oracle.pipeline(pool[j], C, S, TOPK)
+        first.setdefault(j, r)
         n += 1
         px += W * H
     dt = time.perf_counter() - t0
@@ -186,10 +370,18 @@ def cpu_baseline(pool, C, S, budget_s, procs):
                      f"vote over 360 theta, top-8 peaks), single-threaded C oracle, "
                      f"{dt:.1f} s", "frames_per_s": round(n / dt, 4),
            "host_cpu": host_cpu_model(), "host_usable_cores": usable_cores()}
+    checks = {}
+    if gpu256 is not None:
+        for j in range(len(pool)):  # untimed: pool frames the budget did not reach
+            if j not in first:
+                first[j] = oracle.pipeline(pool[j], C, S, TOPK)
+        checks["plan_1080p_x256"] = check_plan_256(first, gpu256)
     procs = min(procs, usable_cores())
     if procs > 1:
         out["all_cores"] = cpu_all_cores(procs, budget_s)
-    return out
+    if mixed_gpu is not None:
+        out["mixed_batch"], checks["mixed_64"] = cpu_mixed(max(procs, 1), mixed_gpu)
+    return out, checks
 
 
 def edge_detectors(n_frames):
@@ -371,13 +563,16 @@ def serving(args):
     res = {"streams": "8x1280x720 + 6x1920x1080 + 2x3840x2160, Poisson arrivals 30 Hz each",
            "seconds": args.serve_seconds}
     pools = None
+    res["pool_frames_per_stream"] = args.serve_pool
     for pruned in (False, True):
+        note(f"serving, {'pruned' if pruned else 'plain'}: {args.serve_seconds} s")
         r, pools = serve.run(args.serve_seconds, pruned=pruned, pool=args.serve_pool, pools=pools,
-                             verbose=False)
+                             verbose=False, verify=True)
+        note(f"serving done: p50 {r['p50_ms']:.4f} ms, p99 {r['p99_ms']:.4f} ms, verified {r['verified']}")
         res["pruned" if pruned else "plain"] = {
             k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
             if k in ("p50_ms", "p99_ms", "max_ms", "frames_per_s", "gpx_per_s", "completed",
-                     "dropped", "mean_batch_frames", "per_size")}
+                     "dropped", "mean_batch_frames", "per_size", "verified")}
     res["p99_pruned_over_plain"] = round(res["pruned"]["p99_ms"] / res["plain"]["p99_ms"], 4)
     return res
 
@@ -398,6 +593,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    note("generating the 1080p pool")
     pool = gen_pool(synth)
     C, S = synth.trig_q14(N_THETA)
     Cd, Sd = torch.from_numpy(C).to(dev), torch.from_numpy(S).to(dev)
@@ -411,6 +607,7 @@ def main():
         tune_info = lane.tune_dict(tune)
     else:
         tune, tune_info = tuner.tuned(pool_d[0], N_THETA, B, W, use_cache=not args.no_tune_cache)
+    note(f"tuned: {tune_info}")
     frames = []
     for i in range(B):
         img = torch.empty((H, W), dtype=torch.uint8, device=dev)
@@ -428,6 +625,7 @@ def main():
     t0 = time.perf_counter()
     ms_step = event_time(torch, lambda: batch.launch(stream), args.steps, stream)
     wall = time.perf_counter() - t0
+    note(f"timed {args.steps} steps of {B} frames: {ms_step:.4f} ms per step")
 
     # per-stage times (same kernels, launched one stage at a time)
     stage_iters = max(3, args.steps // 2)
@@ -440,6 +638,8 @@ def main():
     batch.launch(stream)
     torch.cuda.synchronize()
     counters = torch.stack([f.counters for f in frames]).cpu().numpy()
+    gpu256 = {"peaks": torch.stack([f.peaks for f in frames]).cpu().numpy(), "counters": counters,
+              "acc": [frames[i].acc.cpu().numpy() for i in range(min(POOL, B))]}
     n_edges = counters[:, 0].astype(np.int64)
     dropped = int(counters[:, 1].sum())
     votes = int(n_edges.sum()) * N_THETA
@@ -512,6 +712,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    probe = lds_probe()
+    note(f"LDS increment probe (G/s): {probe}")
     value = px / (ms_step * 1e-3) / 1e6
     out = {
         "metric": METRIC,
@@ -536,9 +738,12 @@ def main():
         "dropped_votes": dropped,
         "stage_ms": {"sobel": round(t_sobel, 4), "vote": round(t_vote, 4),
                      "peaks": round(t_peaks, 4)},
-        "roofline": {"bound": "alu", "kernel": "k_vote_batch", "achieved": round(vote_gvotes, 1),
+        "roofline": {"bound": "lds", "kernel": "k_vote_batch", "achieved": round(vote_gvotes, 1),
                      "peak": round(LDS_BANK_PEAK_GVOTES, 1), "unit": "Gvote/s",
                      "frac": round(vote_gvotes / LDS_BANK_PEAK_GVOTES, 4),
+                     "peak_measured": probe["conflict_free"],
+                     "frac_of_measured": round(vote_gvotes / probe["conflict_free"], 4),
+                     "probe_gadds_per_s": probe,
                      "traffic": profiled_traffic("k_vote_batch", "vote.hip") if B == 256 else None,
                      "votes_per_launch": votes},
         "roofline_sobel": {"bound": "hbm", "kernel": "k_sobel_batch",
@@ -557,17 +762,35 @@ def main():
     batch.close()
     del frames, pool_d
     torch.cuda.empty_cache()
+    mixed_gpu = None
+    if args.mixed:
+        note("mixed-resolution batch: generate, tune, time")
+        out["mixed_batch"], mixed_gpu = mixed_leg(args, torch, lane, synth, stream)
+        note(f"mixed batch: {out['mixed_batch']['ms_per_step']} ms per step")
     if args.edge_frames > 0:
+        note("edge detectors, coarse-to-fine Hough, paired vote")
         out["edge_detectors"] = edge_detectors(args.edge_frames)
     if args.serve_seconds > 0:
         out["serving"] = serving(args)
+    checks = {}
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(pool, C, S, args.cpu_seconds, args.cpu_procs)
+        note("CPU oracle: single thread, all cores, mixed batch (and the checks)")
+        out["cpu_baseline"], checks = cpu_baseline(pool, C, S, args.cpu_seconds, args.cpu_procs,
+                                                   gpu256, mixed_gpu)
+    if args.serve_seconds > 0:
+        for mode in ("plain", "pruned"):
+            v = out["serving"][mode]["verified"]
+            checks["serving_" + mode] = dict(v, ok=v["mismatches"] == 0 and v["checked"] > 0)
+    out["parity"] = dict(checks, ok=all(c["ok"] for c in checks.values()) if checks else None)
     print(json.dumps(out), flush=True)
+    if checks and not out["parity"]["ok"]:
+        sys.exit(1)
 
 
 if __name__ == "__main__":
     if len(sys.argv) == 4 and sys.argv[1] == "--oracle-worker":
         oracle_worker(float(sys.argv[2]), int(sys.argv[3]))
+    elif len(sys.argv) == 3 and sys.argv[1] == "--oracle-mixed-worker":
+        oracle_mixed_worker([int(x) for x in sys.argv[2].split(",")])
     else:
         main()

@@ -412,6 +412,13 @@ int lane_tune_run(const uint8_t *sample, int32_t W, int32_t H, int32_t pitch, in
                   int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune *out,
                   float *ms_opt);
 
+/* Set-up call: the same sweep on the caller's own frames (any mix of sizes;
+ * the plans it times write their outputs), with one more vote setting,
+ * vote_rows = 0 (each frame takes its own default rows: the per-resolution
+ * choice for mixed batches).  Arguments of every frame as for
+ * lane_batch_create; ms_opt as for lane_tune_run. */
+int lane_tune_batch(const lane_frame *frames, int32_t n, lane_tune *out, float *ms_opt);
+
 /* ---------------------------------------------------- learned proposal
  * A small CNN predicts, per 8x8 tile, whether the tile carries lane votes
  * and which theta bands they fall in, so the vote can skip the rest (task

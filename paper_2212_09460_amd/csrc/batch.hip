@@ -659,6 +659,76 @@ float time_stage(lane_batch* b, int stage, int iters, hipStream_t s, hipEvent_t 
     return ms / (float)iters;
 }
 
+// Sweeps the vote's rows per workgroup (T, capped per frame at what its
+// slices fit) and work distribution, then the Sobel strip height and
+// persistent grid, on plans over `frames`, timing each stage alone; the
+// fastest setting goes to *out.  per_frame_default adds T = 0 (each frame
+// its own default rows, the choice for mixed sizes) to the sweep.
+int tune_frames(const lane_frame* frames, int n_frames, int tmax, bool per_frame_default,
+                lane_tune* out, float* ms_opt) {
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LANE_E_DEVICE;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    lane_tune best = {tmax, -1, 0, 0, 0};
+    float best_vote = 1e30f, best_sobel = 1e30f;
+    int status = LANE_OK;
+    std::vector<int> rows;
+    if (per_frame_default) rows.push_back(0);
+    for (int T = tmax; T >= 1 && T * 16 >= tmax; T >>= 1) rows.push_back(T);
+    // theta rows per vote workgroup x work distribution
+    for (int T : rows) {
+        for (int q = 0; q <= 1; ++q) {
+            lane_tune t = {T, q, 0, 0, 0};
+            lane_batch* b = nullptr;
+            status = lane_batch_create(frames, n_frames, &t, &b);
+            if (status != LANE_OK) break;
+            enqueue_stage(b, 0, st);
+            enqueue_stage(b, 1, st);
+            const float ms = time_stage(b, 2, 3, st, e0, e1);
+            lane_batch_destroy(b);
+            if (ms > 0 && ms < best_vote) {
+                best_vote = ms;
+                best.vote_rows = T;
+                best.vote_queue = q;
+            }
+        }
+        if (status != LANE_OK) break;
+    }
+    // Sobel strip height x persistent workgroups per CU
+    const int strips[4] = {16, 32, 64, 128};
+    for (int si = 0; si < 4 && status == LANE_OK; ++si) {
+        for (int gpc = 0; gpc <= 2; ++gpc) {
+            lane_tune t = best;
+            t.sobel_strip_rows = strips[si];
+            t.sobel_groups_per_cu = gpc;
+            lane_batch* b = nullptr;
+            status = lane_batch_create(frames, n_frames, &t, &b);
+            if (status != LANE_OK) break;
+            enqueue_stage(b, 0, st);
+            const float ms = time_stage(b, 1, 3, st, e0, e1);
+            lane_batch_destroy(b);
+            if (ms > 0 && ms < best_sobel) {
+                best_sobel = ms;
+                best.sobel_strip_rows = strips[si];
+                best.sobel_groups_per_cu = gpc;
+            }
+        }
+    }
+    hipStreamSynchronize(st);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(st);
+    if (status != LANE_OK) return status;
+    *out = best;
+    if (ms_opt) {
+        ms_opt[0] = best_vote;
+        ms_opt[1] = best_sobel;
+    }
+    return LANE_OK;
+}
+
 }  // namespace
 
 int lane_tune_run(const uint8_t* sample, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
@@ -711,65 +781,20 @@ int lane_tune_run(const uint8_t* sample, int32_t W, int32_t H, int32_t pitch, in
         f.acc = acc;
         f.counters_opt = cnt;
     }
-    hipStream_t st = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LANE_E_DEVICE;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
     const int tmax = lane_vote_rows_per_group(W, H, n_theta, n_r);
-    lane_tune best = {tmax, -1, 0, 0, 0};
-    float best_vote = 1e30f, best_sobel = 1e30f;
-    int status = LANE_OK;
-    // theta rows per vote workgroup x work distribution
-    for (int T = tmax; T >= 1 && T * 16 >= tmax; T >>= 1) {
-        for (int q = 0; q <= 1; ++q) {
-            lane_tune t = {T, q, 0, 0, 0};
-            lane_batch* b = nullptr;
-            status = lane_batch_create(frames.data(), n_frames, &t, &b);
-            if (status != LANE_OK) break;
-            enqueue_stage(b, 0, st);
-            enqueue_stage(b, 1, st);
-            const float ms = time_stage(b, 2, 3, st, e0, e1);
-            lane_batch_destroy(b);
-            if (ms > 0 && ms < best_vote) {
-                best_vote = ms;
-                best.vote_rows = T;
-                best.vote_queue = q;
-            }
-        }
-        if (status != LANE_OK) break;
+    return tune_frames(frames.data(), n_frames, tmax, false, out, ms_opt);
+}
+
+int lane_tune_batch(const lane_frame* frames, int32_t n, lane_tune* out, float* ms_opt) {
+    if (!frames || !out || n < 1 || n > 4096) return LANE_E_ARG;
+    int tmax = 1;
+    for (int i = 0; i < n; ++i) {
+        const int st = validate(frames[i]);
+        if (st != LANE_OK) return st;
+        tmax = std::max(tmax, lane_vote_rows_per_group(frames[i].W, frames[i].H, frames[i].n_theta,
+                                                        frames[i].n_r));
     }
-    // Sobel strip height x persistent workgroups per CU
-    const int strips[4] = {16, 32, 64, 128};
-    for (int si = 0; si < 4 && status == LANE_OK; ++si) {
-        for (int gpc = 0; gpc <= 2; ++gpc) {
-            lane_tune t = best;
-            t.sobel_strip_rows = strips[si];
-            t.sobel_groups_per_cu = gpc;
-            lane_batch* b = nullptr;
-            status = lane_batch_create(frames.data(), n_frames, &t, &b);
-            if (status != LANE_OK) break;
-            enqueue_stage(b, 0, st);
-            const float ms = time_stage(b, 1, 3, st, e0, e1);
-            lane_batch_destroy(b);
-            if (ms > 0 && ms < best_sobel) {
-                best_sobel = ms;
-                best.sobel_strip_rows = strips[si];
-                best.sobel_groups_per_cu = gpc;
-            }
-        }
-    }
-    hipStreamSynchronize(st);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(st);
-    if (status != LANE_OK) return status;
-    *out = best;
-    if (ms_opt) {
-        ms_opt[0] = best_vote;
-        ms_opt[1] = best_sobel;
-    }
-    return LANE_OK;
+    return tune_frames(frames, n, tmax, true, out, ms_opt);
 }
 
 }  // extern "C"

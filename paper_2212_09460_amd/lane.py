@@ -13,7 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblane.so")
+# LANE_LIB_PATH: another build of the same sources (the host-sanitizer test)
+LIB_PATH = os.environ.get("LANE_LIB_PATH") or os.path.join(_HERE, "liblane.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2212_09460_amd.build.build()")
@@ -88,6 +89,7 @@ EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_of
            "lane_canny_workspace_size", "lane_canny", "lane_hough_progressive_layout",
            "lane_hough_progressive", "lane_batch_create",
            "lane_batch_launch", "lane_batch_launch_stage", "lane_batch_destroy", "lane_tune_run",
+           "lane_tune_batch",
            "lane_cnn_param_count", "lane_cnn_sizes", "lane_cnn_pack", "lane_cnn_forward",
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
            "lane_mask_from_logits", "lane_cnn_infer", "lane_batch_active_flags", "lane_batch_select", "lane_server_plan",
@@ -347,17 +349,18 @@ def canny(img: torch.Tensor, W: int | None = None, t_low: int = 64, t_high: int 
 def hough_lines(edges: torch.Tensor, cos_q14: torch.Tensor, sin_q14: torch.Tensor, r_offset: int,
                 theta_idx: torch.Tensor, r_idx: torch.Tensor, count: torch.Tensor | None = None,
                 fill_gap: int = 20, min_length: int = 40, max_segments: int = 16, W: int | None = None,
-                stream=None):
+                stream=None, segments=None, seg_count=None, npts=None):
     """Line segments along peaks.  edges: device uint8 [H][W].  Returns
-    (segments [k][max_segments][4], seg_count [k], npts [k]) int32 device tensors."""
+    (segments [k][max_segments][4], seg_count [k], npts [k]) int32 device tensors
+    (the given output tensors, if any)."""
     H, pitch = edges.shape
     W = pitch if W is None else W
     assert W == pitch, "the edge map must be [H][W]"
     k = int(theta_idx.numel())
     dev = edges.device
-    segs = torch.empty((k, max_segments, 4), dtype=torch.int32, device=dev)
-    cnt = torch.empty((k,), dtype=torch.int32, device=dev)
-    npts = torch.empty((k,), dtype=torch.int32, device=dev)
+    segs = torch.empty((k, max_segments, 4), dtype=torch.int32, device=dev) if segments is None else segments
+    cnt = torch.empty((k,), dtype=torch.int32, device=dev) if seg_count is None else seg_count
+    npts = torch.empty((k,), dtype=torch.int32, device=dev) if npts is None else npts
     _check(_lines(_p(edges), W, H, _p(cos_q14), _p(sin_q14), int(cos_q14.numel()), int(r_offset),
                   _p(theta_idx), _p(r_idx), None if count is None else _p(count), k, int(fill_gap),
                   int(min_length), int(max_segments), _p(segs), _p(cnt), _p(npts), _stream(stream)),
@@ -420,6 +423,21 @@ def tune_run(sample: torch.Tensor, n_theta: int, n_frames: int, W: int | None = 
     ms = (ctypes.c_float * 2)()
     _check(_tune_run(_p(sample), W, H, pitch, threshold, border_mode, n_theta, n_frames,
                      ctypes.byref(t), ms), "lane_tune_run")
+    return t, float(ms[0]), float(ms[1])
+
+
+_tune_batch = _sig("lane_tune_batch", [ctypes.POINTER(LaneFrame), _i32, ctypes.POINTER(LaneTune),
+                                       ctypes.POINTER(ctypes.c_float)])
+
+
+def tune_batch(frames):
+    """Run the native autotuner on the plan's own frames (FrameBuffers, any
+    mix of sizes); returns (LaneTune, vote_ms, sobel_ms).  The plans it times
+    write the frames' outputs."""
+    arr = (LaneFrame * len(frames))(*[f.desc() for f in frames])
+    t = LaneTune()
+    ms = (ctypes.c_float * 2)()
+    _check(_tune_batch(arr, len(frames), ctypes.byref(t), ms), "lane_tune_batch")
     return t, float(ms[0]), float(ms[1])
 
 

@@ -69,6 +69,69 @@ def frame_pools(streams, pool: int = 64, base_seed: int = 0, workers: int = 16, 
     return out
 
 
+def reference_peaks(streams, pools, pruned: bool = False, conf: float = 0.9, cnn_params=None):
+    """Per stream and pool frame, the peaks of that frame alone through the
+    single-frame entry points -- plain: Sobel, vote, peaks; pruned: the
+    proposal network, its tile mask, the masked vote, peaks -- i.e. what
+    every served result of that frame must equal.  Returns
+    refs[stream][frame] = (count, theta_idx[:k], r_idx[:k], votes[:k])."""
+    import torch
+
+    from . import lane
+
+    net = None
+    if pruned:
+        from .learned.model import ProposalNet, load_params
+
+        net = ProposalNet(load_params() if cnn_params is None else cnn_params)
+    tables = {}
+    out_dev = []
+    for s, st in enumerate(streams):
+        W, H, n_theta, k = st["W"], st["H"], st.get("n_theta", 360), st.get("k", 8)
+        if n_theta not in tables:
+            C, S = lane.make_trig_q14(n_theta)
+            tables[n_theta] = (torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda())
+        Cd, Sd = tables[n_theta]
+        rows = []
+        for j in range(pools[s].shape[0]):
+            img = pools[s][j].cuda(non_blocking=True)
+            mask = None
+            if net is not None:
+                lg = net.forward(img[None])
+                mask = torch.empty((1, (H + 7) // 8, (W + 7) // 8), dtype=torch.uint8, device="cuda")
+                lane.mask_from_logits(lg, W, H, 1, conf, mask)
+                mask = mask[0]
+            r = lane.pipeline(img, Cd, Sd, k, threshold=st.get("threshold", 128),
+                              border_mode=st.get("border_mode", 1), tile_mask=mask)
+            rows.append(torch.cat([r["count"].view(1), r["theta_idx"], r["r_idx"], r["votes"]]))
+        out_dev.append(torch.stack(rows))
+    refs = []
+    for s, st in enumerate(streams):
+        k = st.get("k", 8)
+        a = out_dev[s].cpu().numpy()
+        refs.append([(int(row[0]), row[1:1 + k].tolist(), row[1 + k:1 + 2 * k].tolist(),
+                      row[1 + 2 * k:1 + 3 * k].tolist()) for row in a])
+    return refs
+
+
+def check_results(results, reqs_meta, refs, streams):
+    """Compares every completed result with the reference peaks of its frame;
+    reqs_meta[i] = (stream, pool index) of request i.  Returns (checked,
+    mismatches)."""
+    checked = bad = 0
+    for r in results:
+        if r.status != 0:
+            continue
+        s, j = reqs_meta[int(r.frame_id)]
+        k = streams[s].get("k", 8)
+        c, t, rr, v = refs[s][j]
+        ok = (r.stream == s and r.count == c and list(r.theta_idx[:k]) == t
+              and list(r.r_idx[:k]) == rr and list(r.votes[:k]) == v)
+        checked += 1
+        bad += not ok
+    return checked, bad
+
+
 def requests(schedule, pools):
     ts, ss, ks = schedule
     reqs = []
@@ -104,7 +167,9 @@ def summarize(results, streams, seconds: float):
 def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_params=None,
         rate_hz: float = 30.0, seed: int = 0, pool: int = 64, hbm_budget: int = 8 << 30,
         max_pending: int = 8, vote_rows: int = 0, pools=None, mix=MIX, verbose: bool = True,
-        vote_split: int = 0):
+        vote_split: int = 0, verify: bool = False):
+    """One serving run; with verify, every completed result is compared with
+    its frame alone (reference_peaks) and out["verified"] holds the counts."""
     from . import lane
 
     streams = mix_streams(mix)
@@ -114,6 +179,7 @@ def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_para
         from .learned.model import load_params
 
         cnn_params = load_params()
+    refs = reference_peaks(streams, pools, pruned, conf, cnn_params) if verify else None
     srv = lane.Server(streams, hbm_budget=hbm_budget, pruned=pruned, conf=conf,
                       cnn_params=cnn_params, max_pending=max_pending, vote_rows=vote_rows,
                       vote_split=vote_split)
@@ -130,6 +196,11 @@ def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_para
                   flush=True)
         res = srv.replay(reqs)
         out = summarize(list(res), streams, seconds)
+        if refs is not None:
+            meta = [(int(sched[1][i]), int(sched[2][i]) % pools[int(sched[1][i])].shape[0])
+                    for i in range(len(sched[0]))]
+            checked, bad = check_results(list(res), meta, refs, streams)
+            out["verified"] = dict(checked=checked, mismatches=bad)
         out["mode"] = "pruned" if pruned else "plain"
         out["streams_admitted"] = sum(srv.admitted)
         out["server"] = srv.stats()

@@ -352,3 +352,34 @@ def test_vote_small_tables_many_rows(lane, synth, oracle, q, rows):
         b.launch()
         check(frames, wants)
     b.close()
+
+
+def test_mixed_batch_64_frames_tuned(lane, synth, oracle):
+    """The mixed-resolution batch as specified: 64 frames, 16 each at 640x480,
+    1280x720, 1920x1080 and 3840x2160 with 2..6 lanes, 360 angles, top-8, in
+    one plan whose setting comes from the autotuner run on these frames
+    (lane_tune_batch); every frame bit-exact against the oracle on two graph
+    replays with the outputs scribbled between them."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    say("mixed batch 64 frames: generate, oracle")
+    imgs = [synth.mixed_batch(i) for i in range(64)]
+    assert sorted({im.shape for im in imgs}) == [(480, 640), (720, 1280), (1080, 1920), (2160, 3840)]
+    C, S = synth.trig_q14(360)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        wants = list(ex.map(lambda im: oracle.pipeline(im, C, S, 8), imgs))
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    frames = [lane.FrameBuffers(torch.from_numpy(im).cuda(), im.shape[1], 360, 8, Cd, Sd)
+              for im in imgs]
+    say("mixed batch 64 frames: tune")
+    t, vote_ms, sobel_ms = lane.tune_batch(frames)
+    assert t.vote_rows in (0, 1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1)
+    assert t.sobel_strip_rows in (16, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
+    assert vote_ms > 0 and sobel_ms > 0
+    b = lane.Batch(frames, tune=t)
+    for rep in range(2):
+        say("mixed batch 64 frames: replay", rep, lane.tune_dict(t))
+        scribble(frames)
+        b.launch()
+        check(frames, wants)
+    b.close()

@@ -25,3 +25,61 @@ def test_all_cores_oracle_leg():
     # each worker finishes at least one frame after the go line
     assert r["frames_per_s"] > 0 and r["value"] > 0
     assert "2 single-threaded oracle processes" in r["sample"]
+
+
+def test_mixed_oracle_worker_and_check():
+    """The mixed-batch oracle worker reports per-frame results that the check
+    accepts for identical GPU outputs and rejects for a changed peak or a
+    changed accumulator."""
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--oracle-mixed-worker", "0,1"]
+    res = bench.run_workers([cmd], dict(os.environ, OMP_NUM_THREADS="1"))
+    frames = res[0]["frames"]
+    assert [f["i"] for f in frames] == [0, 1] and res[0]["seconds"] > 0
+    k = bench.TOPK
+    gpu = {}
+    for f in frames:
+        pk = np.array(f["theta_idx"] + f["r_idx"] + f["votes"] + [f["count"]], np.int32)
+        gpu[f["i"]] = {"acc_sha": f["acc_sha"], "peaks": pk,
+                       "counters": np.array([f["n_edges"], f["dropped"]], np.int32)}
+    assert bench.check_mixed(frames, gpu)["ok"]
+    gpu[1]["peaks"] = gpu[1]["peaks"].copy()
+    gpu[1]["peaks"][k] += 1
+    r = bench.check_mixed(frames, gpu)
+    assert not r["ok"] and r["mismatched_frames"] == [1]
+    gpu[1]["peaks"][k] -= 1
+    gpu[0]["acc_sha"] = "0" * 64
+    assert bench.check_mixed(frames, gpu)["mismatched_frames"] == [0]
+
+
+def test_plan_check_covers_every_frame():
+    """check_plan_256 compares every plan frame with the oracle result of its
+    pool frame and the first POOL accumulators in full."""
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    k, P = bench.TOPK, bench.POOL
+    rng = np.random.default_rng(1)
+    ref = {}
+    for j in range(P):
+        ref[j] = {"count": 3, "theta_idx": rng.integers(0, 360, k).astype(np.int32),
+                  "r_idx": rng.integers(0, 999, k).astype(np.int32),
+                  "votes": rng.integers(0, 99, k).astype(np.int32), "n_edges": int(j),
+                  "dropped": 0, "acc": rng.integers(0, 9, (4, 5)).astype(np.int32)}
+    n = 3 * P
+    peaks = np.stack([np.concatenate([ref[i % P]["theta_idx"], ref[i % P]["r_idx"],
+                                      ref[i % P]["votes"], [3]]) for i in range(n)])
+    counters = np.array([[i % P, 0] for i in range(n)], np.int32)
+    gpu = {"peaks": peaks, "counters": counters, "acc": [ref[j]["acc"].copy() for j in range(P)]}
+    r = bench.check_plan_256(ref, gpu)
+    assert r["ok"] and r["frames_peaks_checked"] == n and r["accumulators_checked"] == P
+    gpu["peaks"][2 * P + 5, 2 * k] += 1          # a late frame's votes
+    gpu["acc"][3][1, 2] += 1                     # an early frame's accumulator
+    r = bench.check_plan_256(ref, gpu)
+    assert not r["ok"] and r["mismatched_frames"] == [3, 2 * P + 5]

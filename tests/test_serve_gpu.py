@@ -167,3 +167,44 @@ def test_drops_and_poll(lane, synth):
                 n += 1
     finally:
         srv.close()
+
+
+ROAD_STREAMS = [dict(W=1280, H=720), dict(W=1920, H=1080), dict(W=3840, H=2160), dict(W=1280, H=720)]
+
+
+@pytest.mark.parametrize("pruned", [False, True])
+def test_server_at_serving_sizes(lane, synth, oracle, pruned):
+    """The serving sizes (720p, 1080p, 4K; 360 angles, top-8): a few requests
+    per stream, some sharing a refill, each equal to its frame alone; for the
+    plain path the oracle agrees with the alone path on one frame per size."""
+    say("serve at 720p/1080p/4K, pruned" if pruned else "serve at 720p/1080p/4K, plain")
+    from paper_2212_09460_amd import serve
+
+    P = [torch.from_numpy(np.stack([synth.road(s["W"], s["H"], 900 + 10 * i + j) for j in range(2)]))
+         for i, s in enumerate(ROAD_STREAMS)]
+    params = None
+    if pruned:
+        from paper_2212_09460_amd.learned.model import load_params
+
+        params = load_params()
+    refs = serve.reference_peaks(ROAD_STREAMS, P, pruned, 0.9, params)
+    if not pruned:
+        C, S = synth.trig_q14(360)
+        for s in (0, 1, 2):
+            want = oracle.pipeline(P[s][0].numpy(), C, S, 8)
+            c, t, r, v = refs[s][0]
+            assert c == want["count"] and t == want["theta_idx"].tolist()
+            assert r == want["r_idx"].tolist() and v == want["votes"].tolist()
+    srv = lane.Server(ROAD_STREAMS, hbm_budget=4 << 30, pruned=pruned, conf=0.9, cnn_params=params,
+                      max_pending=16)
+    try:
+        assert all(srv.admitted)
+        sched = schedule(len(ROAD_STREAMS), 24, seed=11)
+        reqs = [(s, t, P[s][i % 2].numpy(), i) for i, (s, t) in enumerate(sched)]
+        out = list(srv.replay(reqs))
+        meta = [(s, i % 2) for i, (s, t) in enumerate(sched)]
+        checked, bad = serve.check_results(out, meta, refs, ROAD_STREAMS)
+        assert checked == len(reqs) and bad == 0
+        assert any(r.batch_frames > 1 for r in out)
+    finally:
+        srv.close()
