@@ -38,9 +38,13 @@ def build(verbose: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        lib = ctypes.CDLL(LIB_PATH)
+        # LANE_ORACLE_LIB: another build of the same source (the sanitizer test)
+        path = os.environ.get("LANE_ORACLE_LIB")
+        if not path:
+            path = LIB_PATH
+            if not os.path.exists(path):
+                build()
+        lib = ctypes.CDLL(path)
         vp, i32 = ctypes.c_void_p, ctypes.c_int
         lib.oracle_sobel_binarize.restype = ctypes.c_int64
         lib.oracle_sobel_binarize.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]

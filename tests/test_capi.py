@@ -11,7 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lane.h")
-LIB = os.path.join(ROOT, "paper_2212_09460_amd", "liblane.so")
+LIB = os.environ.get("LANE_LIB_PATH") or os.path.join(ROOT, "paper_2212_09460_amd", "liblane.so")
 
 E_ARG, E_SIZE, E_RANGE, E_WS, E_UNSUP = -1, -2, -3, -4, -6
 
