@@ -497,6 +497,72 @@ def test_canny_diagonal_step_is_thin_and_continuous(oracle):
         assert e[y].any()
 
 
+def textbook_kept(img, boundary_deg=22.5):
+    """Thinning step of Canny with the gradient direction quantised by its
+    angle (atan2 in double precision, folded into [0, 90] degrees): below the
+    boundary the neighbours along x, above 90 - boundary those along y, else
+    the diagonal the signs of gx, gy point along.  Returns (kept, angle)."""
+    a = img.astype(np.int64)
+    b = (ndimage.correlate(a, np.outer(W5, W5), mode="nearest") + 128) >> 8
+    gx = ndimage.correlate(b, KX, mode="nearest")
+    gy = ndimage.correlate(b, KY, mode="nearest")
+    m = np.abs(gx) + np.abs(gy)
+    ang = np.degrees(np.arctan2(np.abs(gy), np.abs(gx)))
+    H, W = img.shape
+    mp = np.pad(m, 1)                                    # zero outside the frame
+
+    def nb(dx, dy):
+        return mp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+
+    m1 = np.where(ang < boundary_deg, nb(-1, 0),
+                  np.where(ang > 90 - boundary_deg, nb(0, -1),
+                           np.where(gx * gy > 0, nb(-1, -1), nb(1, -1))))
+    m2 = np.where(ang < boundary_deg, nb(1, 0),
+                  np.where(ang > 90 - boundary_deg, nb(0, 1),
+                           np.where(gx * gy > 0, nb(1, 1), nb(-1, 1))))
+    return (m > m1) & (m >= m2) & (m > 0), ang
+
+
+def sector_images():
+    H = W = 64
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    out = []
+    for phi in (20, 25, 65, 70, 110, 115, 155, 160):      # step normals either side of each boundary
+        t = np.radians(phi)
+        d = (xx - 31.3) * np.cos(t) + (yy - 32.6) * np.sin(t)
+        out.append(np.where(d > 0, 205, 55).astype(np.uint8))
+    for seed in range(6):                               # every direction, smoothly varying
+        rng = np.random.default_rng(90 + seed)
+        f = ndimage.gaussian_filter(rng.integers(0, 256, (H, W)).astype(float), 2.5)
+        out.append(np.clip((f - f.mean()) * 8 + 128, 0, 255).astype(np.uint8))
+    return out
+
+
+def test_canny_sectors_match_the_angle(oracle):
+    """Pins the sector boundary tan(22.5 deg) = 13573 / 2^15 of the integer
+    definition: on step edges whose normals lie at 20/25 (and 65/70, ...)
+    degrees and on smooth random images, the thinned pixels (thresholds 0,
+    no ring) equal those of the textbook quantisation of the angle itself.
+    Pixels within 1e-4 degrees of a boundary (where the rounded constant and
+    the exact angle may disagree) are left out; the images hold hundreds of
+    pixels within a degree of each side of 22.5, so a constant off by a few
+    hundredths of a degree already changes the result (checked below with
+    the boundary moved to 22.3 degrees)."""
+    near_lo = near_hi = 0
+    moved_differs = False
+    for img in sector_images():
+        got = oracle.canny(img, t_low=0, t_high=0, border_mode=0)[0] == 255
+        want, ang = textbook_kept(img)
+        exact = (np.abs(ang - 22.5) > 1e-4) & (np.abs(ang - 67.5) > 1e-4)
+        assert (got == want)[exact].all()
+        near_lo += int(((ang > 21.5) & (ang < 22.5)).sum())
+        near_hi += int(((ang > 22.5) & (ang < 23.5)).sum())
+        moved, _ = textbook_kept(img, 22.3)
+        moved_differs |= bool((moved != want)[exact].any())
+    assert near_lo > 100 and near_hi > 100
+    assert moved_differs
+
+
 @pytest.mark.parametrize("seed", range(5))
 def test_canny_hysteresis_is_connected_components(oracle, seed):
     rng = np.random.default_rng(50 + seed)
