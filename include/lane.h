@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LANE_ABI_VERSION 1
+#define LANE_ABI_VERSION 2
 
 enum {
     LANE_OK = 0,
@@ -51,7 +51,8 @@ enum {
     LANE_E_WS = -4,          /* workspace too small */
     LANE_E_DEVICE = -5,      /* HIP launch or runtime error */
     LANE_E_UNSUPPORTED = -6, /* e.g. an unsupported border mode */
-    LANE_E_BUSY = -7         /* serving: request dropped (stream queue full) or a replay already running */
+    LANE_E_BUSY = -7,        /* serving: request dropped (stream queue full) or a replay already running */
+    LANE_E_TIMEOUT = -8      /* serving: request not run, its deadline passed while it waited */
 };
 
 enum { LANE_BORDER_ZERO = 0, LANE_BORDER_ZERO_MASKRING = 1 };
@@ -495,7 +496,11 @@ int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t bat
  * pruned, then clear, Sobel, vote, peaks; switched-off slots return at once),
  * copy the peaks back and complete the requests.  Requests arriving while a
  * batch runs join the next one.  A frame's results do not depend on the
- * other frames of its batch. */
+ * other frames of its batch.  Failures: a request beyond its stream's queue
+ * bound is dropped (LANE_E_BUSY); with a deadline, one that waited too long
+ * is completed unrun (LANE_E_TIMEOUT) and frees its place; a device error
+ * fails that refill's requests and, since the device state can no longer be
+ * trusted, every later one (LANE_E_DEVICE; lane_server_stats.error). */
 #define LANE_SERVE_MAX_K 64
 
 typedef struct lane_stream_cfg {
@@ -515,11 +520,14 @@ typedef struct lane_server_cfg {
     int32_t vote_rows;        /* theta rows per vote workgroup (power of two); 0 = 4 */
     int32_t sobel_strip_rows; /* rows per Sobel work item (multiple of 8); 0 = 8 */
     int32_t vote_split;       /* lane_tune.vote_split for the server's plan; 0 = 8 */
+    int64_t deadline_ns;      /* > 0: a request that has waited longer than this when a refill
+                                 would take it is completed with LANE_E_TIMEOUT instead of run,
+                                 and its stream's next request takes the slot; 0 = no deadline */
 } lane_server_cfg;
 
 typedef struct lane_result {
     int32_t stream;           /* the caller's stream index */
-    int32_t status;           /* LANE_OK, LANE_E_BUSY (dropped) or LANE_E_DEVICE */
+    int32_t status;           /* LANE_OK, LANE_E_BUSY (dropped), LANE_E_TIMEOUT or LANE_E_DEVICE */
     uint64_t frame_id;        /* as submitted */
     int64_t t_submit_ns;      /* steady clock: submission */
     int64_t t_start_ns;       /* its batch taken from the queues */
@@ -542,6 +550,7 @@ typedef struct lane_server_stats {
     int64_t device_bytes;     /* the server's device allocation */
     int32_t streams_admitted;
     int32_t error;            /* LANE_OK, or the first device error */
+    int64_t timed_out;        /* requests completed with LANE_E_TIMEOUT */
 } lane_server_stats;
 
 typedef struct lane_server lane_server;
@@ -575,6 +584,10 @@ int lane_server_poll(lane_server *s, lane_result *out, int32_t max, int32_t wait
  * These results do not go to lane_server_poll.  One replay at a time. */
 int lane_server_replay(lane_server *s, const lane_request *reqs, int32_t n, lane_result *results);
 int lane_server_stats_get(lane_server *s, lane_server_stats *out);
+/* paused = 1: the worker takes no further refill (one already running
+ * finishes) while requests keep queueing and their deadlines keep running;
+ * paused = 0: it resumes.  For draining and maintenance.  Thread-safe. */
+int lane_server_pause(lane_server *s, int32_t paused);
 /* Stops the worker after the batch in flight (queued requests are discarded)
  * and frees everything.  No other call on s may be running. */
 int lane_server_destroy(lane_server *s);

@@ -58,6 +58,7 @@ const char* lane_strerror(int status) {
         case LANE_E_DEVICE: return "HIP device error";
         case LANE_E_UNSUPPORTED: return "unsupported option";
         case LANE_E_BUSY: return "request dropped or server busy";
+        case LANE_E_TIMEOUT: return "request deadline passed";
         default: return "unknown status";
     }
 }

@@ -1,5 +1,6 @@
 // Learned tile / theta-band proposal for gfx950: a 4-layer 3x3 CNN in FP16
-// with FP32 accumulation on MFMA (v_mfma_f32_16x16x16_f16), its backward
+// with FP32 accumulation on MFMA (forward: v_mfma_f32_16x16x16_f16 for
+// conv1, v_mfma_f32_16x16x32_f16 for the 16-channel layers), its backward
 // pass, BCE loss, Adam, plain-pipeline tile labels and the mask rule.
 //
 // Network (zero padding 1):  conv1 1->16 s2 ReLU, conv2 16->16 s2 ReLU,
@@ -9,8 +10,9 @@
 // Layouts.  Activations are NHWC FP16 with 16 channels (32 B per pixel), so
 // the 4 consecutive channels an MFMA lane supplies are one 8-byte load.
 // Every convolution tile is one wave: 16 output pixels of a row x 16 output
-// channels, K = 16 input channels per kernel tap, 9 MFMAs (conv1: K = the 9
-// taps of the single input channel, one MFMA).  With M = output channel and
+// channels; forward, two kernel taps of 16 input channels per 16x16x32 MFMA
+// (five per tile; conv1: K = the 9 taps of the single input channel, one
+// 16x16x16 MFMA); backward, K = 16 per 16x16x16 MFMA, nine per tile.  With M = output channel and
 // N = pixel the accumulator lane holds 4 consecutive channels of one pixel,
 // which is again an 8-byte NHWC store.  Backward data swaps the roles of the
 // channel axes (transposed weights); backward weights reduces over pixels
@@ -56,6 +58,13 @@ __device__ __forceinline__ void st_h4(_Float16* p, h4 v) { *(LANE_GLOBAL h4*)p =
 
 __device__ __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// gfx950's 16x16x32 FP16 MFMA: K = 32 per instruction (two taps of 16
+// channels), each lane supplying 8 consecutive K values of A and of B
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma32(h8 a, h8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // ------------------------------------------------------------------ pack --
@@ -140,7 +149,9 @@ __global__ void __launch_bounds__(256) k_cnn_fwd1(CnnFwd p) {
     }
 }
 
-// conv2 / conv3 / head: 16 input channels, 9 taps
+// conv2 / conv3 / head: 16 input channels, 9 taps as five 16x16x32 MFMAs:
+// K index 8 grp .. 8 grp + 7 of pair q is tap 2q + (grp >> 1), input
+// channels 8 (grp & 1) .. + 7 (tap 9 does not exist: zero weights and input)
 __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
     const int lane = threadIdx.x & 63;
     const _Float16* in = layer == 1 ? p.a1 : layer == 2 ? p.a2 : p.a3;
@@ -161,13 +172,16 @@ __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
     const _Float16* x = in + (size_t)b * si;
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const h4 A = ld_h4(w + (tap * 16 + col) * 16 + 4 * grp);  // W[tap][co = col][ci = 4 grp + j]
-        const int iy = oy * stride + tap / 3 - 1, ix = ox * stride + tap % 3 - 1;
-        h4 B = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0};
-        if (ox < Wo && iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
-            B = ld_h4(x + ((size_t)iy * Wi + ix) * 16 + 4 * grp);  // X[ci = 4 grp + j][pixel = col]
-        acc = mfma16(A, B, acc);
+    for (int q = 0; q < 5; ++q) {
+        const int tap = 2 * q + (grp >> 1);
+        h8 A = {}, B = {};
+        if (tap < 9) {
+            A = *(const LANE_GLOBAL h8*)(w + (tap * 16 + col) * 16 + 8 * (grp & 1));
+            const int iy = oy * stride + tap / 3 - 1, ix = ox * stride + tap % 3 - 1;
+            if (ox < Wo && iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+                B = *(const LANE_GLOBAL h8*)(x + ((size_t)iy * Wi + ix) * 16 + 8 * (grp & 1));
+        }
+        acc = mfma32(A, B, acc);
     }
     if (ox >= Wo) return;
     const float* bias = pk_bias(p.pk, layer);
@@ -189,7 +203,7 @@ __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
 
 // ------------------------------------------------------- fused inference --
 // Forward only, all four layers in one workgroup per 8x8 block of head
-// outputs: the input window (87x87 bytes) and the conv1 / conv2 / conv3
+// outputs: the input window (87x87 pixels) and the conv1 / conv2 / conv3
 // activations the block needs (43x43, 21x21, 10x10 pixels, halo included)
 // stay in LDS, so nothing but the frame and the logits touches HBM.  Every
 // layer issues the same MFMA sequence on the same FP16 values as the
@@ -197,19 +211,32 @@ __global__ void __launch_bounds__(256) k_cnn_fwd16(CnnFwd p, int layer) {
 // Positions outside a layer's output are stored as zero: they are the next
 // layer's zero padding.
 //
-// LDS: windows read at stride 2 (conv1 and conv2 outputs) keep even columns
-// before odd ones, so a 16-lane stride-2 read touches 16 consecutive pixels
-// (each bank four times for 64-bit reads, the minimum); the input window
-// shares its space with the conv2 window (it is dead by then).  76 KB per
-// workgroup: two workgroups per CU.  The next block's input bytes are
-// loaded into registers while the current block computes.
+// Work per block: conv1 as 43 rows x 3 sixteen-pixel groups (one
+// 16x16x16 MFMA each); conv2, conv3 and the head as flat runs of 16 output
+// pixels (28, 7 and 4 tiles: no idle lanes past a row's end), five
+// 16x16x32 MFMAs each.  Every lane's LDS offsets for those tiles depend on
+// the block geometry only and are computed once per kernel.
+//
+// LDS (79.5 KB, two workgroups per CU): the input window converted once to
+// FP16 (rows padded to 98 halves, so the stride-2 taps of the lanes past a
+// row's end stay inside the window) shares its space with the conv2 window;
+// windows read at stride 2 (conv1 and conv2 outputs) keep even columns
+// before odd ones, so a 16-lane stride-2 read touches 16 consecutive
+// pixels; the conv3 window lives in the conv1 window's space (dead by
+// then); the head weights and all biases are staged once per workgroup.
+// The next block's input bytes are loaded into registers while the current
+// block computes.
 constexpr int kFT = 8;                // head outputs per block side
 constexpr int kR3 = kFT + 2;          // conv3 window side
 constexpr int kR2 = 2 * kR3 + 1;      // conv2 window side
 constexpr int kR1 = 2 * kR2 + 1;      // conv1 window side
 constexpr int kR0 = 2 * kR1 + 1;      // input window side
+constexpr int kP0 = 98;               // input window row pitch (halves): > 2 * 47 + 2
 constexpr int kInferThreads = 512;
-constexpr int kR0PerThread = (kR0 * kR0 + kInferThreads - 1) / kInferThreads;
+constexpr int kT2 = (kR2 * kR2 + 15) / 16;  // conv2 tiles (28)
+constexpr int kT3 = (kR3 * kR3 + 15) / 16;  // conv3 tiles (7)
+constexpr int kT4 = (kFT * kFT) / 16;       // head tiles (4)
+constexpr int kU02 = (kR0 * kP0 > kR2 * kR2 * 16 ? kR0 * kP0 : kR2 * kR2 * 16);  // halves
 
 struct CnnInfer {
     const uint8_t* img;
@@ -221,56 +248,67 @@ struct CnnInfer {
     int bx, by;                // blocks per frame along x / y
     int batch;
     const uint8_t* active;     // frame b runs iff active[b] != 0 (null = all)
+    uint8_t* mask;             // [B][H3][W3] tile masks by the rule of k_mask_from_logits, or null
+    float t_hi;                // that rule's threshold
 };
 
 // column of pixel x in a window of side n stored even columns first
 __device__ __forceinline__ int deint(int x, int n) { return (x & 1) ? ((n + 1) >> 1) + (x >> 1) : (x >> 1); }
 
-// The 9 weight tiles of a layer for this lane (A operands), kept in registers.
-struct Taps {
-    h4 a[9];
+// A operands of a 16-channel layer for the five 16x16x32 MFMAs: K index
+// 8 grp .. 8 grp + 7 of pair q is tap 2q + (grp >> 1), input channels
+// 8 (grp & 1) .. + 7 (tap 9 does not exist: zero weights).
+struct Taps2 {
+    h8 a[5];
 };
-__device__ __forceinline__ Taps load_taps(const _Float16* __restrict__ w, int col, int grp) {
-    Taps t;
+__device__ __forceinline__ Taps2 load_taps2(const _Float16* __restrict__ w, int col, int grp) {
+    Taps2 t;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) t.a[tap] = ld_h4(w + (tap * 16 + col) * 16 + 4 * grp);
+    for (int q = 0; q < 5; ++q) {
+        const int tap = 2 * q + (grp >> 1);
+        h8 v = {};
+        if (tap < 9) v = *(const LANE_GLOBAL h8*)(w + (tap * 16 + col) * 16 + 8 * (grp & 1));
+        t.a[q] = v;
+    }
     return t;
 }
 
-// One 16-pixel x 16-channel MFMA tile of a 16-channel layer from an LDS
-// window of side RIN.  `base` addresses input row STRIDE * ly, column
-// lx (stride 2: the window is de-interleaved, so tap kx = 0 / 2 read
-// columns lx / lx + 1 of the even half and kx = 1 column lx of the odd
-// half); every tap is then a constant offset from base.
-template <int STRIDE, int RIN>
-__device__ __forceinline__ f4 conv16_lds(const _Float16* __restrict__ in, int base, const Taps& w) {
+// One 16-pixel x 16-channel tile of a 16-channel layer: lane (col, grp)
+// reads, for each tap pair, 8 input channels of its pixel at the tap its
+// group supplies; tapoff(t) is the LDS offset (halves) of tap t from the
+// pixel's top-left input; tap 9 reuses tap 8's offset (zero weights).
+template <class TapOff>
+__device__ __forceinline__ f4 conv16x32(const _Float16* __restrict__ in, int base, int grp,
+                                        const Taps2& w, TapOff tapoff) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int ch = 8 * (grp & 1), hi = grp >> 1;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int ky = tap / 3, kx = tap % 3;
-        const int off = STRIDE == 2 ? (ky * RIN + ((kx & 1) ? (RIN + 1) / 2 : 0) + (kx >> 1)) * 16
-                                    : (ky * RIN + kx) * 16;
-        const h4 B = *reinterpret_cast<const h4*>(in + base + off);
-        acc = mfma16(w.a[tap], B, acc);
+    for (int q = 0; q < 5; ++q) {
+        const int tap = min(2 * q + hi, 8);
+        const h8 B = *reinterpret_cast<const h8*>(in + base + tapoff(tap) + ch);
+        acc = mfma32(w.a[q], B, acc);
     }
     return acc;
 }
 
-__device__ __forceinline__ void put_relu(_Float16* __restrict__ out, int rout, bool de, int ly, int lx,
-                                         bool inside, f4 acc, const float* bias, int grp) {
+// bias + ReLU, or zero outside the layer's output, as four FP16 channels
+__device__ __forceinline__ h4 relu4(f4 acc, f4 bias, bool inside) {
     h4 o;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        o[j] = inside ? (_Float16)fmaxf(acc[j] + bias[4 * grp + j], 0.f) : (_Float16)0;
-    const int cx = de ? deint(lx, rout) : lx;
-    *reinterpret_cast<h4*>(out + (ly * rout + cx) * 16 + 4 * grp) = o;
+    for (int j = 0; j < 4; ++j) o[j] = (_Float16)fmaxf(acc[j] + bias[j], 0.f);
+    const h4 z = {};
+    return inside ? o : z;
 }
 
-__global__ void __launch_bounds__(kInferThreads) k_cnn_infer(CnnInfer p) {
-    __shared__ __align__(16) _Float16 r1[kR1 * kR1 * 16];
-    __shared__ __align__(16) _Float16 r2[kR2 * kR2 * 16];  // the input window lives here first
-    __shared__ __align__(16) _Float16 r3[kR3 * kR3 * 16];
-    uint8_t* r0 = reinterpret_cast<uint8_t*>(r2);
+__global__ void __launch_bounds__(kInferThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_cnn_infer(CnnInfer p) {
+    __shared__ __align__(16) _Float16 r1[kR1 * kR1 * 16];  // conv1 out; later the conv3 window
+    __shared__ __align__(16) _Float16 u02[kU02];            // input window, then conv2 out
+    __shared__ __align__(16) _Float16 s_w4[9 * 16 * 16];    // head weights [tap][co][ci]
+    __shared__ __align__(16) float s_bias[4 * 16];
+    _Float16* r0 = u02;
+    _Float16* r2 = u02;
+    _Float16* r3 = r1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kInferThreads / 64;
     const int col = lane & 15, grp = lane >> 4;
     const int nblk = p.bx * p.by;
@@ -286,41 +324,68 @@ __global__ void __launch_bounds__(kInferThreads) k_cnn_infer(CnnInfer p) {
         nb = f;
         nblk_out = k;
     };
-    // a block's input bytes, four per register
-    constexpr int kPacked = (kR0PerThread + 3) / 4;
+    // A block's input window: thread t < 435 loads row t / 5, columns
+    // 18 (t % 5) .. + 17 (five runs of 18 cover the 87 columns), one byte
+    // per load at a constant offset from the run's start; bytes outside the
+    // frame or the window are masked to zero (a run on a row outside the
+    // frame reads nothing).  Four bytes per register.
+    constexpr int kRun = 18, kRuns = 5, kPacked = (kRun + 3) / 4;
+    static_assert(kRun * kRuns >= kR0 && kR0 * kRuns <= kInferThreads, "window runs");
+    const int frow = tid / kRuns, fcol = kRun * (tid - frow * kRuns);
     auto fetch = [&](int b, int blk, uint32_t (&v)[kPacked]) {
         const int TY = blk / p.bx, TX = blk - TY * p.bx;
         // input window origin 2 Y1 - 1 = 8 Y4 - 15 (Y1 = 2 Y2 - 1, Y2 = 2 Y3 - 1, Y3 = Y4 - 1)
-        const int Y0 = 8 * TY * kFT - 15, X0 = 8 * TX * kFT - 15;
-        const uint8_t* img = p.img + (size_t)b * p.img_stride;
-        uint32_t t[kR0PerThread];
+        const int y = 8 * TY * kFT - 15 + frow, x0 = 8 * TX * kFT - 15 + fcol;
+        // the frame as a raw buffer: offsets past its end read as zero
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(p.img + (size_t)b * p.img_stride), (short)0,
+            (int)((uint32_t)p.pitch * (uint32_t)p.H), kBufConfig);
+        const bool row_in = tid < kR0 * kRuns && y >= 0 && y < p.H;
+        const uint32_t off = row_in ? (uint32_t)(y * p.pitch + x0) : kBufOutside;
+        uint32_t keep = 0;  // bit j: column x0 + j is inside the frame and the window
 #pragma unroll
-        for (int u = 0; u < kR0PerThread; ++u) {
-            const int i = tid + u * kInferThreads;
-            const int y = Y0 + i / kR0, x = X0 + i % kR0;
-            const bool in = i < kR0 * kR0 && y >= 0 && y < p.H && x >= 0 && x < p.W;
-            t[u] = gld(img + (in ? (size_t)y * p.pitch + x : 0));
-            if (!in) t[u] = 0;
-        }
+        for (int j = 0; j < kRun; ++j)
+            keep |= (uint32_t)(x0 + j >= 0 && x0 + j < p.W && fcol + j < kR0) << j;
 #pragma unroll
-        for (int q = 0; q < kPacked; ++q) {
-            uint32_t w = 0;
+        for (int q = 0; q < kPacked; ++q) v[q] = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (4 * q + k < kR0PerThread) w |= t[4 * q + k] << (8 * k);
-            v[q] = w;
+        for (int j = 0; j < kRun; ++j) {
+            // a column left of the frame gives a negative offset: pass the
+            // out-of-range one instead (the byte is masked anyway)
+            const uint32_t o = off + (uint32_t)j;
+            const uint32_t bj = __builtin_amdgcn_raw_buffer_load_b8(rsrc, x0 + j >= 0 ? o : kBufOutside, 0, 0);
+            v[j >> 2] |= (((keep >> j) & 1u) ? bj : 0u) << (8 * (j & 3));
         }
     };
+    // per-workgroup constants: head weights and biases in LDS
+    for (int i = tid; i < 9 * 16 * 16 / 8; i += kInferThreads)
+        *reinterpret_cast<h8*>(s_w4 + 8 * i) = *(const LANE_GLOBAL h8*)(wk + kPkW4 + 8 * i);
+    if (tid < 64) s_bias[tid] = gld(pk_bias(p.pk, 0) + tid);
     // conv1 taps of this lane: K index 4 grp + j is tap 4 grp + j (taps 9..15
-    // have zero weights, so whatever finite value they read adds nothing)
+    // have zero weights; they read tap 8's pixel)
     int off1[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int tap = min(4 * grp + j, 8);
-        off1[j] = (tap / 3) * kR0 + tap % 3 + 2 * col;
+        off1[j] = (tap / 3) * kP0 + tap % 3;
     }
     const h4 A1 = ld_h4(wk + kPkW1 + col * 16 + 4 * grp);
-    const Taps T2 = load_taps(wk + kPkW2, col, grp);
+    const Taps2 T2 = load_taps2(wk + kPkW2, col, grp);
+    // conv1 lanes: column of each 16-pixel group and its de-interleaved slot
+    int cx1[3];
+#pragma unroll
+    for (int xg = 0; xg < 3; ++xg) cx1[xg] = deint(min(16 * xg + col, kR1 - 1), kR1);
+    // conv3 tile of this wave (waves 0..6) and head tile (waves 0..3)
+    const int n3 = min(16 * wave + col, kR3 * kR3 - 1);
+    const int y3l = n3 / kR3, x3l = n3 - y3l * kR3;
+    const int in3 = (2 * y3l * kR2 + x3l) * 16;
+    const int out3 = (y3l * kR3 + x3l) * 16 + 4 * grp;
+    const int n4 = 16 * (wave & 3) + col;
+    const int y4l = n4 >> 3, x4l = n4 & 7;
+    const int in4 = (y4l * kR3 + x4l) * 16;
+    __syncthreads();
+    const f4 bias1 = *reinterpret_cast<const f4*>(s_bias + 4 * grp);
+    const f4 bias2 = *reinterpret_cast<const f4*>(s_bias + 16 + 4 * grp);
     int b, blk;
     next(0, (int)blockIdx.x - (int)gridDim.x, b, blk);
     uint32_t v[kPacked];
@@ -331,89 +396,145 @@ __global__ void __launch_bounds__(kInferThreads) k_cnn_infer(CnnInfer p) {
         const int Y3 = Y4 - 1, X3 = X4 - 1;
         const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1;
         const int Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1;
+        // the input window, converted once to FP16 (gray / 255), two
+        // columns per 32-bit LDS write
+        if (tid < kR0 * kRuns) {
 #pragma unroll
-        for (int u = 0; u < kR0PerThread; ++u)
-            if (tid + u * kInferThreads < kR0 * kR0)
-                r0[tid + u * kInferThreads] = (uint8_t)(v[u >> 2] >> (8 * (u & 3)));
+            for (int j = 0; j < kRun; j += 2) {
+                if (fcol + j < kR0) {
+                    const uint32_t b0 = (v[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                    const uint32_t b1 = (v[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xFFu;
+                    const _Float16 h0 = (_Float16)((float)b0 * (1.0f / 255.0f));
+                    const _Float16 h1 = (_Float16)((float)b1 * (1.0f / 255.0f));
+                    *reinterpret_cast<uint32_t*>(r0 + frow * kP0 + fcol + j) =
+                        (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                        ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+                }
+            }
+        }
         int nb, nblk2;
         next(b, blk, nb, nblk2);
         __syncthreads();
-        {  // conv1: K = the 9 taps of the single input channel
-            const float* bias = pk_bias(p.pk, 0);
-            constexpr int nxg = (kR1 + 15) / 16;
-            for (int task = wave; task < kR1 * nxg; task += nw) {
-                const int ly = task / nxg, xg = task - ly * nxg;
-                const int lx = xg * 16 + col;
-                const int base = 2 * ly * kR0 + 32 * xg;
-                h4 B;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    B[j] = (_Float16)((float)r0[min(base + off1[j], kR0 * kR0 - 1)] * (1.0f / 255.0f));
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-                acc = mfma16(A1, B, acc);
-                const int y1 = Y1 + ly, x1 = X1 + lx;
-                if (lx < kR1)
-                    put_relu(r1, kR1, true, ly, lx, y1 >= 0 && y1 < p.H1 && x1 >= 0 && x1 < p.W1, acc,
-                             bias, grp);
-            }
-        }
         // the next block's input bytes travel while this one computes
         if (nb < p.batch) fetch(nb, nblk2, v);
-        __syncthreads();
-        {  // conv2, two tiles per wave at a time (independent MFMA chains)
-            const float* bias = pk_bias(p.pk, 1);
-            constexpr int nxg = (kR2 + 15) / 16;
-            constexpr int ntask = kR2 * nxg;
-            for (int t0 = wave; t0 < ntask; t0 += 2 * nw) {
-                const int t1 = min(t0 + nw, ntask - 1);
-                const int ly0 = t0 / nxg, lx0 = (t0 - ly0 * nxg) * 16 + col;
-                const int ly1 = t1 / nxg, lx1 = (t1 - ly1 * nxg) * 16 + col;
-                // columns past the window read a clamped in-window pixel; their
-                // outputs are dropped (a lane's column only feeds its own output)
-                const int b0 = (2 * ly0 * kR1 + min(lx0, kR2 - 1)) * 16 + 4 * grp;
-                const int b1 = (2 * ly1 * kR1 + min(lx1, kR2 - 1)) * 16 + 4 * grp;
-                const f4 a0 = conv16_lds<2, kR1>(r1, b0, T2);
-                const f4 a1 = conv16_lds<2, kR1>(r1, b1, T2);
-                const int y20 = Y2 + ly0, x20 = X2 + lx0, y21 = Y2 + ly1, x21 = X2 + lx1;
-                if (lx0 < kR2)
-                    put_relu(r2, kR2, true, ly0, lx0, y20 >= 0 && y20 < p.H2 && x20 >= 0 && x20 < p.W2,
-                             a0, bias, grp);
-                if (t0 + nw < ntask && lx1 < kR2)
-                    put_relu(r2, kR2, true, ly1, lx1, y21 >= 0 && y21 < p.H2 && x21 >= 0 && x21 < p.W2,
-                             a1, bias, grp);
-            }
-        }
-        __syncthreads();
-        {  // conv3
-            const Taps T3 = load_taps(wk + kPkW3, col, grp);
-            const float* bias = pk_bias(p.pk, 2);
-            for (int ly = wave; ly < kR3; ly += nw) {
-                const int lx = col;
-                const int base = (2 * ly * kR2 + min(lx, kR3 - 1)) * 16 + 4 * grp;
-                const f4 acc = conv16_lds<2, kR2>(r2, base, T3);
-                const int y3 = Y3 + ly, x3 = X3 + lx;
-                if (lx < kR3)
-                    put_relu(r3, kR3, false, ly, lx, y3 >= 0 && y3 < p.H3 && x3 >= 0 && x3 < p.W3, acc,
-                             bias, grp);
-            }
-        }
-        __syncthreads();
-        {  // head: logits, no ReLU
-            const Taps T4 = load_taps(wk + kPkW4, col, grp);
-            const float* bias = pk_bias(p.pk, 3);
-            for (int ly = wave; ly < kFT; ly += nw) {
-                const int lx = col;
-                const int base = (ly * kR3 + min(lx, kFT - 1)) * 16 + 4 * grp;
-                const f4 acc = conv16_lds<1, kR3>(r3, base, T4);
-                const int y4 = Y4 + ly, x4 = X4 + lx;
-                if (lx < kFT && y4 < p.H3 && x4 < p.W3) {
+        {  // conv1: K = the 9 taps of the single input channel; three tiles per row
+            bool xin[3];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int co = 4 * grp + j;
-                        if (co < 9)
-                            gst(p.logits + (((size_t)b * 9 + co) * p.H3 + y4) * p.W3 + x4,
-                                acc[j] + bias[co]);
+            for (int xg = 0; xg < 3; ++xg) {
+                const int x1 = X1 + 16 * xg + col;
+                xin[xg] = x1 >= 0 && x1 < p.W1;
+            }
+            for (int ly = wave; ly < kR1; ly += nw) {
+                const int y1 = Y1 + ly;
+                const bool yin = y1 >= 0 && y1 < p.H1;
+                f4 acc[3];
+#pragma unroll
+                for (int xg = 0; xg < 3; ++xg) {
+                    const _Float16* q = r0 + 2 * ly * kP0 + 2 * (16 * xg + col);
+                    const h4 B = {q[off1[0]], q[off1[1]], q[off1[2]], q[off1[3]]};
+                    const f4 z = {0.f, 0.f, 0.f, 0.f};
+                    acc[xg] = mfma16(A1, B, z);
+                }
+#pragma unroll
+                for (int xg = 0; xg < 3; ++xg)
+                    if (16 * xg + col < kR1)
+                        *reinterpret_cast<h4*>(r1 + (ly * kR1 + cx1[xg]) * 16 + 4 * grp) =
+                            relu4(acc[xg], bias1, yin && xin[xg]);
+            }
+        }
+        __syncthreads();
+        {  // conv2: flat tiles of the 21x21 output, stride 2 from the de-interleaved r1
+            auto tap2 = [](int t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+                return (ky * kR1 + (kx == 1 ? (kR1 + 1) / 2 : kx >> 1)) * 16;
+            };
+            // tile t = wave + 8 i: output pixel (y, x) of the 21x21 window, its
+            // first input in r1 (row 2y, column x of the even half) and its
+            // de-interleaved slot in r2
+#pragma unroll 2
+            for (int i = 0; i < 4; ++i) {
+                if (wave + nw * i < kT2) {
+                    const int n = 16 * (wave + nw * i) + col;
+                    const int nc = min(n, kR2 * kR2 - 1);
+                    const int y = nc / kR2, x = nc - y * kR2;
+                    const f4 acc = conv16x32(r1, (2 * y * kR1 + x) * 16, grp, T2, tap2);
+                    const int y2 = Y2 + y, x2 = X2 + x;
+                    if (n < kR2 * kR2)
+                        *reinterpret_cast<h4*>(r2 + (y * kR2 + deint(x, kR2)) * 16 + 4 * grp) =
+                            relu4(acc, bias2, y2 >= 0 && y2 < p.H2 && x2 >= 0 && x2 < p.W2);
+                }
+            }
+        }
+        __syncthreads();
+        if (wave < kT3) {  // conv3: stride 2 from the de-interleaved r2 into r3 (plain layout)
+            auto tap3 = [](int t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+                return (ky * kR2 + (kx == 1 ? (kR2 + 1) / 2 : kx >> 1)) * 16;
+            };
+            // (conv3's weights come from the L2 here: kept in registers for the
+            // whole kernel they would push it past 128 registers per lane)
+            const Taps2 T3 = load_taps2(wk + kPkW3, col, grp);
+            const f4 acc = conv16x32(r2, in3, grp, T3, tap3);
+            const f4 bias3 = *reinterpret_cast<const f4*>(s_bias + 32 + 4 * grp);
+            const int y3 = Y3 + y3l, x3 = X3 + x3l;
+            if (16 * wave + col < kR3 * kR3)
+                *reinterpret_cast<h4*>(r3 + out3) =
+                    relu4(acc, bias3, y3 >= 0 && y3 < p.H3 && x3 >= 0 && x3 < p.W3);
+        }
+        __syncthreads();
+        if (wave < kT4) {  // head: logits, no ReLU, stride 1 from r3
+            Taps2 T4;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int tap = 2 * q + (grp >> 1);
+                h8 w = {};
+                if (tap < 9) w = *reinterpret_cast<const h8*>(s_w4 + (tap * 16 + col) * 16 + 8 * (grp & 1));
+                T4.a[q] = w;
+            }
+            auto tap4 = [](int t) { return ((t / 3) * kR3 + t - 3 * (t / 3)) * 16; };
+            const f4 acc = conv16x32(r3, in4, grp, T4, tap4);
+            f4 z;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) z[j] = acc[j] + s_bias[48 + min(4 * grp + j, 15)];
+            const int y4 = Y4 + y4l, x4 = X4 + x4l;
+            const bool tile_in = y4 < p.H3 && x4 < p.W3;
+            if (tile_in) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int co = 4 * grp + j;
+                    if (co < 9) gst(p.logits + (((size_t)b * 9 + co) * p.H3 + y4) * p.W3 + x4, z[j]);
+                }
+            }
+            if (p.mask) {
+                // the tile's nine logits meet in its group-0 lane (channels 4..7
+                // from group 1, 8 from group 2), which applies the mask rule
+                float zb[8];
+                zb[0] = z[1];
+                zb[1] = z[2];
+                zb[2] = z[3];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) zb[3 + j] = __shfl(z[j], col + 16);
+                zb[7] = __shfl(z[0], col + 32);
+                if (grp == 0 && tile_in) {
+                    uint8_t m;
+                    if (z[0] >= p.t_hi) {
+                        int bits = 0, arg = 0;
+                        float best = zb[0];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            if (zb[c] >= 0.f) bits |= 1 << c;
+                            if (zb[c] > best) {
+                                best = zb[c];
+                                arg = c;
+                            }
+                        }
+                        m = (uint8_t)(bits ? bits : (1 << arg));
+                    } else if (z[0] <= -p.t_hi) {
+                        m = 0;
+                    } else {
+                        m = 0xFF;
                     }
+                    gst(p.mask + ((size_t)b * p.H3 + y4) * p.W3 + x4, m);
                 }
             }
         }
@@ -910,14 +1031,19 @@ LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t
 
 // Inference with per-frame switches (device uint8 [batch] or null): one
 // persistent launch of the fused kernel; switched-off frames are skipped
-// whole and keep their previous logits.
-LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
-                                        int64_t img_stride, int32_t batch, const void* packed,
-                                        float* logits, const uint8_t* active, void* stream) {
+// whole and keep their previous logits.  With mask != null the kernel also
+// writes the tile masks of lane_mask_from_logits (confidence conf) from the
+// same logits, so no mask pass follows.
+LANE_INTERNAL int lane_cnn_infer_mask_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                             int64_t img_stride, int32_t batch, const void* packed,
+                                             float* logits, float conf, uint8_t* mask,
+                                             const uint8_t* active, void* stream) {
     if (!img || !packed || !logits || W < 1 || H < 1 || pitch < W || batch < 1 ||
         img_stride < (int64_t)H * pitch || !a16(packed))
         return LANE_E_ARG;
+    if (mask && !(conf > 0.5f && conf < 1.f)) return LANE_E_ARG;
     if (W > LANE_MAX_DIM || H > LANE_MAX_DIM || batch > 4096) return LANE_E_SIZE;
+    if ((int64_t)pitch * H > 0x7FFFFFFFll) return LANE_E_SIZE;  // a frame is one raw buffer
     const Geo g = geo(W, H);
     CnnInfer p;
     memset(&p, 0, sizeof(p));
@@ -933,6 +1059,9 @@ LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H
     p.by = (g.H3 + kFT - 1) / kFT;
     p.batch = batch;
     p.active = active;
+    p.mask = mask;
+    // the decision threshold in float32, the same value lane_mask_from_logits uses
+    p.t_hi = mask ? (float)log((double)conf / (1.0 - (double)conf)) : 0.f;
     int dev = 0, cus = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -941,6 +1070,13 @@ LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H
     const int grid = std::max(1, std::min(p.bx * p.by, 2 * cus));
     hipLaunchKernelGGL(k_cnn_infer, dim3(grid), dim3(kInferThreads), 0, (hipStream_t)stream, p);
     return hipGetLastError() == hipSuccess ? LANE_OK : LANE_E_DEVICE;
+}
+
+LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                        int64_t img_stride, int32_t batch, const void* packed,
+                                        float* logits, const uint8_t* active, void* stream) {
+    return lane_cnn_infer_mask_active(img, W, H, pitch, img_stride, batch, packed, logits, 0.f,
+                                      nullptr, active, stream);
 }
 
 int lane_cnn_infer(const uint8_t* img, int32_t W, int32_t H, int32_t pitch, int64_t img_stride,

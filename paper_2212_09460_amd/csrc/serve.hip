@@ -36,12 +36,10 @@
 extern "C" {
 LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
 LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
-LANE_INTERNAL int lane_cnn_infer_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
-                                        int64_t img_stride, int32_t batch, const void* packed,
-                                        float* logits, const uint8_t* active, void* stream);
-LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
-                                               int32_t batch, float conf, uint8_t* mask,
-                                               const uint8_t* active, void* stream);
+LANE_INTERNAL int lane_cnn_infer_mask_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                                             int64_t img_stride, int32_t batch, const void* packed,
+                                             float* logits, float conf, uint8_t* mask,
+                                             const uint8_t* active, void* stream);
 LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream);
 }
 
@@ -76,6 +74,7 @@ int check_cfg(const lane_server_cfg& c) {
     if (c.sobel_strip_rows < 0 || (c.sobel_strip_rows % 8) != 0) return LANE_E_ARG;
     if (c.vote_split < 0 || c.vote_split > 64) return LANE_E_ARG;
     if (c.pruned && (!c.cnn_params || !(c.conf > 0.5f && c.conf < 1.f))) return LANE_E_ARG;
+    if (c.deadline_ns < 0) return LANE_E_ARG;
     return LANE_OK;
 }
 
@@ -211,6 +210,7 @@ struct lane_server {
     lane_result* replay_out = nullptr;
     int64_t replay_left = 0;
     bool stop = false;
+    bool paused = false;
     int error = LANE_OK;
     lane_server_stats stats;
     std::thread worker;
@@ -301,14 +301,26 @@ void worker_main(lane_server* s) {
                 if (!d.empty()) return true;
             return false;
         };
-        s->cv_work.wait(lk, [&] { return s->stop || any(); });
+        s->cv_work.wait(lk, [&] { return s->stop || (!s->paused && any()); });
         if (s->stop) break;
+        // the oldest request of every stream; with a deadline, requests that
+        // waited too long are completed unrun and the next one takes the place
         batch.clear();
+        const int64_t t_take = now_ns();
         for (auto& d : s->pending) {
+            while (!d.empty() && s->cfg.deadline_ns > 0 && t_take - d.front().t_submit > s->cfg.deadline_ns) {
+                lane_result r;
+                fill_result(r, d.front(), LANE_E_TIMEOUT);
+                r.t_start_ns = r.t_done_ns = t_take;
+                s->stats.timed_out += 1;
+                complete(s, r, d.front().tag);
+                d.pop_front();
+            }
             if (d.empty()) continue;
             batch.push_back(d.front());
             d.pop_front();
         }
+        if (batch.empty()) continue;
         const int64_t t_start = now_ns();
         const bool failed = s->error != LANE_OK;
         lk.unlock();
@@ -612,12 +624,10 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
                 if (c < 32 && !((cls_mask >> c) & 1u)) continue;
                 auto& cl = s->classes[c];
                 const uint8_t* fl = s->d_flags + cl.first_slot;
-                cst = lane_cnn_infer_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
-                                            (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
-                                            cl.logits, fl, side);
-                if (cst == LANE_OK)
-                    cst = lane_mask_from_logits_active(cl.logits, cl.cfg.W, cl.cfg.H, cl.n, cfg->conf,
-                                                       cl.mask, fl, side);
+                // network and tile masks in one kernel
+                cst = lane_cnn_infer_mask_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
+                                                 (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
+                                                 cl.logits, cfg->conf, cl.mask, fl, side);
                 if (cst != LANE_OK) break;
             }
             if (e == hipSuccess) e = hipEventRecord(ev_join, side);
@@ -724,6 +734,16 @@ int lane_server_stats_get(lane_server* s, lane_server_stats* out) {
     std::lock_guard<std::mutex> g(s->mu);
     *out = s->stats;
     out->error = s->error;
+    return LANE_OK;
+}
+
+int lane_server_pause(lane_server* s, int32_t paused) {
+    if (!s || (paused != 0 && paused != 1)) return LANE_E_ARG;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->paused = paused != 0;
+    }
+    s->cv_work.notify_all();
     return LANE_OK;
 }
 

@@ -94,7 +94,7 @@ EXPORTS = ("lane_abi_version", "lane_strerror", "lane_make_trig_q14", "lane_r_of
            "lane_cnn_loss", "lane_cnn_backward", "lane_adam_step", "lane_tile_labels",
            "lane_mask_from_logits", "lane_cnn_infer", "lane_batch_active_flags", "lane_batch_select", "lane_server_plan",
            "lane_server_create", "lane_server_submit", "lane_server_poll", "lane_server_replay",
-           "lane_server_stats_get", "lane_server_destroy")
+           "lane_server_stats_get", "lane_server_destroy", "lane_server_pause")
 
 
 class LaneError(RuntimeError):
@@ -678,6 +678,7 @@ def mask_from_logits(logits, W: int, H: int, batch: int, conf: float, mask, stre
 # ---------------------------------------------------------------- serving --
 
 LANE_E_BUSY = -7
+LANE_E_TIMEOUT = -8
 SERVE_MAX_K = 64
 
 
@@ -689,7 +690,7 @@ class StreamCfg(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", _sz), ("pruned", _i32), ("conf", ctypes.c_float),
                 ("cnn_params", _vp), ("max_pending", _i32), ("vote_rows", _i32),
-                ("sobel_strip_rows", _i32), ("vote_split", _i32)]
+                ("sobel_strip_rows", _i32), ("vote_split", _i32), ("deadline_ns", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -709,7 +710,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("dropped", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("frames_in_batches", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("streams_admitted", _i32), ("error", _i32)]
+                ("streams_admitted", _i32), ("error", _i32), ("timed_out", ctypes.c_int64)]
 
 
 _srv_plan = _sig("lane_server_plan", [ctypes.POINTER(StreamCfg), _i32, ctypes.POINTER(ServerCfg),
@@ -723,10 +724,11 @@ _srv_replay = _sig("lane_server_replay", [_vp, ctypes.POINTER(Request), _i32,
                                           ctypes.POINTER(Result)])
 _srv_stats = _sig("lane_server_stats_get", [_vp, ctypes.POINTER(ServerStats)])
 _srv_destroy = _sig("lane_server_destroy", [_vp])
+_srv_pause = _sig("lane_server_pause", [_vp, _i32])
 
 
 def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, sobel_strip_rows,
-                vote_split=0):
+                vote_split=0, deadline_ms=0.0):
     import numpy as np
 
     keep = None
@@ -734,8 +736,20 @@ def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, so
         keep = np.ascontiguousarray(np.asarray(cnn_params, dtype=np.float32))
     cfg = ServerCfg(int(hbm_budget), int(pruned), float(conf),
                     None if keep is None else keep.ctypes.data, int(max_pending), int(vote_rows),
-                    int(sobel_strip_rows), int(vote_split))
+                    int(sobel_strip_rows), int(vote_split), int(round(deadline_ms * 1e6)))
     return cfg, keep
+
+
+def _host_frame(frame):
+    """A frame the server may read later: host uint8 [H][pitch] with rows of
+    contiguous bytes."""
+    import numpy as np
+
+    if not isinstance(frame, np.ndarray) or frame.dtype != np.uint8 or frame.ndim != 2:
+        raise TypeError("a frame is a host numpy uint8 array [H][pitch]")
+    if frame.strides[1] != 1 or frame.strides[0] < frame.shape[1]:
+        raise ValueError("frame rows must be contiguous bytes (strides[1] == 1, pitch >= W)")
+    return frame
 
 
 def _stream_cfgs(streams):
@@ -772,26 +786,34 @@ class Server:
 
     def __init__(self, streams, hbm_budget: int = 8 << 30, pruned: bool = False,
                  conf: float = 0.9, cnn_params=None, max_pending: int = 4, vote_rows: int = 0,
-                 sobel_strip_rows: int = 0, vote_split: int = 0):
+                 sobel_strip_rows: int = 0, vote_split: int = 0, deadline_ms: float = 0.0):
+        import collections
+
         import numpy as np
 
         self.streams = [dict(s) for s in streams]
         arr = _stream_cfgs(streams)
         cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
-                                sobel_strip_rows, vote_split)
+                                sobel_strip_rows, vote_split, deadline_ms)
         adm = np.zeros(len(streams), np.uint8)
         h = _vp()
         _check(_srv_create(arr, len(streams), ctypes.byref(cfg), ctypes.byref(h), adm.ctypes.data),
                "lane_server_create")
         self._h = h
         self.admitted = [bool(a) for a in adm]
-        self._hold = {}
+        # frames submitted and not yet polled, per stream in submission order:
+        # a stream's requests complete in that order, so each polled result
+        # releases the oldest held frame of its stream
+        self._hold = collections.defaultdict(collections.deque)
 
     def submit(self, stream: int, frame, frame_id: int = 0) -> int:
-        """frame: host numpy uint8 [H][pitch]; kept alive until its result is polled."""
+        """frame: host numpy uint8 [H][pitch]; kept alive until its result is
+        polled.  Returns LANE_OK or LANE_E_BUSY (dropped: its result is
+        already complete and holds no frame)."""
+        frame = _host_frame(frame)
         rc = _srv_submit(self._h, stream, frame.ctypes.data, frame.strides[0], frame_id)
         if rc == LANE_OK:
-            self._hold[(stream, frame_id)] = frame
+            self._hold[stream].append(frame)
         elif rc != LANE_E_BUSY:
             _check(rc, "lane_server_submit")
         return rc
@@ -802,13 +824,19 @@ class Server:
         _check(_srv_poll(self._h, out, max_n, wait_ms, ctypes.byref(n)), "lane_server_poll")
         res = [out[i] for i in range(n.value)]
         for r in res:
-            self._hold.pop((r.stream, r.frame_id), None)
+            if r.status != LANE_E_BUSY and self._hold[r.stream]:
+                self._hold[r.stream].popleft()
         return res
+
+    def pause(self, paused: bool = True):
+        """Hold (True) or resume (False) the worker; requests keep queueing."""
+        _check(_srv_pause(self._h, 1 if paused else 0), "lane_server_pause")
 
     def replay(self, reqs):
         """reqs: list of (stream, t_offset_s, frame ndarray, frame_id); returns results in order."""
         arr = (Request * len(reqs))()
         for i, (st, t, fr, fid) in enumerate(reqs):
+            fr = _host_frame(fr)
             arr[i] = Request(st, fr.strides[0], int(round(t * 1e9)), fr.ctypes.data, fid)
         out = (Result * len(reqs))()
         _check(_srv_replay(self._h, arr, len(reqs), out), "lane_server_replay")

@@ -107,7 +107,9 @@ class EvalPlans:
 def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920, H=1080,
              baselines=True, workers=16, verbose=True):
     dev = torch.device("cuda")
-    P = EvalPlans(W, H, batch, dev)
+    # batches of `batch` frames and a last, partial one for the remainder
+    sizes = [batch] * (n_frames // batch) + ([n_frames % batch] if n_frames % batch else [])
+    plans = {b: EvalPlans(W, H, b, dev) for b in sorted(set(sizes))}
     rand_net = ProposalNet(seed=12345) if baselines else None
     gpool = ThreadPoolExecutor(max_workers=workers)
     stream = torch.cuda.current_stream()
@@ -117,11 +119,12 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
                t_fall=0, t_band=0, ms_plain=0.0, ms_pruned=0.0, ms_cnn=0.0, frames=0)
     rnd = dict(m4=0, n4=0, m8=0, n8=0, votes=0)
     heur_stats = []  # per frame: (tile counts, plain peaks) for the budget-matched heuristic
-    nb = n_frames // batch
+    nb = len(sizes)
     scene = synth.scene_road(W, H)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    first = 0
 
-    def run_pruned(mask_src):
+    def run_pruned(P, mask_src):
         P.mask.copy_(mask_src)
         P.pruned_plan.launch(stream)
         torch.cuda.synchronize()
@@ -133,7 +136,10 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
         return out
 
     for bi in range(nb):
-        seeds = [seed_base + bi * batch + i for i in range(batch)]
+        batch = sizes[bi]
+        P = plans[batch]
+        seeds = [seed_base + first + i for i in range(batch)]
+        first += batch
         frames = gen_batch(gpool, W, H, seeds)
         P.imgs.copy_(torch.from_numpy(frames))
         # plain
@@ -199,7 +205,7 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
             rl = rand_net.forward(P.imgs, stream=stream)
             rm = torch.empty_like(P.mask)
             lane.mask_from_logits(rl, W, H, batch, conf, rm, stream)
-            res = run_pruned(rm)
+            res = run_pruned(P, rm)
             for b in range(batch):
                 pp = P.plain[b].peaks.cpu().numpy()
                 pt, pr, pn = pp[:TOPK], pp[TOPK:2 * TOPK], int(pp[3 * TOPK])
@@ -240,11 +246,28 @@ def evaluate(net, n_frames=1000, batch=16, seed_base=2_000_000, conf=0.9, W=1920
         res["random_init"] = dict(
             agreement_top4=rnd["m4"] / max(1, rnd["n4"]), agreement_top8=rnd["m8"] / max(1, rnd["n8"]),
             votes_fraction=rnd["votes"] / max(1, agg["votes_plain"]))
-        res["heuristic"] = heuristic_at_budget(P, heur_stats, frac)
+        res["heuristic"] = heuristic_at_budget(plans[sizes[0]], heur_stats, frac)
     gpool.shutdown()
-    P.plain_plan.close()
-    P.pruned_plan.close()
+    for P in plans.values():
+        P.plain_plan.close()
+        P.pruned_plan.close()
     return res
+
+
+def frontier(net, confs=(0.9, 0.99, 0.999, 0.9999), n_frames=1000, batch=20, verbose=True):
+    """Agreement with the plain top-4 / top-8 against the votes kept, over
+    mask confidences: a higher confidence sends more tiles to the full vote
+    (fallback), trading vote savings for agreement."""
+    rows = []
+    for c in confs:
+        r = evaluate(net, n_frames, batch, conf=c, baselines=False, verbose=verbose)
+        rows.append({k: r[k] for k in ("conf", "frames", "agreement_top4", "agreement_top8",
+                                       "missed_top4", "votes_fraction", "tiles_skip",
+                                       "tiles_band", "tiles_fallback", "lanes_found_top4_pruned",
+                                       "vote_ms_per_frame_plain", "vote_ms_per_frame_pruned")})
+        if verbose:
+            print("[frontier]", json.dumps(rows[-1]), flush=True)
+    return rows
 
 
 def heuristic_at_budget(P, stats, frac):
@@ -300,9 +323,16 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--conf", type=float, nargs="+", default=[0.9])
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--frontier", action="store_true",
+                    help="agreement against votes kept for every --conf (no baselines)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     net, _ = ProposalNet.load(a.weights)
+    if a.frontier:
+        rows = frontier(net, a.conf, a.frames, a.batch)
+        if a.out:
+            json.dump(rows, open(a.out, "w"), indent=1)
+        return
     allres = []
     for c in a.conf:
         res = evaluate(net, a.frames, a.batch, conf=c, baselines=not a.no_baselines)

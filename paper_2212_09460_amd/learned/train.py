@@ -32,12 +32,13 @@ class LabelPlan:
     """Plain batched path over a reusable [B][H][W] image tensor, plus the
     per-frame label buffers."""
 
-    def __init__(self, W: int, H: int, B: int, device="cuda"):
+    def __init__(self, W: int, H: int, B: int, device="cuda", k: int = TOPK):
         self.W, self.H, self.B = W, H, B
         self.imgs = torch.empty((B, H, W), dtype=torch.uint8, device=device)
         C, S = synth.trig_q14(N_THETA)
         self.C, self.S = torch.from_numpy(C).to(device), torch.from_numpy(S).to(device)
-        self.fbs = [lane.FrameBuffers(self.imgs[b], W, N_THETA, TOPK, self.C, self.S)
+        # the labels mark the tiles that vote for the top-k plain peaks
+        self.fbs = [lane.FrameBuffers(self.imgs[b], W, N_THETA, k, self.C, self.S)
                     for b in range(B)]
         self.plan = lane.Batch(self.fbs)
         th, tw = (H + 7) // 8, (W + 7) // 8
@@ -61,17 +62,17 @@ def lr_at(step, total, lr0, lr_min):
 
 def train(n_frames=20000, batch=16, lr=2e-3, lr_min=1e-4, seed_base=1_000_000, out=None,
           resume=None, log_every=50, ckpt_every=250, workers=16, init_seed=0, max_seconds=None,
-          verbose=True, epochs=1):
+          verbose=True, epochs=1, label_k=TOPK):
     """Adam over `epochs` passes of the n_frames training frames (the same
     seeds each pass, each seed always at the same size), cosine LR decay over
-    all steps."""
+    all steps.  label_k: the labels come from the top-label_k plain peaks."""
     dev = torch.device("cuda")
     if resume and os.path.exists(resume):
         net, meta = ProposalNet.load(resume)
         start = int(meta.get("cursor", net.step))
     else:
         net, start = ProposalNet(seed=init_seed), 0
-    plans = {sz: LabelPlan(sz[0], sz[1], batch, dev) for sz in SIZES}
+    plans = {sz: LabelPlan(sz[0], sz[1], batch, dev, label_k) for sz in SIZES}
     per_epoch = n_frames // batch
     total = per_epoch * epochs
     pool = ThreadPoolExecutor(max_workers=workers)
@@ -106,13 +107,14 @@ def train(n_frames=20000, batch=16, lr=2e-3, lr_min=1e-4, seed_base=1_000_000, o
                       f"lr {lr_at(step, total, lr, lr_min):.2e} {time.time() - t0:.1f}s", flush=True)
         if out and ((step + 1) % ckpt_every == 0 or step + 1 == total):
             net.save(out, cursor=np.array(step + 1, np.int64), seed_base=np.array(seed_base),
-                     batch=np.array(batch), n_frames=np.array(n_frames))
+                     batch=np.array(batch), n_frames=np.array(n_frames), label_k=np.array(label_k))
         if max_seconds and time.time() - t0 > max_seconds:
             if verbose:
                 print(f"[train] stopping at step {step + 1} (time limit)", flush=True)
             if out:
                 net.save(out, cursor=np.array(step + 1, np.int64), seed_base=np.array(seed_base),
-                         batch=np.array(batch), n_frames=np.array(n_frames))
+                         batch=np.array(batch), n_frames=np.array(n_frames),
+                         label_k=np.array(label_k))
             break
     pool.shutdown()
     pool_gen.shutdown()
@@ -130,9 +132,11 @@ def main():
     ap.add_argument("--max-seconds", type=float, default=None)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--label-k", type=int, default=TOPK,
+                    help="labels from the top-k plain peaks (default 8)")
     a = ap.parse_args()
     train(a.frames, a.batch, a.lr, out=a.out, resume=a.resume, max_seconds=a.max_seconds,
-          workers=a.workers, epochs=a.epochs)
+          workers=a.workers, epochs=a.epochs, label_k=a.label_k)
 
 
 if __name__ == "__main__":

@@ -42,7 +42,7 @@ def test_binding_lists_every_declared_symbol():
 
 
 def test_abi_version_and_strerror(lib):
-    assert lib.lane_abi_version() == 1
+    assert lib.lane_abi_version() == 2
     lib.lane_strerror.restype = ctypes.c_char_p
     assert lib.lane_strerror(0) == b"ok"
     assert b"workspace" in lib.lane_strerror(E_WS)

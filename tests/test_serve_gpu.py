@@ -208,3 +208,80 @@ def test_server_at_serving_sizes(lane, synth, oracle, pruned):
         assert any(r.batch_frames > 1 for r in out)
     finally:
         srv.close()
+
+
+def test_deadline_frees_places_and_others_run(lane, synth):
+    """Forced from the host: with the worker paused, stream 0 queues two
+    requests (a third is dropped) and waits past its deadline; on resume those
+    two complete unrun with LANE_E_TIMEOUT, stream 1's request submitted just
+    before the resume runs normally, and stream 0's next requests find free
+    places and give the same peaks as their frames alone."""
+    say("serve: deadline, pause, places freed")
+    import time
+
+    P = pools(synth, STREAMS[:2], seed=700)
+    refs = [[alone(lane, P[s][j], STREAMS[s]) for j in range(3)] for s in range(2)]
+    srv = lane.Server(STREAMS[:2], hbm_budget=1 << 30, max_pending=2, deadline_ms=20.0)
+    try:
+        srv.pause(True)
+        assert srv.submit(0, P[0][0], frame_id=1) == 0
+        assert srv.submit(0, P[0][1], frame_id=2) == 0
+        assert srv.submit(0, P[0][2], frame_id=3) == lane.LANE_E_BUSY  # queue full: dropped
+        time.sleep(0.06)                                             # past the deadline
+        assert srv.submit(1, P[1][0], frame_id=10) == 0              # fresh
+        srv.pause(False)
+        got = {}
+        while len(got) < 4:
+            rs = srv.poll(8, wait_ms=5000)
+            assert rs, "poll timed out"
+            for r in rs:
+                got[r.frame_id] = r
+        assert got[1].status == lane.LANE_E_TIMEOUT and got[2].status == lane.LANE_E_TIMEOUT
+        assert got[3].status == lane.LANE_E_BUSY
+        assert got[10].status == 0 and same(got[10], refs[1][0], 8)
+        # stream 0's places are free again
+        for j, fid in ((0, 20), (1, 21)):
+            assert srv.submit(0, P[0][j], frame_id=fid) == 0
+        done = []
+        while len(done) < 2:
+            rs = srv.poll(8, wait_ms=5000)
+            assert rs, "poll timed out"
+            done += rs
+        for r in done:
+            assert r.status == 0 and same(r, refs[0][r.frame_id - 20], 8)
+        st = srv.stats()
+        assert st["timed_out"] == 2 and st["dropped"] == 1 and st["error"] == 0
+        assert st["completed"] == 3
+    finally:
+        srv.close()
+
+
+def test_stalled_stream_does_not_hold_the_others(lane, synth):
+    """Stream 0 sends a burst and then stalls for most of the run while
+    streams 1 and 2 keep sending: every request completes, each with its
+    frame's peaks, and the others' requests never wait for stream 0."""
+    say("serve: stalled stream")
+    streams = STREAMS[:3]
+    P = pools(synth, streams, seed=800)
+    refs = [[alone(lane, P[s][j], streams[s]) for j in range(3)] for s in range(3)]
+    srv = lane.Server(streams, hbm_budget=1 << 30, max_pending=8)
+    try:
+        reqs = [(0, 0.001 * i, P[0][i % 3], i) for i in range(4)]            # burst, then silence
+        t = 0.0
+        for i in range(4, 60):
+            t += 0.002
+            reqs.append((1 + (i % 2), t, P[1 + (i % 2)][i % 3], i))
+        reqs.append((0, t + 0.002, P[0][0], 60))                              # stream 0 returns
+        reqs.sort(key=lambda q: q[1])
+        out = list(srv.replay(reqs))
+        for q, r in zip(reqs, out):
+            s, _, _, fid = q
+            assert r.status == 0 and r.stream == s and r.frame_id == fid
+            j = 0 if fid == 60 else fid % 3
+            assert same(r, refs[s][j], streams[s].get("k", 8)), fid
+        # the other streams' latencies stay at one or two refills (no waiting
+        # on stream 0, which has nothing queued during its silence)
+        lat = [(r.t_done_ns - r.t_submit_ns) / 1e6 for q, r in zip(reqs, out) if q[0] != 0]
+        assert max(lat) < 20.0
+    finally:
+        srv.close()

@@ -125,3 +125,24 @@ def test_create_fails_cleanly_without_budget_or_device(lane):
     with pytest.raises(lane.LaneError) as e:  # no device: an error, not a crash
         lane.Server([dict(W=64, H=64)], hbm_budget=1 << 30)
     assert e.value.code == -5
+
+
+def test_host_frames_are_checked_before_submission(lane):
+    """The binding refuses frames the server could not read as uint8 rows."""
+    ok = np.zeros((4, 8), np.uint8)
+    assert lane._host_frame(ok) is ok
+    assert lane._host_frame(np.zeros((4, 16), np.uint8)[:, :8]) is not None  # pitch 16, W 8
+    with pytest.raises(TypeError):
+        lane._host_frame(np.zeros((4, 8), np.int16))
+    with pytest.raises(TypeError):
+        lane._host_frame(np.zeros((2, 4, 8), np.uint8))
+    with pytest.raises(ValueError):
+        lane._host_frame(np.zeros((8, 4), np.uint8).T)                     # columns not contiguous
+
+
+def test_deadline_must_not_be_negative(lane, serve):
+    st = serve.mix_streams()[:2]
+    cfg, _ = lane._server_cfg(1 << 30, False, 0.9, None, 4, 0, 0, 0, deadline_ms=-1.0)
+    arr = lane._stream_cfgs(st)
+    rc = lane._srv_plan(arr, len(st), ctypes.byref(cfg), None, None, None)
+    assert rc == -1  # LANE_E_ARG
