@@ -24,6 +24,11 @@ __device__ __forceinline__ void gst(T* p, T v) { *(LANE_GLOBAL T*)p = v; }
 __device__ __forceinline__ u32x4 gld4(const void* p) { return *(const LANE_GLOBAL u32x4*)p; }
 __device__ __forceinline__ void gst4(void* p, u32x4 v) { *(LANE_GLOBAL u32x4*)p = v; }
 
+// Raw buffer loads: an offset past the buffer's size returns zero (used for
+// reads outside a frame without branches).
+constexpr uint32_t kBufOutside = 0x80000000u;
+constexpr int kBufConfig = 0x00020000;  // raw buffer, 32-bit format (gfx9 family)
+
 constexpr int kWave = 64;
 constexpr int kTile = 8;                 // edge tiles are 8x8 pixels
 constexpr int kChunkPx = 1024;           // one wave covers 64 lanes x 16 px

@@ -49,8 +49,6 @@ struct RawRow {
 // the frame passes an offset past the end and the hardware returns zeros.
 // No branch and no merge of loaded and zero values, so the loads kept in
 // flight across the row loop never force a wait for all of them.
-constexpr uint32_t kBufOutside = 0x80000000u;
-constexpr int kBufConfig = 0x00020000;  // raw buffer, 32-bit format (gfx9 family)
 
 template <bool FAST>
 __device__ __forceinline__ RawRow load_raw(const uint8_t* __restrict__ img, __amdgpu_buffer_rsrc_t rsrc,
@@ -208,7 +206,9 @@ __device__ __forceinline__ uint32_t vout(const SobelDesc& d, int y, int x0, bool
             }
         }
         if (FAST) {
-            gst4(d.edges + o, u32x4{eb[0], eb[1], eb[2], eb[3]});
+            // written once and not read again by the pass: streaming store
+            __builtin_nontemporal_store(u32x4{eb[0], eb[1], eb[2], eb[3]},
+                                        (LANE_GLOBAL u32x4*)(d.edges + o));
             if (d.mag) gst4(d.mag + o, u32x4{mb[0], mb[1], mb[2], mb[3]});
         } else {
 #pragma unroll
@@ -353,7 +353,10 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
         // whole 16-byte groups; the last may carry up to three stale words
         // past the segment's count, inside the segment's capacity
         for (uint32_t g = (uint32_t)lane * 4u; g < n; g += 4u * kWave)
-            gst4(dst + p0 + g, *reinterpret_cast<const u32x4*>(stage + g));
+            // streaming store too: a launch over many frames reads the list
+            // back only after the whole pass, long after any cache held it
+            __builtin_nontemporal_store(*reinterpret_cast<const u32x4*>(stage + g),
+                                        (LANE_GLOBAL u32x4*)(dst + p0 + g));
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -528,9 +531,13 @@ extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows) {
     return L.nchunk * ((H + strip_rows - 1) / strip_rows);
 }
 
+// The 128-bit path reads the frame as one raw buffer of pitch x H bytes
+// (32-bit offsets, out-of-frame reads past its end), so it needs aligned
+// rows and a frame below 2^31 bytes.
 extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
     const SobelDesc& d = *dp;
     return ((uintptr_t)d.img % 16 == 0) && (d.pitch % 16 == 0) && (d.W % 16 == 0) &&
+           ((int64_t)d.pitch * d.H <= 0x7FFFFFFFll) &&
            (mode == kModeFromEdges ||
             (((uintptr_t)d.edges % 16 == 0) && ((uintptr_t)d.mag % 16 == 0)));
 }
@@ -559,9 +566,7 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* dp, int m
     const SobelDesc& d = *dp;
     const int n_items = lane_sobel_items(d.W, d.H, d.strip_rows);
     const unsigned blocks = (unsigned)((n_items + kSobelWaves - 1) / kSobelWaves);
-    const bool fast = ((uintptr_t)d.img % 16 == 0) && (d.pitch % 16 == 0) && (d.W % 16 == 0) &&
-                      (mode == kModeFromEdges ||
-                       (((uintptr_t)d.edges % 16 == 0) && ((uintptr_t)d.mag % 16 == 0)));
+    const bool fast = lane_sobel_fast_ok(&d, mode) != 0;
     const dim3 grid(blocks), block(kWave * kSobelWaves);
     if (mode == kModeSobel) {
         if (fast) hipLaunchKernelGGL((k_sobel<true, kModeSobel>), grid, block, 0, s, d, n_items);
