@@ -98,9 +98,15 @@ struct StreamSizes {
 int serve_vote_rows(const lane_server_cfg& cfg) { return cfg.vote_rows > 0 ? cfg.vote_rows : 4; }
 int serve_vote_split(const lane_server_cfg& cfg) { return cfg.vote_split > 0 ? cfg.vote_split : 8; }
 
-// device bytes the plan holds for a stream's edge split: none (the parts add
-// into the frame's accumulator)
-size_t split_bytes(const lane_stream_cfg&, const lane_server_cfg&, int) { return 0; }
+// device bytes the plan holds for a stream's edge split: the parts add into
+// the frame's accumulator, but a masked frame (pruned path) votes from a
+// pruned copy of its edge list, which the plan allocates per frame
+size_t split_bytes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
+    if (!cfg.pruned || serve_vote_split(cfg) <= 1) return 0;
+    size_t lb = 0;
+    lane_edge_list_size(c.W, c.H, &lb);
+    return al256(lb);
+}
 
 StreamSizes stream_sizes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
     const int pruned = cfg.pruned;
@@ -123,7 +129,7 @@ StreamSizes stream_sizes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
     z.counters = 256;
     z.mask = pruned ? al256(th * tw) : 0;
     z.logits = pruned ? al256(sizeof(float) * 9 * th * tw) : 0;
-    z.split = split_bytes(c, cfg, (int)n_r);
+    z.split = split_bytes(c, cfg);
     return z;
 }
 

@@ -75,6 +75,13 @@ def test_admission_pruned_counts_network_state(lane, serve):
     _, pruned, tot = lane.server_plan(st, 8 << 30, pruned=True, cnn_params=p)
     assert all(b > a for a, b in zip(plain, pruned))
     assert tot > sum(pruned) - 1  # shared weights on top of the streams
+    # per stream, the pruned state adds the tile mask, the logits and (the
+    # vote being split) the pruned copy of the edge list the plan allocates
+    al = lambda v: (v + 255) // 256 * 256
+    for s_, a, b in zip(st, plain, pruned):
+        th, tw = (s_["H"] + 7) // 8, (s_["W"] + 7) // 8
+        extra = al(th * tw) + al(4 * 9 * th * tw) + al(lane.edge_list_size(s_["W"], s_["H"]))
+        assert b - a == extra
 
 
 @pytest.mark.parametrize("kw,code", [
