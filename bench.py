@@ -155,6 +155,31 @@ def oracle_worker(budget_s, first_seed):
     print(json.dumps({"frames": n, "seconds": time.perf_counter() - t0}), flush=True)
 
 
+def oracle_omp_worker(budget_s):
+    """The OpenMP build of the oracle (Sobel rows and vote rows over the
+    host's cores; LANE_ORACLE_LIB points to it) on frames of the 1080p
+    workload, one frame at a time, for budget_s seconds after the go line;
+    prints the frame count, the time and the SHA-256 of the first frame's
+    accumulator."""
+    import hashlib
+
+    import oracle
+    from paper_2212_09460_amd import synth
+
+    sc = synth.scene_road(W, H)
+    imgs = [synth.gen_frame(sc, synth.frame_seed(0, synth.CONFIG_PLAIN_1080, i)) for i in range(2)]
+    C, S = synth.trig_q14(N_THETA)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    n, t0, sha = 0, time.perf_counter(), None
+    while time.perf_counter() - t0 < budget_s or n == 0:
+        r = oracle.pipeline(imgs[n % 2], C, S, TOPK)
+        if n == 0:
+            sha = hashlib.sha256(r["acc"].tobytes()).hexdigest()
+        n += 1
+    print(json.dumps({"frames": n, "seconds": time.perf_counter() - t0, "acc_sha": sha}), flush=True)
+
+
 def oracle_mixed_worker(indices):
     """One process of the mixed-batch oracle leg (no torch, no GPU): makes
     frames `indices` of the 64-frame mixed batch, reports ready, waits for
@@ -350,6 +375,27 @@ def cpu_all_cores(procs, budget_s):
                       f"processes started together, {span:.1f} s"}
 
 
+def cpu_openmp(threads, budget_s, ref0):
+    """The oracle's OpenMP build in one process with `threads` threads: the
+    per-frame multi-core baseline (Sobel rows and vote rows split over the
+    cores); its first accumulator must equal the single-threaded one."""
+    import hashlib
+
+    import oracle
+
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--oracle-omp-worker", str(budget_s)]
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), LANE_ORACLE_LIB=oracle.OMP_LIB_PATH)
+    r = run_workers([cmd], env)[0]
+    out = {"value": round(r["frames"] * W * H / r["seconds"] / 1e6, 3), "unit": "Mpix/s",
+           "cores": threads, "frames_per_s": round(r["frames"] / r["seconds"], 3),
+           "sample": f"{r['frames']} frames of the same workload, one at a time, oracle built "
+                     f"with OpenMP ({threads} threads: image rows of Sobel, theta rows of the "
+                     f"vote), {r['seconds']:.1f} s"}
+    if ref0 is not None:
+        out["same_result"] = r["acc_sha"] == hashlib.sha256(ref0["acc"].tobytes()).hexdigest()
+    return out
+
+
 def cpu_baseline(pool, C, S, budget_s, procs, gpu256=None, mixed_gpu=None):
     """The oracle timed on the host (single-threaded on the 1080p workload;
     all cores on the same workload and on the mixed batch).  Its results are
@@ -379,6 +425,7 @@ def cpu_baseline(pool, C, S, budget_s, procs, gpu256=None, mixed_gpu=None):
     procs = min(procs, usable_cores())
     if procs > 1:
         out["all_cores"] = cpu_all_cores(procs, budget_s)
+        out["openmp"] = cpu_openmp(procs, budget_s, first.get(0))
     if mixed_gpu is not None:
         out["mixed_batch"], checks["mixed_64"] = cpu_mixed(max(procs, 1), mixed_gpu)
     return out, checks
@@ -790,6 +837,8 @@ def main():
 if __name__ == "__main__":
     if len(sys.argv) == 4 and sys.argv[1] == "--oracle-worker":
         oracle_worker(float(sys.argv[2]), int(sys.argv[3]))
+    elif len(sys.argv) == 3 and sys.argv[1] == "--oracle-omp-worker":
+        oracle_omp_worker(float(sys.argv[2]))
     elif len(sys.argv) == 3 and sys.argv[1] == "--oracle-mixed-worker":
         oracle_mixed_worker([int(x) for x in sys.argv[2].split(",")])
     else:

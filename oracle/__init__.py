@@ -20,18 +20,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblane_oracle.so")
+# the same source built with OpenMP: Sobel rows and vote rows split over the
+# host's cores (the multi-core CPU baseline; results identical)
+OMP_LIB_PATH = os.path.join(_HERE, "liblane_oracle_omp.so")
 _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    """Compile lane_oracle.c with gcc (plain -O2, no vector intrinsics)."""
+    """Compile lane_oracle.c with gcc (plain -O2, no vector intrinsics), once
+    single-threaded and once with OpenMP."""
     src = os.path.join(_HERE, "lane_oracle.c")
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", src, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB_PATH)
+    for path, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+        tmp = path + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, src, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.check_call(cmd)
+        os.replace(tmp, path)
     return LIB_PATH
 
 

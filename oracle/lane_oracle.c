@@ -62,6 +62,8 @@ int64_t oracle_sobel_binarize(const uint8_t *img, int W, int H, int pitch, int T
                               int border_mode, uint8_t *edges, uint8_t *mag)
 {
     int64_t n = 0;
+    /* rows are independent (the OpenMP build splits them over threads) */
+#pragma omp parallel for reduction(+ : n) schedule(static)
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {
             int gx = P(img, W, H, pitch, x + 1, y - 1) + 2 * P(img, W, H, pitch, x + 1, y) +
@@ -105,32 +107,58 @@ int oracle_band_bits(int n_theta, int k)
 /* Sec. 2.3 Eq. (3) voting.  edges[H][epitch]: a pixel votes iff it equals
  * 255.  tile_mask (nullable) [ceil(H/8)][ceil(W/8)]: the pixel votes for bin
  * k only if mask & band_bits(k) != 0.  acc[n_theta][n_r] is overwritten.
- * Returns the number of votes cast into acc; *dropped gets the rest. */
+ * Returns the number of votes cast into acc; *dropped gets the rest (-1 if
+ * the edge set could not be held).
+ *
+ * The edge set E is listed first (row-major), then every theta row k counts
+ * the votes of all of E.  Rows are independent, so the build of this file
+ * with OpenMP (the multi-core CPU baseline) gives each thread whole rows:
+ * no shared counters, and integer sums that do not depend on the split. */
 int64_t oracle_hough_vote(const uint8_t *edges, int W, int H, int epitch, const int16_t *C,
                           const int16_t *S, int n_theta, int r_offset, int n_r,
                           const uint8_t *tile_mask, int32_t *acc, int64_t *dropped)
 {
     int tw = (W + 7) / 8;
-    int64_t cast = 0, drop = 0;
+    int64_t cast = 0, drop = 0, ne = 0;
     memset(acc, 0, sizeof(int32_t) * (size_t)n_theta * (size_t)n_r);
-    for (int y = 0; y < H; ++y) {
-        for (int x = 0; x < W; ++x) {
-            if (edges[(size_t)y * epitch + x] != 255) continue;
-            int m = tile_mask ? tile_mask[(size_t)(y / 8) * tw + (x / 8)] : 0xFF;
-            for (int k = 0; k < n_theta; ++k) {
-                if (tile_mask && (m & oracle_band_bits(n_theta, k)) == 0) continue;
-                int64_t v = (int64_t)x * C[k] + (int64_t)y * S[k];
-                int64_t r = floor_div(v + 8192, 16384);
-                int64_t i = r + r_offset;
-                if (i >= 0 && i < n_r) {
-                    acc[(size_t)k * n_r + (size_t)i] += 1;
-                    ++cast;
-                } else {
-                    ++drop;
-                }
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) ne += edges[(size_t)y * epitch + x] == 255;
+    int32_t *ex = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+    int32_t *ey = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+    if (!ex || !ey) {
+        free(ex);
+        free(ey);
+        if (dropped) *dropped = -1;
+        return 0;
+    }
+    int64_t j = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            if (edges[(size_t)y * epitch + x] == 255) {
+                ex[j] = x;
+                ey[j] = y;
+                ++j;
+            }
+#pragma omp parallel for reduction(+ : cast, drop) schedule(dynamic, 1)
+    for (int k = 0; k < n_theta; ++k) {
+        int bits = tile_mask ? oracle_band_bits(n_theta, k) : 0xFF;
+        int32_t *row = acc + (size_t)k * n_r;
+        for (int64_t e = 0; e < ne; ++e) {
+            int x = ex[e], y = ey[e];
+            if (tile_mask && (tile_mask[(size_t)(y / 8) * tw + (x / 8)] & bits) == 0) continue;
+            int64_t v = (int64_t)x * C[k] + (int64_t)y * S[k];
+            int64_t r = floor_div(v + 8192, 16384);
+            int64_t i = r + r_offset;
+            if (i >= 0 && i < n_r) {
+                row[i] += 1;
+                ++cast;
+            } else {
+                ++drop;
             }
         }
     }
+    free(ex);
+    free(ey);
     if (dropped) *dropped = drop;
     return cast;
 }

@@ -83,3 +83,19 @@ def test_plan_check_covers_every_frame():
     gpu["acc"][3][1, 2] += 1                     # an early frame's accumulator
     r = bench.check_plan_256(ref, gpu)
     assert not r["ok"] and r["mismatched_frames"] == [3, 2 * P + 5]
+
+
+def test_openmp_oracle_leg_matches_single_thread():
+    """The oracle's OpenMP build (the multi-core baseline) in two threads
+    gives the single-threaded accumulator on the workload's first frame."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+    from paper_2212_09460_amd import synth
+
+    img = synth.gen_frame(synth.scene_road(bench.W, bench.H),
+                          synth.frame_seed(0, synth.CONFIG_PLAIN_1080, 0))
+    C, S = synth.trig_q14(bench.N_THETA)
+    ref = oracle.pipeline(img, C, S, bench.TOPK)
+    r = bench.cpu_openmp(2, 0.1, ref)
+    assert r["cores"] == 2 and r["value"] > 0 and r["same_result"] is True
