@@ -358,8 +358,11 @@ typedef struct lane_tune {
                                  fits the half-size LDS variant (two workgroups per CU), unless
                                  the full-size maximum is more than twice that */
     int32_t vote_queue;       /* 1 = dynamic ticket queue (longest items first), 0 = static stride
-                                 with each frame's slices on one XCD, -1 = automatic */
-    int32_t sobel_groups_per_cu; /* persistent Sobel workgroups per CU; 0 = occupancy limit */
+                                 with each frame's slices on one XCD, 2 = one ticket queue per XCD
+                                 over the frames given to it (its L2 shares their edge lists),
+                                 taking from the others once its own is used up; -1 = automatic */
+    int32_t sobel_groups_per_cu; /* Sobel workgroups per CU of a persistent grid; 0 = one
+                                    workgroup per four work items (no persistent grid) */
     int32_t sobel_strip_rows; /* rows per Sobel work item, a multiple of 8; 0 = 32 */
     int32_t vote_split;       /* workgroups per theta slice, each voting a 1/vote_split share of
                                  the edge list (1..64; 0 or 1 = none) and adding its rows into the
@@ -405,9 +408,9 @@ int lane_batch_destroy(lane_batch *b);
 /* Autotuner (set-up call: allocates scratch buffers and synchronizes).
  * Builds plans over n_frames copies of `sample` (device uint8 [H][pitch]),
  * times the vote for every theta-slice width (rows per workgroup, down to
- * 1/16 of the largest that fits LDS) and both work distributions, then the
- * Sobel pass for strip heights 16..128 and 0-2 persistent workgroups per
- * CU, and writes the fastest setting to *out.  ms_opt: host float[2] or
+ * 1/16 of the largest that fits LDS) and the three work distributions, then the
+ * Sobel pass for strip heights 8..128 with and without a persistent grid (1
+ * or 2 workgroups per CU), and writes the fastest setting to *out.  ms_opt: host float[2] or
  * NULL, receives the best vote and Sobel times in ms. */
 int lane_tune_run(const uint8_t *sample, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
                   int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune *out,

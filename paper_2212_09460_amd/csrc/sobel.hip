@@ -482,9 +482,11 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
     sobel_item<FAST, MODE>(d, item, s_stage + wave * kStageCap, s_lut);
 }
 
-// Batched, persistent: each wave walks the (frame, item) table with a grid
-// stride.  Frames of any size mix in one launch; frames whose rows are
-// 16-byte aligned go to the vector-load instance, the rest to the byte one.
+// Batched: each wave walks the (frame, item) table with a grid stride (one
+// item per wave when the grid covers the table, the default; several with a
+// persistent grid).  Frames of any size mix in one launch; frames whose rows
+// are 16-byte aligned go to the vector-load instance, the rest to the byte
+// one.
 template <bool FAST>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items,
@@ -552,14 +554,6 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* des
         hipLaunchKernelGGL(k_sobel_batch<false>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
                            items, counts, 1);
     return hipGetLastError();
-}
-
-extern "C" LANE_INTERNAL int lane_sobel_batch_occupancy() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sobel_batch<true>, kWave * kSobelWaves, 0) !=
-        hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
 }
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* dp, int mode, hipStream_t s) {

@@ -510,19 +510,44 @@ __global__ void __launch_bounds__(kVoteThreads) k_vote(VoteDesc d) {
 
 // Batched, persistent.  queue == null: static grid stride over the item
 // table (the table is laid out so that a frame's slices land on one XCD and
-// share its L2).  queue != null: items are taken in table order from an
-// atomic ticket (longest items first balances mixed sizes).
+// share its L2).  queue != null, xends == null: items are taken in table
+// order from one atomic ticket (longest items first balances mixed sizes).
+// queue and xends != null: the table holds one run of items per XCD (the
+// frames given to that XCD, each frame's slices together), xends[x] the end
+// of run x; a workgroup takes tickets from its own XCD's run (workgroups
+// are dispatched to the XCDs in turn), so the slices running at once on an
+// XCD share the frames whose lists its L2 holds, and when that run is used
+// up it takes from the others in turn.
 template <int LDSW>
 __global__ void __launch_bounds__(kVoteThreads)
     __attribute__((amdgpu_waves_per_eu(LDSW == kVoteLdsWordsHalf ? 8 : 4)))
     k_vote_batch(const VoteDesc* __restrict__ descs, const int2* __restrict__ items,
-                 const int* __restrict__ n_items_ptr, uint32_t* queue) {
+                 const int* __restrict__ n_items_ptr, uint32_t* queue, const int* __restrict__ xends) {
     const int n_items = gld(n_items_ptr);  // in device memory: any selection of frames
     __shared__ VoteLds<LDSW> sm;
     int it = blockIdx.x;
+    int k = 0;  // XCD runs this workgroup has found used up (own first)
+    const int home = (int)(blockIdx.x & 7u);
     for (;;) {
         if (queue) {
-            if (threadIdx.x == 0) sm.item = (int)atomicAdd(queue, 1u);
+            if (threadIdx.x == 0) {
+                int item = n_items;
+                if (xends) {
+                    for (; k < 8; ++k) {
+                        const int x = (home + k) & 7;
+                        const int lo = x ? gld(xends + x - 1) : 0, hi = gld(xends + x);
+                        if (lo >= hi) continue;
+                        const int t = (int)atomicAdd(queue + x, 1u);
+                        if (lo + t < hi) {
+                            item = lo + t;
+                            break;
+                        }
+                    }
+                } else {
+                    item = (int)atomicAdd(queue, 1u);
+                }
+                sm.item = item;
+            }
             __syncthreads();
             it = __builtin_amdgcn_readfirstlane(sm.item);
         }
@@ -548,12 +573,13 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* dp, hipStre
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items,
                                                            const int* n_items, uint32_t* queue,
-                                                           int half_lds, int grid, hipStream_t s) {
+                                                           const int* xends, int half_lds, int grid,
+                                                           hipStream_t s) {
     if (half_lds)
         hipLaunchKernelGGL(k_vote_batch<kVoteLdsWordsHalf>, dim3(grid), dim3(kVoteThreads), 0, s,
-                           descs, items, n_items, queue);
+                           descs, items, n_items, queue, xends);
     else
         hipLaunchKernelGGL(k_vote_batch<kVoteLdsWords>, dim3(grid), dim3(kVoteThreads), 0, s, descs,
-                           items, n_items, queue);
+                           items, n_items, queue, xends);
     return hipGetLastError();
 }

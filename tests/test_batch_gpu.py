@@ -62,7 +62,7 @@ def scribble(frames):
         f.edge_list.fill_(0x7FFF7FFF)
 
 
-@pytest.mark.parametrize("queue", [-1, 0, 1])
+@pytest.mark.parametrize("queue", [-1, 0, 1, 2])
 def test_mixed_batch_graph_replays(lane, synth, oracle, queue):
     say("mixed batch queue", queue)
     specs = [(640, 480, 640, 11, False), (1280, 720, 1280, 12, False), (1920, 1080, 1920, 13, False),
@@ -155,8 +155,8 @@ def test_autotuner_choice_is_valid_and_exact(lane, synth, oracle):
 
     img = torch.from_numpy(synth.road(1280, 720, 4242)).cuda()
     t, info = tuner.tuned(img, 360, 4, use_cache=False)
-    assert t.vote_rows in (1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1)
-    assert t.sobel_strip_rows in (16, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
+    assert t.vote_rows in (1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1, 2)
+    assert t.sobel_strip_rows in (8, 16, 24, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
     assert info["vote_ms"] > 0 and info["sobel_ms"] > 0
     specs = [(1280, 720, 1280, 50 + i, False) for i in range(3)]
     frames, wants = make_frames(lane, synth, oracle, specs)
@@ -177,7 +177,7 @@ def test_sobel_strip_heights(lane, synth, oracle, strip):
     b.close()
 
 
-@pytest.mark.parametrize("queue", [1, 0])
+@pytest.mark.parametrize("queue", [1, 0, 2])
 def test_select_runs_only_selected_frames(lane, synth, oracle, queue):
     """lane_batch_select: selected frames are computed from their current
     images, the others keep every output and counter untouched; a later
@@ -218,7 +218,7 @@ def test_select_runs_only_selected_frames(lane, synth, oracle, queue):
     b.close()
 
 
-@pytest.mark.parametrize("rows,split,queue", [(1, 2, 1), (4, 4, 1), (16, 3, 0), (2, 8, 1), (8, 64, 1)])
+@pytest.mark.parametrize("rows,split,queue", [(1, 2, 1), (4, 4, 1), (16, 3, 0), (2, 8, 1), (8, 64, 1), (4, 8, 2)])
 def test_vote_split(lane, synth, oracle, rows, split, queue):
     """Edge-split vote: several workgroups per slice, each adding its share
     of the rows into the accumulator the plan clears first; exact on every
@@ -373,8 +373,8 @@ def test_mixed_batch_64_frames_tuned(lane, synth, oracle):
               for im in imgs]
     say("mixed batch 64 frames: tune")
     t, vote_ms, sobel_ms = lane.tune_batch(frames)
-    assert t.vote_rows in (0, 1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1)
-    assert t.sobel_strip_rows in (16, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
+    assert t.vote_rows in (0, 1, 2, 4, 8, 16, 32, 64) and t.vote_queue in (0, 1, 2)
+    assert t.sobel_strip_rows in (8, 16, 24, 32, 64, 128) and t.sobel_groups_per_cu in (0, 1, 2)
     assert vote_ms > 0 and sobel_ms > 0
     b = lane.Batch(frames, tune=t)
     for rep in range(2):
