@@ -20,33 +20,10 @@
 #include <string.h>
 #include <vector>
 
-#include "../../include/lane.h"
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 using namespace lane;
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items,
-                                                            const int* counts, int fast, int grid,
-                                                            hipStream_t s);
-extern "C" LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows);
-extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode);
-extern "C" LANE_INTERNAL hipError_t lane_launch_vote_batch(const VoteDesc* descs, const int2* items,
-                                                           const int* n_items, uint32_t* queue,
-                                                           const int* xends,
-                                                           int half_lds, int grid, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
-                                              int total_blocks, int grid_keys, int grid_select,
-                                              hipStream_t s);
-extern "C" LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
-extern "C" LANE_INTERNAL int lane_vote_rows_default(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
-extern "C" LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
-extern "C" LANE_INTERNAL long lane_vote_slice_words(int32_t W, int32_t H, int32_t n_theta, int32_t n_r, int T);
-extern "C" LANE_INTERNAL hipError_t lane_launch_lines_batch(const LinesDesc* descs, int n, int max_k,
-                                                            int max_side, hipStream_t s);
-extern "C" LANE_INTERNAL int lane_peaks_block_log2(int32_t n_theta, int32_t n_r);
-extern "C" LANE_INTERNAL hipError_t lane_launch_prune_batch(const PruneDesc* descs, int n, int max_nseg,
-                                                           hipStream_t s);
-extern "C" LANE_INTERNAL int lane_peaks_blocks_per_row(int32_t n_r, int lg);
 
 namespace {
 

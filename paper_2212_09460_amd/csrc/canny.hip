@@ -23,7 +23,7 @@
 // candidate takes its root, the components holding a strong pixel are
 // flagged, and the edge map is written.  A fixed number of kernels, no host
 // loop, so it can sit in a graph.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

@@ -4,29 +4,10 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "../../include/lane.h"
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 using namespace lane;
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_sobel(const SobelDesc* d, int mode, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_vote(const VoteDesc* d, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
-extern "C" LANE_INTERNAL size_t lane_canny_ws_bytes(int W, int H);
-extern "C" LANE_INTERNAL hipError_t lane_launch_canny(const uint8_t* img, int W, int H, int pitch, int t_low,
-                                                      int t_high, int border_mode, uint8_t* edges,
-                                                      uint8_t* mag, uint32_t* edge_count, void* ws,
-                                                      hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_vote_pair(const VoteDesc* d, int pairing, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_progressive(const ProgDesc* d, const PeaksDesc* pk,
-                                                            hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_lines(const uint8_t* edges, int W, int H, const int16_t* C,
-                                                      const int16_t* S, int n_theta, int r_offset,
-                                                      const int32_t* theta_idx, const int32_t* r_idx,
-                                                      const int32_t* count, int k, int fill_gap,
-                                                      int min_length, int max_seg, int32_t* segs,
-                                                      int32_t* seg_count, int32_t* npts, hipStream_t s);
 
 namespace {
 

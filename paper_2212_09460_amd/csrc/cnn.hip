@@ -26,7 +26,7 @@
 #include <algorithm>
 #include <string.h>
 
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 
@@ -896,7 +896,6 @@ __global__ void k_mask_from_logits(const float* __restrict__ logits, int th, int
 }  // namespace lane
 
 // ------------------------------------------------------------------- ABI --
-#include "../../include/lane.h"
 using namespace lane;
 
 namespace {
@@ -952,14 +951,6 @@ inline bool a16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 }  // namespace
 
 extern "C" {
-
-LANE_INTERNAL int lane_cnn_forward_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
-                                          int64_t img_stride, int32_t batch, const void* packed,
-                                          void* act, float* logits, const uint8_t* active,
-                                          void* stream);
-LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, int32_t H,
-                                               int32_t batch, float conf, uint8_t* mask,
-                                               const uint8_t* active, void* stream);
 
 int lane_cnn_param_count(void) { return kCnnParams; }
 

@@ -20,7 +20,7 @@
 // second pass marks segment starts (squared gap > fill_gap^2), a third keeps
 // the segments whose squared length reaches min_length^2, each compacted by
 // prefix sums so the output order is the line order.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

@@ -30,7 +30,7 @@
 // keys go to a scratch array (two buffers taking turns) and the touched
 // groups are recomputed, so a round costs O(window), one memory round trip
 // and two barriers.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

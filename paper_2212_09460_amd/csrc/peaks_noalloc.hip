@@ -8,17 +8,10 @@
 #include <mutex>
 #include <string.h>
 
-#include "../../include/lane.h"
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 using namespace lane;
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* d, hipStream_t s);
-extern "C" LANE_INTERNAL int lane_peaks_prepare(const int32_t* acc, int32_t n_theta, int32_t n_r,
-                                                int32_t r_offset, int32_t k, int32_t h_theta,
-                                                int32_t h_r, int32_t min_votes, int32_t* theta_idx,
-                                                int32_t* r_idx, int32_t* votes, int32_t* count,
-                                                PeaksDesc* d, size_t* need);
 
 namespace {
 

@@ -30,10 +30,8 @@
 // are cut into parts of segments to fill the GPU.  k_prog_cand: one
 // workgroup per window takes the maximum.
 // k_prog_final: one wave, greedy selection over <= 64 candidates.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const lane::PeaksDesc* d, hipStream_t s);
 
 namespace lane {
 

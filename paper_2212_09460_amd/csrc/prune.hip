@@ -12,7 +12,7 @@
 // the entries of band-restricted tiles (any other non-zero mask) to the back
 // of the segment's slot, which the vote reads after them with the band test
 // entry by entry (few entries: the proposal network restricts few tiles).
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

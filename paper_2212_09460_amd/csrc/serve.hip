@@ -30,18 +30,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/lane.h"
-#include "lane_internal.h"
-
-extern "C" {
-LANE_INTERNAL int lane_vote_rows_per_group(int32_t W, int32_t H, int32_t n_theta, int32_t n_r);
-LANE_INTERNAL int lane_vote_row_cap(int32_t W, int32_t H, int32_t n_r);
-LANE_INTERNAL int lane_cnn_infer_mask_active(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
-                                             int64_t img_stride, int32_t batch, const void* packed,
-                                             float* logits, float conf, uint8_t* mask,
-                                             const uint8_t* active, void* stream);
-LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream);
-}
+#include "lane_entry.h"
 
 namespace {
 

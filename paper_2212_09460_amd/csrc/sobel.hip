@@ -20,7 +20,7 @@
 // Tile counts are prefix-summed across the wave (the segment offsets); each
 // lane places the coordinates of its two tiles' edge pixels in the wave's
 // LDS stage, and the wave writes the stage out with coalesced stores.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

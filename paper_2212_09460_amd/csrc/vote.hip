@@ -22,7 +22,7 @@
 // a slice that does not fit in LDS (possible only with an unusual table),
 // is handled by an exact fallback that adds into global memory with
 // range checks and counts dropped votes.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 

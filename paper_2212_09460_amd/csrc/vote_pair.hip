@@ -21,7 +21,7 @@
 // two differ only in the arithmetic of a vote.  A pair whose rows do not fit
 // in LDS (possible only with an unusual table on a large frame) adds into
 // global memory instead.
-#include "lane_internal.h"
+#include "lane_entry.h"
 
 namespace lane {
 
