@@ -229,15 +229,38 @@ __device__ __forceinline__ unsigned long long make_key(int v, uint32_t idx) {
            (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
+// One step of a wave reduction: the larger of v and the value DPP control
+// CTRL brings from another lane (lanes outside ROW_MASK keep v).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long max_dpp_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)v, (int)(uint32_t)v, CTRL,
+                                                              ROW_MASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(v >> 32), (int)(uint32_t)(v >> 32),
+                                                              CTRL, ROW_MASK, 0xF, false);
+    const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+    return w > v ? w : v;
+}
+
+// Maximum over each DPP row of 16 lanes, returned to every lane of the row.
+__device__ __forceinline__ unsigned long long row_max_u64(unsigned long long v) {
+    v = max_dpp_u64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = max_dpp_u64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = max_dpp_u64<0x141, 0xF>(v);  // row_half_mirror
+    return max_dpp_u64<0x140, 0xF>(v);  // row_mirror
+}
+
+// Maximum over the 64 lanes, returned to every lane.  Data movement by DPP
+// (VALU), not by LDS permutes, which would queue behind a vote's LDS
+// atomics: swaps within quads, then mirrors within half-rows and rows of 16
+// make every row uniform, two row broadcasts carry the rows' maxima to lane
+// 63, and a readlane hands that to the wave.
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
-        const unsigned long long w = ((unsigned long long)hi << 32) | lo;
-        v = w > v ? w : v;
-    }
-    return v;
+    v = row_max_u64(v);
+    v = max_dpp_u64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = max_dpp_u64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 constexpr int kPeaksMaxBlocksLds = 8192;

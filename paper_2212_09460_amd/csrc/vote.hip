@@ -39,8 +39,7 @@ template <int LDSW>
 struct VoteLds {
     int32_t acc[LDSW];
     int lo[kMaxT], win[kMaxT], base[kMaxT];
-    int fast, total, item, last;
-    int pair_ok;  // every row of the slice bounds its cell pairs below 2^14
+    int fast, item;
     int il, lo_min, span;  // layout (0 rows back to back, 1 interleaved, 2 interleaved pairs),
                            // lowest r_idx of the slice, its r span
     uint32_t dropped;
@@ -119,52 +118,70 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     const ListLayout L = list_layout(d.W, d.H);
     const uint32_t* __restrict__ list = d.list;
 
-    if (tid == 0) {
-        sm.fast = 1;
-        sm.pair_ok = 1;
-        sm.dropped = 0;
-    }
-    __syncthreads();
-    if (tid < T) {
-        const int k = k0 + tid;
-        const int C = gld(d.cos_q14 + k), S = gld(d.sin_q14 + k);
-        const int xs[4] = {0, d.W - 1, 0, d.W - 1};
-        const int ys[4] = {0, 0, d.H - 1, d.H - 1};
-        int rmin = 0x7FFFFFFF, rmax = -0x7FFFFFFF;
+    // Set-up, one barrier: every thread clears the LDS counters (the
+    // previous item's rows were read out before the caller's barrier) and
+    // loads its own row's table entries, while wave 0 finds the slice's
+    // layout: each lane q < T the r window its row can reach (the four
+    // corners, where the monotone r is extreme), then a prefix sum of the
+    // windows and the slice's extent across the lanes.
+    for (int c = tid; c < LDSW; c += blockDim.x) sm.acc[c] = 0;
+    const int kk = k0 + j;
+    const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
+    if (wave == 0) {
+        int lo = 0x7FFFFFFF, hi = -1, win = 0;
+        bool fast_ok = true, pair_ok = true;
+        if (lane < T) {
+            const int xs[4] = {0, d.W - 1, 0, d.W - 1};
+            const int ys[4] = {0, 0, d.H - 1, d.H - 1};
+            int rmin = 0x7FFFFFFF, rmax = -0x7FFFFFFF;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int r = (xs[c] * C + ys[c] * S + 8192) >> 14;  // arithmetic shift = floor
-            rmin = min(rmin, r);
-            rmax = max(rmax, r);
+            for (int c = 0; c < 4; ++c) {
+                const int r = (xs[c] * C + ys[c] * S + 8192) >> 14;  // arithmetic shift = floor
+                rmin = min(rmin, r);
+                rmax = max(rmax, r);
+            }
+            lo = rmin + d.r_offset;
+            hi = rmax + d.r_offset;
+            win = hi - lo + 1;
+            fast_ok = lo >= 0 && hi < d.n_r;
+            pair_ok = vote_pair_bound(d.W, d.H, C, S) <= kPairCountMax;
         }
-        const int lo = rmin + d.r_offset, hi = rmax + d.r_offset;
-        sm.lo[tid] = lo;
-        sm.win[tid] = hi - lo + 1;
-        if (lo < 0 || hi >= d.n_r) sm.fast = 0;
-        if (vote_pair_bound(d.W, d.H, C, S) > kPairCountMax) sm.pair_ok = 0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int base = 0, lo_min = 0x7FFFFFFF, hi_max = -1;
-        for (int q = 0; q < T; ++q) {
-            sm.base[q] = base;
-            base += sm.win[q];
-            lo_min = min(lo_min, sm.lo[q]);
-            hi_max = max(hi_max, sm.lo[q] + sm.win[q] - 1);
+        int incl = win;  // inclusive prefix sum of the windows over lanes < T
+        for (int o = 1; o < T; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
         }
-        // layout: pairs when 32 or more rows make them conflict-free, else
-        // interleaved, else pairs to fit, else rows back to back
-        const int span = hi_max - lo_min + 1;
-        auto fits = [&](int w) { return w <= LDSW; };
-        const int il_words = span * T, il2_words = ((span + 1) >> 1) * T;
-        // paired counters only where no row's cell pair can reach 2^14 votes
-        const bool il2_ok = sm.pair_ok != 0 && fits(il2_words);
-        const int mode = (T >= 32 && il2_ok) ? 2 : fits(il_words) ? 1 : il2_ok ? 2 : 0;
-        sm.il = mode;
-        sm.lo_min = lo_min;
-        sm.span = span;
-        sm.total = mode == 2 ? il2_words : mode == 1 ? il_words : base;
-        if (mode == 0 && !fits(base)) sm.fast = 0;
+        int lo_min = lo, hi_max = hi;
+        for (int o = 32; o > 0; o >>= 1) {
+            lo_min = min(lo_min, __shfl_xor(lo_min, o));
+            hi_max = max(hi_max, __shfl_xor(hi_max, o));
+        }
+        const bool all_fast = __ballot(!fast_ok) == 0;
+        const bool all_pair = __ballot(!pair_ok) == 0;
+        const int b2b_words = __shfl(incl, T - 1);
+        if (lane < T) {
+            sm.lo[lane] = lo;
+            sm.win[lane] = win;
+            sm.base[lane] = incl - win;
+        }
+        if (lane == 0) {
+            // layout: pairs when 32 or more rows make them conflict-free, else
+            // interleaved, else pairs to fit, else rows back to back.  The
+            // slice's lowest cell is taken even, so that a pair never
+            // straddles a key block (blocks start at multiples of 64)
+            lo_min &= ~1;
+            const int span = hi_max - lo_min + 1;
+            auto fits = [&](int w) { return w <= LDSW; };
+            const int il_words = span * T, il2_words = ((span + 1) >> 1) * T;
+            // paired counters only where no row's cell pair can reach 2^14 votes
+            const bool il2_ok = all_pair && fits(il2_words);
+            const int mode = (T >= 32 && il2_ok) ? 2 : fits(il_words) ? 1 : il2_ok ? 2 : 0;
+            sm.il = mode;
+            sm.lo_min = lo_min;
+            sm.span = span;
+            sm.fast = all_fast && (mode != 0 || fits(b2b_words)) ? 1 : 0;
+            sm.dropped = 0;
+        }
     }
     __syncthreads();
     const bool fast = sm.fast != 0;
@@ -174,8 +191,6 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     if (!fast && part != 0) return;
     const int seg_lo = fast ? (int)(((long long)L.nseg * part) / E) : 0;
     const int seg_hi = fast ? (int)(((long long)L.nseg * (part + 1)) / E) : L.nseg;
-    const int kk = k0 + j;
-    const int C = gld(d.cos_q14 + kk), S = gld(d.sin_q14 + kk);
     // pruned: the list holds, per segment, the entries of tiles that vote
     // every row (streamed like an unmasked list) and, at the end of the
     // segment's slot, those of band-restricted tiles, tested entry by entry
@@ -188,15 +203,12 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     }
 
     if (fast) {
-        const int total = sm.total;
-        for (int c = tid; c < total; c += blockDim.x) sm.acc[c] = 0;
         const int lo = sm.lo[j], base = sm.base[j];
         const int K = il ? 8192 + (d.r_offset - sm.lo_min) * 16384
                          : 8192 + (base - lo + d.r_offset) * 16384;
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
         const uint32_t jb = 4u * (uint32_t)j;
         const int sh = 2 + d.log2T;
-        __syncthreads();
         auto body = [&](auto mode) {
         constexpr int kIL = decltype(mode)::value;
         auto vote1 = [&](uint32_t xy) {
@@ -229,15 +241,21 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                     u32x4 a[U], b[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) a[u] = gld4(p + 4 * u);
+                    // (the scheduling barriers keep the compiler from hoisting
+                    // the other set's first votes above its wait)
                     for (it = U; it + 2 * U <= nfull; it += 2 * U) {
 #pragma unroll
                         for (int u = 0; u < U; ++u) b[u] = gld4(p + 4 * (it + u));
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int u = 0; u < U; ++u) vote4(a[u]);
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int u = 0; u < U; ++u) a[u] = gld4(p + 4 * (it + U + u));
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int u = 0; u < U; ++u) vote4(b[u]);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                     // a holds entries [it - U, it); fewer than 2U groups remain
                     if (it + U <= nfull) {
@@ -262,9 +280,17 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 }
             };
             if (G <= kSlotsPerSegment) {
-                for (int seg = seg_lo + wave; seg < seg_hi; seg += nwaves) {
-                    const int n = min((int)gld(list + seg), kSegCap);
-                    run_segment(list + L.off_ent + (size_t)seg * kSegCap, n, G, g);
+                // the entry counts of the wave's next 64 segments in one load,
+                // so a segment never waits for its count
+                for (int seg0 = seg_lo + wave; seg0 < seg_hi; seg0 += nwaves * kWave) {
+                    const int sj = seg0 + lane * nwaves;
+                    const int cnt = sj < seg_hi ? min((int)gld(list + sj), kSegCap) : 0;
+                    const int nk = min(kWave, (seg_hi - seg0 + nwaves - 1) / nwaves);
+                    for (int k = 0; k < nk; ++k) {
+                        const int seg = seg0 + k * nwaves;
+                        run_segment(list + L.off_ent + (size_t)seg * kSegCap,
+                                    __builtin_amdgcn_readlane(cnt, k), G, g);
+                    }
                 }
             } else {
                 // few theta rows, many slots: a wave works on G / 8 segments at
@@ -411,6 +437,65 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                 for (int o = tid; o < rwin; o += blockDim.x) {
                     const int v = cell(q, rlo, rwin, rbase, rlo + o);
                     if (v != 0) atomicAdd(out + rlo + o, v);
+                }
+            }
+        } else if (layout != 0 && T >= 4) {
+            // Write the owned rows and, block by block, the peak-search keys,
+            // four rows at a time: lane (r, c) = (lane / 16, lane % 16) takes
+            // LDS words c, c + 16, ... of row 4 grp + r within the block, so
+            // a read touches 16 words of each of 4 rows (at most 4 to a bank,
+            // where 64 cells of one row would put 8 or more there) and the
+            // stores of a row cover 128 contiguous bytes.  Each lane keeps
+            // the first largest of its cells; the 16 lanes of a row, one DPP
+            // row, merge them once per block.
+            const int cpw = layout == 2 ? 2 : 1;                   // cells per LDS word
+            const int npw = layout == 2 ? (span + 1) >> 1 : span;  // LDS words per row
+            const int B = d.keys ? 1 << d.key_log2 : 256;
+            const int nbr = d.keys ? d.nbr : (d.n_r + 255) >> 8;
+            const int r = lane >> 4, c = lane & 15;
+            const int g_lo = q0 >> 2;  // first group with an owned row
+            const int ntask = ((T >> 2) - g_lo) * nbr;
+            for (int task = wave; task < ntask; task += nwaves) {
+                const int grp = g_lo + task / nbr, jb = task % nbr;
+                const int q = 4 * grp + r;
+                const bool own = q >= q0;
+                const int row = k0 + q;
+                int32_t* out = d.acc + (size_t)row * d.n_r;
+                const uint32_t rowc = (uint32_t)row * (uint32_t)d.n_r;
+                const int b0 = jb * B, b1 = min(d.n_r, b0 + B);
+                const int w0 = (b0 - lo_min) / cpw;  // exact: both even when paired
+                const int nw = (b1 - b0 + cpw - 1) / cpw;
+                int bv = -1, bi = 0;
+                for (int w = c; w < nw; w += 16) {
+                    const int m = w0 + w;
+                    const uint32_t x = (m >= 0 && m < npw) ? (uint32_t)sm.acc[m * T + q] : 0u;
+                    const int i = b0 + w * cpw;
+                    if (layout == 2) {
+                        const int odd = (int)(x >> 14), even = (int)(x & 0x3FFFu) - odd;
+                        if (own) gst(out + i, even);
+                        if (even > bv) {
+                            bv = even;
+                            bi = i;
+                        }
+                        if (i + 1 < b1) {
+                            if (own) gst(out + i + 1, odd);
+                            if (odd > bv) {
+                                bv = odd;
+                                bi = i + 1;
+                            }
+                        }
+                    } else {
+                        if (own) gst(out + i, (int)x);
+                        if ((int)x > bv) {
+                            bv = (int)x;
+                            bi = i;
+                        }
+                    }
+                }
+                if (d.keys) {
+                    unsigned long long key = bv >= 0 ? make_key(bv, rowc + (uint32_t)bi) : 0ull;
+                    key = row_max_u64(key);
+                    if (own && c == 0) gst(d.keys + (size_t)row * d.nbr + jb, key);
                 }
             }
         } else if (d.keys) {
