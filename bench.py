@@ -234,7 +234,9 @@ def run_workers(cmds, env):
 def lds_probe():
     """Rate of LDS atomic increments (ds_add_u32) on this GPU from the probe
     library: conflict-free (the 64 lanes of an instruction on 64 consecutive
-    words) and hashed addresses over a 64 KB table, the best over 1, 2 and 4
+    words), hashed addresses over a 64 KB table, and the vote's own pattern
+    and instruction mix (16 angle rows x 4 pixel slots, paired counters,
+    four VALU instructions per increment); the best over 1, 2 and 4
     workgroups of 1024 threads per CU; in G increments per second."""
     import ctypes
 
@@ -244,7 +246,7 @@ def lds_probe():
     f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                   ctypes.POINTER(ctypes.c_uint64)]
     out = {}
-    for random, name in ((0, "conflict_free"), (1, "hashed")):
+    for random, name in ((0, "conflict_free"), (1, "hashed"), (2, "vote_pattern")):
         best = 0.0
         for groups in (CUS, 2 * CUS, 4 * CUS):
             steps = 1000
@@ -790,6 +792,7 @@ def main():
                      "frac": round(vote_gvotes / LDS_BANK_PEAK_GVOTES, 4),
                      "peak_measured": probe["conflict_free"],
                      "frac_of_measured": round(vote_gvotes / probe["conflict_free"], 4),
+                     "frac_of_vote_pattern": round(vote_gvotes / probe["vote_pattern"], 4),
                      "probe_gadds_per_s": probe,
                      "traffic": profiled_traffic("k_vote_batch", "vote.hip") if B == 256 else None,
                      "votes_per_launch": votes},

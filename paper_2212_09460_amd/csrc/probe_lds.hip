@@ -7,6 +7,12 @@
 // k_lds_add_random: the same count of increments to hashed addresses spread
 // over the workgroup's words (the bank pattern of votes from scattered
 // pixels), for comparison.
+// k_lds_add_vote: the vote's own instruction mix and bank pattern: 16 angle
+// rows x 4 pixel slots per wave, each increment preceded by the vote's four
+// VALU instructions (dot product, shift, shift-or for the address, and-or
+// for the increment) into 16-row interleaved pairs of 14-bit counters; the
+// rate a vote can reach when nothing else (loads, set-up, write-out) costs
+// anything.
 //
 // Built into its own library (liblaneprobe.so): it is a measurement, not part
 // of the lane-detection path.
@@ -57,12 +63,60 @@ __global__ void __launch_bounds__(kThreads) k_lds_add_random(uint32_t* __restric
     out[(size_t)blockIdx.x * kThreads + t] = sum;
 }
 
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// inc_mask is zero at run time (every increment is 1, so the counters can be
+// checked) but unknown to the compiler, which keeps the and-or.
+__global__ void __launch_bounds__(kThreads) k_lds_add_vote(uint32_t* __restrict__ out, int steps, uint32_t inc_mask) {
+    __shared__ uint32_t s[kWords];
+    const int t = threadIdx.x, lane = t & 63, j = lane & 15, slot = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) s[t + u * kThreads] = 0;
+    __syncthreads();
+    // row j: angle (blockIdx.x * 7 % 164 + j) / 2 degrees, in [0, 90): C, S >= 0
+    const float th = (float)((blockIdx.x * 7u) % 164u + (uint32_t)j) * (3.14159265f / 360.f);
+    const int C = (int)(16384.f * cosf(th) + 0.5f), S = (int)(16384.f * sinf(th) + 0.5f);
+    const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
+    // one pixel per slot and unroll step (x, y < 512), shared by the slot's 16 rows
+    uint32_t xy[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t h = mix32(((blockIdx.x * 16u + (uint32_t)(t >> 6)) * 4u + (uint32_t)slot) * 16u + (uint32_t)u);
+        xy[u] = ((h >> 16) & 511u) << 16 | (h & 511u);
+    }
+    const uint32_t jb = 4u * (uint32_t)j;
+    for (int i = 0; i < steps; ++i) {
+        const int K = (int)(((uint32_t)i * 2654435761u) >> 8);  // < 2^24: pairs stay below 1024
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            int v;
+            asm volatile("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(v) : "v"((int)xy[u]), "v"(CS), "v"(K));
+            const uint32_t adr = (((uint32_t)v >> 15) << 6) | jb;  // pair * 16 rows * 4 B + row
+            const uint32_t inc = ((uint32_t)v & inc_mask) | 1u;
+            atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(s) + adr), inc);
+        }
+    }
+    __syncthreads();
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) sum += s[t + u * kThreads];
+    out[(size_t)blockIdx.x * kThreads + t] = sum;
+}
+
 }  // namespace
 
 extern "C" {
 
 // Runs `groups` workgroups of 1024 threads, each doing `steps` x 16 LDS
-// increments per thread (random = 0: conflict-free; 1: hashed addresses),
+// increments per thread (random = 0: conflict-free; 1: hashed addresses;
+// 2: the vote's pattern and instruction mix),
 // timed with HIP events on a stream of its own after one untimed launch.
 // *adds_per_s receives increments per second; *checksum the number of
 // increments the counters hold (for the caller to compare with
@@ -70,7 +124,8 @@ extern "C" {
 // error.
 int lane_probe_lds_add(int32_t groups, int32_t steps, int32_t random, double* adds_per_s,
                        uint64_t* checksum) {
-    if (groups < 1 || groups > 65536 || steps < 1 || steps > (1 << 20) || !adds_per_s || !checksum)
+    if (groups < 1 || groups > 65536 || steps < 1 || steps > (1 << 20) || random < 0 || random > 2 ||
+        !adds_per_s || !checksum)
         return -1;
     uint32_t* out = nullptr;
     const size_t n = (size_t)groups * kThreads;
@@ -81,7 +136,9 @@ int lane_probe_lds_add(int32_t groups, int32_t steps, int32_t random, double* ad
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
         hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
         auto launch = [&]() {
-            if (random)
+            if (random == 2)
+                hipLaunchKernelGGL(k_lds_add_vote, dim3(groups), dim3(kThreads), 0, st, out, steps, 0u);
+            else if (random)
                 hipLaunchKernelGGL(k_lds_add_random, dim3(groups), dim3(kThreads), 0, st, out, steps);
             else
                 hipLaunchKernelGGL(k_lds_add, dim3(groups), dim3(kThreads), 0, st, out, steps);

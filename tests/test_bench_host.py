@@ -99,3 +99,17 @@ def test_openmp_oracle_leg_matches_single_thread():
     ref = oracle.pipeline(img, C, S, bench.TOPK)
     r = bench.cpu_openmp(2, 0.1, ref)
     assert r["cores"] == 2 and r["value"] > 0 and r["same_result"] is True
+
+
+def test_lds_probe_rejects_bad_arguments():
+    """The probe's argument checks come before any HIP call (CPU only)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2212_09460_amd", "liblaneprobe.so"))
+    f = lib.lane_probe_lds_add
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_uint64)]
+    rate, chk = ctypes.c_double(0.0), ctypes.c_uint64(0)
+    for args in ((0, 1, 0), (1, 0, 0), (1, 1, 3), (1, 1, -1), (70000, 1, 0)):
+        assert f(*args, ctypes.byref(rate), ctypes.byref(chk)) == -1
+    assert f(1, 1, 0, None, ctypes.byref(chk)) == -1
