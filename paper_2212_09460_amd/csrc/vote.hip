@@ -109,12 +109,17 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
     const int nwaves = blockDim.x >> 6;
-    const int T = d.T;
+    const int own_from = slice * d.T;  // rows below this belong to the previous slice
+    // where the slice height d.T does not divide the angle count, the last
+    // slice takes only the rows it owns, rounded up to a power of two (360
+    // angles in slices of 16: the last votes 8 rows, not 16)
+    int lg = d.log2T;
+    while (lg > 0 && (1 << (lg - 1)) >= d.n_theta - own_from) --lg;
+    const int T = 1 << lg;
     const int j = lane & (T - 1);
-    const int g = lane >> d.log2T;
-    const int G = kWave >> d.log2T;
-    const int k0 = min(slice * T, d.n_theta - T);
-    const int own_from = slice * T;  // rows below this belong to the previous slice
+    const int g = lane >> lg;
+    const int G = kWave >> lg;
+    const int k0 = min(own_from, d.n_theta - T);
     const ListLayout L = list_layout(d.W, d.H);
     const uint32_t* __restrict__ list = d.list;
 
@@ -208,7 +213,7 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
                          : 8192 + (base - lo + d.r_offset) * 16384;
         const int CS = (int)(((uint32_t)(uint16_t)S << 16) | (uint32_t)(uint16_t)C);
         const uint32_t jb = 4u * (uint32_t)j;
-        const int sh = 2 + d.log2T;
+        const int sh = 2 + lg;
         auto body = [&](auto mode) {
         constexpr int kIL = decltype(mode)::value;
         auto vote1 = [&](uint32_t xy) {
