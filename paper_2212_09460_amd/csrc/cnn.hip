@@ -250,6 +250,7 @@ struct CnnInfer {
     const uint8_t* active;     // frame b runs iff active[b] != 0 (null = all)
     uint8_t* mask;             // [B][H3][W3] tile masks by the rule of k_mask_from_logits, or null
     float t_hi;                // that rule's threshold
+    int wide;                  // frames, pitch and stride 16-byte aligned: 16-byte input loads
 };
 
 // column of pixel x in a window of side n stored even columns first
@@ -324,36 +325,64 @@ k_cnn_infer(CnnInfer p) {
         nb = f;
         nblk_out = k;
     };
-    // A block's input window: thread t < 435 loads row t / 5, columns
-    // 18 (t % 5) .. + 17 (five runs of 18 cover the 87 columns), one byte
-    // per load at a constant offset from the run's start; bytes outside the
-    // frame or the window are masked to zero (a run on a row outside the
-    // frame reads nothing).  Four bytes per register.
-    constexpr int kRun = 18, kRuns = 5, kPacked = (kRun + 3) / 4;
+    // A block's input window (window position q <-> frame column x0 + q,
+    // x0 = 64 TX - 15), into eight registers per thread, in one of two forms.
+    // Wide (16-byte aligned frames): thread t < 261 loads row t / 3, frame
+    // columns x0 - 1 + 32 (t % 3) .. + 31 as two 16-byte loads; a chunk
+    // left of the frame or on a row outside it reads as zero through the
+    // buffer's range check (chunks start at multiples of 16, so none
+    // straddles column 0), and bytes at columns >= W are masked.  Narrow:
+    // thread t < 435 loads row t / 5, columns 18 (t % 5) .. + 17, one byte
+    // per load, bytes outside the frame or the window masked; four bytes per
+    // register.
+    constexpr int kRun = 18, kRuns = 5;
     static_assert(kRun * kRuns >= kR0 && kR0 * kRuns <= kInferThreads, "window runs");
-    const int frow = tid / kRuns, fcol = kRun * (tid - frow * kRuns);
-    auto fetch = [&](int b, int blk, uint32_t (&v)[kPacked]) {
+    constexpr int kParts = 3;  // 32-byte parts per row in the wide form
+    static_assert(32 * kParts >= kR0 + 1 && kR0 * kParts <= kInferThreads, "wide window");
+    const bool wide = p.wide != 0;
+    const int frow = wide ? tid / kParts : tid / kRuns;
+    const int fcol = wide ? 32 * (tid - frow * kParts) : kRun * (tid - frow * kRuns);
+    auto fetch = [&](int b, int blk, uint32_t (&v)[8]) {
         const int TY = blk / p.bx, TX = blk - TY * p.bx;
         // input window origin 2 Y1 - 1 = 8 Y4 - 15 (Y1 = 2 Y2 - 1, Y2 = 2 Y3 - 1, Y3 = Y4 - 1)
-        const int y = 8 * TY * kFT - 15 + frow, x0 = 8 * TX * kFT - 15 + fcol;
+        const int y = 8 * TY * kFT - 15 + frow, x0 = 8 * TX * kFT - 15;
         // the frame as a raw buffer: offsets past its end read as zero
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(p.img + (size_t)b * p.img_stride), (short)0,
             (int)((uint32_t)p.pitch * (uint32_t)p.H), kBufConfig);
+        if (wide) {
+            const bool row_in = tid < kR0 * kParts && y >= 0 && y < p.H;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = x0 - 1 + fcol + 16 * h;  // a multiple of 16
+                const bool in = row_in && c >= 0 && c < p.W;
+                const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(
+                    rsrc, in ? (uint32_t)(y * p.pitch + c) : kBufOutside, 0, 0);
+                const int nv = p.W - c;  // bytes of the chunk inside the frame
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int keep = nv - 4 * d;  // bytes of this word to keep
+                    const uint32_t m = keep >= 4 ? 0xFFFFFFFFu : keep <= 0 ? 0u : (1u << (8 * keep)) - 1u;
+                    v[4 * h + d] = q[d] & m;
+                }
+            }
+            return;
+        }
+        const int xr = x0 + fcol;
         const bool row_in = tid < kR0 * kRuns && y >= 0 && y < p.H;
-        const uint32_t off = row_in ? (uint32_t)(y * p.pitch + x0) : kBufOutside;
-        uint32_t keep = 0;  // bit j: column x0 + j is inside the frame and the window
+        const uint32_t off = row_in ? (uint32_t)(y * p.pitch + xr) : kBufOutside;
+        uint32_t keep = 0;  // bit j: column xr + j is inside the frame and the window
 #pragma unroll
         for (int j = 0; j < kRun; ++j)
-            keep |= (uint32_t)(x0 + j >= 0 && x0 + j < p.W && fcol + j < kR0) << j;
+            keep |= (uint32_t)(xr + j >= 0 && xr + j < p.W && fcol + j < kR0) << j;
 #pragma unroll
-        for (int q = 0; q < kPacked; ++q) v[q] = 0;
+        for (int q = 0; q < 8; ++q) v[q] = 0;
 #pragma unroll
         for (int j = 0; j < kRun; ++j) {
             // a column left of the frame gives a negative offset: pass the
             // out-of-range one instead (the byte is masked anyway)
             const uint32_t o = off + (uint32_t)j;
-            const uint32_t bj = __builtin_amdgcn_raw_buffer_load_b8(rsrc, x0 + j >= 0 ? o : kBufOutside, 0, 0);
+            const uint32_t bj = __builtin_amdgcn_raw_buffer_load_b8(rsrc, xr + j >= 0 ? o : kBufOutside, 0, 0);
             v[j >> 2] |= (((keep >> j) & 1u) ? bj : 0u) << (8 * (j & 3));
         }
     };
@@ -388,7 +417,7 @@ k_cnn_infer(CnnInfer p) {
     const f4 bias2 = *reinterpret_cast<const f4*>(s_bias + 16 + 4 * grp);
     int b, blk;
     next(0, (int)blockIdx.x - (int)gridDim.x, b, blk);
-    uint32_t v[kPacked];
+    uint32_t v[8];
     if (b < p.batch) fetch(b, blk, v);
     while (b < p.batch) {
         const int TY = blk / p.bx, TX = blk - TY * p.bx;
@@ -396,20 +425,29 @@ k_cnn_infer(CnnInfer p) {
         const int Y3 = Y4 - 1, X3 = X4 - 1;
         const int Y2 = 2 * Y3 - 1, X2 = 2 * X3 - 1;
         const int Y1 = 2 * Y2 - 1, X1 = 2 * X2 - 1;
-        // the input window, converted once to FP16 (gray / 255), two
-        // columns per 32-bit LDS write
-        if (tid < kR0 * kRuns) {
+        // the input window, converted once to FP16 (gray / 255)
+        auto h16 = [&](int i) {  // byte i of the thread's registers as FP16 bits
+            const uint32_t by = (v[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+            return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)((float)by * (1.0f / 255.0f)));
+        };
+        if (wide) {
+            // byte i is window position fcol - 1 + i: positions of odd i
+            // start a pair (a 32-bit write); bytes 0 and 31 go alone
+            if (tid < kR0 * kParts) {
+                const int at = frow * kP0 + fcol - 1;  // LDS half of byte 0
+                uint16_t* r0h = reinterpret_cast<uint16_t*>(r0);
+                if (fcol > 0) r0h[at] = (uint16_t)h16(0);
+#pragma unroll
+                for (int i = 1; i < 31; i += 2)
+                    *reinterpret_cast<uint32_t*>(r0h + at + i) = h16(i) | (h16(i + 1) << 16);
+                if (fcol + 30 < kP0) r0h[at + 31] = (uint16_t)h16(31);
+            }
+        } else if (tid < kR0 * kRuns) {
+            // two columns per 32-bit LDS write
 #pragma unroll
             for (int j = 0; j < kRun; j += 2) {
-                if (fcol + j < kR0) {
-                    const uint32_t b0 = (v[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-                    const uint32_t b1 = (v[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xFFu;
-                    const _Float16 h0 = (_Float16)((float)b0 * (1.0f / 255.0f));
-                    const _Float16 h1 = (_Float16)((float)b1 * (1.0f / 255.0f));
-                    *reinterpret_cast<uint32_t*>(r0 + frow * kP0 + fcol + j) =
-                        (uint32_t)__builtin_bit_cast(uint16_t, h0) |
-                        ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-                }
+                if (fcol + j < kR0)
+                    *reinterpret_cast<uint32_t*>(r0 + frow * kP0 + fcol + j) = h16(j) | (h16(j + 1) << 16);
             }
         }
         int nb, nblk2;
@@ -1051,6 +1089,7 @@ LANE_INTERNAL int lane_cnn_infer_mask_active(const uint8_t* img, int32_t W, int3
     p.batch = batch;
     p.active = active;
     p.mask = mask;
+    p.wide = ((uintptr_t)img % 16 == 0 && pitch % 16 == 0 && img_stride % 16 == 0) ? 1 : 0;
     // the decision threshold in float32, the same value lane_mask_from_logits uses
     p.t_hi = mask ? (float)log((double)conf / (1.0 - (double)conf)) : 0.f;
     int dev = 0, cus = 256;

@@ -76,6 +76,28 @@ def test_fused_inference_equals_layers(lane, synth, W, H, B):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("W,H,pitch,B", [(1001, 70, 1008, 2), (200, 136, 208, 1), (1913, 1080, 1920, 1),
+                                         (33, 17, 48, 2)])
+def test_fused_inference_padded_rows(lane, synth, W, H, pitch, B):
+    """Frames whose rows are padded to a 16-byte pitch (the 16-byte input
+    loads of the fused kernel, whose last chunk of a row straddles the
+    frame's right edge): bytes past the width are bright and must not count;
+    the logits equal the layer kernels' on the same padded frames and those
+    of the unpadded frames."""
+    say("cnn fused, padded rows", W, H, pitch, B)
+    net, _ = make_net(7, bias_scale=0.5)
+    core = frames(synth, max(W, 16), max(H, 16), B, 60)[:, :H, :W]
+    pad = np.full((B, H, pitch), 255, np.uint8)
+    pad[:, :, :W] = core
+    imgs = torch.from_numpy(pad).cuda()
+    a = net.forward(imgs, W).clone()
+    b = net.forward_layers(imgs, W).clone()
+    c = net.forward(torch.from_numpy(core.copy()).cuda()).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
 def _labels(rng, th, tw):
     keep = (rng.random((th, tw)) < 0.3).astype(np.uint8)
     keep[0, 0] = 1
