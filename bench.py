@@ -42,6 +42,7 @@ METRIC = "Mpix/s & frames/s Sobel+Hough at 1080p; p99 frame latency, pruned vs p
 W, H, N_THETA, TOPK = 1920, 1080, 360, 8
 POOL = 16            # distinct generated frames; copied to distinct HBM buffers
 HBM_PEAK_GBS = 8000.0
+MFMA_FP16_PEAK_TFLOPS = 2500.0  # dense FP16 MFMA, published
 CUS, CLOCK_GHZ = 256, 2.4
 # LDS: 32 banks, one 4-byte access per bank per clock per CU
 LDS_BANK_PEAK_GVOTES = CUS * 32 * CLOCK_GHZ
@@ -258,6 +259,36 @@ def lds_probe():
             best = max(best, rate.value)
         out[name] = round(best / 1e9, 1)
     return out
+
+
+def cnn_flops(W, H):
+    """Useful FLOPs of the proposal network on one W x H frame (2 per
+    multiply-add; zero padding and MFMA padding not counted): conv1 1->16,
+    conv2 and conv3 16->16 at stride 2, head 16->9, all 3x3."""
+    h1, w1 = (H + 1) // 2, (W + 1) // 2
+    h2, w2 = (h1 + 1) // 2, (w1 + 1) // 2
+    h3, w3 = (h2 + 1) // 2, (w2 + 1) // 2
+    return 2 * 9 * (h1 * w1 * 16 * 1 + h2 * w2 * 16 * 16 + h3 * w3 * 16 * 16 + h3 * w3 * 9 * 16)
+
+
+def cnn_roofline(torch, lane, pool_d, stream, iters=20):
+    """The fused proposal network (lane_cnn_infer) on the 16 pool frames in
+    one call, trained weights: us per frame and useful TFLOP/s against the
+    dense FP16 MFMA peak."""
+    from paper_2212_09460_amd.learned.model import ProposalNet, load_params
+    net = ProposalNet(load_params())
+    imgs = torch.stack(pool_d)
+    n = imgs.shape[0]
+    logits = torch.empty((n, 9, (H + 7) // 8, (W + 7) // 8), dtype=torch.float32, device=imgs.device)
+    run = lambda: lane.cnn_infer(imgs, net.packed, logits, stream=stream)
+    run()
+    ms = event_time(torch, run, iters, stream)
+    tflops = cnn_flops(W, H) * n / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": "k_cnn_infer", "frames_per_call": n,
+            "us_per_frame": round(ms * 1e3 / n, 2), "achieved": round(tflops, 1),
+            "peak": MFMA_FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / MFMA_FP16_PEAK_TFLOPS, 4),
+            "flops_per_frame": cnn_flops(W, H)}
 
 
 def mixed_leg(args, torch, lane, synth, stream):
@@ -763,6 +794,8 @@ def main():
 
     probe = lds_probe()
     note(f"LDS increment probe (G/s): {probe}")
+    cnn = cnn_roofline(torch, lane, pool_d, stream)
+    note(f"proposal network: {cnn}")
     value = px / (ms_step * 1e-3) / 1e6
     out = {
         "metric": METRIC,
@@ -803,6 +836,7 @@ def main():
                            "bytes_per_launch": sobel_bytes,
                            "device_copy_gbs": round(copy_gbs, 1),
                            "frac_of_device_copy": round(sobel_gbs / copy_gbs, 4)},
+        "roofline_cnn": cnn,
         "latency_ms_single_frame_gpu": {"p50": round(float(np.percentile(lat, 50)), 4),
                                         "p99": round(float(np.percentile(lat, 99)), 4),
                                         "max": round(float(np.max(lat)), 4), "runs": int(lat.size)},

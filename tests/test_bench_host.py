@@ -113,3 +113,31 @@ def test_lds_probe_rejects_bad_arguments():
     for args in ((0, 1, 0), (1, 0, 0), (1, 1, 3), (1, 1, -1), (70000, 1, 0)):
         assert f(*args, ctypes.byref(rate), ctypes.byref(chk)) == -1
     assert f(1, 1, 0, None, ctypes.byref(chk)) == -1
+
+
+def test_cnn_flops_match_the_oracle_layer_shapes():
+    """The proposal network's FLOP count used for its roofline equals
+    2 x (output pixels x c_out x c_in x 9) summed over the oracle's layers,
+    with the output shapes the oracle's forward pass produces."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle import cnn as ocnn
+    rng = np.random.default_rng(3)
+    params = ocnn.unflatten(rng.standard_normal(6105) * 0.1)
+    for W, H in ((16, 16), (37, 21), (1920, 1080)):
+        img = np.zeros((H, W), np.uint8) if W * H > 100000 else rng.integers(0, 256, (H, W)).astype(np.uint8)
+        if W * H > 100000:
+            # shapes only: the layers' outputs of a strided 3x3 with padding 1
+            shapes, h, w = [], H, W
+            for (_, _, s, _) in ocnn.LAYERS:
+                h, w = (h + s - 1) // s, (w + s - 1) // s
+                shapes.append((h, w))
+        else:
+            _, acts = ocnn.forward(img, params)
+            shapes = [a.shape[1:] for a in acts[1:]]
+        want = 0
+        for (h, w), (wt, _) in zip(shapes, params):
+            c_out, c_in = wt.shape[0], wt.shape[1]
+            want += 2 * h * w * c_out * c_in * 9
+        assert bench.cnn_flops(W, H) == want, (W, H)
