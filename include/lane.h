@@ -498,7 +498,10 @@ int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t bat
  * on exactly those slots, launch one graph (network and mask per class when
  * pruned, then clear, Sobel, vote, peaks; switched-off slots return at once),
  * copy the peaks back and complete the requests.  Requests arriving while a
- * batch runs join the next one.  A frame's results do not depend on the
+ * batch runs join the next one; the frame of a request that heads the queue
+ * of a stream not in the running batch is copied to its slot at once, on a
+ * copy stream of its own, so that copy overlaps the running batch and the
+ * next one starts with it in place.  A frame's results do not depend on the
  * other frames of its batch.  Failures: a request beyond its stream's queue
  * bound is dropped (LANE_E_BUSY); with a deadline, one that waited too long
  * is completed unrun (LANE_E_TIMEOUT) and frees its place; a device error
@@ -571,8 +574,11 @@ int lane_server_plan(const lane_stream_cfg *streams, int32_t n, const lane_serve
 int lane_server_create(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,
                        lane_server **out, uint8_t *admitted_opt);
 /* Queue a frame (host uint8 [H][pitch] of the stream's size).  The bytes are
- * read when the request's batch starts, so they must stay valid and unchanged
- * until its result is taken (page-locked memory copies fastest).  Returns
+ * read when the request heads its stream's queue with the stream idle (the
+ * copy ahead, started by this call then) or when its batch starts, so they
+ * must stay valid and unchanged until its result is taken (page-locked
+ * memory copies asynchronously; a pageable frame makes the copy ahead, and
+ * so this call, wait for the bytes to be read).  Returns
  * LANE_E_BUSY, and completes the request as dropped, when the stream already
  * has max_pending requests waiting; LANE_E_ARG for a stream not admitted.
  * Thread-safe. */

@@ -160,7 +160,10 @@ struct Req {
     const uint8_t* frame;
     uint64_t frame_id;
     int64_t t_submit;
-    int64_t tag;  // >= 0: index in the running replay
+    int64_t tag;    // >= 0: index in the running replay
+    uint64_t id;    // unique per request (copy-ahead bookkeeping)
+    bool ahead;     // (taken into a refill) its frame was copied ahead
+    bool after_up;  // (taken) a copy ahead went to its slot: order after it
 };
 
 }  // namespace
@@ -191,6 +194,16 @@ struct lane_server {
     uint8_t* d_flags = nullptr;            // the plan's flags
     lane_batch* plan = nullptr;
     hipStream_t stream = nullptr;
+    // copy-ahead: the frame of the request at the head of an idle slot's
+    // queue is copied to the slot on its own stream as soon as it is
+    // known, so the copy overlaps the refill running meanwhile; up_id[slot]
+    // = the request whose copy up_ev[slot] marks (0: none); busy[slot]: the
+    // slot is in the running refill (its frame buffer still being read)
+    hipStream_t up_stream = nullptr;
+    std::vector<hipEvent_t> up_ev;
+    std::vector<uint64_t> up_id;
+    std::vector<uint8_t> busy;
+    uint64_t next_id = 1;
     // graphs[m]: the refill whose active slots lie in the classes of bit
     // mask m (pruned, up to kSubsetClasses classes: only those classes run
     // their network and masks); otherwise graphs[0] serves every refill
@@ -233,6 +246,26 @@ void complete(lane_server* s, lane_result& r, int64_t tag) {
     s->cv_done.notify_all();
 }
 
+// a request's frame into its slot's buffer on `st`
+hipError_t copy_frame(lane_server* s, int slot, const Req& q, hipStream_t st) {
+    const lane_server::Class& c = s->classes[s->class_of[slot]];
+    if (q.pitch == c.cfg.W && c.pitch == c.cfg.W)  // one contiguous copy
+        return hipMemcpyAsync(s->slot_img[slot], q.frame, (size_t)c.cfg.W * c.cfg.H, hipMemcpyHostToDevice, st);
+    return hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch, (size_t)c.cfg.W,
+                            (size_t)c.cfg.H, hipMemcpyHostToDevice, st);
+}
+
+// (caller holds s->mu) copy the frame of the request at the head of the
+// slot's queue ahead, if the slot is idle and that copy is not out yet
+void copy_ahead(lane_server* s, int slot) {
+    if (!s->up_stream || s->busy[slot] || s->error != LANE_OK) return;
+    const auto& d = s->pending[slot];
+    if (d.empty() || s->up_id[slot] == d.front().id) return;
+    hipError_t e = copy_frame(s, slot, d.front(), s->up_stream);
+    if (e == hipSuccess) e = hipEventRecord(s->up_ev[slot], s->up_stream);
+    s->up_id[slot] = e == hipSuccess ? d.front().id : 0;
+}
+
 int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_result>& out) {
     const int n_slots = (int)s->streams.size();
     memset(s->h_flags, 0, (size_t)n_slots);
@@ -243,13 +276,8 @@ int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_re
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const Req& q = batch[i];
         const int slot = s->slot_of[q.stream];
-        const lane_server::Class& c = s->classes[s->class_of[slot]];
-        if (q.pitch == c.cfg.W && c.pitch == c.cfg.W)  // one contiguous copy
-            e = hipMemcpyAsync(s->slot_img[slot], q.frame, (size_t)c.cfg.W * c.cfg.H,
-                               hipMemcpyHostToDevice, s->stream);
-        else
-            e = hipMemcpy2DAsync(s->slot_img[slot], (size_t)c.pitch, q.frame, (size_t)q.pitch,
-                                 (size_t)c.cfg.W, (size_t)c.cfg.H, hipMemcpyHostToDevice, s->stream);
+        if (q.after_up) e = hipStreamWaitEvent(s->stream, s->up_ev[slot], 0);
+        if (e == hipSuccess && !q.ahead) e = copy_frame(s, slot, q, s->stream);
     }
     uint32_t cls_mask = 0;
     if (s->per_subset)
@@ -303,6 +331,7 @@ void worker_main(lane_server* s) {
         batch.clear();
         const int64_t t_take = now_ns();
         for (auto& d : s->pending) {
+            const int slot = (int)(&d - &s->pending[0]);
             while (!d.empty() && s->cfg.deadline_ns > 0 && t_take - d.front().t_submit > s->cfg.deadline_ns) {
                 lane_result r;
                 fill_result(r, d.front(), LANE_E_TIMEOUT);
@@ -312,7 +341,14 @@ void worker_main(lane_server* s) {
                 d.pop_front();
             }
             if (d.empty()) continue;
-            batch.push_back(d.front());
+            // a copy ahead into this slot (this request's, or one of a
+            // request that timed out) is ordered before the refill's use
+            Req q = d.front();
+            q.ahead = s->up_id[slot] == q.id;
+            q.after_up = s->up_id[slot] != 0;
+            s->up_id[slot] = 0;
+            s->busy[slot] = 1;
+            batch.push_back(q);
             d.pop_front();
         }
         if (batch.empty()) continue;
@@ -334,6 +370,12 @@ void worker_main(lane_server* s) {
             s->stats.completed += 1;
             complete(s, out[i], batch[i].tag);
         }
+        // the slots are free again: the next frames of their streams may go ahead
+        for (const Req& q : batch) {
+            const int slot = s->slot_of[q.stream];
+            s->busy[slot] = 0;
+            copy_ahead(s, slot);
+        }
     }
 }
 
@@ -346,8 +388,11 @@ int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, u
     q.frame_id = frame_id;
     q.t_submit = now_ns();
     q.tag = tag;
+    q.id = s->next_id++;
+    q.ahead = q.after_up = false;
     s->stats.submitted += 1;
-    auto& d = s->pending[s->slot_of[stream]];
+    const int slot = s->slot_of[stream];
+    auto& d = s->pending[slot];
     if ((int)d.size() >= s->cfg.max_pending) {
         s->stats.dropped += 1;
         lane_result r;
@@ -357,6 +402,7 @@ int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, u
         return LANE_E_BUSY;
     }
     d.push_back(q);
+    if (d.size() == 1) copy_ahead(s, slot);
     s->cv_work.notify_one();
     return LANE_OK;
 }
@@ -379,6 +425,12 @@ void free_server(lane_server* s) {
         s->worker.join();
     }
     if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->up_stream) {
+        hipStreamSynchronize(s->up_stream);
+        hipStreamDestroy(s->up_stream);
+    }
+    for (auto ev : s->up_ev)
+        if (ev) hipEventDestroy(ev);
     for (auto x : s->execs)
         if (x) hipGraphExecDestroy(x);
     for (auto g : s->graphs)
@@ -501,6 +553,12 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     s->stats.streams_admitted = n_slots;
     bool ok = hipMalloc(&s->dmem, off) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) == hipSuccess;
+    s->up_ev.assign(n_slots, nullptr);
+    s->up_id.assign(n_slots, 0);
+    s->busy.assign(n_slots, 0);
+    for (int i = 0; i < n_slots && ok; ++i)
+        ok = hipEventCreateWithFlags(&s->up_ev[i], hipEventDisableTiming) == hipSuccess;
     size_t hp = 0;
     s->h_peak_off.resize(n_slots);
     for (int i = 0; i < n_slots; ++i) {

@@ -256,6 +256,39 @@ def test_deadline_frees_places_and_others_run(lane, synth):
         srv.close()
 
 
+def test_copy_ahead_then_timeout(lane, synth):
+    """A request that heads an idle stream's queue has its frame copied to
+    the stream's slot at once (overlapping whatever runs); when it then times
+    out, the next request of that stream, taken in the same pass, is copied
+    after that early copy and gives its own frame's peaks; a request whose
+    copy went ahead and runs gives its frame's peaks too."""
+    say("serve: copy ahead, timeout, next request")
+    import time
+
+    P = pools(synth, STREAMS[:1], n=3, seed=900)
+    refs = [alone(lane, P[0][j], STREAMS[0]) for j in range(3)]
+    srv = lane.Server(STREAMS[:1], hbm_budget=1 << 30, max_pending=2, deadline_ms=20.0)
+    try:
+        srv.pause(True)
+        assert srv.submit(0, P[0][0], frame_id=1) == 0  # heads the idle queue: copied ahead
+        time.sleep(0.06)                                # past its deadline
+        assert srv.submit(0, P[0][1], frame_id=2) == 0  # fresh, behind it
+        srv.pause(False)
+        got = {}
+        while len(got) < 2:
+            rs = srv.poll(8, wait_ms=5000)
+            assert rs, "poll timed out"
+            for r in rs:
+                got[r.frame_id] = r
+        assert got[1].status == lane.LANE_E_TIMEOUT
+        assert got[2].status == 0 and same(got[2], refs[1], 8)
+        assert srv.submit(0, P[0][2], frame_id=3) == 0  # idle again: copied ahead, then run
+        rs = srv.poll(8, wait_ms=5000)
+        assert rs and rs[0].frame_id == 3 and rs[0].status == 0 and same(rs[0], refs[2], 8)
+    finally:
+        srv.close()
+
+
 def test_stalled_stream_does_not_hold_the_others(lane, synth):
     """Stream 0 sends a burst and then stalls for most of the run while
     streams 1 and 2 keep sending: every request completes, each with its
