@@ -428,13 +428,17 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_vote = off; off = al(off + sizeof(VoteDesc) * n);
     const size_t o_peaks = off; off = al(off + sizeof(PeaksDesc) * std::max<size_t>(pd.size(), 1));
     const size_t o_lines = off; off = al(off + sizeof(LinesDesc) * std::max<size_t>(ld.size(), 1));
-    const size_t o_sitems = off; off = al(off + sizeof(int2) * sitems.size());
-    const size_t o_vitems = off; off = al(off + sizeof(int2) * vitems.size());
+
     const size_t o_prefix = off; off = al(off + sizeof(int) * prefix.size());
     const size_t o_cnt = off; off = al(off + sizeof(uint32_t*) * n);
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 16);
-    const size_t o_active = off; off = al(off + (size_t)n);
-    const size_t o_counts = off; off = al(off + sizeof(int) * 16);
+    // the selection block, laid out as the host staging of lane_batch_select
+    // so that one copy refreshes it: switches | counts | Sobel items | vote items
+    const size_t o_active = off;
+    const size_t o_counts = o_active + (((size_t)n + 15) & ~(size_t)15);
+    const size_t o_sitems = o_counts + sizeof(int) * 16;
+    const size_t o_vitems = o_sitems + sizeof(int2) * sitems.size();
+    off = al(o_vitems + sizeof(int2) * vitems.size());
     const size_t o_prune = off; off = al(off + sizeof(PruneDesc) * std::max<size_t>(prd.size(), 1));
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         free_plan(b);
@@ -630,13 +634,11 @@ int lane_batch_select(lane_batch* b, const uint8_t* active, void* stream) {
     cnt[1] = ns[1];
     cnt[2] = nv;
     cnt[3] = 0;
+    // one copy: the device block has the staging's layout; the Sobel items
+    // past ns[0] + ns[1] travel too (unused), the vote items up to nv
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(b->d_active, fl, (size_t)n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_counts, cnt, sizeof(int) * 16, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && ns[0] + ns[1] > 0)
-        e = hipMemcpyAsync(b->d_sobel_items, si, sizeof(int2) * (ns[0] + ns[1]), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && nv > 0)
-        e = hipMemcpyAsync(b->d_vote_items, vi, sizeof(int2) * nv, hipMemcpyHostToDevice, s);
+    const size_t bytes = (size_t)((char*)(vi + nv) - (char*)b->h_stage);
+    const hipError_t e = hipMemcpyAsync(b->d_active, b->h_stage, bytes, hipMemcpyHostToDevice, s);
     return e == hipSuccess ? LANE_OK : LANE_E_DEVICE;
 }
 
