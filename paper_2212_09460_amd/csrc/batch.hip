@@ -4,8 +4,9 @@
 // Each stage is one persistent kernel walking a work table built here:
 //   Sobel  (frame, strip item) pairs, one wave each, grid = occupancy limit;
 //   vote   (frame, theta slice) pairs, one 1024-thread workgroup each;
-//   peaks  block keys over a per-frame prefix table, then one workgroup per
-//          frame for the greedy selection.
+//   peaks  block keys (written by the vote, or after a split vote by a key
+//          pass over the selected frames), then one workgroup per frame for
+//          the greedy selection.
 // The vote table is laid out for the XCD round-robin of workgroup dispatch:
 // with a static stride that is a multiple of 8, table slot i always runs on
 // XCD i mod 8, so slots are filled such that all slices of a frame share one
@@ -63,7 +64,7 @@ struct lane_batch {
     int n_lines_frames = 0, lines_max_k = 0, lines_max_side = 0;
     int2* d_sobel_items = nullptr;
     int2* d_vote_items = nullptr;
-    int* d_prefix = nullptr;
+    int* d_pk_list = nullptr;      // frames (peak descriptor indices) of the key pass; count in d_counts[3]
     uint32_t** d_counters = nullptr;
     uint32_t* d_queue = nullptr;
     uint8_t* d_active = nullptr;   // one flag per frame, 1 after creation
@@ -75,7 +76,8 @@ struct lane_batch {
     std::vector<int> h_vxcd;               // per frame: its XCD run (per-XCD queues), else -1
     std::vector<int> h_sgroup;             // per frame: 0 aligned, 1 other
     char* h_stage = nullptr;               // page-locked staging for the selection copies
-    int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0, total_blocks = 0;
+    int n_sobel_items = 0, n_sobel_fast = 0, n_vote_items = 0;
+    std::vector<int> h_pk_frame;           // peak descriptor -> its frame
     int grid_sobel = 1, grid_sobel_slow = 1, grid_vote = 1, grid_keys = 1, grid_select = 1;
     bool vote_dynamic = false;
     bool vote_xcd = false;   // per-XCD ticket queues
@@ -174,7 +176,7 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s, bool pass = fa
         case 3:
             if (b->n_peak_frames == 0) return hipSuccess;
             // keys: written by the vote, or by a pass of their own after a split vote
-            return lane_launch_peaks_batch(b->d_peaks, b->d_prefix, b->n_peak_frames, b->total_blocks,
+            return lane_launch_peaks_batch(b->d_peaks, b->d_pk_list, b->d_counts, b->n_peak_frames,
                                            b->vote_split > 1 ? b->grid_keys : 0, b->grid_select, s);
         case 4:
             if (b->n_lines_frames == 0) return hipSuccess;
@@ -227,7 +229,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     std::vector<int> ld_frame;
     int lines_max_k = 0, lines_max_side = 0;
     std::vector<int2> sitems, sitems_slow, vitems;
-    std::vector<int> prefix(1, 0);
     std::vector<uint32_t*> counters(n, nullptr);
     std::vector<PruneDesc> prd;  // masked frames of a split vote
     std::vector<size_t> prune_bytes;
@@ -344,7 +345,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
                 v.key_log2 = p.block_log2;
                 v.nbr = p.nbr;
             }
-            prefix.push_back(prefix.back() + p.n_blocks);
         }
     }
     // vote table
@@ -414,7 +414,6 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->lines_max_side = lines_max_side;
     b->n_sobel_items = (int)sitems.size();
     b->n_vote_items = (int)vitems.size();
-    b->total_blocks = prefix.back();
     b->vote_dynamic = dynamic;
     b->vote_xcd = per_xcd;
     b->h_vxcd = vxcd;
@@ -429,14 +428,16 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     const size_t o_peaks = off; off = al(off + sizeof(PeaksDesc) * std::max<size_t>(pd.size(), 1));
     const size_t o_lines = off; off = al(off + sizeof(LinesDesc) * std::max<size_t>(ld.size(), 1));
 
-    const size_t o_prefix = off; off = al(off + sizeof(int) * prefix.size());
     const size_t o_cnt = off; off = al(off + sizeof(uint32_t*) * n);
     const size_t o_queue = off; off = al(off + sizeof(uint32_t) * 16);
     // the selection block, laid out as the host staging of lane_batch_select
-    // so that one copy refreshes it: switches | counts | Sobel items | vote items
+    // so that one copy refreshes it: switches | counts | key-pass frames |
+    // Sobel items | vote items
+    const size_t n_pk = pd.size();
     const size_t o_active = off;
     const size_t o_counts = o_active + (((size_t)n + 15) & ~(size_t)15);
-    const size_t o_sitems = o_counts + sizeof(int) * 16;
+    const size_t o_pklist = o_counts + sizeof(int) * 16;
+    const size_t o_sitems = o_pklist + sizeof(int) * ((n_pk + 1) & ~(size_t)1);
     const size_t o_vitems = o_sitems + sizeof(int2) * sitems.size();
     off = al(o_vitems + sizeof(int2) * vitems.size());
     const size_t o_prune = off; off = al(off + sizeof(PruneDesc) * std::max<size_t>(prd.size(), 1));
@@ -466,11 +467,11 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->d_lines = (LinesDesc*)(base + o_lines);
     b->d_sobel_items = (int2*)(base + o_sitems);
     b->d_vote_items = (int2*)(base + o_vitems);
-    b->d_prefix = (int*)(base + o_prefix);
     b->d_counters = (uint32_t**)(base + o_cnt);
     b->d_queue = (uint32_t*)(base + o_queue);
     b->d_active = (uint8_t*)(base + o_active);
     b->d_counts = (int*)(base + o_counts);
+    b->d_pk_list = (int*)(base + o_pklist);
     b->d_prune = (PruneDesc*)(base + o_prune);
     b->n_prune = (int)prd.size();
     for (int i = 0; i < n; ++i) {
@@ -490,11 +491,17 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         ok = ok && hipMemcpy(b->d_lines, ld.data(), sizeof(LinesDesc) * ld.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_sobel_items, sitems.data(), sizeof(int2) * sitems.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_vote_items, vitems.data(), sizeof(int2) * vitems.size(), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_counters, counters.data(), sizeof(uint32_t*) * n, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_queue, 0, sizeof(uint32_t) * 16) == hipSuccess;
     ok = ok && hipMemset(b->d_active, 1, (size_t)n) == hipSuccess;
-    const int counts0[16] = {n_fast, b->n_sobel_items - n_fast, b->n_vote_items, 0,
+    std::vector<int> pk_all(pd.size());
+    for (size_t j = 0; j < pd.size(); ++j) {
+        pk_all[j] = (int)j;
+        b->h_pk_frame.push_back(pd[j].active_index);
+    }
+    if (!pk_all.empty())
+        ok = ok && hipMemcpy(b->d_pk_list, pk_all.data(), sizeof(int) * pk_all.size(), hipMemcpyHostToDevice) == hipSuccess;
+    const int counts0[16] = {n_fast, b->n_sobel_items - n_fast, b->n_vote_items, (int)pd.size(),
                              xends[0], xends[1], xends[2], xends[3],
                              xends[4], xends[5], xends[6], xends[7], 0, 0, 0, 0};
     ok = ok && hipMemcpy(b->d_counts, counts0, sizeof(counts0), hipMemcpyHostToDevice) == hipSuccess;
@@ -524,7 +531,8 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         for (int i = a; i < a + c && b->h_vfirst[f] >= 0; ++i)
             if (vitems[i].x != f) b->h_vfirst[f] = -2;
     }
-    const size_t stage_bytes = (((size_t)n + 15) & ~(size_t)15) + 64 + sizeof(int2) * (sitems.size() + vitems.size());
+    const size_t stage_bytes = (((size_t)n + 15) & ~(size_t)15) + 64 + sizeof(int) * ((pd.size() + 1) & ~(size_t)1) +
+                               sizeof(int2) * (sitems.size() + vitems.size());
     ok = ok && hipHostMalloc((void**)&b->h_stage, al(stage_bytes), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         free_plan(b);
@@ -550,11 +558,12 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
         // a multiple of 8 keeps every table slot on its XCD
         b->grid_vote = std::max(8, std::min(b->n_vote_items, cus * vote_per_cu) / 8 * 8);
     }
-    // key pass (split votes): workgroups per frame, about 2048 in all
+    // key pass (split votes)
     int max_blocks = 1;
     for (const auto& p : pd) max_blocks = std::max(max_blocks, p.n_blocks);
-    b->grid_keys = std::max(1, std::min((max_blocks + 3) / 4,
-                                        std::max(64, 2048 / std::max(1, b->n_peak_frames))));
+    // (shared out over the frames selected at launch: enough for four
+    // blocks per wave when up to four frames run, fewer per frame beyond)
+    b->grid_keys = std::max(64, (max_blocks + 15) / 16) * std::max(1, std::min(b->n_peak_frames, 4));
     b->grid_select = std::max(1, std::min(b->n_peak_frames, cus));
 
     // capture the stages into one graph
@@ -594,7 +603,9 @@ int lane_batch_select(lane_batch* b, const uint8_t* active, void* stream) {
     // staging: flags | counts (16) | Sobel items (aligned group, then the other) | vote items
     uint8_t* fl = (uint8_t*)b->h_stage;
     int* cnt = (int*)(b->h_stage + ((n + 15) & ~15));
-    int2* si = (int2*)(cnt + 16);
+    int* pl = cnt + 16;  // frames of the key pass
+    const int n_pk = (int)b->h_pk_frame.size();
+    int2* si = (int2*)(pl + ((n_pk + 1) & ~1));
     int2* vi = si + b->h_sitems.size();
     int ns[2] = {0, 0};
     for (int g = 0; g < 2; ++g) {
@@ -633,7 +644,10 @@ int lane_batch_select(lane_batch* b, const uint8_t* active, void* stream) {
     cnt[0] = ns[0];
     cnt[1] = ns[1];
     cnt[2] = nv;
-    cnt[3] = 0;
+    int na = 0;
+    for (int j = 0; j < n_pk; ++j)
+        if (active[b->h_pk_frame[j]]) pl[na++] = j;
+    cnt[3] = na;
     // one copy: the device block has the staging's layout; the Sobel items
     // past ns[0] + ns[1] travel too (unused), the vote items up to nv
     hipStream_t s = (hipStream_t)stream;

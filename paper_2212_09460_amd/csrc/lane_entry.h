@@ -28,8 +28,8 @@ LANE_INTERNAL hipError_t lane_launch_prune_batch(const lane::PruneDesc* descs, i
 
 // peaks.hip
 LANE_INTERNAL hipError_t lane_launch_peaks(const lane::PeaksDesc* d, hipStream_t s);
-LANE_INTERNAL hipError_t lane_launch_peaks_batch(const lane::PeaksDesc* descs, const int* prefix,
-                                                 int n_frames, int total_blocks, int grid_keys,
+LANE_INTERNAL hipError_t lane_launch_peaks_batch(const lane::PeaksDesc* descs, const int* list,
+                                                 const int* counts, int n_frames, int grid_keys,
                                                  int grid_select, hipStream_t s);
 
 // lines.hip, canny.hip, progressive.hip

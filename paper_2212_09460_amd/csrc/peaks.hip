@@ -86,12 +86,22 @@ __global__ void __launch_bounds__(256) k_block_keys(PeaksDesc d) {
 // of up to 256 cells go four at a time, every load of the four issued
 // before the first maximum (a wave walks many blocks: one memory round trip
 // per four instead of one per block).
-__global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs) {
-    const PeaksDesc d = descs[blockIdx.y];
+// Block keys of the frames in `list` (device: counts[3] frame indices,
+// refreshed per selection), after a split vote: the grid is shared out
+// evenly over those frames, so one frame alone gets all of it.
+__global__ void __launch_bounds__(256) k_block_keys_batch(const PeaksDesc* __restrict__ descs,
+                                                          const int* __restrict__ list,
+                                                          const int* __restrict__ counts) {
+    const int na = gld(counts + 3);
+    if (na <= 0) return;
+    const int per = max(1, (int)gridDim.x / na);  // workgroups per frame
+    const int fi = (int)blockIdx.x / per;
+    if (fi >= na) return;
+    const PeaksDesc d = descs[gld(list + fi)];
     if (!frame_on(d.active)) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int stride = gridDim.x * 4;
-    int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int stride = per * 4;
+    int b = ((int)blockIdx.x - fi * per) * 4 + (threadIdx.x >> 6);
     if (d.block_log2 <= 8) {
         constexpr int U = 4, Q = 4;  // blocks per round, cells per lane and block
         const int B = 1 << d.block_log2;
@@ -620,11 +630,11 @@ extern "C" LANE_INTERNAL hipError_t lane_launch_peaks(const PeaksDesc* dp, hipSt
     return hipGetLastError();
 }
 
-extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* prefix, int n_frames,
-                                              int total_blocks, int grid_keys, int grid_select,
-                                              hipStream_t s) {
+extern "C" LANE_INTERNAL hipError_t lane_launch_peaks_batch(const PeaksDesc* descs, const int* list,
+                                                            const int* counts, int n_frames, int grid_keys,
+                                                            int grid_select, hipStream_t s) {
     if (grid_keys > 0) {  // 0: the vote already wrote the keys
-        hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys, n_frames), dim3(256), 0, s, descs);
+        hipLaunchKernelGGL(k_block_keys_batch, dim3(grid_keys), dim3(256), 0, s, descs, list, counts);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
