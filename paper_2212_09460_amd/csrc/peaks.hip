@@ -174,32 +174,6 @@ __device__ __forceinline__ bool in_window_fast(int t, int i, int tp, int ip, con
     return false;
 }
 
-// max(v, v of the lane CTRL names); lanes whose source is outside the row
-// (or rows outside ROW_MASK) keep v
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ unsigned long long dpp_max(unsigned long long v) {
-    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-    const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
-    const uint32_t hi2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
-    const unsigned long long w = ((unsigned long long)hi2 << 32) | lo2;
-    return w > v ? w : v;
-}
-
-// Maximum over the 64 lanes, in every lane (all lanes active): row shifts
-// make lane 15 of each row its row's maximum, two row broadcasts carry
-// rows 0-1 and 2-3 into lane 63, which is read back.
-__device__ __forceinline__ unsigned long long wave_max_all(unsigned long long v) {
-    v = dpp_max<0x111, 0xF>(v);  // row_shr:1
-    v = dpp_max<0x112, 0xF>(v);  // row_shr:2
-    v = dpp_max<0x114, 0xF>(v);  // row_shr:4
-    v = dpp_max<0x118, 0xF>(v);  // row_shr:8
-    v = dpp_max<0x142, 0xA>(v);  // row_bcast:15
-    v = dpp_max<0x143, 0xC>(v);  // row_bcast:31
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 __device__ __forceinline__ int wave_max_i32(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
@@ -354,10 +328,10 @@ __device__ int peaks_candidates(const PeaksDesc& d, int floor_votes, int vmax) {
         unsigned long long best = 0;
 #pragma unroll
         for (int m = 0; m < kCandSlots; ++m) best = ck[m] > best ? ck[m] : best;
-        best = wave_max_all(best);
+        best = wave_max_u64(best);
         if (lane == 0) s_wbest[j & 1][wave] = best;
         __syncthreads();
-        const unsigned long long mx = wave_max_all(lane < nwaves ? s_wbest[j & 1][lane] : 0ull);
+        const unsigned long long mx = wave_max_u64(lane < nwaves ? s_wbest[j & 1][lane] : 0ull);
         if (mx == 0ull) {
             ran_out = true;
             break;
@@ -394,7 +368,7 @@ __device__ int peaks_general(const PeaksDesc& d, int floor_votes) {
     for (int g = wave; g < n_groups; g += nwaves) {
         const int b = (g << kGroupLog2) + (lane & 31);
         const unsigned long long v = (lane < 32 && b < d.n_blocks) ? s_keys[b] : 0ull;
-        const unsigned long long m = wave_max_all(v);
+        const unsigned long long m = wave_max_u64(v);
         if (lane == 0) s_gkey[g] = m;
     }
     __syncthreads();
@@ -411,7 +385,7 @@ __device__ int peaks_general(const PeaksDesc& d, int floor_votes) {
         // every wave finds the largest key itself: no barrier to share it
         unsigned long long best = 0;
         for (int g = lane; g < n_groups; g += kWave) best = s_gkey[g] > best ? s_gkey[g] : best;
-        const unsigned long long m = wave_max_all(best);
+        const unsigned long long m = wave_max_u64(best);
         if (m == 0 || key_value(m) < floor_votes) break;  // the same decision in every wave
         const uint32_t idx = key_index(m);
         const int t = (int)(idx / (uint32_t)d.n_r), i = (int)(idx % (uint32_t)d.n_r);
@@ -552,7 +526,7 @@ __device__ int peaks_general(const PeaksDesc& d, int floor_votes) {
                 }
                 v = tb >= 0 ? snew[tb] : s_keys[b];
             }
-            const unsigned long long gm = wave_max_all(v);
+            const unsigned long long gm = wave_max_u64(v);
             if (lane == 0) s_gkey[g] = gm;
             if (tb >= 0) s_keys[b] = v;
         }
