@@ -222,11 +222,22 @@ __device__ void vote_item(VoteLds<LDSW>& sm, const VoteDesc& d, int code) {
             else if constexpr (kIL == 1) lds_vote_il(sm, v, jb, sh);
             else lds_vote(sm, v);
         };
+        auto voteV = [&](uint32_t v) {
+            if constexpr (kIL == 2) lds_vote_il2(sm, v, jb, sh);
+            else if constexpr (kIL == 1) lds_vote_il(sm, v, jb, sh);
+            else lds_vote(sm, v);
+        };
+        // four entries: the four dot products first, so no address waits on
+        // the product just issued
         auto vote4 = [&](u32x4 q) {
-            vote1(q.x);
-            vote1(q.y);
-            vote1(q.z);
-            vote1(q.w);
+            const uint32_t v0 = (uint32_t)dot2_i16((int)q.x, CS, K);
+            const uint32_t v1 = (uint32_t)dot2_i16((int)q.y, CS, K);
+            const uint32_t v2 = (uint32_t)dot2_i16((int)q.z, CS, K);
+            const uint32_t v3 = (uint32_t)dot2_i16((int)q.w, CS, K);
+            voteV(v0);
+            voteV(v1);
+            voteV(v2);
+            voteV(v3);
         };
         if (!masked) {
             // One segment's entries split over Gs slots (slot gs): each slot
