@@ -410,8 +410,11 @@ int lane_batch_destroy(lane_batch *b);
  * times the vote for every theta-slice width (rows per workgroup, down to
  * 1/16 of the largest that fits LDS) and the three work distributions, then the
  * Sobel pass for strip heights 8..128 with and without a persistent grid (1
- * or 2 workgroups per CU), and writes the fastest setting to *out.  ms_opt: host float[2] or
- * NULL, receives the best vote and Sobel times in ms. */
+ * or 2 workgroups per CU), and writes the fastest setting to *out (a vote
+ * setting with per-XCD queues is taken over a faster one within 1 %: the same
+ * time within measurement noise, with far less traffic from beyond the L2).
+ * ms_opt: host float[2] or NULL, receives the chosen vote and the best Sobel
+ * times in ms. */
 int lane_tune_run(const uint8_t *sample, int32_t W, int32_t H, int32_t pitch, int32_t threshold,
                   int32_t border_mode, int32_t n_theta, int32_t n_frames, lane_tune *out,
                   float *ms_opt);

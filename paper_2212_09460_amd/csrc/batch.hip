@@ -727,7 +727,14 @@ int tune_frames(const lane_frame* frames, int n_frames, int tmax, bool per_frame
     std::vector<int> rows;
     if (per_frame_default) rows.push_back(0);
     for (int T = tmax; T >= 1 && T * 16 >= tmax; T >>= 1) rows.push_back(T);
-    // theta rows per vote workgroup x work distribution
+    // theta rows per vote workgroup x work distribution; of the settings
+    // within 1 % of the fastest (timing noise), the per-XCD queues win, whose
+    // slices of a frame share one L2 (far less traffic from beyond it)
+    struct Trial {
+        int T, q;
+        float ms;
+    };
+    std::vector<Trial> trials;
     for (int T : rows) {
         for (int q = 0; q <= 2; ++q) {
             lane_tune t = {T, q, 0, 0, 0};
@@ -736,8 +743,9 @@ int tune_frames(const lane_frame* frames, int n_frames, int tmax, bool per_frame
             if (status != LANE_OK) break;
             enqueue_stage(b, 0, st);
             enqueue_stage(b, 1, st);
-            const float ms = time_stage(b, 2, 3, st, e0, e1);
+            const float ms = time_stage(b, 2, 5, st, e0, e1);
             lane_batch_destroy(b);
+            if (ms > 0) trials.push_back({T, q, ms});
             if (ms > 0 && ms < best_vote) {
                 best_vote = ms;
                 best.vote_rows = T;
@@ -745,6 +753,14 @@ int tune_frames(const lane_frame* frames, int n_frames, int tmax, bool per_frame
             }
         }
         if (status != LANE_OK) break;
+    }
+    const Trial* xcd = nullptr;  // the fastest per-XCD setting
+    for (const Trial& tr : trials)
+        if (tr.q == 2 && (!xcd || tr.ms < xcd->ms)) xcd = &tr;
+    if (xcd && best.vote_queue != 2 && xcd->ms <= 1.01f * best_vote) {
+        best.vote_rows = xcd->T;
+        best.vote_queue = 2;
+        best_vote = xcd->ms;
     }
     // Sobel strip height x persistent workgroups per CU
     const int strips[6] = {8, 16, 24, 32, 64, 128};
