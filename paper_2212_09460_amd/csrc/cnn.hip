@@ -391,13 +391,17 @@ k_cnn_infer(CnnInfer p) {
         *reinterpret_cast<h8*>(s_w4 + 8 * i) = *(const LANE_GLOBAL h8*)(wk + kPkW4 + 8 * i);
     if (tid < 64) s_bias[tid] = gld(pk_bias(p.pk, 0) + tid);
     // conv1 taps of this lane: K index 4 grp + j is tap 4 grp + j (taps 9..15
-    // have zero weights; they read tap 8's pixel)
-    int off1[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int tap = min(4 * grp + j, 8);
-        off1[j] = (tap / 3) * kP0 + tap % 3;
-    }
+    // have zero weights).  The four halves come from three 32-bit LDS words
+    // at the lane's pixel p (even, so every word is aligned): w0 at p + a1,
+    // w1 right after it (one ds_read2), w2 at p + c1; two byte permutes
+    // put them in K order.  Group 0: taps (0,0) (0,1) | (0,2) (1,0) = w0 |
+    // w1.lo w2.lo; group 1: (1,1) (1,2) | (2,0) (2,1) = w0.hi w1.lo | w2;
+    // groups 2, 3: tap (2,2) = w1.lo first, the rest (zero weights) finite
+    // neighbours in the same row.
+    const int a1 = grp == 0 ? 0 : grp == 1 ? kP0 : 2 * kP0;
+    const int c1 = grp == 0 ? kP0 : 2 * kP0;
+    const uint32_t sel0 = grp == 0 ? 0x03020100u : grp == 1 ? 0x05040302u : 0x01000504u;
+    const uint32_t sel1 = grp == 0 ? 0x05040100u : grp == 1 ? 0x07060504u : 0x03020100u;
     const h4 A1 = ld_h4(wk + kPkW1 + col * 16 + 4 * grp);
     const Taps2 T2 = load_taps2(wk + kPkW2, col, grp);
     // conv1 lanes: column of each 16-pixel group and its de-interleaved slot
@@ -469,7 +473,11 @@ k_cnn_infer(CnnInfer p) {
 #pragma unroll
                 for (int xg = 0; xg < 3; ++xg) {
                     const _Float16* q = r0 + 2 * ly * kP0 + 2 * (16 * xg + col);
-                    const h4 B = {q[off1[0]], q[off1[1]], q[off1[2]], q[off1[3]]};
+                    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+                    const uint32_t w0 = qw[a1 >> 1], w1 = qw[(a1 >> 1) + 1], w2 = qw[c1 >> 1];
+                    const uint32_t d0 = __builtin_amdgcn_perm(w1, w0, sel0);
+                    const uint32_t d1 = __builtin_amdgcn_perm(w2, w1, sel1);
+                    const h4 B = __builtin_bit_cast(h4, (unsigned long long)d0 | ((unsigned long long)d1 << 32));
                     const f4 z = {0.f, 0.f, 0.f, 0.f};
                     acc[xg] = mfma16(A1, B, z);
                 }
