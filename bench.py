@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of each serving run, plain and pruned (0 = skip)")
     ap.add_argument("--serve-pool", type=int, default=64, help="pre-generated frames per stream")
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="refills the server may run at once (1: one refill at a time)")
     ap.add_argument("--mixed", type=int, default=1,
                     help="run the 64-frame mixed-resolution batch leg (0 = skip)")
     ap.add_argument("--edge-frames", type=int, default=64,
@@ -644,10 +646,11 @@ def serving(args):
            "seconds": args.serve_seconds}
     pools = None
     res["pool_frames_per_stream"] = args.serve_pool
+    res["refill_lanes"] = args.serve_lanes
     for pruned in (False, True):
         note(f"serving, {'pruned' if pruned else 'plain'}: {args.serve_seconds} s")
         r, pools = serve.run(args.serve_seconds, pruned=pruned, pool=args.serve_pool, pools=pools,
-                             verbose=False, verify=True)
+                             verbose=False, verify=True, lanes=args.serve_lanes)
         note(f"serving done: p50 {r['p50_ms']:.4f} ms, p99 {r['p99_ms']:.4f} ms, verified {r['verified']}")
         res["pruned" if pruned else "plain"] = {
             k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()

@@ -496,21 +496,26 @@ int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t bat
  * accumulator, peak buffers and, when pruned, the proposal logits and tile
  * mask.  Streams with the same configuration form a class whose frame slots
  * are contiguous, so the proposal network runs over a class as one batch.
- * One worker thread repeats: take the oldest pending request of every
- * stream (at most one per stream), copy those frames into their slots, switch
- * on exactly those slots, launch one graph (network and mask per class when
- * pruned, then clear, Sobel, vote, peaks; switched-off slots return at once),
- * copy the peaks back and complete the requests.  Requests arriving while a
- * batch runs join the next one; the frame of a request that heads the queue
- * of a stream not in the running batch is copied to its slot at once, on a
- * copy stream of its own, so that copy overlaps the running batch and the
- * next one starts with it in place.  A frame's results do not depend on the
- * other frames of its batch.  Failures: a request beyond its stream's queue
+ * Each of a few refill lanes (a worker thread with its own batch plan,
+ * graphs and compute stream) repeats: take the oldest pending request of
+ * every stream that is not in a running refill (at most one per stream),
+ * copy those frames into their slots, switch on exactly those slots, launch
+ * one graph (network and mask per class when pruned, then clear, Sobel, vote,
+ * peaks; switched-off slots return at once), copy the peaks back and complete
+ * the requests.  With two or more lanes, a request of a stream that is not in
+ * the running refill starts at once beside it instead of waiting for it; a
+ * stream's requests still run one at a time, in submission order.  The frame
+ * of a request that heads the queue of a stream not in a running refill is
+ * copied to its slot at once, on a copy stream of its own, so that copy
+ * overlaps the running refills and the next one starts with it in place.  A
+ * frame's results do not depend on the other frames of its batch or on the
+ * refills running beside it.  Failures: a request beyond its stream's queue
  * bound is dropped (LANE_E_BUSY); with a deadline, one that waited too long
  * is completed unrun (LANE_E_TIMEOUT) and frees its place; a device error
  * fails that refill's requests and, since the device state can no longer be
  * trusted, every later one (LANE_E_DEVICE; lane_server_stats.error). */
 #define LANE_SERVE_MAX_K 64
+#define LANE_SERVE_MAX_LANES 4
 
 typedef struct lane_stream_cfg {
     int32_t W, H;             /* frame size */
@@ -532,6 +537,9 @@ typedef struct lane_server_cfg {
     int64_t deadline_ns;      /* > 0: a request that has waited longer than this when a refill
                                  would take it is completed with LANE_E_TIMEOUT instead of run,
                                  and its stream's next request takes the slot; 0 = no deadline */
+    int32_t lanes;            /* refills that may run at once, 1..LANE_SERVE_MAX_LANES; 0 = 2.
+                                 Each lane holds its own plan (for a pruned server with a split
+                                 vote, a pruned copy of each stream's edge list per lane) */
 } lane_server_cfg;
 
 typedef struct lane_result {
@@ -572,8 +580,9 @@ typedef struct lane_server lane_server;
 int lane_server_plan(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,
                      uint8_t *admitted, size_t *stream_bytes, size_t *total_bytes);
 /* Set-up call: admits as lane_server_plan, allocates the device state in one
- * allocation plus page-locked result buffers, builds the plan and graph and
- * starts the worker thread.  LANE_E_WS if no stream fits the budget. */
+ * allocation plus page-locked result buffers, builds each lane's plan and
+ * graphs and starts the lanes' worker threads.  LANE_E_WS if no stream fits
+ * the budget. */
 int lane_server_create(const lane_stream_cfg *streams, int32_t n, const lane_server_cfg *cfg,
                        lane_server **out, uint8_t *admitted_opt);
 /* Queue a frame (host uint8 [H][pitch] of the stream's size).  The bytes are
@@ -596,11 +605,11 @@ int lane_server_poll(lane_server *s, lane_result *out, int32_t max, int32_t wait
  * These results do not go to lane_server_poll.  One replay at a time. */
 int lane_server_replay(lane_server *s, const lane_request *reqs, int32_t n, lane_result *results);
 int lane_server_stats_get(lane_server *s, lane_server_stats *out);
-/* paused = 1: the worker takes no further refill (one already running
- * finishes) while requests keep queueing and their deadlines keep running;
+/* paused = 1: the lanes take no further refill (those already running
+ * finish) while requests keep queueing and their deadlines keep running;
  * paused = 0: it resumes.  For draining and maintenance.  Thread-safe. */
 int lane_server_pause(lane_server *s, int32_t paused);
-/* Stops the worker after the batch in flight (queued requests are discarded)
+/* Stops the lanes after the refills in flight (queued requests are discarded)
  * and frees everything.  No other call on s may be running. */
 int lane_server_destroy(lane_server *s);
 

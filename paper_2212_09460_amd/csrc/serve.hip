@@ -4,18 +4,25 @@
 // lines (Sec. 5); a deployment feeds many cameras at once.  The server keeps
 // every admitted stream's state resident in device memory (frame slot, edge
 // map, edge list, accumulator, peak buffers, and for the pruned path the
-// proposal logits and tile mask) and runs one worker thread:
+// proposal logits and tile mask) and runs a few refill lanes, each a worker
+// thread with its own batch plan over all slots, its own graphs and its own
+// compute stream:
 //
-//   wait for requests -> take the oldest request of every stream (one per
-//   stream) -> copy those frames into their slots -> write the per-slot flags
-//   -> one graph launch over all slots (proposal network and mask per size
-//   class when pruned, then clear, Sobel, vote, peaks; switched-off slots
-//   return at once) -> copy the peaks back -> complete the requests.
+//   wait for requests -> take the oldest request of every stream not in a
+//   running refill (one per stream) -> copy those frames into their slots ->
+//   write the lane's per-slot flags -> one graph launch over all slots
+//   (proposal network and mask per size class when pruned, then clear,
+//   Sobel, vote, peaks; switched-off slots return at once) -> copy the peaks
+//   back -> complete the requests.
 //
-// Requests that arrive while a batch runs wait for the next refill.  Streams
-// with the same configuration form a class whose frame slots are contiguous,
-// so the network runs over a class as one batch.  Admission: streams are
-// taken in order while their device state fits the HBM budget.
+// A slot belongs to one refill at a time, so the lanes never share a frame's
+// buffers, and a stream's requests run in order.  A single frame fills only
+// part of the GPU (a 1080p vote is 23 theta slices x 8 edge parts), so a
+// request that arrives while another stream's refill runs starts beside it
+// on a second lane rather than queueing behind it.  Streams with the same
+// configuration form a class whose frame slots are contiguous, so the
+// network runs over a class as one batch.  Admission: streams are taken in
+// order while their device state fits the HBM budget.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +44,8 @@ namespace {
 // a pruned server with at most this many classes keeps one graph per
 // non-empty subset of classes (2^n - 1 graphs)
 constexpr int kSubsetClasses = 4;
+
+int serve_lanes(const lane_server_cfg& cfg) { return cfg.lanes > 0 ? cfg.lanes : 2; }
 
 int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -64,6 +73,7 @@ int check_cfg(const lane_server_cfg& c) {
     if (c.vote_split < 0 || c.vote_split > 64) return LANE_E_ARG;
     if (c.pruned && (!c.cnn_params || !(c.conf > 0.5f && c.conf < 1.f))) return LANE_E_ARG;
     if (c.deadline_ns < 0) return LANE_E_ARG;
+    if (c.lanes < 0 || c.lanes > LANE_SERVE_MAX_LANES) return LANE_E_ARG;
     return LANE_OK;
 }
 
@@ -87,14 +97,14 @@ struct StreamSizes {
 int serve_vote_rows(const lane_server_cfg& cfg) { return cfg.vote_rows > 0 ? cfg.vote_rows : 4; }
 int serve_vote_split(const lane_server_cfg& cfg) { return cfg.vote_split > 0 ? cfg.vote_split : 8; }
 
-// device bytes the plan holds for a stream's edge split: the parts add into
-// the frame's accumulator, but a masked frame (pruned path) votes from a
-// pruned copy of its edge list, which the plan allocates per frame
+// device bytes the lanes' plans hold for a stream's edge split: the parts
+// add into the frame's accumulator, but a masked frame (pruned path) votes
+// from a pruned copy of its edge list, which each plan allocates per frame
 size_t split_bytes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
     if (!cfg.pruned || serve_vote_split(cfg) <= 1) return 0;
     size_t lb = 0;
     lane_edge_list_size(c.W, c.H, &lb);
-    return al256(lb);
+    return al256(lb) * (size_t)serve_lanes(cfg);
 }
 
 StreamSizes stream_sizes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
@@ -190,25 +200,31 @@ struct lane_server {
     size_t dbytes = 0;
     int32_t* h_peaks = nullptr;            // pinned, per slot (3k+1) at h_peak_off[slot]
     std::vector<size_t> h_peak_off;
-    uint8_t* h_flags = nullptr;            // one per slot
-    uint8_t* d_flags = nullptr;            // the plan's flags
-    lane_batch* plan = nullptr;
-    hipStream_t stream = nullptr;
+    // a refill lane: its worker runs refills on its own stream with its own
+    // plan (flags, work lists, queues) and graphs; h_flags: one per slot
+    struct Lane {
+        lane_batch* plan = nullptr;
+        uint8_t* h_flags = nullptr;
+        uint8_t* d_flags = nullptr;        // the plan's flags
+        hipStream_t stream = nullptr;
+        // graphs[m]: the refill whose active slots lie in the classes of bit
+        // mask m (pruned, up to kSubsetClasses classes: only those classes
+        // run their network and masks); otherwise graphs[0] serves every refill
+        std::vector<hipGraph_t> graphs;
+        std::vector<hipGraphExec_t> execs;
+        std::thread worker;
+    };
+    std::vector<Lane> lanes;
     // copy-ahead: the frame of the request at the head of an idle slot's
     // queue is copied to the slot on its own stream as soon as it is
     // known, so the copy overlaps the refill running meanwhile; up_id[slot]
     // = the request whose copy up_ev[slot] marks (0: none); busy[slot]: the
-    // slot is in the running refill (its frame buffer still being read)
+    // slot is in a running refill (its buffers still in use)
     hipStream_t up_stream = nullptr;
     std::vector<hipEvent_t> up_ev;
     std::vector<uint64_t> up_id;
     std::vector<uint8_t> busy;
     uint64_t next_id = 1;
-    // graphs[m]: the refill whose active slots lie in the classes of bit
-    // mask m (pruned, up to kSubsetClasses classes: only those classes run
-    // their network and masks); otherwise graphs[0] serves every refill
-    std::vector<hipGraph_t> graphs;
-    std::vector<hipGraphExec_t> execs;
     bool per_subset = false;
 
     std::mutex mu;
@@ -221,7 +237,6 @@ struct lane_server {
     bool paused = false;
     int error = LANE_OK;
     lane_server_stats stats;
-    std::thread worker;
 };
 
 namespace {
@@ -266,30 +281,33 @@ void copy_ahead(lane_server* s, int slot) {
     s->up_id[slot] = e == hipSuccess ? d.front().id : 0;
 }
 
-int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_result>& out) {
+// one refill on lane L (its slots marked busy by the caller, so no other
+// lane touches their buffers meanwhile)
+int run_batch(lane_server* s, lane_server::Lane& L, const std::vector<Req>& batch,
+              std::vector<lane_result>& out) {
     const int n_slots = (int)s->streams.size();
-    memset(s->h_flags, 0, (size_t)n_slots);
-    for (const Req& q : batch) s->h_flags[s->slot_of[q.stream]] = 1;
+    memset(L.h_flags, 0, (size_t)n_slots);
+    for (const Req& q : batch) L.h_flags[s->slot_of[q.stream]] = 1;
     // switches and the work lists of exactly these slots
-    hipError_t e = lane_batch_select(s->plan, s->h_flags, s->stream) == LANE_OK ? hipSuccess
-                                                                                : hipErrorUnknown;
+    hipError_t e = lane_batch_select(L.plan, L.h_flags, L.stream) == LANE_OK ? hipSuccess
+                                                                              : hipErrorUnknown;
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const Req& q = batch[i];
         const int slot = s->slot_of[q.stream];
-        if (q.after_up) e = hipStreamWaitEvent(s->stream, s->up_ev[slot], 0);
-        if (e == hipSuccess && !q.ahead) e = copy_frame(s, slot, q, s->stream);
+        if (q.after_up) e = hipStreamWaitEvent(L.stream, s->up_ev[slot], 0);
+        if (e == hipSuccess && !q.ahead) e = copy_frame(s, slot, q, L.stream);
     }
     uint32_t cls_mask = 0;
     if (s->per_subset)
         for (const Req& q : batch) cls_mask |= 1u << s->class_of[s->slot_of[q.stream]];
-    if (e == hipSuccess) e = hipGraphLaunch(s->execs[s->per_subset ? cls_mask : 0], s->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(L.execs[s->per_subset ? cls_mask : 0], L.stream);
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const int slot = s->slot_of[batch[i].stream];
         const int k = s->streams[slot].k;
         e = hipMemcpyAsync(s->h_peaks + s->h_peak_off[slot], s->slot_peaks[slot],
-                           sizeof(int32_t) * (3 * (size_t)k + 1), hipMemcpyDeviceToHost, s->stream);
+                           sizeof(int32_t) * (3 * (size_t)k + 1), hipMemcpyDeviceToHost, L.stream);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L.stream);
     const int64_t t_done = now_ns();
     const int status = e == hipSuccess ? LANE_OK : LANE_E_DEVICE;
     out.resize(batch.size());
@@ -313,25 +331,28 @@ int run_batch(lane_server* s, const std::vector<Req>& batch, std::vector<lane_re
     return status;
 }
 
-void worker_main(lane_server* s) {
+void worker_main(lane_server* s, int li) {
     hipSetDevice(s->dev);
+    lane_server::Lane& L = s->lanes[li];
     std::vector<Req> batch;
     std::vector<lane_result> out;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
+        // work for this lane: a request of a stream that is not in a running refill
         auto any = [&] {
-            for (auto& d : s->pending)
-                if (!d.empty()) return true;
+            for (size_t slot = 0; slot < s->pending.size(); ++slot)
+                if (!s->pending[slot].empty() && !s->busy[slot]) return true;
             return false;
         };
         s->cv_work.wait(lk, [&] { return s->stop || (!s->paused && any()); });
         if (s->stop) break;
-        // the oldest request of every stream; with a deadline, requests that
-        // waited too long are completed unrun and the next one takes the place
+        // the oldest request of every such stream; with a deadline, requests
+        // that waited too long are completed unrun and the next one takes the place
         batch.clear();
         const int64_t t_take = now_ns();
         for (auto& d : s->pending) {
             const int slot = (int)(&d - &s->pending[0]);
+            if (s->busy[slot]) continue;
             while (!d.empty() && s->cfg.deadline_ns > 0 && t_take - d.front().t_submit > s->cfg.deadline_ns) {
                 lane_result r;
                 fill_result(r, d.front(), LANE_E_TIMEOUT);
@@ -356,7 +377,7 @@ void worker_main(lane_server* s) {
         const bool failed = s->error != LANE_OK;
         lk.unlock();
         int st = LANE_E_DEVICE;
-        if (!failed) st = run_batch(s, batch, out);
+        if (!failed) st = run_batch(s, L, batch, out);
         lk.lock();
         if (failed) {
             out.resize(batch.size());
@@ -416,30 +437,32 @@ int check_submit(lane_server* s, int32_t stream, const uint8_t* frame, int32_t p
 }
 
 void free_server(lane_server* s) {
-    if (s->worker.joinable()) {
-        {
-            std::lock_guard<std::mutex> g(s->mu);
-            s->stop = true;
-        }
-        s->cv_work.notify_all();
-        s->worker.join();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
     }
-    if (s->stream) hipStreamSynchronize(s->stream);
+    s->cv_work.notify_all();
+    for (auto& L : s->lanes)
+        if (L.worker.joinable()) L.worker.join();
+    for (auto& L : s->lanes)
+        if (L.stream) hipStreamSynchronize(L.stream);
     if (s->up_stream) {
         hipStreamSynchronize(s->up_stream);
         hipStreamDestroy(s->up_stream);
     }
     for (auto ev : s->up_ev)
         if (ev) hipEventDestroy(ev);
-    for (auto x : s->execs)
-        if (x) hipGraphExecDestroy(x);
-    for (auto g : s->graphs)
-        if (g) hipGraphDestroy(g);
-    if (s->plan) lane_batch_destroy(s->plan);
-    if (s->stream) hipStreamDestroy(s->stream);
+    for (auto& L : s->lanes) {
+        for (auto x : L.execs)
+            if (x) hipGraphExecDestroy(x);
+        for (auto g : L.graphs)
+            if (g) hipGraphDestroy(g);
+        if (L.plan) lane_batch_destroy(L.plan);
+        if (L.stream) hipStreamDestroy(L.stream);
+        if (L.h_flags) hipHostFree(L.h_flags);
+    }
     if (s->dmem) hipFree(s->dmem);
     if (s->h_peaks) hipHostFree(s->h_peaks);
-    if (s->h_flags) hipHostFree(s->h_flags);
     delete s;
 }
 
@@ -552,7 +575,11 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     s->stats.device_bytes = (int64_t)off;
     s->stats.streams_admitted = n_slots;
     bool ok = hipMalloc(&s->dmem, off) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    s->lanes.resize((size_t)serve_lanes(*cfg));
+    for (auto& L : s->lanes) {
+        ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&L.h_flags, (size_t)n_slots, hipHostMallocDefault) == hipSuccess;
+    }
     ok = ok && hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) == hipSuccess;
     s->up_ev.assign(n_slots, nullptr);
     s->up_id.assign(n_slots, 0);
@@ -566,15 +593,15 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         hp += 3 * (size_t)s->streams[i].k + 1;
     }
     ok = ok && hipHostMalloc((void**)&s->h_peaks, sizeof(int32_t) * hp, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&s->h_flags, (size_t)n_slots, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         free_server(s);
         return LANE_E_DEVICE;
     }
     char* base = (char*)s->dmem;
     // zeroed state first: every slot starts with an empty frame and no peaks
-    ok = ok && hipMemsetAsync(s->dmem, 0, off, s->stream) == hipSuccess;
-    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+    hipStream_t st0 = s->lanes[0].stream;
+    ok = ok && hipMemsetAsync(s->dmem, 0, off, st0) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st0) == hipSuccess;
     // trig tables (host helper, then one copy each)
     for (auto& t : trig_off) {
         std::vector<int16_t> cs(2 * (size_t)t.first);
@@ -585,9 +612,9 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     if (cfg->pruned) {
         ok = ok && hipMemcpy(base + o_par, cfg->cnn_params, sizeof(float) * LANE_CNN_PARAMS,
                              hipMemcpyHostToDevice) == hipSuccess;
-        ok = ok && lane_cnn_pack((const float*)(base + o_par), base + o_pk, s->stream) == LANE_OK;
+        ok = ok && lane_cnn_pack((const float*)(base + o_par), base + o_pk, st0) == LANE_OK;
     }
-    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st0) == hipSuccess;
     std::vector<lane_frame> frames(n_slots);
     s->slot_img.resize(n_slots);
     s->slot_peaks.resize(n_slots);
@@ -641,8 +668,10 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     }
     lane_tune tune = {serve_vote_rows(*cfg), 1, 0, cfg->sobel_strip_rows > 0 ? cfg->sobel_strip_rows : 8,
                       serve_vote_split(*cfg)};
-    if (ok && lane_batch_create(frames.data(), n_slots, &tune, &s->plan) != LANE_OK) ok = false;
-    ok = ok && lane_batch_active_flags(s->plan, &s->d_flags) == LANE_OK;
+    for (auto& L : s->lanes) {
+        if (ok && lane_batch_create(frames.data(), n_slots, &tune, &L.plan) != LANE_OK) ok = false;
+        ok = ok && lane_batch_active_flags(L.plan, &L.d_flags) == LANE_OK;
+    }
     if (!ok) {
         free_server(s);
         return LANE_E_DEVICE;
@@ -666,8 +695,8 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
     }
     int cst = LANE_OK;
-    // one capture: the classes of cls_mask run their network and masks
-    auto capture = [&](uint32_t cls_mask, hipGraph_t* gout, hipGraphExec_t* xout) {
+    // one capture for lane L: the classes of cls_mask run their network and masks
+    auto capture = [&](lane_server::Lane& L, uint32_t cls_mask, hipGraph_t* gout, hipGraphExec_t* xout) {
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return;
         if (cfg->pruned) {
@@ -676,7 +705,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
             for (size_t c = 0; c < s->classes.size() && e == hipSuccess; ++c) {
                 if (c < 32 && !((cls_mask >> c) & 1u)) continue;
                 auto& cl = s->classes[c];
-                const uint8_t* fl = s->d_flags + cl.first_slot;
+                const uint8_t* fl = L.d_flags + cl.first_slot;
                 // network and tile masks in one kernel
                 cst = lane_cnn_infer_mask_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
                                                  (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
@@ -690,7 +719,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
                 e = hipStreamWaitEvent(cs, ev_join, 0);
                 if (e != hipSuccess) break;
             }
-            cst = lane_batch_enqueue_pass_stage(s->plan, stg, cs);
+            cst = lane_batch_enqueue_pass_stage(L.plan, stg, cs);
         }
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -705,13 +734,15 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     const size_t n_cls = s->classes.size();
     s->per_subset = cfg->pruned && n_cls > 1 && n_cls <= (size_t)kSubsetClasses;
     const size_t n_graphs = s->per_subset ? ((size_t)1 << n_cls) : 1;
-    s->graphs.assign(n_graphs, nullptr);
-    s->execs.assign(n_graphs, nullptr);
-    if (s->per_subset) {
-        for (size_t m = 1; m < n_graphs && e == hipSuccess && cst == LANE_OK; ++m)
-            capture((uint32_t)m, &s->graphs[m], &s->execs[m]);
-    } else {
-        capture(0xFFFFFFFFu, &s->graphs[0], &s->execs[0]);
+    for (auto& L : s->lanes) {
+        L.graphs.assign(n_graphs, nullptr);
+        L.execs.assign(n_graphs, nullptr);
+        if (s->per_subset) {
+            for (size_t m = 1; m < n_graphs && e == hipSuccess && cst == LANE_OK; ++m)
+                capture(L, (uint32_t)m, &L.graphs[m], &L.execs[m]);
+        } else if (e == hipSuccess && cst == LANE_OK) {
+            capture(L, 0xFFFFFFFFu, &L.graphs[0], &L.execs[0]);
+        }
     }
     hipStreamDestroy(cs);
     if (side) (void)hipStreamDestroy(side);
@@ -721,7 +752,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         free_server(s);
         return LANE_E_DEVICE;
     }
-    s->worker = std::thread(worker_main, s);
+    for (size_t li = 0; li < s->lanes.size(); ++li) s->lanes[li].worker = std::thread(worker_main, s, (int)li);
     *out = s;
     return LANE_OK;
 }

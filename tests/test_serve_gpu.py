@@ -61,8 +61,9 @@ def schedule(n_streams, n, seed):
     return reqs
 
 
-def test_plain_server_matches_alone(lane, synth, oracle):
-    say("serve plain")
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_plain_server_matches_alone(lane, synth, oracle, lanes):
+    say("serve plain, lanes", lanes)
     P = pools(synth, STREAMS)
     refs = [[alone(lane, P[s][j], STREAMS[s]) for j in range(len(P[s]))] for s in range(len(STREAMS))]
     # the oracle agrees with the alone path on two of the frames
@@ -72,7 +73,7 @@ def test_plain_server_matches_alone(lane, synth, oracle):
         want = oracle.pipeline(P[s][0], C, S, st.get("k", 8))
         c, t, r, v = refs[s][0]
         assert c == want["count"] and (t == want["theta_idx"]).all() and (v == want["votes"]).all()
-    srv = lane.Server(STREAMS, hbm_budget=1 << 30, max_pending=64)
+    srv = lane.Server(STREAMS, hbm_budget=1 << 30, max_pending=64, lanes=lanes)
     try:
         for rep in range(2):
             sched = schedule(len(STREAMS), 40, seed=rep)
@@ -85,10 +86,11 @@ def test_plain_server_matches_alone(lane, synth, oracle):
                 assert r.t_done_ns >= r.t_start_ns >= r.t_submit_ns
                 assert same(r, refs[s][i % len(P[s])], STREAMS[s].get("k", 8)), (rep, i, s)
                 batched += r.batch_frames > 1
-            assert batched > 0  # some requests shared a batch
+            if lanes == 1:
+                assert batched > 0  # some requests shared a batch
         st = srv.stats()
         assert st["completed"] == 80 and st["dropped"] == 0 and st["error"] == 0
-        assert st["frames_in_batches"] == 80 and st["batches"] < 80
+        assert st["frames_in_batches"] == 80 and st["batches"] <= 80
     finally:
         srv.close()
 
@@ -172,12 +174,13 @@ def test_drops_and_poll(lane, synth):
 ROAD_STREAMS = [dict(W=1280, H=720), dict(W=1920, H=1080), dict(W=3840, H=2160), dict(W=1280, H=720)]
 
 
-@pytest.mark.parametrize("pruned", [False, True])
-def test_server_at_serving_sizes(lane, synth, oracle, pruned):
+@pytest.mark.parametrize("pruned,lanes", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_server_at_serving_sizes(lane, synth, oracle, pruned, lanes):
     """The serving sizes (720p, 1080p, 4K; 360 angles, top-8): a few requests
-    per stream, some sharing a refill, each equal to its frame alone; for the
-    plain path the oracle agrees with the alone path on one frame per size."""
-    say("serve at 720p/1080p/4K, pruned" if pruned else "serve at 720p/1080p/4K, plain")
+    per stream, some sharing a refill (one lane) or running beside another
+    refill (two lanes), each equal to its frame alone; for the plain path the
+    oracle agrees with the alone path on one frame per size."""
+    say("serve at 720p/1080p/4K,", "pruned" if pruned else "plain", "lanes", lanes)
     from paper_2212_09460_amd import serve
 
     P = [torch.from_numpy(np.stack([synth.road(s["W"], s["H"], 900 + 10 * i + j) for j in range(2)]))
@@ -196,7 +199,7 @@ def test_server_at_serving_sizes(lane, synth, oracle, pruned):
             assert c == want["count"] and t == want["theta_idx"].tolist()
             assert r == want["r_idx"].tolist() and v == want["votes"].tolist()
     srv = lane.Server(ROAD_STREAMS, hbm_budget=4 << 30, pruned=pruned, conf=0.9, cnn_params=params,
-                      max_pending=16)
+                      max_pending=16, lanes=lanes)
     try:
         assert all(srv.admitted)
         sched = schedule(len(ROAD_STREAMS), 24, seed=11)
@@ -205,7 +208,44 @@ def test_server_at_serving_sizes(lane, synth, oracle, pruned):
         meta = [(s, i % 2) for i, (s, t) in enumerate(sched)]
         checked, bad = serve.check_results(out, meta, refs, ROAD_STREAMS)
         assert checked == len(reqs) and bad == 0
-        assert any(r.batch_frames > 1 for r in out)
+        if lanes == 1:
+            assert any(r.batch_frames > 1 for r in out)
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_lanes_run_refills_side_by_side(lane, synth, lanes):
+    """A 640x480 request that arrives 0.2 ms after a 4K request: with two
+    lanes it starts while the 4K refill still runs (in some of 16 trials,
+    whatever the host's timing), with one lane never before that refill
+    ends unless both share one refill; every result equals its frame alone."""
+    say("serve: refills side by side, lanes", lanes)
+    streams = [dict(W=3840, H=2160), dict(W=640, H=480)]
+    P = pools(synth, streams, n=2, seed=950)
+    refs = [[alone(lane, P[s][j], streams[s]) for j in range(2)] for s in range(2)]
+    # page-locked frames: a pageable one makes its submission wait for the copy
+    Pin = [torch.from_numpy(p).pin_memory().numpy() for p in P]
+    srv = lane.Server(streams, hbm_budget=2 << 30, max_pending=4, lanes=lanes)
+    try:
+        reqs = []
+        for i in range(16):
+            t = 0.005 * i
+            reqs.append((0, t, Pin[0][i % 2], 2 * i))
+            reqs.append((1, t + 0.0002, Pin[1][i % 2], 2 * i + 1))
+        out = list(srv.replay(reqs))
+        beside = 0
+        for i in range(16):
+            big, small = out[2 * i], out[2 * i + 1]
+            assert big.status == 0 and same(big, refs[0][i % 2], 8), i
+            assert small.status == 0 and same(small, refs[1][i % 2], 8), i
+            shared = big.t_start_ns == small.t_start_ns and big.batch_frames == 2
+            if not shared and small.t_start_ns < big.t_done_ns:
+                beside += 1
+        if lanes == 1:
+            assert beside == 0
+        else:
+            assert beside >= 1
     finally:
         srv.close()
 

@@ -77,16 +77,22 @@ def test_admission_pruned_counts_network_state(lane, serve):
     assert tot > sum(pruned) - 1  # shared weights on top of the streams
     # per stream, the pruned state adds the tile mask, the logits and (the
     # vote being split) the pruned copy of the edge list the plan allocates
+    # (one per refill lane: two by default)
     al = lambda v: (v + 255) // 256 * 256
-    for s_, a, b in zip(st, plain, pruned):
+    _, pruned1, _ = lane.server_plan(st, 8 << 30, pruned=True, cnn_params=p, lanes=1)
+    _, plain3, _ = lane.server_plan(st, 8 << 30, lanes=3)
+    assert plain3 == plain  # the plain path's plans hold no per-stream state
+    for s_, a, b, b1 in zip(st, plain, pruned, pruned1):
         th, tw = (s_["H"] + 7) // 8, (s_["W"] + 7) // 8
-        extra = al(th * tw) + al(4 * 9 * th * tw) + al(lane.edge_list_size(s_["W"], s_["H"]))
-        assert b - a == extra
+        lst = al(lane.edge_list_size(s_["W"], s_["H"]))
+        extra = al(th * tw) + al(4 * 9 * th * tw)
+        assert b - a == extra + 2 * lst and b1 - a == extra + lst
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(vote_rows=3), -1), (dict(max_pending=0), -1), (dict(sobel_strip_rows=12), -1),
     (dict(pruned=True, conf=0.4), -1), (dict(pruned=True), -1),  # no weights
+    (dict(lanes=-1), -1), (dict(lanes=5), -1),
 ])
 def test_plan_rejects_bad_config(lane, kw, code):
     args = dict(hbm_budget=1 << 30)
