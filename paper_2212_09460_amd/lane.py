@@ -831,7 +831,7 @@ class Server:
         return res
 
     def pause(self, paused: bool = True):
-        """Hold (True) or resume (False) the worker; requests keep queueing."""
+        """Hold (True) or resume (False) the refill lanes; requests keep queueing."""
         _check(_srv_pause(self._h, 1 if paused else 0), "lane_server_pause")
 
     def replay(self, reqs):

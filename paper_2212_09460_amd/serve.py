@@ -1,5 +1,5 @@
 """Serving workload: many camera streams, Poisson arrivals, continuous
-batching through lane_server (native worker thread, device-resident
+batching through lane_server (native refill lanes, device-resident
 per-stream state, HBM-budget admission).
 
 The stream mix is 8 x 1280x720, 6 x 1920x1080 and 2 x 3840x2160 at 30
