@@ -12,8 +12,9 @@
 //   running refill (one per stream) -> copy those frames into their slots ->
 //   write the lane's per-slot flags -> one graph launch over all slots
 //   (proposal network and mask per size class when pruned, then clear,
-//   Sobel, vote, peaks; switched-off slots return at once) -> copy the peaks
-//   back -> complete the requests.
+//   Sobel, vote, peaks; switched-off slots return at once; the peak search
+//   writes each slot's peaks straight into page-locked host memory) ->
+//   complete the requests.
 //
 // A slot belongs to one refill at a time, so the lanes never share a frame's
 // buffers, and a stream's requests run in order.  A single frame fills only
@@ -85,9 +86,9 @@ ClassKey key_of(const lane_stream_cfg& c) {
 // Device bytes of one stream's buffers (the fused proposal network needs no
 // activation workspace).
 struct StreamSizes {
-    size_t img, edges, list, acc, peaks, peaks_ws, counters, mask, logits, split;
+    size_t img, edges, list, acc, peaks_ws, counters, mask, logits, split;
     size_t total() const {
-        return img + edges + list + acc + peaks + peaks_ws + counters + mask + logits + split;
+        return img + edges + list + acc + peaks_ws + counters + mask + logits + split;
     }
 };
 
@@ -121,7 +122,6 @@ StreamSizes stream_sizes(const lane_stream_cfg& c, const lane_server_cfg& cfg) {
     lane_edge_list_size(c.W, c.H, &lb);
     z.list = al256(lb);
     z.acc = al256(sizeof(int32_t) * (size_t)c.n_theta * n_r);
-    z.peaks = al256(sizeof(int32_t) * (3 * (size_t)c.k + 1));
     size_t ws = 0;
     lane_hough_peaks_workspace_size(c.n_theta, (int32_t)n_r, &ws);
     z.peaks_ws = al256(ws);
@@ -195,10 +195,12 @@ struct lane_server {
     std::vector<Class> classes;
     std::vector<int> class_of;             // slot -> class
     std::vector<uint8_t*> slot_img;
-    std::vector<int32_t*> slot_peaks;
     void* dmem = nullptr;
     size_t dbytes = 0;
-    int32_t* h_peaks = nullptr;            // pinned, per slot (3k+1) at h_peak_off[slot]
+    // page-locked, per slot (3k+1) at h_peak_off[slot]: the plan's peak
+    // outputs (the peak search stores into it through its device address,
+    // so no copy follows the refill)
+    int32_t* h_peaks = nullptr;
     std::vector<size_t> h_peak_off;
     // a refill lane: its worker runs refills on its own stream with its own
     // plan (flags, work lists, queues) and graphs; h_flags: one per slot
@@ -301,12 +303,7 @@ int run_batch(lane_server* s, lane_server::Lane& L, const std::vector<Req>& batc
     if (s->per_subset)
         for (const Req& q : batch) cls_mask |= 1u << s->class_of[s->slot_of[q.stream]];
     if (e == hipSuccess) e = hipGraphLaunch(L.execs[s->per_subset ? cls_mask : 0], L.stream);
-    for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
-        const int slot = s->slot_of[batch[i].stream];
-        const int k = s->streams[slot].k;
-        e = hipMemcpyAsync(s->h_peaks + s->h_peak_off[slot], s->slot_peaks[slot],
-                           sizeof(int32_t) * (3 * (size_t)k + 1), hipMemcpyDeviceToHost, L.stream);
-    }
+    // (the peaks of these slots are in h_peaks once the graph has run)
     if (e == hipSuccess) e = hipStreamSynchronize(L.stream);
     const int64_t t_done = now_ns();
     const int status = e == hipSuccess ? LANE_OK : LANE_E_DEVICE;
@@ -593,12 +590,14 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         hp += 3 * (size_t)s->streams[i].k + 1;
     }
     ok = ok && hipHostMalloc((void**)&s->h_peaks, sizeof(int32_t) * hp, hipHostMallocDefault) == hipSuccess;
+    int32_t* d_peaks = nullptr;  // h_peaks as the device addresses it
+    ok = ok && hipHostGetDevicePointer((void**)&d_peaks, s->h_peaks, 0) == hipSuccess;
     if (!ok) {
         free_server(s);
         return LANE_E_DEVICE;
     }
     char* base = (char*)s->dmem;
-    // zeroed state first: every slot starts with an empty frame and no peaks
+    // zeroed state first: every slot starts with an empty frame
     hipStream_t st0 = s->lanes[0].stream;
     ok = ok && hipMemsetAsync(s->dmem, 0, off, st0) == hipSuccess;
     ok = ok && hipStreamSynchronize(st0) == hipSuccess;
@@ -617,7 +616,6 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     ok = ok && hipStreamSynchronize(st0) == hipSuccess;
     std::vector<lane_frame> frames(n_slots);
     s->slot_img.resize(n_slots);
-    s->slot_peaks.resize(n_slots);
     for (size_t c = 0; c < s->classes.size() && ok; ++c) {
         auto& cl = s->classes[c];
         cl.img = (uint8_t*)(base + o_img[c]);
@@ -657,9 +655,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
             f.h_theta = std::max(1, (sc.n_theta + 99) / 100);
             f.h_r = std::max(1, (f.n_r + 99) / 100);
             f.min_votes = 1;
-            f.peaks = (int32_t*)p;
-            s->slot_peaks[i] = f.peaks;
-            p += z.peaks;
+            f.peaks = d_peaks + s->h_peak_off[i];
             f.peaks_ws = p;
             f.peaks_ws_bytes = z.peaks_ws;
             p += z.peaks_ws;
