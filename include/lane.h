@@ -541,6 +541,10 @@ typedef struct lane_server_cfg {
     int32_t lanes;            /* refills that may run at once, 1..LANE_SERVE_MAX_LANES; 0 = 2.
                                  Each lane holds its own plan (for a pruned server with a split
                                  vote, a pruned copy of each stream's edge list per lane) */
+    int32_t spin_us;          /* 0: an idle lane sleeps until work arrives; > 0 (at most 10^7):
+                                 it first polls for this long, so a request arriving meanwhile
+                                 starts without a thread wake-up (about 10-20 us), at the cost
+                                 of a busy host core per polling lane */
 } lane_server_cfg;
 
 typedef struct lane_result {

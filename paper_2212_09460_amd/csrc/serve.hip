@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -75,6 +76,7 @@ int check_cfg(const lane_server_cfg& c) {
     if (c.pruned && (!c.cnn_params || !(c.conf > 0.5f && c.conf < 1.f))) return LANE_E_ARG;
     if (c.deadline_ns < 0) return LANE_E_ARG;
     if (c.lanes < 0 || c.lanes > LANE_SERVE_MAX_LANES) return LANE_E_ARG;
+    if (c.spin_us < 0 || c.spin_us > 10000000) return LANE_E_ARG;
     return LANE_OK;
 }
 
@@ -231,6 +233,10 @@ struct lane_server {
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    // bumped (under mu) whenever a lane may find new work: a submission, a
+    // refill's slots freed, resume, stop; an idle lane that polls
+    // (cfg.spin_us) watches it instead of sleeping on cv_work
+    std::atomic<uint64_t> work_gen{0};
     std::vector<std::deque<Req>> pending;
     std::deque<lane_result> done;
     lane_result* replay_out = nullptr;
@@ -341,7 +347,20 @@ void worker_main(lane_server* s, int li) {
                 if (!s->pending[slot].empty() && !s->busy[slot]) return true;
             return false;
         };
-        s->cv_work.wait(lk, [&] { return s->stop || (!s->paused && any()); });
+        auto ready = [&] { return s->stop || (!s->paused && any()); };
+        if (!ready() && s->cfg.spin_us > 0) {
+            // poll for up to spin_us before sleeping: a request then starts
+            // without the wake-up of a sleeping thread
+            const int64_t until = now_ns() + (int64_t)s->cfg.spin_us * 1000;
+            while (!ready() && now_ns() < until) {
+                const uint64_t g0 = s->work_gen.load(std::memory_order_acquire);
+                lk.unlock();
+                while (s->work_gen.load(std::memory_order_acquire) == g0 && now_ns() < until) {
+                }
+                lk.lock();
+            }
+        }
+        s->cv_work.wait(lk, ready);
         if (s->stop) break;
         // the oldest request of every such stream; with a deadline, requests
         // that waited too long are completed unrun and the next one takes the place
@@ -394,6 +413,7 @@ void worker_main(lane_server* s, int li) {
             s->busy[slot] = 0;
             copy_ahead(s, slot);
         }
+        s->work_gen.fetch_add(1, std::memory_order_release);
     }
 }
 
@@ -421,6 +441,7 @@ int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, u
     }
     d.push_back(q);
     if (d.size() == 1) copy_ahead(s, slot);
+    s->work_gen.fetch_add(1, std::memory_order_release);
     s->cv_work.notify_one();
     return LANE_OK;
 }
@@ -437,6 +458,7 @@ void free_server(lane_server* s) {
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->stop = true;
+        s->work_gen.fetch_add(1, std::memory_order_release);
     }
     s->cv_work.notify_all();
     for (auto& L : s->lanes)
@@ -822,6 +844,7 @@ int lane_server_pause(lane_server* s, int32_t paused) {
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->paused = paused != 0;
+        s->work_gen.fetch_add(1, std::memory_order_release);
     }
     s->cv_work.notify_all();
     return LANE_OK;

@@ -691,7 +691,7 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", _sz), ("pruned", _i32), ("conf", ctypes.c_float),
                 ("cnn_params", _vp), ("max_pending", _i32), ("vote_rows", _i32),
                 ("sobel_strip_rows", _i32), ("vote_split", _i32), ("deadline_ns", ctypes.c_int64),
-                ("lanes", _i32)]
+                ("lanes", _i32), ("spin_us", _i32)]
 
 
 class Result(ctypes.Structure):
@@ -729,7 +729,7 @@ _srv_pause = _sig("lane_server_pause", [_vp, _i32])
 
 
 def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, sobel_strip_rows,
-                vote_split=0, deadline_ms=0.0, lanes=0):
+                vote_split=0, deadline_ms=0.0, lanes=0, spin_us=0):
     import numpy as np
 
     keep = None
@@ -737,7 +737,8 @@ def _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows, so
         keep = np.ascontiguousarray(np.asarray(cnn_params, dtype=np.float32))
     cfg = ServerCfg(int(hbm_budget), int(pruned), float(conf),
                     None if keep is None else keep.ctypes.data, int(max_pending), int(vote_rows),
-                    int(sobel_strip_rows), int(vote_split), int(round(deadline_ms * 1e6)), int(lanes))
+                    int(sobel_strip_rows), int(vote_split), int(round(deadline_ms * 1e6)), int(lanes),
+                    int(spin_us))
     return cfg, keep
 
 
@@ -764,13 +765,13 @@ def _stream_cfgs(streams):
 
 def server_plan(streams, hbm_budget: int, pruned: bool = False, conf: float = 0.9,
                 cnn_params=None, max_pending: int = 4, vote_rows: int = 0, sobel_strip_rows: int = 0,
-                vote_split: int = 0, lanes: int = 0):
+                vote_split: int = 0, lanes: int = 0, spin_us: int = 0):
     """Host-only admission plan: (admitted list of bool, per-stream bytes, total bytes)."""
     import numpy as np
 
     arr = _stream_cfgs(streams)
     cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
-                            sobel_strip_rows, vote_split, lanes=lanes)
+                            sobel_strip_rows, vote_split, lanes=lanes, spin_us=spin_us)
     adm = np.zeros(len(streams), np.uint8)
     sb = np.zeros(len(streams), np.uint64)
     tot = _sz(0)
@@ -783,12 +784,13 @@ class Server:
     """Continuous-batching server over camera streams (lane_server_*).
 
     streams: list of dicts with W, H and optionally n_theta, k, threshold,
-    border_mode; lanes: refills that may run at once (0: the library's 2)."""
+    border_mode; lanes: refills that may run at once (0: the library's 2);
+    spin_us: how long an idle lane polls for work before it sleeps."""
 
     def __init__(self, streams, hbm_budget: int = 8 << 30, pruned: bool = False,
                  conf: float = 0.9, cnn_params=None, max_pending: int = 4, vote_rows: int = 0,
                  sobel_strip_rows: int = 0, vote_split: int = 0, deadline_ms: float = 0.0,
-                 lanes: int = 0):
+                 lanes: int = 0, spin_us: int = 0):
         import collections
 
         import numpy as np
@@ -796,7 +798,7 @@ class Server:
         self.streams = [dict(s) for s in streams]
         arr = _stream_cfgs(streams)
         cfg, keep = _server_cfg(hbm_budget, pruned, conf, cnn_params, max_pending, vote_rows,
-                                sobel_strip_rows, vote_split, deadline_ms, lanes)
+                                sobel_strip_rows, vote_split, deadline_ms, lanes, spin_us)
         adm = np.zeros(len(streams), np.uint8)
         h = _vp()
         _check(_srv_create(arr, len(streams), ctypes.byref(cfg), ctypes.byref(h), adm.ctypes.data),

@@ -167,7 +167,7 @@ def summarize(results, streams, seconds: float):
 def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_params=None,
         rate_hz: float = 30.0, seed: int = 0, pool: int = 64, hbm_budget: int = 8 << 30,
         max_pending: int = 8, vote_rows: int = 0, pools=None, mix=MIX, verbose: bool = True,
-        vote_split: int = 0, verify: bool = False, lanes: int = 0):
+        vote_split: int = 0, verify: bool = False, lanes: int = 0, spin_us: int = 0):
     """One serving run; with verify, every completed result is compared with
     its frame alone (reference_peaks) and out["verified"] holds the counts."""
     from . import lane
@@ -182,7 +182,7 @@ def run(seconds: float = 20.0, pruned: bool = False, conf: float = 0.9, cnn_para
     refs = reference_peaks(streams, pools, pruned, conf, cnn_params) if verify else None
     srv = lane.Server(streams, hbm_budget=hbm_budget, pruned=pruned, conf=conf,
                       cnn_params=cnn_params, max_pending=max_pending, vote_rows=vote_rows,
-                      vote_split=vote_split, lanes=lanes)
+                      vote_split=vote_split, lanes=lanes, spin_us=spin_us)
     try:
         # warm-up: one frame per stream through the server
         warm = [(s, 0.0, pools[s].numpy()[0], s) for s in range(len(streams)) if srv.admitted[s]]
@@ -218,6 +218,7 @@ def main():
     ap.add_argument("--vote-rows", type=int, default=0)
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--spin-us", type=int, default=0)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     modes = [False, True] if a.both else [a.pruned]
@@ -225,7 +226,7 @@ def main():
     allres = []
     for m in modes:
         r, pools = run(a.seconds, m, a.conf, pool=a.pool, pools=pools, vote_rows=a.vote_rows,
-                       lanes=a.lanes)
+                       lanes=a.lanes, spin_us=a.spin_us)
         print(json.dumps(r), flush=True)
         allres.append(r)
     if a.out:

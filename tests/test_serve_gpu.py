@@ -61,9 +61,9 @@ def schedule(n_streams, n, seed):
     return reqs
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_plain_server_matches_alone(lane, synth, oracle, lanes):
-    say("serve plain, lanes", lanes)
+@pytest.mark.parametrize("lanes,spin_us", [(1, 0), (2, 0), (2, 5000)])
+def test_plain_server_matches_alone(lane, synth, oracle, lanes, spin_us):
+    say("serve plain, lanes", lanes, "spin_us", spin_us)
     P = pools(synth, STREAMS)
     refs = [[alone(lane, P[s][j], STREAMS[s]) for j in range(len(P[s]))] for s in range(len(STREAMS))]
     # the oracle agrees with the alone path on two of the frames
@@ -73,7 +73,7 @@ def test_plain_server_matches_alone(lane, synth, oracle, lanes):
         want = oracle.pipeline(P[s][0], C, S, st.get("k", 8))
         c, t, r, v = refs[s][0]
         assert c == want["count"] and (t == want["theta_idx"]).all() and (v == want["votes"]).all()
-    srv = lane.Server(STREAMS, hbm_budget=1 << 30, max_pending=64, lanes=lanes)
+    srv = lane.Server(STREAMS, hbm_budget=1 << 30, max_pending=64, lanes=lanes, spin_us=spin_us)
     try:
         for rep in range(2):
             sched = schedule(len(STREAMS), 40, seed=rep)

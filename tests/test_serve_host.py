@@ -92,7 +92,7 @@ def test_admission_pruned_counts_network_state(lane, serve):
 @pytest.mark.parametrize("kw,code", [
     (dict(vote_rows=3), -1), (dict(max_pending=0), -1), (dict(sobel_strip_rows=12), -1),
     (dict(pruned=True, conf=0.4), -1), (dict(pruned=True), -1),  # no weights
-    (dict(lanes=-1), -1), (dict(lanes=5), -1),
+    (dict(lanes=-1), -1), (dict(lanes=5), -1), (dict(spin_us=-1), -1), (dict(spin_us=10 ** 7 + 1), -1),
 ])
 def test_plan_rejects_bad_config(lane, kw, code):
     args = dict(hbm_budget=1 << 30)
