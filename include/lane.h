@@ -595,7 +595,7 @@ int lane_server_create(const lane_stream_cfg *streams, int32_t n, const lane_ser
  * copy ahead, started by this call then) or when its batch starts, so they
  * must stay valid and unchanged until its result is taken (page-locked
  * memory copies asynchronously; a pageable frame makes the copy ahead, and
- * so this call, wait for the bytes to be read).  Returns
+ * so this call, wait for the bytes to be read, while the lanes go on).  Returns
  * LANE_E_BUSY, and completes the request as dropped, when the stream already
  * has max_pending requests waiting; LANE_E_ARG for a stream not admitted.
  * Thread-safe. */

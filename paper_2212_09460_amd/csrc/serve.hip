@@ -222,8 +222,9 @@ struct lane_server {
     // copy-ahead: the frame of the request at the head of an idle slot's
     // queue is copied to the slot on its own stream as soon as it is
     // known, so the copy overlaps the refill running meanwhile; up_id[slot]
-    // = the request whose copy up_ev[slot] marks (0: none); busy[slot]: the
-    // slot is in a running refill (its buffers still in use)
+    // = the request whose copy up_ev[slot] marks (0: none); busy[slot]: 1
+    // the slot is in a running refill (its buffers still in use), 2 a copy
+    // ahead into it is being issued
     hipStream_t up_stream = nullptr;
     std::vector<hipEvent_t> up_ev;
     std::vector<uint64_t> up_id;
@@ -278,15 +279,44 @@ hipError_t copy_frame(lane_server* s, int slot, const Req& q, hipStream_t st) {
                             (size_t)c.cfg.H, hipMemcpyHostToDevice, st);
 }
 
-// (caller holds s->mu) copy the frame of the request at the head of the
-// slot's queue ahead, if the slot is idle and that copy is not out yet
-void copy_ahead(lane_server* s, int slot) {
-    if (!s->up_stream || s->busy[slot] || s->error != LANE_OK) return;
+// Copy ahead, in two steps so that the copy is issued without the lock (a
+// pageable frame makes the copy call wait for the bytes, and the lanes
+// need the lock to take and complete requests meanwhile).
+// (caller holds s->mu) claim the request at the head of an idle slot's
+// queue if its frame is not copied yet: the slot is marked copying (busy 2),
+// so no lane takes it until the copy and its event are issued
+bool copy_ahead_claim(lane_server* s, int slot, std::vector<std::pair<int, Req>>& claims) {
+    if (!s->up_stream || s->busy[slot] || s->error != LANE_OK) return false;
     const auto& d = s->pending[slot];
-    if (d.empty() || s->up_id[slot] == d.front().id) return;
-    hipError_t e = copy_frame(s, slot, d.front(), s->up_stream);
-    if (e == hipSuccess) e = hipEventRecord(s->up_ev[slot], s->up_stream);
-    s->up_id[slot] = e == hipSuccess ? d.front().id : 0;
+    if (d.empty() || s->up_id[slot] == d.front().id) return false;
+    s->busy[slot] = 2;
+    claims.emplace_back(slot, d.front());
+    return true;
+}
+
+// (lk holds s->mu) issue the claimed copies with the lock released, then
+// release their slots and wake the lanes
+void copy_ahead_issue(lane_server* s, std::unique_lock<std::mutex>& lk,
+                      std::vector<std::pair<int, Req>>& claims) {
+    if (claims.empty()) return;
+    std::vector<uint8_t> ok(claims.size());
+    lk.unlock();
+    for (size_t i = 0; i < claims.size(); ++i) {
+        const int slot = claims[i].first;
+        hipError_t e = copy_frame(s, slot, claims[i].second, s->up_stream);
+        if (e == hipSuccess) e = hipEventRecord(s->up_ev[slot], s->up_stream);
+        ok[i] = e == hipSuccess;
+    }
+    lk.lock();
+    for (size_t i = 0; i < claims.size(); ++i) {
+        const int slot = claims[i].first;
+        // the copy did not go out: the refill that takes the request copies it
+        s->up_id[slot] = ok[i] ? claims[i].second.id : 0;
+        s->busy[slot] = 0;
+    }
+    claims.clear();
+    s->work_gen.fetch_add(1, std::memory_order_release);
+    s->cv_work.notify_all();
 }
 
 // one refill on lane L (its slots marked busy by the caller, so no other
@@ -339,6 +369,7 @@ void worker_main(lane_server* s, int li) {
     lane_server::Lane& L = s->lanes[li];
     std::vector<Req> batch;
     std::vector<lane_result> out;
+    std::vector<std::pair<int, Req>> claims;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         // work for this lane: a request of a stream that is not in a running refill
@@ -411,14 +442,17 @@ void worker_main(lane_server* s, int li) {
         for (const Req& q : batch) {
             const int slot = s->slot_of[q.stream];
             s->busy[slot] = 0;
-            copy_ahead(s, slot);
+            copy_ahead_claim(s, slot, claims);
         }
         s->work_gen.fetch_add(1, std::memory_order_release);
+        copy_ahead_issue(s, lk, claims);
     }
 }
 
-int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, uint64_t frame_id,
-                  int64_t tag) {
+// (lk holds s->mu) queue one request; a copy ahead of its frame is issued
+// with the lock released
+int submit_locked(lane_server* s, std::unique_lock<std::mutex>& lk, int stream, const uint8_t* frame,
+                  int pitch, uint64_t frame_id, int64_t tag, std::vector<std::pair<int, Req>>& claims) {
     Req q;
     q.stream = stream;
     q.pitch = pitch;
@@ -440,7 +474,10 @@ int submit_locked(lane_server* s, int stream, const uint8_t* frame, int pitch, u
         return LANE_E_BUSY;
     }
     d.push_back(q);
-    if (d.size() == 1) copy_ahead(s, slot);
+    if (d.size() == 1 && copy_ahead_claim(s, slot, claims)) {
+        copy_ahead_issue(s, lk, claims);  // wakes the lanes
+        return LANE_OK;
+    }
     s->work_gen.fetch_add(1, std::memory_order_release);
     s->cv_work.notify_one();
     return LANE_OK;
@@ -779,8 +816,9 @@ int lane_server_submit(lane_server* s, int32_t stream, const uint8_t* frame, int
                        uint64_t frame_id) {
     const int st = check_submit(s, stream, frame, pitch);
     if (st != LANE_OK) return st;
-    std::lock_guard<std::mutex> g(s->mu);
-    return submit_locked(s, stream, frame, pitch, frame_id, -1);
+    std::vector<std::pair<int, Req>> claims;
+    std::unique_lock<std::mutex> lk(s->mu);
+    return submit_locked(s, lk, stream, frame, pitch, frame_id, -1, claims);
 }
 
 int lane_server_poll(lane_server* s, lane_result* out, int32_t max, int32_t wait_ms, int32_t* n_out) {
@@ -814,6 +852,8 @@ int lane_server_replay(lane_server* s, const lane_request* reqs, int32_t n, lane
         s->replay_out = results;
         s->replay_left = n;
     }
+    std::vector<std::pair<int, Req>> claims;
+    claims.reserve(1);
     const int64_t t0 = now_ns();
     for (int i = 0; i < n; ++i) {
         const int64_t target = t0 + reqs[i].t_offset_ns;
@@ -822,8 +862,8 @@ int lane_server_replay(lane_server* s, const lane_request* reqs, int32_t n, lane
         if (early > 0) std::this_thread::sleep_for(std::chrono::nanoseconds(early));
         while (now_ns() < target) {
         }
-        std::lock_guard<std::mutex> g(s->mu);
-        submit_locked(s, reqs[i].stream, reqs[i].frame, reqs[i].pitch, reqs[i].frame_id, i);
+        std::unique_lock<std::mutex> lk(s->mu);
+        submit_locked(s, lk, reqs[i].stream, reqs[i].frame, reqs[i].pitch, reqs[i].frame_id, i, claims);
     }
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] { return s->replay_left == 0; });
