@@ -9,16 +9,18 @@
 // compute stream:
 //
 //   wait for requests -> take the oldest request of every stream not in a
-//   running refill (one per stream) -> copy those frames into their slots ->
-//   write the lane's per-slot flags -> one graph launch over all slots
-//   (proposal network and mask per size class when pruned, then clear,
-//   Sobel, vote, peaks; switched-off slots return at once; the peak search
-//   writes each slot's peaks straight into page-locked host memory) ->
-//   complete the requests.
+//   running refill (one per stream) -> write the lane's per-slot flags ->
+//   the set-up kernel (counters, queue, split accumulators) -> copy those
+//   frames into their slots (or wait for their copies ahead) -> one graph
+//   launch over all slots (proposal network and mask per size class when
+//   pruned, beside Sobel, then vote, peaks; switched-off slots return at
+//   once; the peak search writes each slot's peaks straight into
+//   page-locked host memory) -> complete the requests.
 //
 // A slot belongs to one refill at a time, so the lanes never share a frame's
-// buffers, and a stream's requests run in order.  A single frame fills only
-// part of the GPU (a 1080p vote is 23 theta slices x 8 edge parts), so a
+// buffers, and a stream's requests run in order.  Most kernels of a
+// one-frame refill leave much of the GPU idle (the Sobel pass, key pass and
+// peak search of one frame, the vote's last round of workgroups), so a
 // request that arrives while another stream's refill runs starts beside it
 // on a second lane rather than queueing behind it.  Streams with the same
 // configuration form a class whose frame slots are contiguous, so the
@@ -326,9 +328,12 @@ int run_batch(lane_server* s, lane_server::Lane& L, const std::vector<Req>& batc
     const int n_slots = (int)s->streams.size();
     memset(L.h_flags, 0, (size_t)n_slots);
     for (const Req& q : batch) L.h_flags[s->slot_of[q.stream]] = 1;
-    // switches and the work lists of exactly these slots
+    // switches and the work lists of exactly these slots, then the set-up
+    // kernel (counters, the vote's queue and split accumulators), which does
+    // not read the frames and so runs while their copies may still be going
     hipError_t e = lane_batch_select(L.plan, L.h_flags, L.stream) == LANE_OK ? hipSuccess
                                                                               : hipErrorUnknown;
+    if (e == hipSuccess && lane_batch_enqueue_pass_stage(L.plan, 0, L.stream) != LANE_OK) e = hipErrorUnknown;
     for (size_t i = 0; i < batch.size() && e == hipSuccess; ++i) {
         const Req& q = batch[i];
         const int slot = s->slot_of[q.stream];
@@ -738,7 +743,7 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         return LANE_E_DEVICE;
     }
     // pruned: the network and the masks need only the frames, so they form a
-    // branch of their own beside the counter clear and the Sobel pass (a side
+    // branch of their own beside the Sobel pass (a side
     // stream forked and joined with events inside the capture), joined
     // before the vote
     hipStream_t side = nullptr;
@@ -769,7 +774,9 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
             }
             if (e == hipSuccess) e = hipEventRecord(ev_join, side);
         }
-        for (int stg = 0; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
+        // (stage 0, the set-up kernel, is launched by the refill ahead of the
+        // wait for its frames' copies: it does not read the frames)
+        for (int stg = 1; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
             if (stg == 2 && cfg->pruned) {
                 e = hipStreamWaitEvent(cs, ev_join, 0);
                 if (e != hipSuccess) break;
