@@ -83,6 +83,7 @@ struct lane_batch {
     bool vote_xcd = false;   // per-XCD ticket queues
     int vote_split = 1;      // workgroups per theta slice (E)
     int vote_half_lds = 0;   // every slice fits half the LDS: two vote workgroups per CU
+    int sobel_latency = 0;   // the Sobel pass with the large list stage (few frames at once)
     // split vote with tile masks: pruned copies of those frames' edge lists
     PruneDesc* d_prune = nullptr;
     int n_prune = 0, prune_max_nseg = 0;
@@ -149,9 +150,10 @@ hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s, bool pass = fa
             // aligned frames first (vector loads), then the rest
             hipError_t e = hipSuccess;
             if (b->n_sobel_fast > 0)
-                e = lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 1, b->grid_sobel, s);
+                e = lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 1, b->sobel_latency,
+                                            b->grid_sobel, s);
             if (e != hipSuccess || b->n_sobel_items == b->n_sobel_fast) return e;
-            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 0,
+            return lane_launch_sobel_batch(b->d_sobel, b->d_sobel_items, b->d_counts, 0, b->sobel_latency,
                                            b->grid_sobel_slow, s);
         }
         case 2:
@@ -200,8 +202,12 @@ void free_plan(lane_batch* b) {
 
 extern "C" {
 
-int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune_opt,
-                      lane_batch** out) {
+// latency: 1 = the plan serves few frames at a time (the Sobel pass with the
+// large list stage), 0 = many, -1 = decided from the plan's size (large
+// stage when every Sobel item of all its frames fits one round of the GPU at
+// the large stage's two workgroups per CU)
+LANE_INTERNAL int lane_batch_create_shaped(const lane_frame* frames, int32_t n, const lane_tune* tune_opt,
+                                           int latency, lane_batch** out) {
     if (!frames || n < 1 || !out) return LANE_E_ARG;
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
@@ -418,6 +424,7 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     b->vote_xcd = per_xcd;
     b->h_vxcd = vxcd;
     b->vote_half_lds = all_half ? 1 : 0;
+    b->sobel_latency = latency >= 0 ? (latency ? 1 : 0) : (b->n_sobel_items <= cus * 2 * kSobelWaves ? 1 : 0);
     b->vote_split = E;
 
     // one device allocation for every table
@@ -590,6 +597,11 @@ int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune
     }
     *out = b;
     return LANE_OK;
+}
+
+int lane_batch_create(const lane_frame* frames, int32_t n, const lane_tune* tune_opt,
+                      lane_batch** out) {
+    return lane_batch_create_shaped(frames, n, tune_opt, -1, out);
 }
 
 int lane_batch_launch(lane_batch* b, void* stream) {

@@ -13,7 +13,8 @@ extern "C" {
 LANE_INTERNAL hipError_t lane_launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 LANE_INTERNAL hipError_t lane_launch_sobel(const lane::SobelDesc* d, int mode, hipStream_t s);
 LANE_INTERNAL hipError_t lane_launch_sobel_batch(const lane::SobelDesc* descs, const int2* items,
-                                                 const int* counts, int fast, int grid, hipStream_t s);
+                                                 const int* counts, int fast, int latency, int grid,
+                                                 hipStream_t s);
 LANE_INTERNAL int lane_sobel_items(int W, int H, int strip_rows);
 LANE_INTERNAL int lane_sobel_fast_ok(const lane::SobelDesc* d, int mode);
 
@@ -77,6 +78,8 @@ LANE_INTERNAL int lane_mask_from_logits_active(const float* logits, int32_t W, i
                                                const uint8_t* active, void* stream);
 
 // batch.hip
+LANE_INTERNAL int lane_batch_create_shaped(const lane_frame* frames, int32_t n, const lane_tune* tune_opt,
+                                           int latency, lane_batch** out);
 LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream);
 
 }  // extern "C"

@@ -729,7 +729,8 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     lane_tune tune = {serve_vote_rows(*cfg), 1, 0, cfg->sobel_strip_rows > 0 ? cfg->sobel_strip_rows : 8,
                       serve_vote_split(*cfg)};
     for (auto& L : s->lanes) {
-        if (ok && lane_batch_create(frames.data(), n_slots, &tune, &L.plan) != LANE_OK) ok = false;
+        // a refill runs one or a few frames: the latency shape of the Sobel pass
+        if (ok && lane_batch_create_shaped(frames.data(), n_slots, &tune, 1, &L.plan) != LANE_OK) ok = false;
         ok = ok && lane_batch_active_flags(L.plan, &L.d_flags) == LANE_OK;
     }
     if (!ok) {

@@ -239,9 +239,16 @@ __device__ __forceinline__ uint32_t raw_edge_bits(const RawRow& r, int x0, int W
 // Each lane first places its two tiles' coordinates in the wave's LDS
 // stage (at their final offsets), then the wave copies the stage out with
 // 128-bit stores, so every store instruction writes 1 KB of consecutive
-// entries instead of 64 scattered words.  A tile row with more than
-// kStageCap edges goes out in several passes.
+// entries instead of 64 scattered words.  A tile row with more than CAP
+// edges goes out in several passes of CAP entries: in each, the lanes whose
+// runs lie inside the pass write them the fast way, the one or two lanes
+// whose runs cross its bounds entry by entry.  Two stage sizes: 2048 entries
+// (8 KB per wave) keeps enough Sobel workgroups per CU for a pass over many
+// frames; 4096 (16 KB per wave, two workgroups per CU) puts nearly every
+// tile row of a road frame in one pass, which shortens the slowest wave of a
+// pass over one or a few frames (a 720p frame 22 -> 14 us).
 constexpr int kStageCap = 2048;
+constexpr int kStageCapLatency = 4096;
 
 static_assert(kWave * kSobelWaves == 256, "one table entry per thread");
 
@@ -258,6 +265,7 @@ __device__ __forceinline__ uint2 row_byte_columns(uint32_t b) {
     return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 }
 
+template <int CAP>
 __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListLayout& L, int chunk,
                                                  int ty, uint64_t m0, uint64_t m1, int lane,
                                                  uint32_t* __restrict__ stage,
@@ -285,16 +293,17 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     const uint32_t xa = (uint32_t)(txa * kTile);
     const uint32_t y0 = (uint32_t)(ty * kTile) << 16;
     const uint32_t end = off + tot;
-    for (uint32_t p0 = 0; p0 < total; p0 += kStageCap) {
-        if (total <= (uint32_t)kStageCap) {
-            // One pass.  The lane's 16 row bytes (tile a rows 0-7, tile b
-            // rows 0-7) in order: each writes its entries as a block of 8
-            // (the row's columns from the table; the slots past its count
-            // hold junk that the next row byte overwrites), as long as the
-            // block ends inside the lane's run.  The row bytes after that
-            // (their entries are the run's last seven or fewer) go one
-            // entry at a time.
-            uint32_t p = off, nfull = 0;
+    for (uint32_t p0 = 0; p0 < total; p0 += CAP) {
+        if (off >= p0 && end <= p0 + (uint32_t)CAP) {
+            // The run inside this pass.  The lane's 16 row bytes (tile a
+            // rows 0-7, tile b rows 0-7) in order: each writes its entries
+            // as a block of 8 (the row's columns from the table; the slots
+            // past its count hold junk that the next row byte overwrites),
+            // as long as the block ends inside the lane's run.  The row
+            // bytes after that (their entries are the run's last seven or
+            // fewer) go one entry at a time.
+            uint32_t p = off - p0, nfull = 0;  // stage positions: entry p0 + i at stage[i]
+            const uint32_t end_s = end - p0;
 #pragma unroll 1  // (unrolled, the table reads of all 16 hoist and spill)
             for (int g = 0; g < 4; ++g) {  // four row bytes at a time: their table reads go out together
                 const uint32_t w = (uint32_t)((g < 2 ? m0 : m1) >> (32 * (g & 1)));
@@ -305,7 +314,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
                 for (int i = 0; i < 4; ++i) {
                     const int j = 4 * g + i;
                     const uint32_t rb = y0 + ((uint32_t)(j & 7) << 16) + xa + (j < 8 ? 0u : (uint32_t)kTile);
-                    if (p + 8u <= end) {
+                    if (p + 8u <= end_s) {
                         uint32_t* q = stage + p;
 #pragma unroll
                         for (int c = 0; c < 4; ++c) q[c] = rb + ((cols[i].x >> (8 * c)) & 0xFFu);
@@ -319,7 +328,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
             // row bytes nfull .. 15
             uint64_t t0 = nfull >= 8 ? 0ull : (m0 >> (8 * nfull)) << (8 * nfull);
             uint64_t t1 = nfull <= 8 ? m1 : nfull >= 16 ? 0ull : (m1 >> (8 * (nfull - 8))) << (8 * (nfull - 8));
-            uint32_t e = end - (uint32_t)(__popcll(t0) + __popcll(t1));
+            uint32_t e = end_s - (uint32_t)(__popcll(t0) + __popcll(t1));
             while (t0 | t1) {
                 const bool in_a = t0 != 0;
                 const uint64_t m = in_a ? t0 : t1;
@@ -328,10 +337,11 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
                 if (in_a) t0 &= t0 - 1ull;
                 else t1 &= t1 - 1ull;
             }
-        } else {
-            // this lane's run, tile a then tile b, row-major in a tile; only
-            // the entries of the current pass land in the stage
-            uint32_t e = off - p0;  // wraps for runs before the pass: then >= kStageCap
+        } else if (off < p0 + (uint32_t)CAP && end > p0) {
+            // a run crossing the pass's bounds: tile a then tile b,
+            // row-major in a tile; only the entries of this pass land in the
+            // stage
+            uint32_t e = off - p0;  // wraps for runs before the pass: then >= CAP
 #pragma unroll
             for (int q = 0; q < 4; ++q) {  // (tile a, rows 0-3), (a, 4-7), (b, 0-3), (b, 4-7)
                 uint32_t m = (uint32_t)(((q < 2) ? m0 : m1) >> ((q & 1) * 32));
@@ -339,7 +349,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
                 while (m) {
                     const uint32_t bit = (uint32_t)__builtin_ctz(m);
                     m &= m - 1u;
-                    if (e < (uint32_t)kStageCap) stage[e] = base + ((bit >> 3) << 16) + (bit & 7u);
+                    if (e < (uint32_t)CAP) stage[e] = base + ((bit >> 3) << 16) + (bit & 7u);
                     ++e;
                 }
             }
@@ -349,7 +359,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t n = min(total - p0, (uint32_t)kStageCap);
+        const uint32_t n = min(total - p0, (uint32_t)CAP);
         // whole 16-byte groups; the last may carry up to three stale words
         // past the segment's count, inside the segment's capacity
         for (uint32_t g = (uint32_t)lane * 4u; g < n; g += 4u * kWave)
@@ -363,7 +373,7 @@ __device__ __forceinline__ void compact_tile_row(const SobelDesc& d, const ListL
     }
 }
 
-template <bool FAST, int MODE>
+template <bool FAST, int MODE, int CAP>
 __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ stage,
                            const uint2* __restrict__ lut) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -385,7 +395,7 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
         m1 |= (uint64_t)((bits >> 8) & 0xFFu) << (ly * 8);
     };
     auto flush = [&](int ty) {
-        if (d.list) compact_tile_row(d, L, chunk, ty, m0, m1, lane, stage, lut);
+        if (d.list) compact_tile_row<CAP>(d, L, chunk, ty, m0, m1, lane, stage, lut);
         m0 = 0;
         m1 = 0;
     };
@@ -469,17 +479,18 @@ __device__ void sobel_item(const SobelDesc& d, int item, uint32_t* __restrict__ 
     }
 }
 
+// (one frame: the latency stage)
 template <bool FAST, int MODE>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel(SobelDesc d, int n_items) {
-    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
+    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCapLatency];
     __shared__ uint2 s_lut[256];
     s_lut[threadIdx.x] = row_byte_columns(threadIdx.x);  // 256 threads
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int item = blockIdx.x * kSobelWaves + wave;
     if (item >= n_items) return;  // whole wave leaves; no barriers after this
-    sobel_item<FAST, MODE>(d, item, s_stage + wave * kStageCap, s_lut);
+    sobel_item<FAST, MODE, kStageCapLatency>(d, item, s_stage + wave * kStageCapLatency, s_lut);
 }
 
 // Batched: each wave walks the (frame, item) table with a grid stride (one
@@ -487,7 +498,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
 // persistent grid).  Frames of any size mix in one launch; frames whose rows
 // are 16-byte aligned go to the vector-load instance, the rest to the byte
 // one.
-template <bool FAST>
+template <bool FAST, int CAP>
 __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_waves_per_eu(4)))
     k_sobel_batch(const SobelDesc* __restrict__ descs, const int2* __restrict__ items,
                   const int* __restrict__ counts, int group) {
@@ -496,7 +507,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
     const int first = group == 0 ? 0 : gld(counts);
     const int n_items = gld(counts + group);
     items += first;
-    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * kStageCap];
+    __shared__ __align__(16) uint32_t s_stage[kSobelWaves * CAP];
     __shared__ uint2 s_lut[256];
     s_lut[threadIdx.x] = row_byte_columns(threadIdx.x);  // 256 threads
     __syncthreads();
@@ -507,7 +518,7 @@ __global__ void __launch_bounds__(kWave * kSobelWaves) __attribute__((amdgpu_wav
         if (w.x < 0) continue;
         const SobelDesc d = descs[w.x];
         if (!frame_on(d.active)) continue;
-        sobel_item<FAST, kModeSobel>(d, w.y, s_stage + wave * kStageCap, s_lut);
+        sobel_item<FAST, kModeSobel, CAP>(d, w.y, s_stage + wave * CAP, s_lut);
     }
 }
 
@@ -545,14 +556,17 @@ extern "C" LANE_INTERNAL int lane_sobel_fast_ok(const SobelDesc* dp, int mode) {
 }
 
 extern "C" LANE_INTERNAL hipError_t lane_launch_sobel_batch(const SobelDesc* descs, const int2* items,
-                                                            const int* counts, int fast, int grid,
-                                                            hipStream_t s) {
-    if (fast)
-        hipLaunchKernelGGL(k_sobel_batch<true>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
-                           items, counts, 0);
+                                                            const int* counts, int fast, int latency,
+                                                            int grid, hipStream_t s) {
+    const dim3 g(grid), blk(kWave * kSobelWaves);
+    if (fast && latency)
+        hipLaunchKernelGGL((k_sobel_batch<true, kStageCapLatency>), g, blk, 0, s, descs, items, counts, 0);
+    else if (fast)
+        hipLaunchKernelGGL((k_sobel_batch<true, kStageCap>), g, blk, 0, s, descs, items, counts, 0);
+    else if (latency)
+        hipLaunchKernelGGL((k_sobel_batch<false, kStageCapLatency>), g, blk, 0, s, descs, items, counts, 1);
     else
-        hipLaunchKernelGGL(k_sobel_batch<false>, dim3(grid), dim3(kWave * kSobelWaves), 0, s, descs,
-                           items, counts, 1);
+        hipLaunchKernelGGL((k_sobel_batch<false, kStageCap>), g, blk, 0, s, descs, items, counts, 1);
     return hipGetLastError();
 }
 
