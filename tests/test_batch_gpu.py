@@ -383,3 +383,31 @@ def test_mixed_batch_64_frames_tuned(lane, synth, oracle):
         b.launch()
         check(frames, wants)
     b.close()
+
+
+def test_sobel_list_stages_agree(lane, synth, oracle):
+    """A frame whose tile rows hold up to 8192 edges (every pass count of
+    both list stages) gives the oracle's edge map, count and accumulator in
+    a plan of few frames (the large list stage) and in one of many (the
+    small one)."""
+    say("sobel list stages")
+    C, S = synth.trig_q14(360)
+    Cd, Sd = torch.from_numpy(C).cuda(), torch.from_numpy(S).cuda()
+    rng = np.random.default_rng(4242)
+    W, H = 1100, 64
+    img = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    img[:, 512:600] = 0  # flat band: tile rows of every density
+    want = oracle.pipeline(img, C, S, 8, threshold=40)
+    assert want["n_edges"] > 0.6 * W * H
+    road = synth.gen_frame(synth.scene_road(1920, 1080), 77)
+    want_road = oracle.pipeline(road, C, S, 8)
+    for n_road in (0, 8):  # 8 1080p frames: more items than one round of the large stage
+        fb = lane.FrameBuffers(torch.from_numpy(img).cuda(), W, 360, 8, Cd, Sd, threshold=40)
+        others = [lane.FrameBuffers(torch.from_numpy(road).cuda(), 1920, 360, 8, Cd, Sd)
+                  for _ in range(n_road)]
+        b = lane.Batch([fb] + others, vote_rows=16)
+        for rep in range(2):
+            scribble([fb] + others)
+            b.launch()
+            check([fb] + others, [want] + [want_road] * n_road)
+        b.close()
