@@ -499,11 +499,12 @@ int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t bat
  * Each of a few refill lanes (a worker thread with its own batch plan,
  * graphs and compute stream) repeats: take the oldest pending request of
  * every stream that is not in a running refill (at most one per stream),
- * copy those frames into their slots, switch on exactly those slots, launch
- * one graph (network and mask per class when pruned, then clear, Sobel, vote,
- * peaks; switched-off slots return at once; the peak search stores each
- * slot's peaks in page-locked host memory, so no copy follows) and complete
- * the requests.  With two or more lanes, a request of a stream that is not in
+ * switch on exactly those slots, run the set-up kernel (counters and
+ * accumulators, no frame read), copy those frames into their slots (or wait
+ * for their copies ahead), launch one graph (network and mask per class when
+ * pruned, beside Sobel, then vote, peaks; switched-off slots return at once;
+ * the peak search stores each slot's peaks in page-locked host memory, so no
+ * copy follows) and complete the requests.  With two or more lanes, a request of a stream that is not in
  * the running refill starts at once beside it instead of waiting for it; a
  * stream's requests still run one at a time, in submission order.  The frame
  * of a request that heads the queue of a stream not in a running refill is
