@@ -358,3 +358,29 @@ def test_stalled_stream_does_not_hold_the_others(lane, synth):
         assert max(lat) < 20.0
     finally:
         srv.close()
+
+
+def test_polling_lanes_pause_and_stop(lane, synth):
+    """Idle lanes that poll for work (spin_us) still honour pause, resume and
+    destroy: a server destroyed while its lanes poll returns at once, a
+    paused one runs nothing until resumed, and then runs the queued frame."""
+    say("serve: polling lanes, pause and stop")
+    import time
+
+    P = pools(synth, STREAMS[:1], n=1, seed=970)
+    ref = alone(lane, P[0][0], STREAMS[0])
+    srv = lane.Server(STREAMS[:1], hbm_budget=1 << 30, max_pending=2, lanes=2, spin_us=2000000)
+    t0 = time.monotonic()
+    srv.close()  # both lanes polling
+    assert time.monotonic() - t0 < 1.0
+    srv = lane.Server(STREAMS[:1], hbm_budget=1 << 30, max_pending=2, lanes=2, spin_us=2000000)
+    try:
+        srv.pause(True)
+        assert srv.submit(0, P[0][0], frame_id=5) == 0
+        time.sleep(0.05)
+        assert srv.poll(8, wait_ms=0) == []  # paused: not run
+        srv.pause(False)
+        rs = srv.poll(8, wait_ms=5000)
+        assert len(rs) == 1 and rs[0].frame_id == 5 and rs[0].status == 0 and same(rs[0], ref, 8)
+    finally:
+        srv.close()
