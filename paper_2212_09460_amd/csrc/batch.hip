@@ -132,8 +132,8 @@ int pow2_floor(int v) {
     return p;
 }
 
-// pass: the stage is part of a whole pass (the plan's graph, the serving
-// graph), where stage 0 also does the vote's set-up (its queue, split
+// pass: the stage is part of a whole pass (the plan's graph, a serving
+// refill), where stage 0 also does the vote's set-up (its queue, split
 // accumulators) so that one kernel does all of it; otherwise every stage
 // stands alone.
 hipError_t enqueue_stage(lane_batch* b, int stage, hipStream_t s, bool pass = false) {
@@ -680,7 +680,9 @@ int lane_batch_launch_stage(lane_batch* b, int32_t stage, void* stream) {
 }
 
 // One stage of a whole pass (stage 0 also does the vote's set-up), for a
-// graph that puts other work between the stages (the serving loop).
+// caller that puts other work between the stages (a serving refill: its
+// set-up kernel ahead of the frame copies, its network beside the Sobel
+// pass in a graph of its own).
 LANE_INTERNAL int lane_batch_enqueue_pass_stage(lane_batch* b, int32_t stage, void* stream) {
     if (!b || stage < 0 || stage > 4) return LANE_E_ARG;
     return enqueue_stage(b, stage, (hipStream_t)stream, true) == hipSuccess ? LANE_OK : LANE_E_DEVICE;
