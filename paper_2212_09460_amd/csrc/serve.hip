@@ -647,11 +647,13 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
     s->busy.assign(n_slots, 0);
     for (int i = 0; i < n_slots && ok; ++i)
         ok = hipEventCreateWithFlags(&s->up_ev[i], hipEventDisableTiming) == hipSuccess;
+    // each slot's peaks on cache lines of their own (256 bytes): two lanes'
+    // refills store into the buffer while the other's results are read
     size_t hp = 0;
     s->h_peak_off.resize(n_slots);
     for (int i = 0; i < n_slots; ++i) {
         s->h_peak_off[i] = hp;
-        hp += 3 * (size_t)s->streams[i].k + 1;
+        hp += (3 * (size_t)s->streams[i].k + 1 + 63) & ~(size_t)63;
     }
     ok = ok && hipHostMalloc((void**)&s->h_peaks, sizeof(int32_t) * hp, hipHostMallocDefault) == hipSuccess;
     int32_t* d_peaks = nullptr;  // h_peaks as the device addresses it
