@@ -502,7 +502,7 @@ int lane_mask_from_logits(const float *logits, int32_t W, int32_t H, int32_t bat
  * switch on exactly those slots, run the set-up kernel (counters and
  * accumulators, no frame read), copy those frames into their slots (or wait
  * for their copies ahead), launch one graph (network and mask per class when
- * pruned, beside Sobel, then vote, peaks; switched-off slots return at once;
+ * pruned, then Sobel, vote, peaks; switched-off slots return at once;
  * the peak search stores each slot's peaks in page-locked host memory, so no
  * copy follows) and complete the requests.  With two or more lanes, a request of a stream that is not in
  * the running refill starts at once beside it instead of waiting for it; a

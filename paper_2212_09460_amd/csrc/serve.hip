@@ -13,9 +13,9 @@
 //   the set-up kernel (counters, queue, split accumulators) -> copy those
 //   frames into their slots (or wait for their copies ahead) -> one graph
 //   launch over all slots (proposal network and mask per size class when
-//   pruned, beside Sobel, then vote, peaks; switched-off slots return at
-//   once; the peak search writes each slot's peaks straight into
-//   page-locked host memory) -> complete the requests.
+//   pruned, then Sobel, vote, peaks; switched-off slots return at once;
+//   the peak search writes each slot's peaks straight into page-locked
+//   host memory) -> complete the requests.
 //
 // A slot belongs to one refill at a time, so the lanes never share a frame's
 // buffers, and a stream's requests run in order.  Most kernels of a
@@ -745,26 +745,17 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         free_server(s);
         return LANE_E_DEVICE;
     }
-    // pruned: the network and the masks need only the frames, so they form a
-    // branch of their own beside the Sobel pass (a side
-    // stream forked and joined with events inside the capture), joined
-    // before the vote
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // pruned: the network and the masks run first, in the same sequence as
+    // the rest (a branch of their own beside the Sobel pass, forked and
+    // joined inside the graph, measured the same at p50 and worse in the
+    // tails, with a second lane's refill sharing the GPU)
     hipError_t e = hipSuccess;
-    if (cfg->pruned) {
-        e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming);
-    }
     int cst = LANE_OK;
     // one capture for lane L: the classes of cls_mask run their network and masks
     auto capture = [&](lane_server::Lane& L, uint32_t cls_mask, hipGraph_t* gout, hipGraphExec_t* xout) {
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return;
         if (cfg->pruned) {
-            e = hipEventRecord(ev_fork, cs);
-            if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
             for (size_t c = 0; c < s->classes.size() && e == hipSuccess; ++c) {
                 if (c < 32 && !((cls_mask >> c) & 1u)) continue;
                 auto& cl = s->classes[c];
@@ -772,20 +763,14 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
                 // network and tile masks in one kernel
                 cst = lane_cnn_infer_mask_active(cl.img, cl.cfg.W, cl.cfg.H, cl.pitch,
                                                  (int64_t)sz[cl.first_slot].img, cl.n, base + o_pk,
-                                                 cl.logits, cfg->conf, cl.mask, fl, side);
+                                                 cl.logits, cfg->conf, cl.mask, fl, cs);
                 if (cst != LANE_OK) break;
             }
-            if (e == hipSuccess) e = hipEventRecord(ev_join, side);
         }
         // (stage 0, the set-up kernel, is launched by the refill ahead of the
         // wait for its frames' copies: it does not read the frames)
-        for (int stg = 1; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg) {
-            if (stg == 2 && cfg->pruned) {
-                e = hipStreamWaitEvent(cs, ev_join, 0);
-                if (e != hipSuccess) break;
-            }
+        for (int stg = 1; stg < 4 && e == hipSuccess && cst == LANE_OK; ++stg)
             cst = lane_batch_enqueue_pass_stage(L.plan, stg, cs);
-        }
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
@@ -810,9 +795,6 @@ int lane_server_create(const lane_stream_cfg* streams, int32_t n, const lane_ser
         }
     }
     hipStreamDestroy(cs);
-    if (side) (void)hipStreamDestroy(side);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
     if (e != hipSuccess || cst != LANE_OK) {
         free_server(s);
         return LANE_E_DEVICE;
